@@ -1,0 +1,199 @@
+"""CPU oracle for the spin spherical-harmonic and Wigner transforms.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.  The heavy
+lifting is plain C (``s2oracle.c``: direct sums, Wigner-d by a recursion in
+degree l, exact Gauss-Legendre quadrature for the MW forward transform); this
+module only marshals numpy arrays through ctypes.
+
+Arrays are numpy ``complex128``.  Layouts:
+  * spherical-harmonic coefficients ``flm[l, m + L - 1]`` (zeros for
+    ``l < max(|m|, |s|)``);
+  * MW maps ``f[t, p]`` with ``theta_t = (2t+1) pi/(2L-1)``,
+    ``phi_p = 2 pi p/(2L-1)`` (paper Sec. 4.2, MW);
+  * HEALPix maps as the RING-ordered pixel vector;
+  * Wigner coefficients ``flmn[n + N - 1, l, m + L - 1]`` and SO(3) maps
+    ``f[k, t, p]`` with ``gamma_k = 2 pi k/(2N-1)`` (Sec. 4.5).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "s2oracle.c")
+_LIB = os.path.join(_HERE, "_s2oracle.so")
+_lib = None
+
+MW, HEALPIX = 0, 1
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O3, OpenMP)."""
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lp = ctypes.POINTER(ctypes.c_longlong)
+    i = ctypes.c_int
+    lib.or_mw_thetas.argtypes = [i, dp]
+    lib.or_healpix_rings.argtypes = [i, dp, ip, lp, ip]
+    lib.or_gauss_legendre.argtypes = [i, dp, dp]
+    lib.or_wigner_d_ell.argtypes = [i, i, i, ctypes.c_double, dp]
+    lib.or_s2_inverse.argtypes = [i, i, i, i, dp, dp, i, ip]
+    lib.or_s2_forward.argtypes = [i, i, i, i, dp, dp, i, ip]
+    lib.or_s2_inverse_adjoint.argtypes = [i, i, i, i, dp, dp, i, ip]
+    lib.or_so3_inverse.argtypes = [i, i, dp, dp]
+    lib.or_so3_forward.argtypes = [i, i, dp, dp]
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _sel(sel):
+    if sel is None:
+        return -1, None
+    arr = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+    return int(arr.size), arr
+
+
+# ----------------------------------------------------------------- geometry
+def mw_thetas(L):
+    """MW colatitudes theta_t = (2t+1) pi/(2L-1), t < L (Sec. 4.2)."""
+    out = np.empty(L)
+    _load().or_mw_thetas(L, _dp(out))
+    return out
+
+
+def healpix_rings(nside):
+    """HEALPix RING geometry: (theta, nphi, start, shift) per ring."""
+    nr = 4 * nside - 1
+    th = np.empty(nr)
+    nphi = np.empty(nr, dtype=np.int32)
+    start = np.empty(nr, dtype=np.int64)
+    shift = np.empty(nr, dtype=np.int32)
+    _load().or_healpix_rings(nside, _dp(th), _ip(nphi),
+                             start.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _ip(shift))
+    return th, nphi, start, shift
+
+
+def healpix_phis(nside):
+    """Longitude of every RING-ordered pixel: phi_j = (pi/nphi)(2j + shift)."""
+    th, nphi, start, shift = healpix_rings(nside)
+    out = np.empty(12 * nside * nside)
+    for r in range(th.size):
+        j = np.arange(nphi[r])
+        out[start[r]:start[r] + nphi[r]] = np.pi * (2 * j + shift[r]) / nphi[r]
+    return out
+
+
+def gauss_legendre(n):
+    x = np.empty(n)
+    w = np.empty(n)
+    _load().or_gauss_legendre(n, _dp(x), _dp(w))
+    return x, w
+
+
+def num_rings(L, sampling, nside=0):
+    return L if sampling == MW else 4 * nside - 1
+
+
+def map_size(L, sampling, nside=0):
+    return L * (2 * L - 1) if sampling == MW else 12 * nside * nside
+
+
+# ----------------------------------------------------------------- Wigner d
+def wigner_d(L, m, n, beta):
+    """d^l_{mn}(beta) for l = 0..L-1 (independent l-recursion)."""
+    out = np.empty(L)
+    _load().or_wigner_d_ell(L, int(m), int(n), float(beta), _dp(out))
+    return out
+
+
+# ----------------------------------------------------------------- S2 transforms
+def s2_inverse(flm, L, spin=0, sampling=MW, nside=0, rings=None):
+    """Inverse spin SHT by direct summation (Eqs. 4, 32-33).
+
+    Returns the MW map [L, 2L-1] / HEALPix pixel vector, or, with ``rings``,
+    the concatenated samples of the selected rings."""
+    flm = _c128(flm)
+    assert flm.shape == (L, 2 * L - 1)
+    lib = _load()
+    nsel, sel = _sel(rings)
+    if sampling == MW:
+        nout = (L if nsel < 0 else nsel) * (2 * L - 1)
+    else:
+        _, nphi, _, _ = healpix_rings(nside)
+        nout = int(nphi.sum()) if nsel < 0 else int(nphi[np.asarray(rings)].sum())
+    f = np.empty(nout, dtype=np.complex128)
+    lib.or_s2_inverse(L, spin, sampling, nside, _dp(flm.view(np.float64)), _dp(f.view(np.float64)),
+                      nsel, _ip(sel) if sel is not None else None)
+    if sampling == MW and nsel < 0:
+        return f.reshape(L, 2 * L - 1)
+    return f
+
+
+def s2_forward(f, L, spin=0, sampling=MW, nside=0, ms=None):
+    """Forward spin SHT: exact MW transform (GL route) or HEALPix quadrature.
+
+    With ``ms`` only those order columns are computed (others are zero)."""
+    f = _c128(f).reshape(-1)
+    assert f.size == map_size(L, sampling, nside)
+    flm = np.empty((L, 2 * L - 1), dtype=np.complex128)
+    nsel, sel = _sel(ms)
+    _load().or_s2_forward(L, spin, sampling, nside, _dp(f.view(np.float64)), _dp(flm.view(np.float64)),
+                          nsel, _ip(sel) if sel is not None else None)
+    return flm
+
+
+def s2_inverse_adjoint(g, L, spin=0, sampling=MW, nside=0, ms=None):
+    """Hermitian adjoint of the inverse SHT: sum_{t,p} g conj(sY_lm)."""
+    g = _c128(g).reshape(-1)
+    assert g.size == map_size(L, sampling, nside)
+    out = np.empty((L, 2 * L - 1), dtype=np.complex128)
+    nsel, sel = _sel(ms)
+    _load().or_s2_inverse_adjoint(L, spin, sampling, nside, _dp(g.view(np.float64)),
+                                  _dp(out.view(np.float64)), nsel, _ip(sel) if sel is not None else None)
+    return out
+
+
+# ----------------------------------------------------------------- SO(3) transforms
+def so3_inverse(flmn, L, N):
+    """Inverse Wigner transform (Eq. 13), MW in (beta, alpha), 2N-1 gammas."""
+    flmn = _c128(flmn)
+    assert flmn.shape == (2 * N - 1, L, 2 * L - 1)
+    f = np.empty((2 * N - 1, L, 2 * L - 1), dtype=np.complex128)
+    _load().or_so3_inverse(L, N, _dp(flmn.view(np.float64)), _dp(f.view(np.float64)))
+    return f
+
+
+def so3_forward(f, L, N):
+    """Forward Wigner transform (Eq. 14), exact for MW sampling."""
+    f = _c128(f)
+    assert f.shape == (2 * N - 1, L, 2 * L - 1)
+    flmn = np.empty((2 * N - 1, L, 2 * L - 1), dtype=np.complex128)
+    _load().or_so3_forward(L, N, _dp(f.view(np.float64)), _dp(flmn.view(np.float64)))
+    return flmn

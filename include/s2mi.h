@@ -1,0 +1,181 @@
+/*
+ * s2mi.h -- C ABI of the MI355X (gfx950) spin spherical-harmonic and Wigner
+ * transform library.
+ *
+ * Method: Price & McEwen, "Differentiable and accelerated spherical harmonic
+ * and Wigner transforms" (arXiv 2311.14670).  The O(L^3) stage -- Wigner-d
+ * functions d^l_{m,n}(theta) generated on the fly by the descending-m
+ * three-term recursion (Sec. 3.3, Eqs. 25-27) with running renormalisation
+ * (Sec. 3.4) and contracted against coefficients (Eq. 33) or ring Fourier
+ * modes (Eq. 30) -- runs in hand-written HIP kernels; the per-ring phi-DFT
+ * (Eqs. 31-32) runs in the library's own FFT kernels.
+ *
+ * Conventions
+ *   spin harmonics  sY_lm(theta,phi) = (-1)^s sqrt((2l+1)/4pi) e^{i m phi} d^l_{m,-s}(theta)
+ *                   (Eqs. 9-10; Condon-Shortley phase, Eq. 1).
+ *   bandlimit L     coefficients vanish for l >= L (Sec. 2.4).
+ *   coefficients    complex128 (interleaved re, im), dense [l][m + L - 1],
+ *                   l < L, |m| < L.  Entries with l < max(|m|, |spin|) are
+ *                   ignored on input and written as 0 on output.
+ *   MW map          complex128 [t][p], theta_t = (2t+1) pi/(2L-1), t < L
+ *                   (t = L-1 is the south pole), phi_p = 2 pi p/(2L-1),
+ *                   p < 2L-1 (Sec. 4.2, MW).
+ *   HEALPix map     complex128 RING-ordered pixel vector of 12 nside^2
+ *                   samples (Sec. 4.2, HEALPix; geometry of Gorski et al.
+ *                   2005).  The forward transform is the quadrature of
+ *                   Eq. 19 with q = 4 pi / Npix (approximate: no sampling
+ *                   theorem).
+ *   Wigner (SO(3))  coefficients [n + N - 1][l][m + L - 1] (zero for
+ *                   l < max(|m|, |n|)); maps [k][t][p] with
+ *                   gamma_k = 2 pi k/(2N-1), MW in (beta, alpha) (Sec. 4.5,
+ *                   Eqs. 13-18).
+ *   batch           the batch dimension is outermost and contiguous.
+ *
+ * Memory and streams
+ *   All data pointers passed to transforms are DEVICE pointers owned by the
+ *   caller, 16-byte aligned.  Inputs are never modified.  The workspace is a
+ *   caller-owned device buffer of at least s2_plan_info().workspace_bytes.
+ *   Transforms are enqueued asynchronously on `hip_stream` (a hipStream_t, or
+ *   NULL for the default stream) and never synchronise the host; outputs are
+ *   undefined until the stream reaches the enqueued work, and undefined if the
+ *   call returns an error.  A plan owns its device constants and is immutable
+ *   after creation: one plan may be used concurrently on several streams
+ *   provided each call has its own workspace.
+ *
+ * Errors
+ *   Every function returns S2_OK (0) or a negative code.  Argument validation
+ *   is synchronous, on the host, and happens before any device work is
+ *   enqueued.  No C++ exception crosses this interface.  The message of the
+ *   last error on the calling thread is available from
+ *   s2_last_error_message().
+ */
+#ifndef S2MI_H
+#define S2MI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define S2_OK               0
+#define S2_ERR_INVALID_ARG (-1)   /* bad L/spin/N/nside/batch, null or misaligned pointer */
+#define S2_ERR_UNSUPPORTED (-2)   /* valid request this build does not implement          */
+#define S2_ERR_OOM         (-3)   /* device or host allocation failed                     */
+#define S2_ERR_HIP         (-4)   /* HIP runtime or launch error (message kept)           */
+
+typedef struct s2_plan_s *s2_plan_t;
+
+typedef enum { S2_MW = 0, S2_HEALPIX = 1 } s2_sampling_t;
+
+/* Arithmetic of the l/theta contraction.  The Wigner-d recursion, its
+ * renormalisation, the quadrature weights and the phi-DFT are FP64 in every
+ * mode; inputs and outputs are always complex128. */
+typedef enum { S2_FP64 = 0, S2_CONTRACT_FP32 = 1, S2_CONTRACT_SPLIT_BF16 = 2 } s2_precision_t;
+
+typedef struct {
+    int L, spin, N, nside, sampling, precision, max_batch;
+    int nrings;                 /* isolatitude rings of the sphere sampling          */
+    long long nsamples;         /* complex samples per map (SO(3): per gamma slice)  */
+    long long ncoeffs;          /* L * (2L-1) per (map, n-slice): dense layout size  */
+    size_t workspace_bytes;     /* device workspace one call needs at max_batch      */
+    size_t plan_device_bytes;   /* device memory held by the plan                    */
+} s2_plan_info_t;
+
+/*
+ * Create a plan.  Paper: Sec. 4 (the separable transform of Eqs. 30-33 on an
+ * isolatitude sampling) with the Wigner recursion of Sec. 3.
+ *   L          bandlimit, 2 <= L <= 4096 (l < L).
+ *   spin       |spin| < L (S2 transforms).  Ignored (must be 0) when N > 1.
+ *   N          azimuthal band of SO(3) transforms, 1 <= N <= L; N = 1 for
+ *              sphere-only plans.  An SO(3) plan (N > 1) serves so3_*; a plan
+ *              with N == 1 serves s2_* (and so3_* with N = 1).
+ *   sampling   S2_MW or S2_HEALPIX (HEALPix: nside >= 1 and L <= 3*nside+1 is
+ *              not enforced; the caller picks L, typically 2*nside).
+ *              SO(3) plans require S2_MW.
+ *   max_batch  largest batch any call will pass (sizes the workspace), >= 1.
+ *   prec       contraction arithmetic (see s2_precision_t).
+ *   hip_stream stream on which the plan's constants are uploaded; the plan is
+ *              ready when that stream has reached the upload (callers using
+ *              another stream synchronise it first).
+ * Ownership: *out receives a plan owned by the caller, freed by
+ * s2_plan_destroy.  On error *out is set to NULL.
+ */
+int s2_plan_create(s2_plan_t *out, int L, int spin, int N, s2_sampling_t sampling,
+                   int nside, int max_batch, s2_precision_t prec, void *hip_stream);
+
+/* Free a plan and its device memory (synchronises the device first).  NULL is a no-op. */
+int s2_plan_destroy(s2_plan_t plan);
+
+/* Sizes of a plan (host only, no device work). */
+int s2_plan_info(s2_plan_t plan, s2_plan_info_t *info);
+
+/*
+ * Inverse spin SHT (Eq. 4; separable form Eqs. 32-33):
+ *   f(theta_t, phi_p) = sum_m e^{i m phi_p} sum_l (-1)^s sqrt((2l+1)/4pi) flm[l][m] d^l_{m,-s}(theta_t)
+ *   flm  [batch][L][2L-1] complex128 (device, read)
+ *   f    [batch][nsamples] complex128 (device, written)
+ */
+int s2_inverse(s2_plan_t plan, const void *flm, void *f, int batch, void *workspace,
+               void *hip_stream);
+
+/*
+ * Forward spin SHT (Eq. 5 discretised as Eqs. 30-31).
+ *   MW: exact for band-limited signals (sampling theorem, Sec. 4.2): the ring
+ *       DFT extended to the theta-torus and integrated against sin(theta) on
+ *       [0, pi].  HEALPix: quadrature of Eq. 19 with q = 4 pi / Npix.
+ *   f    [batch][nsamples] complex128 (device, read)
+ *   flm  [batch][L][2L-1] complex128 (device, written; zero outside l >= max(|m|,|s|))
+ */
+int s2_forward(s2_plan_t plan, const void *f, void *flm, int batch, void *workspace,
+               void *hip_stream);
+
+/*
+ * Hermitian adjoint of the inverse SHT (the VJP of Eqs. 56-58 in the
+ * conjugate convention PyTorch uses for complex gradients):
+ *   g_flm[l][m] = sum_{t,p} g(theta_t, phi_p) conj(sY_lm(theta_t, phi_p))
+ * i.e. an unnormalised forward phi-DFT followed by a forward-type d-stage
+ * sweep over the sampling's own rings, with d recomputed on the fly.
+ *   g      [batch][nsamples] complex128 (device, read)
+ *   g_flm  [batch][L][2L-1] complex128 (device, written)
+ */
+int s2_inverse_adjoint(s2_plan_t plan, const void *g, void *g_flm, int batch, void *workspace,
+                       void *hip_stream);
+
+/*
+ * Inverse Wigner transform (Eq. 13 with Eq. 10):
+ *   f(alpha_p, beta_t, gamma_k) = sum_n e^{i n gamma_k} sum_m e^{i m alpha_p}
+ *                                 sum_l (2l+1)/(8 pi^2) flmn[n][l][m] d^l_{mn}(beta_t)
+ *   flmn [batch][2N-1][L][2L-1], f [batch][2N-1][L][2L-1] (MW only).
+ */
+int so3_inverse(s2_plan_t plan, const void *flmn, void *f, int batch, void *workspace,
+                void *hip_stream);
+
+/*
+ * Forward Wigner transform (Eq. 14), exact for MW sampling: gamma and alpha
+ * DFTs with weights 2pi/(2N-1), 2pi/(2L-1), then per n the exact MW theta
+ * integral (spin -n torus extension, Eqs. 15-16) with weight 1.
+ */
+int so3_forward(s2_plan_t plan, const void *f, void *flmn, int batch, void *workspace,
+                void *hip_stream);
+
+/*
+ * Debug/validation: export the GPU recursion's d^l_{m,n}(theta_r) for one
+ * run n (n = -spin or +spin) at rings r = 0 .. nrings-1 (sampling order),
+ * for all l < L and 0 <= m <= l, into out[r][m][l] (double, device,
+ * written; entries with l < max(m, |n|) are 0).  Used to check the
+ * recursion against closed forms and the addition theorem.
+ */
+int s2_debug_wigner_d(s2_plan_t plan, int n, void *out, void *hip_stream);
+
+/* Human-readable name of an error code (static string). */
+const char *s2_error_string(int code);
+
+/* Message of the last error reported on the calling thread ("" if none). */
+const char *s2_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S2MI_H */

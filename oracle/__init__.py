@@ -31,7 +31,7 @@ MW, HEALPIX = 0, 1
 
 def build(force=True):
     """Compile the oracle with gcc (-O3, OpenMP)."""
-    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared",
            "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(_LIB + ".tmp", _LIB)

@@ -1,0 +1,196 @@
+"""Thin ctypes binding over the C ABI of include/s2mi.h.
+
+Argument marshalling only: tensors are checked (dtype, device, shape,
+contiguity) and their device pointers handed to the native library together
+with torch's current HIP stream.  Every step of every transform runs in the
+library's own kernels; if the library is missing, loading it raises.
+"""
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libs2mi.so"
+
+MW, HEALPIX = 0, 1
+FP64, CONTRACT_FP32, CONTRACT_SPLIT_BF16 = 0, 1, 2
+_SAMPLING = {"mw": MW, "healpix": HEALPIX, MW: MW, HEALPIX: HEALPIX}
+_PRECISION = {"fp64": FP64, "fp32": CONTRACT_FP32, "split_bf16": CONTRACT_SPLIT_BF16,
+              FP64: FP64, CONTRACT_FP32: CONTRACT_FP32, CONTRACT_SPLIT_BF16: CONTRACT_SPLIT_BF16}
+
+S2_OK = 0
+
+
+class S2Error(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"s2mi error {code}: {message}")
+        self.code = code
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("spin", ctypes.c_int), ("N", ctypes.c_int), ("nside", ctypes.c_int),
+                ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("nrings", ctypes.c_int), ("nsamples", ctypes.c_longlong), ("ncoeffs", ctypes.c_longlong),
+                ("workspace_bytes", ctypes.c_size_t), ("plan_device_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def library_path():
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def load_library():
+    """Load libs2mi.so (built in-tree by paper_2311_14670_amd.build); raise if absent."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        path = library_path()
+        if not os.path.exists(path):
+            raise S2Error(-4, f"native library {path} not found: build it with "
+                              "`python -m paper_2311_14670_amd.build` (there is no fallback path)")
+        lib = ctypes.CDLL(path)
+        vp, i, P = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p
+        lib.s2_plan_create.argtypes = [ctypes.POINTER(P), i, i, i, i, i, i, i, vp]
+        lib.s2_plan_destroy.argtypes = [P]
+        lib.s2_plan_info.argtypes = [P, ctypes.POINTER(_PlanInfo)]
+        for name in ["s2_inverse", "s2_forward", "s2_inverse_adjoint", "so3_inverse", "so3_forward"]:
+            getattr(lib, name).argtypes = [P, vp, vp, i, vp, vp]
+            getattr(lib, name).restype = i
+        lib.s2_debug_wigner_d.argtypes = [P, i, vp, vp]
+        lib.s2_error_string.restype = ctypes.c_char_p
+        lib.s2_error_string.argtypes = [i]
+        lib.s2_last_error_message.restype = ctypes.c_char_p
+        lib.s2_last_error_message.argtypes = []
+        _lib = lib
+        return lib
+
+
+def _check(rc):
+    if rc != S2_OK:
+        lib = load_library()
+        raise S2Error(rc, lib.s2_last_error_message().decode())
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A transform plan: bandlimit L, spin, azimuthal band N (SO(3) when N > 1),
+    sampling 'mw' or 'healpix' (nside), max_batch, contraction precision.
+
+    Holds its device constants (freed with the plan) and one workspace tensor;
+    calls on one Plan object are therefore serialised on the stream they are
+    issued on (use one Plan per concurrent stream)."""
+
+    def __init__(self, L, spin=0, N=1, sampling="mw", nside=0, max_batch=1, precision="fp64", device=None):
+        self._lib = load_library()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self._lib.s2_plan_create(ctypes.byref(self._handle), int(L), int(spin), int(N),
+                                            _SAMPLING[sampling], int(nside), int(max_batch),
+                                            _PRECISION[precision], _stream_handle(self.device)))
+        info = _PlanInfo()
+        _check(self._lib.s2_plan_info(self._handle, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
+        self.L, self.spin, self.N = info.L, info.spin, info.N
+        self.sampling = "mw" if info.sampling == MW else "healpix"
+        self.nside, self.max_batch = info.nside, info.max_batch
+        self.nsamples = info.nsamples
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            self._lib.s2_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    @property
+    def workspace(self):
+        if self._ws is None:
+            n = max(int(self.info["workspace_bytes"]), 256)
+            self._ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    @property
+    def coeff_shape(self):
+        return (self.L, 2 * self.L - 1)
+
+    @property
+    def map_shape(self):
+        return (self.L, 2 * self.L - 1) if self.sampling == "mw" else (self.nsamples,)
+
+    def _prep(self, x, tail, what):
+        if not isinstance(x, torch.Tensor):
+            raise TypeError(f"{what}: expected a torch.Tensor")
+        if x.dtype != torch.complex128:
+            raise TypeError(f"{what}: expected complex128, got {x.dtype}")
+        if x.device != self.device:
+            raise ValueError(f"{what}: tensor on {x.device}, plan on {self.device}")
+        batched = x.dim() == len(tail) + 1
+        if tuple(x.shape[-len(tail):]) != tuple(tail) or x.dim() not in (len(tail), len(tail) + 1):
+            raise ValueError(f"{what}: shape {tuple(x.shape)} does not end in {tuple(tail)}")
+        return x.contiguous(), (x.shape[0] if batched else 1), batched
+
+    def _call(self, fn, x, in_tail, out_tail, what):
+        x, B, batched = self._prep(x, in_tail, what)
+        out = torch.empty(((B,) if batched else ()) + tuple(out_tail), dtype=torch.complex128, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(fn(self._handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(B),
+                      ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(self.device)))
+        return out
+
+    # ------------------------------------------------------------ transforms
+    def inverse(self, flm):
+        """Inverse spin SHT: flm [B?, L, 2L-1] -> map."""
+        return self._call(self._lib.s2_inverse, flm, self.coeff_shape, self.map_shape, "inverse")
+
+    def forward(self, f):
+        """Forward spin SHT: map -> flm [B?, L, 2L-1]."""
+        return self._call(self._lib.s2_forward, f, self.map_shape, self.coeff_shape, "forward")
+
+    def inverse_adjoint(self, g):
+        """Hermitian adjoint of the inverse SHT: map-space cotangent -> coefficients."""
+        return self._call(self._lib.s2_inverse_adjoint, g, self.map_shape, self.coeff_shape, "inverse_adjoint")
+
+    def so3_inverse(self, flmn):
+        """Inverse Wigner transform: flmn [B?, 2N-1, L, 2L-1] -> f [B?, 2N-1, L, 2L-1]."""
+        shp = (2 * self.N - 1,) + self.coeff_shape
+        return self._call(self._lib.so3_inverse, flmn, shp, shp, "so3_inverse")
+
+    def so3_forward(self, f):
+        """Forward Wigner transform: f [B?, 2N-1, L, 2L-1] -> flmn."""
+        shp = (2 * self.N - 1,) + self.coeff_shape
+        return self._call(self._lib.so3_forward, f, shp, shp, "so3_forward")
+
+    def debug_wigner_d(self, n):
+        """d^l_{m,n}(theta_r) from the GPU recursion: [rings swept, m, l] (float64)."""
+        nreg = self.L - 1 if self.sampling == "mw" else self.info["nrings"]
+        out = torch.empty((nreg, self.L, self.L), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self._lib.s2_debug_wigner_d(self._handle, int(n), ctypes.c_void_p(out.data_ptr()),
+                                               _stream_handle(self.device)))
+        return out
+
+
+def plan_create_raw(L, spin=0, N=1, sampling=MW, nside=0, max_batch=1, precision=FP64, stream=None):
+    """Call s2_plan_create directly; returns (rc, handle).  For tests of the error model."""
+    lib = load_library()
+    h = ctypes.c_void_p()
+    rc = lib.s2_plan_create(ctypes.byref(h), int(L), int(spin), int(N), int(sampling), int(nside), int(max_batch),
+                            int(precision), stream)
+    return rc, h

@@ -1,0 +1,636 @@
+// s2mi_capi.hip -- the C ABI of include/s2mi.h: plan construction, argument
+// validation and the launch sequence of each transform.
+//
+// Paper: Price & McEwen, arXiv 2311.14670.  Spin SHT = phi-DFT (Eqs. 31-32) +
+// Wigner d-stage (Eqs. 30, 33) on an isolatitude sampling (Sec. 4.1-4.2);
+// Wigner transform = gamma-DFT + one spin SHT per n (Sec. 4.5, Eqs. 15-18).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/s2mi.h"
+#include "s2mi_internal.h"
+#include "s2mi_kernels.h"
+
+using namespace s2mi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hipfail(hipError_t e, const char *what)
+{
+    return fail(S2_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                      \
+    do {                                        \
+        hipError_t _e = (expr);                 \
+        if (_e != hipSuccess) return hipfail(_e, what); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+struct s2_plan_s {
+    int L = 0, spin = 0, N = 1, sampling = 0, nside = 0, max_batch = 1, prec = 0;
+    int nslice = 1;                       // 1 for S2, 2N-1 for SO(3)
+    std::vector<int> slice_spin;          // spin of each slice (SO(3) slice k: n = k-(N-1), spin -n)
+    int nring = 0, nreg = 0;              // rings of the sampling; rings the d-stage sweeps
+    long long nsamp = 0;                  // samples per slice map
+    std::vector<Run> runs;
+
+    // device memory owned by the plan
+    std::vector<void *> allocs;
+    size_t plan_bytes = 0;
+
+    // geometry (regular rings first; MW adds the south pole as ring nreg)
+    double *cot = nullptr, *csc = nullptr, *lsin = nullptr, *lcos = nullptr;
+    int *ring_nphi = nullptr, *ring_shift = nullptr, *ring_fft = nullptr;
+    long long *ring_start = nullptr;
+    // recursion tables
+    double *kap = nullptr, *gtab = nullptr;
+    std::vector<double *> lbin;   // per run
+    std::vector<double *> lam;    // per run [L][nreg]
+    // per-slice weights: SHT (Eqs. 30, 33), SO(3) inverse (Eq. 13), SO(3) forward (Eq. 14)
+    std::vector<double *> w_sht, w_so3i, w_so3f;
+    // FFT
+    std::vector<FftArgs> ffts_h;
+    FftArgs *ffts = nullptr;
+    int fft_threads = 64;
+    size_t fft_lds = 0;
+    FftArgs fN{};                          // MW ring / theta-torus length 2L-1
+    double *wq = nullptr, *ph = nullptr;   // MW theta filter
+    double *groots = nullptr;              // e^{-2 pi i k/(2N-1)}
+    // d-stage work assignment
+    int inv_nblk = 1, inv_waves = 4;
+    int *lslot = nullptr, *mtop = nullptr;
+    int fwd_nblk = 1, fwd_waves = 4, G = 1;
+    int *rslot = nullptr;
+    // workspace layout (bytes)
+    size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
+    size_t szC = 0, szP = 0, szF = 0, szQ = 0;
+
+    template <typename T>
+    int dalloc(T **p, size_t count, const char *what)
+    {
+        void *q = nullptr;
+        const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return fail(S2_ERR_OOM, "hipMalloc(%zu) for %s: %s", bytes, what, hipGetErrorString(e));
+        allocs.push_back(q);
+        plan_bytes += bytes;
+        *p = static_cast<T *>(q);
+        return S2_OK;
+    }
+    ~s2_plan_s()
+    {
+        for (void *q : allocs) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+// factor n over the engine radices; returns remainder (1 if fully factored)
+int factor_radices(int n, std::vector<int> &rad)
+{
+    rad.clear();
+    while (n % 8 == 0) { rad.push_back(8); n /= 8; }
+    while (n % 4 == 0) { rad.push_back(4); n /= 4; }
+    while (n % 2 == 0) { rad.push_back(2); n /= 2; }
+    for (int p : {13, 11, 7, 5, 3})
+        while (n % p == 0) { rad.push_back(p); n /= p; }
+    return n;
+}
+
+// host staging kept alive until the plan's upload has completed
+struct Staging {
+    std::vector<std::vector<double>> d;
+    std::vector<std::vector<int>> i;
+    std::vector<std::vector<long long>> ll;
+};
+
+template <typename T>
+int upload(s2_plan_s *P, T **dst, const std::vector<T> &src, hipStream_t st, const char *what)
+{
+    int rc = P->dalloc(dst, src.size(), what);
+    if (rc) return rc;
+    if (!src.empty()) HIPCHK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st), what);
+    return S2_OK;
+}
+
+int build_fft(s2_plan_s *P, int n, Staging &stg, hipStream_t st, FftArgs *out)
+{
+    FftArgs f{};
+    std::vector<int> rad;
+    const int rem = factor_radices(n, rad);
+    f.n = n;
+    if (rem == 1) {
+        f.blue = 0;
+        f.len = n;
+    } else {
+        f.blue = 1;
+        int M = 1;
+        while (M < 2 * n - 1) M *= 2;
+        f.len = M;
+        factor_radices(M, rad);
+    }
+    if (f.len > FFT_MAX_LEN)
+        return fail(S2_ERR_UNSUPPORTED, "DFT length %d needs an engine of %d points (> %d)", n, f.len, FFT_MAX_LEN);
+    if ((int)rad.size() > FFT_MAX_STAGES) return fail(S2_ERR_UNSUPPORTED, "too many FFT stages for %d", n);
+    f.nst = (int)rad.size();
+    for (int s = 0; s < f.nst; ++s) f.rad[s] = rad[s];
+    stg.d.emplace_back();
+    host_roots(f.len, &stg.d.back());
+    double *tw;
+    int rc = upload(P, &tw, stg.d.back(), st, "fft twiddles");
+    if (rc) return rc;
+    f.tw = tw;
+    if (f.blue) {
+        stg.d.emplace_back();
+        host_chirp(n, &stg.d.back());
+        double *ch, *bf;
+        if ((rc = upload(P, &ch, stg.d.back(), st, "bluestein chirp"))) return rc;
+        if ((rc = P->dalloc(&bf, 2 * (size_t)f.len, "bluestein filter"))) return rc;
+        f.chirp = ch;
+        f.bflt = bf;
+    }
+    *out = f;
+    return S2_OK;
+}
+
+int fft_threads_for(int len) { return std::min(1024, std::max(64, ((len / 8 + 63) / 64) * 64)); }
+
+// Inverse d-stage: deal l = L-1, L-2, ... over (block, wave) bins in snake order
+// so every wave's work sum_l (l + 1) is balanced; slots in a wave descend in l.
+void assign_inverse(int L, int nblk, int W, std::vector<int> &lslot, std::vector<int> &mtop)
+{
+    const int nbin = nblk * W;
+    lslot.assign((size_t)nbin * INV_J, -1);
+    std::vector<int> fill(nbin, 0);
+    int idx = 0;
+    for (int l = L - 1; l >= 0; --l, ++idx) {
+        const int round = idx / nbin, pos = idx % nbin;
+        const int bin = (round % 2 == 0) ? pos : nbin - 1 - pos;
+        lslot[(size_t)bin * INV_J + fill[bin]++] = l;
+    }
+    mtop.assign(nblk, 0);
+    for (int b = 0; b < nblk; ++b)
+        for (int k = 0; k < W * INV_J; ++k) mtop[b] = std::max(mtop[b], lslot[(size_t)b * W * INV_J + k]);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *s2_error_string(int code)
+{
+    switch (code) {
+    case S2_OK: return "ok";
+    case S2_ERR_INVALID_ARG: return "invalid argument";
+    case S2_ERR_UNSUPPORTED: return "unsupported";
+    case S2_ERR_OOM: return "out of memory";
+    case S2_ERR_HIP: return "HIP runtime error";
+    default: return "unknown error";
+    }
+}
+
+const char *s2_last_error_message(void) { return g_last_error.c_str(); }
+
+int s2_plan_info(s2_plan_t P, s2_plan_info_t *info)
+{
+    if (!P || !info) return fail(S2_ERR_INVALID_ARG, "s2_plan_info: null argument");
+    info->L = P->L;
+    info->spin = P->spin;
+    info->N = P->N;
+    info->nside = P->nside;
+    info->sampling = P->sampling;
+    info->precision = P->prec;
+    info->max_batch = P->max_batch;
+    info->nrings = P->nring;
+    info->nsamples = P->nsamp;
+    info->ncoeffs = (long long)P->L * (2 * P->L - 1);
+    info->workspace_bytes = P->ws_bytes;
+    info->plan_device_bytes = P->plan_bytes;
+    return S2_OK;
+}
+
+int s2_plan_destroy(s2_plan_t P)
+{
+    if (!P) return S2_OK;
+    (void)hipDeviceSynchronize();
+    delete P;
+    return S2_OK;
+}
+
+static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_t sampling, int nside, int max_batch,
+                            s2_precision_t prec, void *hip_stream)
+{
+    if (!out) return fail(S2_ERR_INVALID_ARG, "s2_plan_create: out is NULL");
+    *out = nullptr;
+    if (L < 2 || L > 4096) return fail(S2_ERR_INVALID_ARG, "L=%d outside [2, 4096]", L);
+    if (N < 1 || N > L) return fail(S2_ERR_INVALID_ARG, "N=%d outside [1, L]", N);
+    if (N > 8) return fail(S2_ERR_UNSUPPORTED, "N=%d: SO(3) plans support N <= 8", N);
+    if (N > 1 && spin != 0) return fail(S2_ERR_INVALID_ARG, "SO(3) plans (N > 1) take spin 0");
+    if (spin <= -L || spin >= L) return fail(S2_ERR_INVALID_ARG, "|spin|=%d must be < L=%d", spin, L);
+    if (sampling != S2_MW && sampling != S2_HEALPIX) return fail(S2_ERR_INVALID_ARG, "unknown sampling %d", (int)sampling);
+    if (sampling == S2_HEALPIX && (nside < 1 || nside > 2048)) return fail(S2_ERR_INVALID_ARG, "nside=%d outside [1, 2048]", nside);
+    if (sampling == S2_HEALPIX && N > 1) return fail(S2_ERR_UNSUPPORTED, "SO(3) plans need MW sampling");
+    if (max_batch < 1) return fail(S2_ERR_INVALID_ARG, "max_batch=%d < 1", max_batch);
+    if (prec != S2_FP64) return fail(S2_ERR_UNSUPPORTED, "precision mode %d not available in this build", (int)prec);
+    hipStream_t st = (hipStream_t)hip_stream;
+
+    s2_plan_s *P = new (std::nothrow) s2_plan_s();
+    if (!P) return fail(S2_ERR_OOM, "host allocation of the plan failed");
+    P->L = L; P->spin = spin; P->N = N; P->sampling = sampling; P->nside = nside; P->max_batch = max_batch; P->prec = prec;
+    P->nslice = 2 * N - 1;
+    const bool so3 = N > 1;
+    Staging stg;
+    int rc;
+    auto bail = [&](int code) { delete P; return code; };
+
+    // slices and runs
+    P->slice_spin.resize(P->nslice);
+    if (!so3) P->slice_spin[0] = spin;
+    else for (int k = 0; k < P->nslice; ++k) P->slice_spin[k] = -(k - (N - 1));
+    auto slice_of_spin = [&](int s) {
+        for (int k = 0; k < P->nslice; ++k) if (P->slice_spin[k] == s) return k;
+        return -1;
+    };
+    {
+        std::vector<int> ns;
+        for (int k = 0; k < P->nslice; ++k) {
+            const int s = P->slice_spin[k];
+            for (int n : {-s, s}) if (std::find(ns.begin(), ns.end(), n) == ns.end()) ns.push_back(n);
+        }
+        for (int n : ns) P->runs.push_back(Run{n, slice_of_spin(-n), slice_of_spin(n)});
+    }
+
+    // geometry
+    RingConsts rc_h;
+    std::vector<int> nphi, shift;
+    std::vector<long long> start;
+    if (sampling == S2_MW) {
+        host_mw_rings(L, &rc_h);
+        P->nreg = L - 1;
+        P->nring = L;
+        nphi.assign(L, 2 * L - 1);
+        shift.assign(L, 0);
+        start.resize(L);
+        for (int t = 0; t < L; ++t) start[t] = (long long)t * (2 * L - 1);
+        P->nsamp = (long long)L * (2 * L - 1);
+    } else {
+        host_healpix_rings(nside, &rc_h, &nphi, &start, &shift);
+        P->nring = 4 * nside - 1;
+        P->nreg = P->nring;
+        P->nsamp = 12LL * nside * nside;
+    }
+    if ((rc = upload(P, &P->cot, rc_h.cot, st, "cot"))) return bail(rc);
+    if ((rc = upload(P, &P->csc, rc_h.csc, st, "csc"))) return bail(rc);
+    if ((rc = upload(P, &P->lsin, rc_h.lsin, st, "lsin"))) return bail(rc);
+    if ((rc = upload(P, &P->lcos, rc_h.lcos, st, "lcos"))) return bail(rc);
+    if ((rc = upload(P, &P->ring_nphi, nphi, st, "ring_nphi"))) return bail(rc);
+    if ((rc = upload(P, &P->ring_shift, shift, st, "ring_shift"))) return bail(rc);
+    if ((rc = upload(P, &P->ring_start, start, st, "ring_start"))) return bail(rc);
+
+    // FFTs: one per distinct ring length
+    {
+        std::vector<int> lens, rf(P->nring);
+        for (int r = 0; r < P->nring; ++r) {
+            auto it = std::find(lens.begin(), lens.end(), nphi[r]);
+            if (it == lens.end()) { lens.push_back(nphi[r]); rf[r] = (int)lens.size() - 1; }
+            else rf[r] = (int)(it - lens.begin());
+        }
+        int maxlen = 0;
+        for (int n : lens) {
+            FftArgs f;
+            if ((rc = build_fft(P, n, stg, st, &f))) return bail(rc);
+            P->ffts_h.push_back(f);
+            maxlen = std::max(maxlen, f.len);
+        }
+        if (sampling == S2_MW) P->fN = P->ffts_h[0];
+        P->fft_threads = fft_threads_for(maxlen);
+        P->fft_lds = (size_t)maxlen * sizeof(double2);
+        if ((rc = upload(P, &P->ring_fft, rf, st, "ring_fft"))) return bail(rc);
+        if ((rc = upload(P, &P->ffts, P->ffts_h, st, "fft table"))) return bail(rc);
+        HIPCHK(set_kernel_lds_limits(P->fft_lds), "LDS limits");
+        int nblue = 0;
+        for (auto &f : P->ffts_h) nblue += f.blue;
+        if (nblue) HIPCHK(launch_bluestein_filter(st, (int)P->ffts_h.size(), P->ffts, P->fft_threads, P->fft_lds), "bluestein filters");
+    }
+    if (sampling == S2_MW) {
+        stg.d.emplace_back(); std::vector<double> &wq = stg.d.back();
+        stg.d.emplace_back(); std::vector<double> &ph = stg.d.back();
+        host_mw_filter(L, &wq, &ph);
+        if ((rc = upload(P, &P->wq, wq, st, "mw filter weights"))) return bail(rc);
+        if ((rc = upload(P, &P->ph, ph, st, "mw half-shift phases"))) return bail(rc);
+    }
+    if (sampling == S2_MW && spin == 0) {
+        stg.d.emplace_back();
+        host_roots(2 * N - 1, &stg.d.back());
+        if ((rc = upload(P, &P->groots, stg.d.back(), st, "gamma roots"))) return bail(rc);
+    }
+
+    // recursion tables
+    {
+        stg.d.emplace_back(); std::vector<double> &kap = stg.d.back();
+        stg.d.emplace_back(); std::vector<double> &g = stg.d.back();
+        host_recursion_tables(L, &kap, &g);
+        if ((rc = upload(P, &P->kap, kap, st, "kappa table"))) return bail(rc);
+        if ((rc = upload(P, &P->gtab, g, st, "g table"))) return bail(rc);
+    }
+    for (const Run &r : P->runs) {
+        stg.d.emplace_back();
+        host_log2_binom(L, r.n, &stg.d.back());
+        double *lb, *lam;
+        if ((rc = upload(P, &lb, stg.d.back(), st, "log2 binomials"))) return bail(rc);
+        if ((rc = P->dalloc(&lam, (size_t)L * P->nreg, "lambda table"))) return bail(rc);
+        HIPCHK(launch_lambda_table(st, L, P->nreg, r.n, P->cot, P->csc, lam), "lambda table");
+        P->lbin.push_back(lb);
+        P->lam.push_back(lam);
+    }
+    for (int k = 0; k < P->nslice; ++k) {
+        for (int kind = 0; kind < 3; ++kind) {
+            stg.d.emplace_back();
+            host_weights(L, kind, P->slice_spin[k], &stg.d.back());
+            double *a;
+            if ((rc = upload(P, &a, stg.d.back(), st, "weights"))) return bail(rc);
+            (kind == 0 ? P->w_sht : kind == 1 ? P->w_so3i : P->w_so3f).push_back(a);
+        }
+    }
+
+    // inverse d-stage assignment
+    {
+        P->inv_nblk = (L + 16 * INV_J - 1) / (16 * INV_J);
+        P->inv_waves = std::min(16, std::max(4, (L + P->inv_nblk * INV_J - 1) / (P->inv_nblk * INV_J)));
+        stg.i.emplace_back(); std::vector<int> &ls = stg.i.back();
+        stg.i.emplace_back(); std::vector<int> &mt = stg.i.back();
+        assign_inverse(L, P->inv_nblk, P->inv_waves, ls, mt);
+        if ((rc = upload(P, &P->lslot, ls, st, "inverse slots"))) return bail(rc);
+        if ((rc = upload(P, &P->mtop, mt, st, "inverse mtop"))) return bail(rc);
+    }
+    // forward d-stage assignment: rings in contiguous chunks of waves x FWD_R
+    {
+        P->G = (L + 63) / 64;
+        const int pairs = (P->G + 1) / 2;
+        int nb = std::max(1, std::min(256 / pairs, (P->nreg + 4 * FWD_R - 1) / (4 * FWD_R)));
+        int W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R);
+        while (W > 16) { ++nb; W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R); }
+        W = std::max(W, 4);
+        P->fwd_nblk = nb;
+        P->fwd_waves = W;
+        // wave w of block b sweeps rings (b W + w) FWD_R .. + FWD_R - 1 (clipped at nreg)
+    }
+
+    // workspace layout
+    {
+        const size_t S = P->nslice;
+        P->szC = (size_t)P->inv_nblk * P->inv_waves * INV_J * L * 5 * sizeof(double);
+        P->szP = (size_t)P->inv_nblk * P->nreg * L * 4 * sizeof(double);
+        P->szF = (size_t)L * P->nring * 4 * sizeof(double);
+        P->szQ = (size_t)P->fwd_nblk * L * L * 4 * sizeof(double);
+        size_t o = 0;
+        P->off_C = o; o += align256(P->szC * P->runs.size());
+        P->off_P = o; o += align256(P->szP * S);
+        P->off_maps = o; o += (sampling == S2_MW && spin == 0) ? align256((size_t)P->nsamp * S * sizeof(double2)) : 0;
+        P->off_F = o; o += align256(P->szF * S);
+        P->off_Q = o; o += align256(P->szQ * S);
+        P->off_hpole = o; o += align256((size_t)(2 * L - 1) * S * sizeof(double2));
+        P->ws_bytes = o;
+    }
+    HIPCHK(hipStreamSynchronize(st), "plan upload");
+    HIPCHK(hipGetLastError(), "plan kernels");
+    *out = P;
+    return S2_OK;
+}
+
+int s2_plan_create(s2_plan_t *out, int L, int spin, int N, s2_sampling_t sampling, int nside, int max_batch,
+                   s2_precision_t prec, void *hip_stream)
+{
+    try {
+        return plan_create_impl(out, L, spin, N, sampling, nside, max_batch, prec, hip_stream);
+    } catch (const std::bad_alloc &) {
+        return fail(S2_ERR_OOM, "host allocation failed during plan creation");
+    } catch (...) {
+        return fail(S2_ERR_HIP, "unexpected exception during plan creation");
+    }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ transforms
+namespace {
+
+int check_call(const char *fn, s2_plan_t P, const void *in, const void *out, int batch, void *ws)
+{
+    if (!P) return fail(S2_ERR_INVALID_ARG, "%s: plan is NULL", fn);
+    if (!in || !out) return fail(S2_ERR_INVALID_ARG, "%s: NULL data pointer", fn);
+    if (!ws) return fail(S2_ERR_INVALID_ARG, "%s: NULL workspace", fn);
+    if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(S2_ERR_INVALID_ARG, "%s: data pointers must be 16-byte aligned", fn);
+    if ((uintptr_t)ws & 255) return fail(S2_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", fn);
+    if (batch < 1 || batch > P->max_batch)
+        return fail(S2_ERR_INVALID_ARG, "%s: batch=%d outside [1, max_batch=%d]", fn, batch, P->max_batch);
+    return S2_OK;
+}
+
+// inverse of one (map, all slices): flm slices [S][L][2L-1] -> slice maps
+int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, const std::vector<double *> &wl,
+                char *ws, hipStream_t st)
+{
+    const int L = P->L;
+    const size_t slab = (size_t)L * (2 * L - 1);
+    double *C0 = (double *)(ws + P->off_C);
+    double *P0 = (double *)(ws + P->off_P);
+    const size_t nP = P->szP / sizeof(double), nC = P->szC / sizeof(double);
+    for (size_t ri = 0; ri < P->runs.size(); ++ri) {
+        const Run &r = P->runs[ri];
+        const double2 *fa = r.sliceA >= 0 ? flm + r.sliceA * slab : nullptr;
+        const double2 *fb = r.sliceB >= 0 ? flm + r.sliceB * slab : nullptr;
+        double *C = C0 + ri * nC;
+        HIPCHK(launch_pack_inv(st, L, r.n, P->inv_nblk, P->inv_waves * INV_J, P->lslot, fa, fb,
+                               r.sliceA >= 0 ? wl[r.sliceA] : nullptr, r.sliceB >= 0 ? wl[r.sliceB] : nullptr, P->kap,
+                               P->gtab, C), "pack");
+        HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nreg, r.n, P->cot, P->csc, P->lsin, P->lcos,
+                                 P->lbin[ri], C, P->lslot, P->mtop,
+                                 r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
+                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr), "inverse d-stage");
+    }
+    for (int k = 0; k < P->nslice; ++k)
+        HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, P->nreg, P->inv_nblk, P->slice_spin[k],
+                              P0 + k * nP, P->mtop, flm + k * slab, wl[k], P->ring_nphi, P->ring_start,
+                              P->ring_shift, P->ring_fft, P->ffts, slice_maps[k]), "inverse phi-DFT");
+    return S2_OK;
+}
+
+// forward d-stage of one map from the filtered ring spectra H (slices) -> flm slices
+int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *flm, const std::vector<double *> &wl,
+                       char *ws, hipStream_t st)
+{
+    const int L = P->L;
+    const size_t slab = (size_t)L * (2 * L - 1);
+    const size_t nF = P->szF / sizeof(double), nQ = P->szQ / sizeof(double);
+    double *Q0 = (double *)(ws + P->off_Q);
+    for (size_t ri = 0; ri < P->runs.size(); ++ri) {
+        const Run &r = P->runs[ri];
+        const double *HA = r.sliceA >= 0 ? H0 + r.sliceA * nF : H0 + r.sliceB * nF;
+        const double *HB = r.sliceB >= 0 ? H0 + r.sliceB * nF : HA;
+        HIPCHK(launch_dstage_fwd(st, P->fwd_waves, P->fwd_nblk, P->G, L, P->nreg, P->nring, r.n, P->lam[ri], P->lsin,
+                                 P->lcos, P->lbin[ri], P->kap, P->gtab, HA, HB,
+                                 r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
+                                 r.sliceB >= 0 ? Q0 + r.sliceB * nQ : nullptr), "forward d-stage");
+    }
+    for (int k = 0; k < P->nslice; ++k) {
+        const int s = P->slice_spin[k];
+        HIPCHK(launch_finish_fwd(st, L, P->fwd_nblk, s, s, Q0 + k * nQ, wl[k],
+                                 hpole0 ? hpole0 + k * (2 * L - 1) : nullptr, flm + k * slab), "forward finish");
+    }
+    return S2_OK;
+}
+
+// forward of one map: slice maps -> flm slices.  adjoint: unit phi weight, no theta filter.
+int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, const std::vector<double *> &wl,
+                char *ws, hipStream_t st, bool adjoint)
+{
+    const int L = P->L;
+    const size_t nF = P->szF / sizeof(double);
+    double *F0 = (double *)(ws + P->off_F);
+    double2 *hp0 = (double2 *)(ws + P->off_hpole);
+    const bool mw = P->sampling == S2_MW;
+    double q;
+    if (adjoint) q = 1.0;
+    else if (mw) q = 2.0 * M_PI / (double)(2 * L - 1);
+    else q = 4.0 * M_PI / (double)P->nsamp;
+    for (int k = 0; k < P->nslice; ++k) {
+        double *F = F0 + k * nF;
+        HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, L, q, slice_maps[k], P->ring_nphi,
+                              P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F), "forward phi-DFT");
+        if (mw && !adjoint)
+            HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->slice_spin[k], P->ffts, P->wq, P->ph, F,
+                                    hp0 + k * (2 * L - 1)), "MW theta filter");
+        else if (mw)
+            HIPCHK(launch_pole_from_F(st, L, P->nring, L - 1, F, hp0 + k * (2 * L - 1)), "pole line");
+    }
+    return run_forward_dstage(P, F0, mw ? hp0 : nullptr, flm, wl, ws, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int s2_inverse(s2_plan_t P, const void *flm, void *f, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_inverse", P, flm, f, batch, workspace);
+    if (rc) return rc;
+    if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_inverse: plan was created for SO(3) (N=%d)", P->N);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b) {
+        double2 *out = (double2 *)f + (size_t)b * P->nsamp;
+        if ((rc = run_inverse(P, (const double2 *)flm + b * slab, &out, P->w_sht, (char *)workspace, st))) return rc;
+    }
+    return S2_OK;
+}
+
+int s2_forward(s2_plan_t P, const void *f, void *flm, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_forward", P, f, flm, batch, workspace);
+    if (rc) return rc;
+    if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_forward: plan was created for SO(3) (N=%d)", P->N);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b) {
+        const double2 *in = (const double2 *)f + (size_t)b * P->nsamp;
+        if ((rc = run_forward(P, &in, (double2 *)flm + b * slab, P->w_sht, (char *)workspace, st, false))) return rc;
+    }
+    return S2_OK;
+}
+
+int s2_inverse_adjoint(s2_plan_t P, const void *g, void *g_flm, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_inverse_adjoint", P, g, g_flm, batch, workspace);
+    if (rc) return rc;
+    if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_inverse_adjoint: plan was created for SO(3) (N=%d)", P->N);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b) {
+        const double2 *in = (const double2 *)g + (size_t)b * P->nsamp;
+        if ((rc = run_forward(P, &in, (double2 *)g_flm + b * slab, P->w_sht, (char *)workspace, st, true))) return rc;
+    }
+    return S2_OK;
+}
+
+int so3_inverse(s2_plan_t P, const void *flmn, void *f, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("so3_inverse", P, flmn, f, batch, workspace);
+    if (rc) return rc;
+    if (P->sampling != S2_MW || P->spin != 0) return fail(S2_ERR_INVALID_ARG, "so3_inverse: needs an MW spin-0 plan");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int S = P->nslice;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b) {
+        double2 *out = (double2 *)f + (size_t)b * S * P->nsamp;
+        std::vector<double2 *> maps(S);
+        double2 *tmp = (S > 1) ? (double2 *)((char *)workspace + P->off_maps) : out;
+        for (int k = 0; k < S; ++k) maps[k] = tmp + (size_t)k * P->nsamp;
+        if ((rc = run_inverse(P, (const double2 *)flmn + (size_t)b * S * slab, maps.data(), P->w_so3i,
+                              (char *)workspace, st))) return rc;
+        if (S > 1) HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, +1, 1.0, P->groots, tmp, out), "gamma DFT");
+    }
+    return S2_OK;
+}
+
+int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("so3_forward", P, f, flmn, batch, workspace);
+    if (rc) return rc;
+    if (P->sampling != S2_MW || P->spin != 0) return fail(S2_ERR_INVALID_ARG, "so3_forward: needs an MW spin-0 plan");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int S = P->nslice;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b) {
+        const double2 *in = (const double2 *)f + (size_t)b * S * P->nsamp;
+        std::vector<const double2 *> maps(S);
+        double2 *tmp = (double2 *)((char *)workspace + P->off_maps);
+        // f_n = 2pi/(2N-1) sum_k f(gamma_k) e^{-i n gamma_k}  (Eq. 16, exact equispaced rule)
+        HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, -1, 2.0 * M_PI / (double)S, P->groots, in, tmp), "gamma DFT");
+        for (int k = 0; k < S; ++k) maps[k] = tmp + (size_t)k * P->nsamp;
+        if ((rc = run_forward(P, maps.data(), (double2 *)flmn + (size_t)b * S * slab, P->w_so3f, (char *)workspace,
+                              st, false))) return rc;
+    }
+    return S2_OK;
+}
+
+int s2_debug_wigner_d(s2_plan_t P, int n, void *out, void *hip_stream)
+{
+    if (!P || !out) return fail(S2_ERR_INVALID_ARG, "s2_debug_wigner_d: null argument");
+    int ri = -1;
+    for (size_t i = 0; i < P->runs.size(); ++i) if (P->runs[i].n == n) ri = (int)i;
+    if (ri < 0) return fail(S2_ERR_INVALID_ARG, "s2_debug_wigner_d: n=%d is not a run of this plan", n);
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIPCHK(hipMemsetAsync(out, 0, (size_t)P->nreg * P->L * P->L * sizeof(double), st), "memset");
+    HIPCHK(launch_debug_d(st, P->L, P->nreg, n, P->cot, P->csc, P->lsin, P->lcos, P->lbin[ri], P->kap, P->gtab,
+                          (double *)out), "debug d");
+    return S2_OK;
+}
+
+}  // extern "C"

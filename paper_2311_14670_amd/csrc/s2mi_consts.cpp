@@ -1,0 +1,228 @@
+// s2mi_consts.cpp -- host-side generation of the plan constants in quad
+// precision (libquadmath), rounded once to double or split into double-double.
+//
+// Nothing here touches the GPU; s2mi_capi.hip uploads the arrays.
+//
+// Paper references (Price & McEwen, arXiv 2311.14670):
+//   ring geometry      Sec. 4.2 (MW: theta_t = (2t+1) pi/(2L-1); HEALPix RING
+//                      geometry of Gorski et al. 2005)
+//   recursion          Sec. 3.3, Eqs. 25-26 (descending-m three-term recursion)
+//   initial values     Eq. 27, computed in log space (Sec. 3.3)
+//   MW theta weights   Sec. 4.2, Eqs. 41-42 (band-limited sin(theta) 1_[0,pi])
+#include <quadmath.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "s2mi_internal.h"
+
+namespace s2mi {
+
+namespace {
+using q = __float128;
+const q QPI = M_PIq;
+
+inline void split_dd(q v, double *hi, double *lo)
+{
+    const double h = (double)v;
+    *hi = h;
+    *lo = (double)(v - (q)h);
+}
+}  // namespace
+
+// Regular (non-polar) MW colatitudes t = 0 .. L-2.
+void host_mw_rings(int L, RingConsts *rc)
+{
+    const int nreg = L - 1;
+    rc->theta.resize(nreg);
+    rc->cot.resize(nreg);
+    rc->csc.resize(nreg);
+    rc->lsin.resize(2 * nreg);
+    rc->lcos.resize(2 * nreg);
+    for (int t = 0; t < nreg; ++t) {
+        const q th = (2 * (q)t + 1) * QPI / (2 * (q)L - 1);
+        fill_ring(rc, t, th);
+    }
+}
+
+void fill_ring(RingConsts *rc, int r, __float128 th)
+{
+    const q s = sinq(th), c = cosq(th);
+    rc->theta[r] = (double)th;
+    rc->cot[r] = (double)(c / s);
+    rc->csc[r] = (double)(1 / s);
+    split_dd(log2q(sinq(th / 2)), &rc->lsin[2 * r], &rc->lsin[2 * r + 1]);
+    split_dd(log2q(cosq(th / 2)), &rc->lcos[2 * r], &rc->lcos[2 * r + 1]);
+}
+
+// HEALPix RING geometry (Gorski et al. 2005), ring r = 0 .. 4 nside - 2, i = r + 1:
+//   i <  nside:          cos(theta) = 1 - i^2/(3 nside^2), 4i pixels, half-pixel shift
+//   nside <= i <= 3nside: cos(theta) = 4/3 - 2i/(3 nside), 4 nside pixels,
+//                         shift when (i - nside) is even
+//   i > 3 nside:          mirror of ring 4 nside - i.
+// Pixel j of ring r sits at phi = pi (2j + shift_r) / nphi_r.
+void host_healpix_rings(int nside, RingConsts *rc, std::vector<int> *nphi,
+                        std::vector<long long> *start, std::vector<int> *shift)
+{
+    const int nring = 4 * nside - 1;
+    rc->theta.resize(nring);
+    rc->cot.resize(nring);
+    rc->csc.resize(nring);
+    rc->lsin.resize(2 * nring);
+    rc->lcos.resize(2 * nring);
+    nphi->resize(nring);
+    start->resize(nring);
+    shift->resize(nring);
+    long long pix = 0;
+    const q ns = nside;
+    for (int r = 0; r < nring; ++r) {
+        const int i = r + 1;
+        q th;
+        int np, sh;
+        if (i < nside) {
+            th = 2 * asinq((q)i / (sqrtq((q)6) * ns));
+            np = 4 * i;
+            sh = 1;
+        } else if (i <= 3 * nside) {
+            th = acosq((q)4 / 3 - 2 * (q)i / (3 * ns));
+            np = 4 * nside;
+            sh = ((i - nside) % 2 == 0) ? 1 : 0;
+        } else {
+            const int ii = 4 * nside - i;
+            th = QPI - 2 * asinq((q)ii / (sqrtq((q)6) * ns));
+            np = 4 * ii;
+            sh = 1;
+        }
+        fill_ring(rc, r, th);
+        (*nphi)[r] = np;
+        (*start)[r] = pix;
+        (*shift)[r] = sh;
+        pix += np;
+    }
+}
+
+// 0.5 * log2 binom(2l, l - n) for l = |n| .. L-1 as double-double (zero below |n|).
+void host_log2_binom(int L, int n, std::vector<double> *out)
+{
+    out->assign(2 * (size_t)L, 0.0);
+    const int an = n < 0 ? -n : n;
+    for (int l = an; l < L; ++l) {
+        const q v = 0.5q * (lgammaq(2 * (q)l + 1) - lgammaq((q)(l - n) + 1) - lgammaq((q)(l + n) + 1)) / logq((q)2);
+        split_dd(v, &(*out)[2 * l], &(*out)[2 * l + 1]);
+    }
+}
+
+// Rescaled recursion.  With alpha_k = sqrt((l+k)(l-k+1)), Eq. 25 reads
+//   alpha_m d_{m-1} = 2 lambda_m d_m - alpha_{m+1} d_{m+1}.
+// Writing d_m = e_m g_m with g_l = g_{l-1} = 1, g_{m-1} = g_{m+1} alpha_{m+1}/alpha_m
+// turns it into  e_{m-1} = kappa_m lambda_m e_m - e_{m+1},
+//   kappa_m = 2 g_m / (alpha_m g_{m-1}).
+// Tables are indexed by the order being produced: kap[m][l] = kappa_{m+1} (m < l),
+// gtab[m][l] = g_m (m <= l).  Both [L][L], l fastest.  Long double: the even
+// and odd g-chains accumulate ~1e-19 per step, and every product of consecutive
+// kappas telescopes to exact alpha ratios, so no error drifts through the sweep.
+void host_recursion_tables(int L, std::vector<double> *kap, std::vector<double> *gtab)
+{
+    kap->assign((size_t)L * L, 0.0);
+    gtab->assign((size_t)L * L, 0.0);
+    std::vector<long double> g(L + 1);
+    for (int l = 0; l < L; ++l) {
+        auto al = [l](int k) { return sqrtl((long double)(l + k) * (long double)(l - k + 1)); };
+        g[l] = 1.0L;
+        if (l >= 1) g[l - 1] = 1.0L;
+        for (int m = l - 1; m >= 1; --m) g[m - 1] = g[m + 1] * al(m + 1) / al(m);
+        for (int m = 0; m <= l; ++m) (*gtab)[(size_t)m * L + l] = (double)g[m];
+        for (int m = 0; m < l; ++m) {
+            const int mp = m + 1;   // kappa_{m+1} produces order m
+            (*kap)[(size_t)m * L + l] = (double)(2.0L * g[mp] / (al(mp) * g[mp - 1]));
+        }
+    }
+}
+
+// e^{-2 pi i k / n}, k < n, interleaved (long double evaluation of the reduced angle).
+void host_roots(int n, std::vector<double> *out)
+{
+    out->resize(2 * (size_t)n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < n; ++k) {
+        const long double a = 2.0L * pi * (long double)k / (long double)n;
+        (*out)[2 * k] = (double)cosl(a);
+        (*out)[2 * k + 1] = -(double)sinl(a);
+    }
+}
+
+// Bluestein chirp c_k = e^{i pi (k^2 mod 2n) / n}, k < n.
+void host_chirp(int n, std::vector<double> *out)
+{
+    out->resize(2 * (size_t)n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (long long k = 0; k < n; ++k) {
+        const long long r = (k * k) % (2LL * n);
+        const long double a = pi * (long double)r / (long double)n;
+        (*out)[2 * k] = (double)cosl(a);
+        (*out)[2 * k + 1] = (double)sinl(a);
+    }
+}
+
+// MW theta filter constants for N = 2L-1 torus points theta_t = (2t+1) pi/N and
+// midpoints mu_t = theta_t + pi/N:
+//   wq[t], wq[N + t]  = P_{2L-2}[sin(theta) 1_[0,pi]] at theta_t and mu_t.  The
+//       Fourier coefficients c_d = (1/2pi) int_0^pi sin(th) e^{-i d th} are
+//       c_{+-1} = -+ i/4, c_d = 1/(pi (1 - d^2)) for even d, 0 for other odd d
+//       (Eq. 42 up to the 2pi normalisation and the sign of d), so
+//       P[...](th) = sin(th)/2 + c_0 + 2 sum_{even d >= 2} c_d cos(d th);
+//   ph[k] = e^{i k' pi / N} / N for DFT bin k with signed frequency
+//       k' = k (k <= L-1) or k - N (k >= L): the half-sample shift.
+void host_mw_filter(int L, std::vector<double> *wq, std::vector<double> *ph)
+{
+    const int N = 2 * L - 1;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    wq->assign(2 * (size_t)N, 0.0);
+    for (int which = 0; which < 2; ++which) {
+        for (int t = 0; t < N; ++t) {
+            const long double th = (2.0L * t + 1.0L + which) * pi / (long double)N;
+            long double acc = 1.0L / pi + 0.5L * sinl(th);
+            const long double c2 = cosl(2.0L * th);
+            long double cprev = 1.0L, ccur = c2;   // cos(0 th), cos(2 th)
+            for (int d = 2; d <= 2 * L - 2; d += 2) {
+                if ((d & 127) == 0) {                                   // re-anchor the recurrence
+                    ccur = cosl((long double)d * th);
+                    cprev = cosl((long double)(d - 2) * th);
+                }
+                acc += 2.0L / (pi * (1.0L - (long double)d * d)) * ccur;
+                const long double cnext = 2.0L * c2 * ccur - cprev;
+                cprev = ccur; ccur = cnext;
+            }
+            (*wq)[(size_t)which * N + t] = (double)acc;
+        }
+    }
+    ph->resize(2 * (size_t)N);
+    for (int k = 0; k < N; ++k) {
+        const int ks = (k <= L - 1) ? k : k - N;
+        const long double a = (long double)ks * pi / (long double)N;
+        (*ph)[2 * k] = (double)(cosl(a) / (long double)N);
+        (*ph)[2 * k + 1] = (double)(sinl(a) / (long double)N);
+    }
+}
+
+// Per-l weights: SHT (-1)^s sqrt((2l+1)/4pi) (Eqs. 30, 33); SO(3) inverse
+// (2l+1)/(8 pi^2) (Eq. 13); SO(3) forward 1 (Eq. 14).
+void host_weights(int L, int kind, int spin, std::vector<double> *w)
+{
+    w->resize(L);
+    for (int l = 0; l < L; ++l) {
+        q v;
+        if (kind == 0) {
+            v = sqrtq((2 * (q)l + 1) / (4 * QPI));
+            if ((spin < 0 ? -spin : spin) % 2) v = -v;
+        } else if (kind == 1) {
+            v = (2 * (q)l + 1) / (8 * QPI * QPI);
+        } else {
+            v = 1;
+        }
+        (*w)[l] = (double)v;
+    }
+}
+
+}  // namespace s2mi

@@ -1,0 +1,63 @@
+// s2mi_internal.h -- library-internal declarations shared by the host constant
+// generator (g++), the kernels and the C-ABI layer (hipcc).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace s2mi {
+
+// ----------------------------------------------------------------- host constants
+struct RingConsts {
+    std::vector<double> theta, cot, csc;   // per ring
+    std::vector<double> lsin, lcos;        // per ring, double-double (hi, lo): log2 sin(th/2), log2 cos(th/2)
+};
+
+#ifdef __SIZEOF_FLOAT128__
+#if !defined(__HIP_DEVICE_COMPILE__) && !defined(__HIPCC__)
+void fill_ring(RingConsts *rc, int r, __float128 th);
+#endif
+#endif
+void host_mw_rings(int L, RingConsts *rc);
+void host_healpix_rings(int nside, RingConsts *rc, std::vector<int> *nphi,
+                        std::vector<long long> *start, std::vector<int> *shift);
+void host_log2_binom(int L, int n, std::vector<double> *out);
+void host_recursion_tables(int L, std::vector<double> *kap, std::vector<double> *gtab);
+void host_roots(int n, std::vector<double> *out);
+void host_chirp(int n, std::vector<double> *out);
+void host_mw_filter(int L, std::vector<double> *wq, std::vector<double> *ph);
+void host_weights(int L, int kind, int spin, std::vector<double> *w);
+
+// ----------------------------------------------------------------- FFT
+constexpr int FFT_MAX_STAGES = 16;
+constexpr int FFT_MAX_LEN = 8192;        // LDS-resident engine length (complex doubles)
+constexpr int FFT_THREADS = 1024;
+
+// Everything a kernel needs to run one DFT of length n in LDS (passed by value).
+struct FftArgs {
+    int n;            // logical DFT length
+    int len;          // engine length: n (mixed radix) or a power of two >= 2n-1 (Bluestein)
+    int blue;         // 1: Bluestein
+    int nst;          // engine stages
+    int rad[FFT_MAX_STAGES];
+    const double *tw;     // e^{-2 pi i k/len}, k < len (interleaved)
+    const double *chirp;  // Bluestein: e^{+i pi k^2/n}, k < n
+    const double *bflt;   // Bluestein: FFT_len of the chirp filter, divided by len
+};
+
+// ----------------------------------------------------------------- d-stage geometry
+constexpr int INV_J = 16;       // l-slots per wave in the inverse d-stage
+constexpr int FWD_R = 16;       // ring-slots per wave in the forward d-stage
+constexpr int MAX_WAVES = 16;
+
+// One recursion run: fixed second index n of d^l_{m,n}; its A side feeds the
+// slice of spin -n at orders +m, its B side the slice of spin +n at orders -m.
+struct Run {
+    int n;
+    int sliceA;   // slice index or -1
+    int sliceB;   // slice index or -1
+};
+
+}  // namespace s2mi

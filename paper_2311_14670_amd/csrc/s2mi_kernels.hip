@@ -1,0 +1,818 @@
+// s2mi_kernels.hip -- gfx950 kernels of the spin SHT / Wigner transforms.
+//
+// Paper: Price & McEwen, arXiv 2311.14670.
+//   d-stage   Wigner d^l_{m,n}(theta) by the descending-m recursion (Sec. 3.3,
+//             Eqs. 25-26) started from Eq. 27 in log space, renormalised as it
+//             runs (Sec. 3.4), fused with the l-contraction of Eq. 33 (inverse)
+//             or the theta-contraction of Eq. 30 (forward) -- Sec. 4.4.
+//   phi-DFT   Eqs. 31-32 per isolatitude ring; HEALPix rings repeat / fold the
+//             Fourier line (Sec. 4.2, HEALPix).
+//   MW theta  the exact MW theta integral (Sec. 4.2, MW): torus extension,
+//             band-limited sin(theta) weight, evaluated on the L rings.
+//
+// Recursion in rescaled form.  With alpha_k = sqrt((l+k)(l-k+1)) and
+// d_m = e_m g_m (g from the plan tables), Eq. 25 becomes
+//     e_{m-1} = kappa_m lambda_m e_m - e_{m+1},  lambda_m = (n - m cos th)/sin th,
+// two FP64 operations per step.  Each (ring, l) carries (e_m, e_{m+1}, E) with
+// d = e g 2^E.  While E < 0 the pair is renormalised every step by an exact
+// power of two; once the value is within 2^-600 of unity scale it is held
+// unscaled (E = 0): |d| <= 1 and the recursion runs downhill in m, so it can
+// no longer overflow or meaningfully underflow.  A wave switches a slot to the
+// unscaled fast path when all its lanes have E = 0.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "s2mi_fft.h"
+#include "s2mi_internal.h"
+#include "s2mi_kernels.h"
+
+namespace s2mi {
+
+constexpr int RT = 600;   // realise once the scale exponent is above -RT
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD dd_from(const double *p) { return DD{p[0], p[1]}; }
+
+__device__ __forceinline__ DD two_sum(double a, double b)
+{
+    const double s = a + b;
+    const double bb = s - a;
+    const double e = (a - (s - bb)) + (b - bb);
+    return DD{s, e};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b)
+{
+    DD s = two_sum(a.hi, b.hi);
+    s.lo += a.lo + b.lo;
+    return two_sum(s.hi, s.lo);
+}
+
+__device__ __forceinline__ DD dd_mul_d(DD a, double k)   // k an exact small integer
+{
+    const double p = a.hi * k;
+    const double e = fma(a.hi, k, -p);
+    return two_sum(p, e + a.lo * k);
+}
+
+// d^l_{l,n}(theta) of Eq. 27 as (mantissa e, exponent E): log2|d| =
+// lbin + (l-n) log2 sin(th/2) + (l+n) log2 cos(th/2) in double-double, sign (-1)^{l-n}.
+// Realised (E = 0) directly when the value is not tiny.
+__device__ __forceinline__ void d_init(int l, int n, DD lbin, DD ls, DD lc, double &e, int &E)
+{
+    DD x = dd_add(lbin, dd_add(dd_mul_d(ls, (double)(l - n)), dd_mul_d(lc, (double)(l + n))));
+    double fl = floor(x.hi);
+    double f = (x.hi - fl) + x.lo;
+    if (f < 0.0) { f += 1.0; fl -= 1.0; }
+    if (f >= 1.0) { f -= 1.0; fl += 1.0; }
+    double v = exp2(f);
+    if ((l - n) & 1) v = -v;
+    int ex = (int)fl;
+    if (ex >= -RT) { v = ldexp(v, ex); ex = 0; }
+    e = v;
+    E = ex;
+}
+
+// exact power-of-two renormalisation of the pair (e, ep) carrying exponent E
+__device__ __forceinline__ void renorm(double &e, double &ep, int &E)
+{
+    const double mx = fmax(fabs(e), fabs(ep));
+    const int k = mx > 0.0 ? ilogb(mx) : 0;          // a not-yet-started (zero) state keeps E
+    const bool real = (E + k >= -RT);
+    const int sh = real ? E : -k;
+    e = ldexp(e, sh);
+    ep = ldexp(ep, sh);
+    E = real ? 0 : E + k;
+}
+
+// ------------------------------------------------------------------ inverse pack
+// Records in the inverse sweep's slot order, C[blk][m][wave][slot] = 5 doubles
+//   {kappa_{m+1}^l, wA_l g_m^l flmA[l][m], wB_l g_m^l (-1)^{m-n} flmB[l][-m]}
+// for l = lslot[blk][wave][slot]; zeros where the run does not reach
+// (l < max(m, |n|), empty slot) or the side is absent.  A wave then reads the
+// records of one order at fixed offsets from a single base address.
+__global__ void k_pack_inv(int L, int n, int nslot, int S, const int *__restrict__ lslot, const double2 *__restrict__ flmA,
+                           const double2 *__restrict__ flmB, const double *__restrict__ wA,
+                           const double *__restrict__ wB, const double *__restrict__ kap,
+                           const double *__restrict__ gtab, double *__restrict__ C)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // i = (m, blk, slot-in-block)
+    const int m = blockIdx.y;
+    if (i >= (size_t)nslot) return;
+    const int M = 2 * L - 1;
+    const int an = n < 0 ? -n : n;
+    const int l = lslot[i];
+    double rec[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (l >= 0 && l >= m && l >= an) {
+        const double g = gtab[(size_t)m * L + l];
+        if (l > m) rec[0] = kap[(size_t)m * L + l];
+        if (flmA) {
+            const double2 a = flmA[(size_t)l * M + (L - 1) + m];
+            const double sa = wA[l] * g;
+            rec[1] = sa * a.x;
+            rec[2] = sa * a.y;
+        }
+        if (flmB && m > 0) {
+            const double2 b = flmB[(size_t)l * M + (L - 1) - m];
+            double sb = wB[l] * g;
+            if ((m - n) & 1) sb = -sb;
+            rec[3] = sb * b.x;
+            rec[4] = sb * b.y;
+        }
+    }
+    // slot index i = blk * S + s (S slots per block); record at ((blk * L + m) * S + s)
+    const int blk = (int)(i / S), s = (int)(i % S);
+    double *o = C + (((size_t)blk * L + m) * S + s) * 5;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) o[q] = rec[q];
+}
+
+// ------------------------------------------------------------------ inverse d-stage
+// Lanes = 64 rings; each wave owns INV_J l-slots (wave-uniform, from lslot);
+// waves of a workgroup share the rings and split the l-range.  At order m:
+//   acc_A(ring) = sum_{slots} e g 2^E * C[m][l].A,  acc_B likewise,
+// reduced over the waves in LDS and written to partA/partB[blk][ring][m].
+// The two state registers of a slot alternate roles between consecutive
+// orders (PAR = 0: X newest, Y older; the step overwrites Y), so the recursion
+// needs no register moves.
+template <int J, int PAR>
+__device__ __forceinline__ void inv_step(int m, int L, int n, int an, int ring0, int nreg, int lane, int w, int W,
+                                         const int (&lsl)[J], double (&X)[J], double (&Y)[J], int (&E)[J],
+                                         uint32_t &fast, double ct, double ncs, DD ls, DD lc,
+                                         const double *__restrict__ lbin, const double *__restrict__ C, double *red,
+                                         int blk, double *__restrict__ partA, double *__restrict__ partB)
+{
+    const double lam = fma(-(double)(m + 1), ct, ncs);   // lambda_{m+1}: produces order m
+    double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
+    const double *Cw = C + (((size_t)blk * L + m) * W + w) * J * 5;   // this wave's records at order m
+    // at most one slot starts at this order (distinct l per wave): initialise it once
+    int jin = -1;
+#pragma unroll
+    for (int j = 0; j < J; ++j) if (lsl[j] == m && m >= an) jin = j;
+    double e0 = 0.0;
+    int E0 = 0;
+    if (jin >= 0) d_init(m, n, dd_from(lbin + 2 * m), ls, lc, e0, E0);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int l = lsl[j];
+        if (l < m || l < an) continue;                    // slot not started, empty (-1), or below |n|
+        double &nw = PAR == 0 ? Y[j] : X[j];              // receives order m
+        double &od = PAR == 0 ? X[j] : Y[j];              // holds order m+1
+        if (j == jin) {
+            nw = e0;
+            od = 0.0;
+            E[j] = E0;
+            fast = __all(E0 == 0) ? (fast | (1u << j)) : (fast & ~(1u << j));
+        } else {
+            nw = fma(Cw[j * 5] * lam, od, -nw);
+            if (!((fast >> j) & 1u)) {
+                renorm(nw, od, E[j]);
+                if (__all(E[j] == 0)) fast |= (1u << j);
+            }
+        }
+        const double t = ((fast >> j) & 1u) ? nw : nw * ldexp(1.0, E[j]);
+        const double *c = Cw + j * 5 + 1;
+        aAr = fma(t, c[0], aAr);
+        aAi = fma(t, c[1], aAi);
+        aBr = fma(t, c[2], aBr);
+        aBi = fma(t, c[3], aBi);
+    }
+    double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
+    rb[(w * 4 + 0) * 64 + lane] = aAr;
+    rb[(w * 4 + 1) * 64 + lane] = aAi;
+    rb[(w * 4 + 2) * 64 + lane] = aBr;
+    rb[(w * 4 + 3) * 64 + lane] = aBi;
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int rl = threadIdx.x & 63, comp = threadIdx.x >> 6;
+        double s = 0.0;
+        for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
+        double *dst = comp < 2 ? partA : partB;
+        if (dst && ring0 + rl < nreg) dst[(((size_t)blk * nreg + ring0 + rl) * L + m) * 4 + comp] = s;
+    }
+}
+
+template <int J>
+__global__ __launch_bounds__(1024) void k_dstage_inv(
+    int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
+    const double *__restrict__ lsin, const double *__restrict__ lcos, const double *__restrict__ lbin,
+    const double *__restrict__ C, const int *__restrict__ lslot, const int *__restrict__ mtop,
+    double *__restrict__ partA, double *__restrict__ partB)
+{
+    __shared__ double red[2 * MAX_WAVES * 4 * 64];
+    const int an = n < 0 ? -n : n;
+    const int lane = threadIdx.x & 63;
+    const int w = ufl(threadIdx.x >> 6);
+    const int W = blockDim.x >> 6;
+    const int blk = blockIdx.y;
+    const int ring0 = blockIdx.x * 64;
+    const int ring = min(ring0 + lane, nreg - 1);
+    const double ct = cot[ring], cs = csc[ring];
+    const double ncs = (double)n * cs;
+    const DD ls = dd_from(lsin + 2 * ring), lc = dd_from(lcos + 2 * ring);
+
+    int lsl[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) lsl[j] = ufl(lslot[((size_t)blk * W + w) * J + j]);
+    double X[J], Y[J];
+    int E[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) { X[j] = 0.0; Y[j] = 0.0; E[j] = 0; }
+    uint32_t fast = 0;
+
+    const int mt = ufl(mtop[blk]);
+    for (int m = mt; m >= 0; m -= 2) {
+        inv_step<J, 0>(m, L, n, an, ring0, nreg, lane, w, W, lsl, X, Y, E, fast, ct, ncs, ls, lc, lbin, C, red,
+                       blk, partA, partB);
+        if (m >= 1)
+            inv_step<J, 1>(m - 1, L, n, an, ring0, nreg, lane, w, W, lsl, X, Y, E, fast, ct, ncs, ls, lc, lbin, C,
+                           red, blk, partA, partB);
+    }
+}
+
+// ------------------------------------------------------------------ forward d-stage
+// Lanes = 64 consecutive l (group g); each wave owns FWD_R ring slots; waves of
+// a workgroup share the l-group and split the rings.  A workgroup runs group p
+// then group G-1-p so all workgroups carry equal work.  At order m:
+//   acc(l) = g_m^l sum_{slots} e 2^E * H[m][ring],
+// reduced over the waves in LDS and written to QA/QB[blk][l][m].  Register
+// roles alternate between orders as in the inverse sweep.
+template <int R, int PAR, bool HEAD>
+__device__ __forceinline__ void fwd_step(int m, int g, int l, int lc, int L, int n, int an, int lane, int w, int W,
+                                         int hstride, int my_ring, int rbase, int rcnt, double (&X)[R],
+                                         double (&Y)[R], int (&E)[R], uint32_t &fast,
+                                         const double *__restrict__ lam, const double *__restrict__ lsin,
+                                         const double *__restrict__ lcos, const double *__restrict__ lbin,
+                                         const double *__restrict__ kap, const double *__restrict__ gtab,
+                                         const double *__restrict__ HA, const double *__restrict__ HB,
+                                         double (*ini_e)[R], int (*ini_E)[R], double *red, int blk,
+                                         double *__restrict__ QA, double *__restrict__ QB)
+{
+    if constexpr (HEAD) {
+        // some lane may initialise at this order: d^m_{m,n}(theta_slot) for every
+        // slot of this wave, one slot per lane, broadcast through LDS
+        if (my_ring >= 0 && m >= an) {
+            double v;
+            int ex;
+            d_init(m, n, dd_from(lbin + 2 * m), dd_from(lsin + 2 * my_ring), dd_from(lcos + 2 * my_ring), v, ex);
+            ini_e[w][lane] = v;
+            ini_E[w][lane] = ex;
+        }
+        __syncthreads();
+    }
+    const double kk = (l > m && l < L) ? kap[(size_t)m * L + lc] : 0.0;
+    double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
+    const double *HAm = HA + ((size_t)m * hstride + rbase) * 4;    // slot k = ring rbase + k
+    const double *HBm = HB + ((size_t)m * hstride + rbase) * 4 + 2;
+    const double *Lm = lam + rbase;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (k >= rcnt) continue;
+        double &nw = PAR == 0 ? Y[k] : X[k];
+        double &od = PAR == 0 ? X[k] : Y[k];
+        nw = fma(kk * Lm[k], od, -nw);
+        if constexpr (HEAD) {
+            if (l == m && l >= an) {
+                nw = ini_e[w][k];
+                E[k] = ini_E[w][k];
+                od = 0.0;
+            }
+            if (!((fast >> k) & 1u)) renorm(nw, od, E[k]);
+            fast = __all(E[k] == 0) ? (fast | (1u << k)) : (fast & ~(1u << k));
+        } else if (!((fast >> k) & 1u)) {
+            renorm(nw, od, E[k]);
+            if (__all(E[k] == 0)) fast |= (1u << k);
+        }
+        const double t = ((fast >> k) & 1u) ? nw : nw * ldexp(1.0, E[k]);
+        const double *ha = HAm + k * 4;
+        const double *hb = HBm + k * 4;
+        aAr = fma(t, ha[0], aAr);
+        aAi = fma(t, ha[1], aAi);
+        aBr = fma(t, hb[0], aBr);
+        aBi = fma(t, hb[1], aBi);
+    }
+    const double gm = (l >= m && l < L) ? gtab[(size_t)m * L + lc] : 0.0;
+    double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
+    rb[(w * 4 + 0) * 64 + lane] = aAr * gm;
+    rb[(w * 4 + 1) * 64 + lane] = aAi * gm;
+    rb[(w * 4 + 2) * 64 + lane] = aBr * gm;
+    rb[(w * 4 + 3) * 64 + lane] = aBi * gm;
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int ll = threadIdx.x & 63, comp = threadIdx.x >> 6;
+        const int lo = 64 * g + ll;
+        double s = 0.0;
+        for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + ll];
+        double *dst = comp < 2 ? QA : QB;
+        if (dst && lo < L && lo >= m) dst[(((size_t)blk * L + lo) * L + m) * 4 + comp] = s;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(1024) void k_dstage_fwd(
+    int L, int nreg, int hstride, int n, int G, const double *__restrict__ lam, const double *__restrict__ lsin,
+    const double *__restrict__ lcos, const double *__restrict__ lbin, const double *__restrict__ kap,
+    const double *__restrict__ gtab, const double *__restrict__ HA, const double *__restrict__ HB,
+    double *__restrict__ QA, double *__restrict__ QB)
+{
+    __shared__ double red[2 * MAX_WAVES * 4 * 64];
+    __shared__ double ini_e[MAX_WAVES][R];
+    __shared__ int ini_E[MAX_WAVES][R];
+    const int an = n < 0 ? -n : n;
+    const int lane = threadIdx.x & 63;
+    const int w = ufl(threadIdx.x >> 6);
+    const int W = blockDim.x >> 6;
+    const int blk = blockIdx.y;
+    const int p = blockIdx.x;
+    // this wave's rings: rbase .. rbase + rcnt - 1 (contiguous)
+    const int rbase = (blk * W + w) * R;
+    const int rcnt = ufl(max(0, min(R, nreg - rbase)));
+    const int my_ring = lane < rcnt ? rbase + lane : -1;   // slot 'lane'
+
+    for (int pass = 0; pass < 2; ++pass) {
+        const int g = pass == 0 ? p : G - 1 - p;
+        if (pass == 1 && g == p) break;
+        const int l = 64 * g + lane;
+        const int lc = min(l, L - 1);
+        double X[R], Y[R];
+        int E[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) { X[k] = 0.0; Y[k] = 0.0; E[k] = 0; }
+        uint32_t fast = (1u << R) - 1u;
+        const int mstart = min(64 * g + 63, L - 1);
+        // head: the orders at which lanes of this group start (an even number of
+        // steps so the register roles line up with the main loop)
+        const int hend = ((mstart - 64 * g + 1) % 2 == 0) ? 64 * g : 64 * g - 1;
+        int m = mstart;
+        for (; m >= hend && m >= 0; m -= 2) {
+            fwd_step<R, 0, true>(m, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
+                                 lam + (size_t)m * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E, red, blk,
+                                 QA, QB);
+            if (m >= 1)
+                fwd_step<R, 1, true>(m - 1, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
+                                     lam + (size_t)(m - 1) * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E,
+                                     red, blk, QA, QB);
+        }
+        for (; m >= 0; m -= 2) {
+            fwd_step<R, 0, false>(m, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
+                                  lam + (size_t)m * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E, red, blk,
+                                  QA, QB);
+            if (m >= 1)
+                fwd_step<R, 1, false>(m - 1, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
+                                      lam + (size_t)(m - 1) * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E,
+                                      red, blk, QA, QB);
+        }
+        __syncthreads();   // the LDS buffers are reused by the next pass
+    }
+}
+
+// 2 lambda table for the forward sweep: lam[m][r] = n csc_r - (m+1) cot_r
+// (the same FMA the inverse sweep evaluates inline).
+__global__ void k_lambda_table(int L, int nreg, int n, const double *__restrict__ cot,
+                               const double *__restrict__ csc, double *__restrict__ lam)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)L * nreg) return;
+    const int m = (int)(i / nreg), r = (int)(i % nreg);
+    lam[i] = fma(-(double)(m + 1), cot[r], (double)n * csc[r]);
+}
+
+// ------------------------------------------------------------------ phi-DFT: inverse
+// One workgroup per (map, ring).  X_k = ftilde at orders m == k mod nphi
+// (summed over the d-stage blocks), times the ring's half-pixel phase, then an
+// inverse DFT of length nphi.  MW rings: nphi = 2L-1 and the order line maps
+// one-to-one onto the bins.  The MW south pole (ring == nreg) has the closed
+// form d^l_{m,-s}(pi) = (-1)^{l+m} delta_{m,s} (Eq. 29).
+__global__ __launch_bounds__(1024) void k_phi_inv(
+    int L, int nreg, int nblk, int spin, const double *__restrict__ part, const int *__restrict__ mtop,
+    const double2 *__restrict__ flm,
+    const double *__restrict__ wl, const int *__restrict__ ring_nphi, const long long *__restrict__ ring_start,
+    const int *__restrict__ ring_shift, const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts,
+    double2 *__restrict__ map)
+{
+    extern __shared__ double2 buf[];
+    __shared__ double2 red[1024];
+    const int r = blockIdx.x;
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int nphi = ring_nphi[r];
+    const FftArgs *f = ffts + ring_fft[r];
+    const int shift = ring_shift[r];
+    const int M = 2 * L - 1;
+    if (r < nreg) {
+        const double *pr = part + (size_t)r * L * 4;
+        const size_t bstride = (size_t)nreg * L * 4;
+        for (int k = tid; k < nphi; k += T) {
+            double2 acc = make_double2(0.0, 0.0);
+            // orders m = k + q nphi within [-(L-1), L-1]
+            int m = k - ((k + L - 1) / nphi) * nphi;
+            for (; m <= L - 1; m += nphi) {
+                const int am = m < 0 ? -m : m;
+                const int off = am * 4 + (m < 0 ? 2 : 0);
+                double2 v = make_double2(0.0, 0.0);
+                for (int b = 0; b < nblk; ++b) {
+                    if (am > mtop[b]) continue;              // that block's sweep never reached order m
+                    const double *pp = pr + b * bstride + off;
+                    v.x += pp[0];
+                    v.y += pp[1];
+                }
+                if (shift) {
+                    double s, c;   // e^{i pi m / nphi}
+                    sincospi((double)(((long long)m % (2 * nphi) + 2 * nphi) % (2 * nphi)) / (double)nphi, &s, &c);
+                    v = cmul(v, make_double2(c, s));
+                }
+                acc = cadd(acc, v);
+            }
+            buf[k] = acc;
+        }
+    } else {
+        // south pole: only m = s contributes, value sum_l (-1)^{l+s} w_l flm[l][s]
+        double2 acc = make_double2(0.0, 0.0);
+        const int as = spin < 0 ? -spin : spin;
+        for (int l = as + tid; l < L; l += T) {
+            double2 v = flm[(size_t)l * M + (L - 1) + spin];
+            const double c = ((l + spin) & 1) ? -wl[l] : wl[l];
+            acc.x += c * v.x;
+            acc.y += c * v.y;
+        }
+        red[tid] = acc;
+        __syncthreads();
+        int p2 = 1;
+        while (p2 < T) p2 <<= 1;
+        for (int s = p2 / 2; s > 0; s >>= 1) {   // T need not be a power of two
+            if (tid < s && tid + s < T) red[tid] = cadd(red[tid], red[tid + s]);
+            __syncthreads();
+        }
+        for (int k = tid; k < nphi; k += T) buf[k] = make_double2(0.0, 0.0);
+        __syncthreads();
+        if (tid == 0) buf[((spin % nphi) + nphi) % nphi] = red[0];
+    }
+    __syncthreads();
+    dft_lds(buf, f, +1);
+    double2 *out = map + ring_start[r];
+    for (int k = tid; k < nphi; k += T) out[k] = buf[k];
+}
+
+// ------------------------------------------------------------------ phi-DFT: forward
+// One workgroup per (map, ring): X = DFT_nphi(ring); ftilde_m = q e^{-i pi m s_r/nphi} X[m mod nphi]
+// for |m| < L (the periodic repeat of Sec. 4.2 for short HEALPix rings), written
+// to F[m][ring] = {ftilde_m, ftilde_-m}.
+__global__ __launch_bounds__(1024) void k_phi_fwd(
+    int L, int nring, double q, const double2 *__restrict__ map, const int *__restrict__ ring_nphi,
+    const long long *__restrict__ ring_start, const int *__restrict__ ring_shift,
+    const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, double *__restrict__ F)
+{
+    extern __shared__ double2 buf[];
+    const int r = blockIdx.x;
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int nphi = ring_nphi[r];
+    const FftArgs *f = ffts + ring_fft[r];
+    const int shift = ring_shift[r];
+    const double2 *in = map + ring_start[r];
+    for (int k = tid; k < nphi; k += T) buf[k] = in[k];
+    __syncthreads();
+    dft_lds(buf, f, -1);
+    for (int m = tid; m < L; m += T) {
+        double2 a = buf[m % nphi];
+        double2 b = buf[(nphi - (m % nphi)) % nphi];
+        if (shift) {
+            double s, c;   // e^{-i pi m / nphi}
+            sincospi((double)(m % (2 * nphi)) / (double)nphi, &s, &c);
+            a = cmul(a, make_double2(c, -s));
+            b = cmul(b, make_double2(c, s));
+        }
+        double *o = F + ((size_t)m * nring + r) * 4;
+        *reinterpret_cast<double2 *>(o) = make_double2(q * a.x, q * a.y);
+        *reinterpret_cast<double2 *>(o + 2) = make_double2(q * b.x, q * b.y);
+    }
+}
+
+// ------------------------------------------------------------------ MW theta filter
+// One workgroup per order m >= 0, both signs.  For g = the torus extension of
+// ftilde_{+-m} (g(2pi - th) = (-1)^{m+s} g(th)), compute on the L rings
+//   h~(theta_t) = (2pi/N) [h(theta_t) + (-1)^{m+s} h(theta_{N-1-t})]  (t < L-1),
+//   h~(pi)      = (2pi/N) h(pi),
+//   h = P_{L-1}[g w'],   w' = P_{2L-2}[sin(theta) 1_[0,pi]],
+// so that sum_t h~(theta_t) d(theta_t) = int_0^pi g d sin(theta) exactly.  On the
+// doubled grid {theta_t} u {mu_t = theta_t + pi/N}:
+//   h = (g w'_theta + S-[w'_mu S+ g]) / 2,
+// S+-: band-limited half-sample shifts (DFT, phase e^{+-i k pi/N}/N, inverse DFT).
+// In place: F[m][t] -> H[m][t]; the south-pole value goes to hpole[m].
+__global__ __launch_bounds__(1024) void k_mw_filter(int L, int spin, const FftArgs *__restrict__ fN,
+                                                    const double *__restrict__ wq, const double *__restrict__ ph,
+                                                    double *__restrict__ F, double2 *__restrict__ hpole)
+{
+    extern __shared__ double2 buf[];
+    const int m = blockIdx.x;
+    const int N = 2 * L - 1;
+    const int T = blockDim.x, tid = threadIdx.x;
+    const double par = ((m + spin) & 1) ? -1.0 : 1.0;
+    const double2 *phc = reinterpret_cast<const double2 *>(ph);
+    for (int side = 0; side < 2; ++side) {
+        if (side == 1 && m == 0) break;
+        // torus samples
+        for (int t = tid; t < N; t += T) {
+            const int tt = t < L ? t : N - 1 - t;
+            const double *src = F + ((size_t)m * L + tt) * 4 + 2 * side;
+            double2 g = make_double2(src[0], src[1]);
+            if (t >= L) { g.x *= par; g.y *= par; }
+            buf[t] = g;
+        }
+        __syncthreads();
+        dft_lds(buf, fN, -1);
+        for (int k = tid; k < N; k += T) buf[k] = cmul(buf[k], phc[k]);              // shift +pi/N
+        __syncthreads();
+        dft_lds(buf, fN, +1);
+        for (int t = tid; t < N; t += T) { const double wv = wq[N + t]; buf[t].x *= wv; buf[t].y *= wv; }
+        __syncthreads();
+        dft_lds(buf, fN, -1);
+        for (int k = tid; k < N; k += T) buf[k] = cmulc(buf[k], phc[k]);             // shift -pi/N
+        __syncthreads();
+        dft_lds(buf, fN, +1);
+        for (int t = tid; t < N; t += T) {          // + g w'_theta (g re-read: F is rewritten only below)
+            const int tt = t < L ? t : N - 1 - t;
+            const double *src = F + ((size_t)m * L + tt) * 4 + 2 * side;
+            const double wv = (t >= L ? par : 1.0) * wq[t];
+            buf[t] = make_double2(0.5 * fma(src[0], wv, buf[t].x), 0.5 * fma(src[1], wv, buf[t].y));
+        }
+        __syncthreads();
+        const double sc = 2.0 * M_PI / (double)N;
+        for (int t = tid; t < L; t += T) {
+            double2 h = buf[t];
+            if (t < L - 1) {
+                const double2 hr = buf[N - 1 - t];
+                h.x += par * hr.x;
+                h.y += par * hr.y;
+            }
+            h.x *= sc;
+            h.y *= sc;
+            if (t < L - 1) {
+                double *dst = F + ((size_t)m * L + t) * 4 + 2 * side;
+                dst[0] = h.x;
+                dst[1] = h.y;
+            } else {
+                hpole[side == 0 ? (L - 1) + m : (L - 1) - m] = h;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ forward finish
+// flm[l][m] = w_l * (sum_b Q[b][l][|m|].side) * ((-1)^{|m|-nB} for m < 0)
+//           + MW south pole: w_l (-1)^{l+s} h~_s(pi) at m = s  (Eq. 29).
+// Zero where l < max(|m|, |spin|).
+__global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__restrict__ Q,
+                             const double *__restrict__ wl, const double2 *__restrict__ hpole,
+                             double2 *__restrict__ flm)
+{
+    const int M = 2 * L - 1;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)L * M) return;
+    const int l = (int)(i / M), m = (int)(i % M) - (L - 1);
+    const int am = m < 0 ? -m : m, as = spin < 0 ? -spin : spin;
+    double2 v = make_double2(0.0, 0.0);
+    if (l >= am && l >= as) {
+        const int off = m < 0 ? 2 : 0;
+        for (int b = 0; b < nblk; ++b) {
+            const double *q = Q + (((size_t)b * L + l) * L + am) * 4 + off;
+            v.x += q[0];
+            v.y += q[1];
+        }
+        if (m < 0 && ((am - nB) & 1)) { v.x = -v.x; v.y = -v.y; }
+        v.x *= wl[l];
+        v.y *= wl[l];
+        if (hpole && m == spin) {
+            const double2 hp = hpole[(L - 1) + m];
+            const double c = ((l + spin) & 1) ? -wl[l] : wl[l];
+            v.x += c * hp.x;
+            v.y += c * hp.y;
+        }
+    }
+    flm[i] = v;
+}
+
+// ------------------------------------------------------------------ SO(3) gamma DFT
+// inverse: out[k][i] = sum_n e^{i n gamma_k} in[n][i];  forward: out[n][i] = q sum_k e^{-i n gamma_k} in[k][i]
+__global__ void k_gamma_dft(int N, long long nper, int sign, double q, const double *__restrict__ roots,
+                            const double2 *__restrict__ in, double2 *__restrict__ out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nper) return;
+    const int G = 2 * N - 1;
+    double2 v[15];
+    for (int a = 0; a < G; ++a) v[a] = in[(size_t)a * nper + i];
+    for (int b = 0; b < G; ++b) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int a = 0; a < G; ++a) {
+            // sign = +1 (inverse): a = n index (n = a-(N-1)), b = k;  sign = -1: a = k, b = n index
+            const int nn = (sign > 0 ? a : b) - (N - 1);
+            const int kk = sign > 0 ? b : a;
+            const int idx = (int)((((long long)nn * kk) % G + G) % G);
+            const double2 rt = ldroot(roots, idx, sign);
+            acc = cadd(acc, cmul(v[a], rt));
+        }
+        out[(size_t)b * nper + i] = make_double2(q * acc.x, q * acc.y);
+    }
+}
+
+// ------------------------------------------------------------------ debug export of d
+// out[r][m][l] = d^l_{m,n}(theta_r) from the same init / step / renormalisation
+// as the sweeps (one thread per (ring, l)).
+__global__ void k_debug_d(int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
+                          const double *__restrict__ lsin, const double *__restrict__ lcos,
+                          const double *__restrict__ lbin, const double *__restrict__ kap,
+                          const double *__restrict__ gtab, double *__restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (r >= nreg) return;
+    const int an = n < 0 ? -n : n;
+    double *o = out + (size_t)r * L * L;
+    for (int m = 0; m <= l; ++m) o[(size_t)m * L + l] = 0.0;
+    if (l < an) return;
+    double e, ep = 0.0;
+    int E;
+    d_init(l, n, dd_from(lbin + 2 * l), dd_from(lsin + 2 * r), dd_from(lcos + 2 * r), e, E);
+    o[(size_t)l * L + l] = ldexp(e * gtab[(size_t)l * L + l], E);
+    for (int m = l - 1; m >= 0; --m) {
+        const double lam = fma(-(double)(m + 1), cot[r], (double)n * csc[r]);
+        const double en = fma(kap[(size_t)m * L + l] * lam, e, -ep);
+        ep = e;
+        e = en;
+        if (E != 0) renorm(e, ep, E);
+        o[(size_t)m * L + l] = ldexp(e * gtab[(size_t)m * L + l], E);
+    }
+}
+
+// ------------------------------------------------------------------ Bluestein filters
+// For every Bluestein transform: bflt = DFT_len(b) / len with b_j = c_j (j < n),
+// b_{len-j} = c_j (0 < j < n), 0 elsewhere -- the circular form of the chirp.
+__global__ __launch_bounds__(1024) void k_bluestein_prep(const FftArgs *__restrict__ ffts)
+{
+    extern __shared__ double2 buf[];
+    const FftArgs *f = ffts + blockIdx.x;
+    if (!f->blue) return;
+    const int n = f->n, len = f->len;
+    const double2 *ch = reinterpret_cast<const double2 *>(f->chirp);
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+        double2 v = make_double2(0.0, 0.0);
+        if (i < n) v = ch[i];
+        else if (i > len - n) v = ch[len - i];
+        buf[i] = v;
+    }
+    __syncthreads();
+    fft_engine(buf, f, -1);
+    double2 *out = reinterpret_cast<double2 *>(const_cast<double *>(f->bflt));
+    const double inv = 1.0 / (double)len;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) out[i] = make_double2(buf[i].x * inv, buf[i].y * inv);
+}
+
+// pole[(L-1) + m] = F[|m|][ring].side(m): the MW south-pole ring's Fourier line
+__global__ void k_pole_from_F(int L, int nring, int ring, const double *__restrict__ F, double2 *__restrict__ pole)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * L - 1) return;
+    const int m = i - (L - 1), am = m < 0 ? -m : m;
+    const double *src = F + ((size_t)am * nring + ring) * 4 + (m < 0 ? 2 : 0);
+    pole[i] = make_double2(src[0], src[1]);
+}
+
+// ------------------------------------------------------------------ launchers
+#define S2_LAUNCH_CHECK() do { hipError_t _e = hipGetLastError(); if (_e != hipSuccess) return _e; } while (0)
+
+hipError_t launch_pack_inv(hipStream_t st, int L, int n, int nblk, int slots_per_blk, const int *lslot,
+                           const double2 *flmA, const double2 *flmB, const double *wA, const double *wB,
+                           const double *kap, const double *gtab, double *C)
+{
+    const int nslot = nblk * slots_per_blk;
+    dim3 grid((nslot + 255) / 256, L);
+    hipLaunchKernelGGL(k_pack_inv, grid, dim3(256), 0, st, L, n, nslot, slots_per_blk, lslot, flmA, flmB, wA, wB, kap,
+                       gtab, C);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nreg, int n, const double *cot,
+                             const double *csc, const double *lsin, const double *lcos, const double *lbin,
+                             const double *C, const int *lslot, const int *mtop, double *partA, double *partB)
+{
+    dim3 grid((nreg + 63) / 64, nblk);
+    hipLaunchKernelGGL(k_dstage_inv<INV_J>, grid, dim3(64 * nwaves), 0, st, L, nreg, n, cot, csc, lsin, lcos,
+                       lbin, C, lslot, mtop, partA, partB);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nreg, int hstride, int n,
+                             const double *lam, const double *lsin, const double *lcos, const double *lbin,
+                             const double *kap, const double *gtab, const double *HA, const double *HB,
+                             double *QA, double *QB)
+{
+    dim3 grid((G + 1) / 2, nblk);
+    hipLaunchKernelGGL(k_dstage_fwd<FWD_R>, grid, dim3(64 * nwaves), 0, st, L, nreg, hstride, n, G, lam, lsin,
+                       lcos, lbin, kap, gtab, HA, HB, QA, QB);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_lambda_table(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
+                               double *lam)
+{
+    const size_t tot = (size_t)L * nreg;
+    hipLaunchKernelGGL(k_lambda_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nreg, n, cot,
+                       csc, lam);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk, int spin,
+                          const double *part, const int *mtop, const double2 *flm, const double *wl,
+                          const int *ring_nphi, const long long *ring_start, const int *ring_shift,
+                          const int *ring_fft, const FftArgs *ffts, double2 *map)
+{
+    hipLaunchKernelGGL(k_phi_inv, dim3(nring), dim3(nthreads), lds, st, L, nreg, nblk, spin, part, mtop, flm, wl,
+                       ring_nphi, ring_start, ring_shift, ring_fft, ffts, map);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, int L, double q, const double2 *map,
+                          const int *ring_nphi, const long long *ring_start, const int *ring_shift,
+                          const int *ring_fft, const FftArgs *ffts, double *F)
+{
+    hipLaunchKernelGGL(k_phi_fwd, dim3(nring), dim3(nthreads), lds, st, L, nring, q, map, ring_nphi, ring_start,
+                       ring_shift, ring_fft, ffts, F);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int spin, const FftArgs *fN,
+                            const double *wq, const double *ph, double *F, double2 *hpole)
+{
+    hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, spin, fN, wq, ph, F, hpole);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *wl,
+                             const double2 *hpole, double2 *flm)
+{
+    const size_t tot = (size_t)L * (2 * L - 1);
+    hipLaunchKernelGGL(k_finish_fwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, nB, Q,
+                       wl, hpole, flm);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_gamma_dft(hipStream_t st, int N, long long nper, int sign, double q, const double *roots,
+                            const double2 *in, double2 *out)
+{
+    hipLaunchKernelGGL(k_gamma_dft, dim3((unsigned)((nper + 255) / 256)), dim3(256), 0, st, N, nper, sign, q, roots,
+                       in, out);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
+                          const double *lsin, const double *lcos, const double *lbin, const double *kap,
+                          const double *gtab, double *out)
+{
+    dim3 grid((nreg + 63) / 64, L);
+    hipLaunchKernelGGL(k_debug_d, grid, dim3(64), 0, st, L, nreg, n, cot, csc, lsin, lcos, lbin, kap, gtab, out);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_bluestein_filter(hipStream_t st, int nfft, const FftArgs *ffts, int nthreads, size_t lds)
+{
+    hipLaunchKernelGGL(k_bluestein_prep, dim3(nfft), dim3(nthreads), lds, st, ffts);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_pole_from_F(hipStream_t st, int L, int nring, int ring, const double *F, double2 *pole)
+{
+    hipLaunchKernelGGL(k_pole_from_F, dim3((2 * L - 1 + 255) / 256), dim3(256), 0, st, L, nring, ring, F, pole);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+// Kernels with large dynamic LDS need the per-kernel limit raised.
+hipError_t set_kernel_lds_limits(size_t max_dyn)
+{
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_phi_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_phi_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_mw_filter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_bluestein_prep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+}  // namespace s2mi

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <string>
 #include <vector>
@@ -123,11 +124,12 @@ int factor_radices(int n, std::vector<int> &rad)
     return n;
 }
 
-// host staging kept alive until the plan's upload has completed
+// host staging kept alive until the plan's upload has completed (deque: references
+// to earlier entries stay valid while later ones are added)
 struct Staging {
-    std::vector<std::vector<double>> d;
-    std::vector<std::vector<int>> i;
-    std::vector<std::vector<long long>> ll;
+    std::deque<std::vector<double>> d;
+    std::deque<std::vector<int>> i;
+    std::deque<std::vector<long long>> ll;
 };
 
 template <typename T>

@@ -1,0 +1,146 @@
+#!/usr/bin/env python3
+"""Throughput of the spin spherical-harmonic transform on one MI355X.
+
+A step is one inverse + forward SHT pair (the paper's round-trip timing, Sec.
+6.3.2) of one MW map at L = 2048, spin 0, FP64, on synthetic Gaussian
+coefficients scaled by 1/(1+l) (seed 1), with inputs resident in HBM.  Prints
+one JSON line with pairs/s, the dominant kernel's FP64 roofline fraction
+(algorithmic flops / live HIP-event launch duration), the round-trip error,
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_flops(L, spin, rings):
+    """Per direction per map: 6 flop per (ring, l, m) triple at spin 0, 8 otherwise
+    (4 contraction + 4 recursion per generated d; spin 0 generates d for m >= 0 only)."""
+    T = rings * (L * L - spin * spin)
+    return (6 if spin == 0 else 8) * T
+
+
+def cpu_baseline(L, spin, flm, nring_sample, norder_sample):
+    import oracle
+    oracle._load()
+    rings = np.unique(np.linspace(0, L - 1, nring_sample).astype(int))
+    ms = np.unique(np.linspace(-(L - 1), L - 1, norder_sample).astype(int))
+    g = np.random.default_rng(11).standard_normal((L, 2 * L - 1)) + 0j
+    t0 = time.perf_counter()
+    oracle.s2_inverse(flm, L, spin, rings=rings)
+    t1 = time.perf_counter()
+    oracle.s2_forward(g, L, spin, ms=ms)
+    t2 = time.perf_counter()
+    pair_s = (t1 - t0) * L / rings.size + (t2 - t1) * (2 * L - 1) / ms.size
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / pair_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"inverse on {rings.size} of {L} rings + forward on {ms.size} of {2 * L - 1} orders, "
+                      f"L={L} MW spin {spin}, extrapolated to one pair ({t2 - t0:.1f} s measured)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=2048)
+    ap.add_argument("--spin", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rings", type=int, default=64)
+    ap.add_argument("--cpu-orders", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the transform is not sharded "
+              "across GPUs in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2311_14670_amd import binding
+    from paper_2311_14670_amd.synth import flm_gaussian
+
+    L, spin = args.L, args.spin
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    flm = flm_gaussian(L, spin, seed=1, scale="inv1pl")
+    x = torch.from_numpy(flm).to(dev)
+    plan = binding.Plan(L, spin=spin, device=dev)
+    _ = plan.workspace
+    for _ in range(args.warmup):
+        y = plan.forward(plan.inverse(x))
+    torch.cuda.synchronize()
+
+    plan.set_timing(True)
+    plan.read_timing()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        y = plan.forward(plan.inverse(x))
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = plan.read_timing()
+    plan.set_timing(False)
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    wall_ms_step = (t1 - t0) * 1e3 / args.steps
+
+    # accuracy of the benchmarked pair (round trip of band-limited input)
+    yh = y.cpu().numpy()
+    rt_err = float(np.linalg.norm(yh - flm) / np.linalg.norm(flm))
+
+    # dominant kernel and its FP64 roofline
+    dom = max(stages, key=lambda s: stages[s][0])
+    dom_ms = stages[dom][0] / max(stages[dom][1], 1)
+    flops = algorithmic_flops(L, spin, L)
+    if dom in ("dstage_inv", "dstage_fwd"):
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_launch": flops, "avg_launch_ms": dom_ms}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "avg_launch_ms": dom_ms}
+    # whole-pair FP64 fraction (both d-stage directions' algorithmic flops over the step time)
+    pair_frac = 2 * flops / (ms_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
+
+    out = {
+        "metric": "SHT pairs/s at L=2048 (err<=1e-11)",
+        "value": 1e3 / ms_step,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "wall_ms_per_step": wall_ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"MW L={L} spin-{spin} inverse+forward SHT pair, one map, complex128 "
+                               "Gaussian coefficients x 1/(1+l), seed 1",
+                   "L": L, "spin": spin, "sampling": "mw", "batch": 1},
+        "roundtrip_rel_l2": rt_err,
+        "pair_fp64_frac": pair_frac,
+        "stage_ms_per_step": {s: v[0] / args.steps for s, v in stages.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L, spin, flm, args.cpu_rings, args.cpu_orders)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,25 @@ int so3_forward(s2_plan_t plan, const void *f, void *flmn, int batch, void *work
  */
 int s2_debug_wigner_d(s2_plan_t plan, int n, void *out, void *hip_stream);
 
+/*
+ * Stage timing (profiling aid).  When enabled, every kernel launch of the
+ * plan's transforms is bracketed by HIP events recorded on the launch stream;
+ * s2_plan_read_timing() waits for those events, accumulates the elapsed time
+ * and launch count per stage into `out`, and clears the record.  Stages:
+ */
+#define S2_STAGE_PACK        0   /* inverse coefficient pack            */
+#define S2_STAGE_DSTAGE_INV  1   /* inverse Wigner-d sweep (Eq. 33)     */
+#define S2_STAGE_PHI_INV     2   /* inverse phi-DFT (Eq. 32)            */
+#define S2_STAGE_PHI_FWD     3   /* forward phi-DFT (Eq. 31)            */
+#define S2_STAGE_MW_THETA    4   /* MW theta filter (exact quadrature)  */
+#define S2_STAGE_DSTAGE_FWD  5   /* forward Wigner-d sweep (Eq. 30)     */
+#define S2_STAGE_FINISH      6   /* forward weights and layout          */
+#define S2_STAGE_GAMMA       7   /* SO(3) gamma DFT                     */
+#define S2_NSTAGES           8
+typedef struct { double ms[S2_NSTAGES]; long long launches[S2_NSTAGES]; } s2_timing_t;
+int s2_plan_set_timing(s2_plan_t plan, int enable);
+int s2_plan_read_timing(s2_plan_t plan, s2_timing_t *out);
+
 /* Human-readable name of an error code (static string). */
 const char *s2_error_string(int code);
 

@@ -29,6 +29,13 @@ class S2Error(RuntimeError):
         self.code = code
 
 
+STAGES = ["pack", "dstage_inv", "phi_inv", "phi_fwd", "mw_theta", "dstage_fwd", "finish", "gamma"]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_longlong * 8)]
+
+
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("spin", ctypes.c_int), ("N", ctypes.c_int), ("nside", ctypes.c_int),
                 ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("max_batch", ctypes.c_int),
@@ -63,6 +70,8 @@ def load_library():
             getattr(lib, name).argtypes = [P, vp, vp, i, vp, vp]
             getattr(lib, name).restype = i
         lib.s2_debug_wigner_d.argtypes = [P, i, vp, vp]
+        lib.s2_plan_set_timing.argtypes = [P, i]
+        lib.s2_plan_read_timing.argtypes = [P, ctypes.POINTER(_Timing)]
         lib.s2_error_string.restype = ctypes.c_char_p
         lib.s2_error_string.argtypes = [i]
         lib.s2_last_error_message.restype = ctypes.c_char_p
@@ -176,6 +185,16 @@ class Plan:
         """Forward Wigner transform: f [B?, 2N-1, L, 2L-1] -> flmn."""
         shp = (2 * self.N - 1,) + self.coeff_shape
         return self._call(self._lib.so3_forward, f, shp, shp, "so3_forward")
+
+    def set_timing(self, enable=True):
+        """Record HIP events around every kernel launch of this plan's transforms."""
+        _check(self._lib.s2_plan_set_timing(self._handle, 1 if enable else 0))
+
+    def read_timing(self):
+        """{stage: (total_ms, launches)} since the last read (waits for the events)."""
+        t = _Timing()
+        _check(self._lib.s2_plan_read_timing(self._handle, ctypes.byref(t)))
+        return {s: (t.ms[i], t.launches[i]) for i, s in enumerate(STAGES) if t.launches[i]}
 
     def debug_wigner_d(self, n):
         """d^l_{m,n}(theta_r) from the GPU recursion: [rings swept, m, l] (float64)."""

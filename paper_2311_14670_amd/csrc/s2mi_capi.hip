@@ -92,6 +92,11 @@ struct s2_plan_s {
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
     size_t szC = 0, szP = 0, szF = 0, szQ = 0;
 
+    // stage timing
+    bool timing = false;
+    struct TimedLaunch { int stage; hipEvent_t a, b; };
+    std::vector<TimedLaunch> tl;
+
     template <typename T>
     int dalloc(T **p, size_t count, const char *what)
     {
@@ -106,6 +111,7 @@ struct s2_plan_s {
     }
     ~s2_plan_s()
     {
+        for (auto &t : tl) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
         for (void *q : allocs) (void)hipFree(q);
     }
 };
@@ -443,6 +449,29 @@ int s2_plan_create(s2_plan_t *out, int L, int spin, int N, s2_sampling_t samplin
 // ------------------------------------------------------------------ transforms
 namespace {
 
+// Bracket one launch with events when the plan records stage timing.
+struct StageTimer {
+    s2_plan_t P;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(s2_plan_t P_, int stage_, hipStream_t st_) : P(P_), stage(stage_), st(st_)
+    {
+        if (P->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, st);
+    }
+    ~StageTimer()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, st);
+            P->tl.push_back({stage, a, b});
+        }
+    }
+};
+#define S2_CAT2(a, b) a##b
+#define S2_CAT(a, b) S2_CAT2(a, b)
+#define TIMED(stage) StageTimer S2_CAT(_timer_, __LINE__)(P, stage, st)
+
 int check_call(const char *fn, s2_plan_t P, const void *in, const void *out, int batch, void *ws)
 {
     if (!P) return fail(S2_ERR_INVALID_ARG, "%s: plan is NULL", fn);
@@ -469,18 +498,24 @@ int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, con
         const double2 *fa = r.sliceA >= 0 ? flm + r.sliceA * slab : nullptr;
         const double2 *fb = r.sliceB >= 0 ? flm + r.sliceB * slab : nullptr;
         double *C = C0 + ri * nC;
+        {
+        TIMED(S2_STAGE_PACK);
         HIPCHK(launch_pack_inv(st, L, r.n, P->inv_nblk, P->inv_waves * INV_J, P->lslot, fa, fb,
                                r.sliceA >= 0 ? wl[r.sliceA] : nullptr, r.sliceB >= 0 ? wl[r.sliceB] : nullptr, P->kap,
                                P->gtab, C), "pack");
+        }
+        TIMED(S2_STAGE_DSTAGE_INV);
         HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nreg, r.n, P->cot, P->csc, P->lsin, P->lcos,
                                  P->lbin[ri], C, P->lslot, P->mtop,
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
                                  r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr), "inverse d-stage");
     }
-    for (int k = 0; k < P->nslice; ++k)
+    for (int k = 0; k < P->nslice; ++k) {
+        TIMED(S2_STAGE_PHI_INV);
         HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, P->nreg, P->inv_nblk, P->slice_spin[k],
                               P0 + k * nP, P->mtop, flm + k * slab, wl[k], P->ring_nphi, P->ring_start,
                               P->ring_shift, P->ring_fft, P->ffts, slice_maps[k]), "inverse phi-DFT");
+    }
     return S2_OK;
 }
 
@@ -496,6 +531,7 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *
         const Run &r = P->runs[ri];
         const double *HA = r.sliceA >= 0 ? H0 + r.sliceA * nF : H0 + r.sliceB * nF;
         const double *HB = r.sliceB >= 0 ? H0 + r.sliceB * nF : HA;
+        TIMED(S2_STAGE_DSTAGE_FWD);
         HIPCHK(launch_dstage_fwd(st, P->fwd_waves, P->fwd_nblk, P->G, L, P->nreg, P->nring, r.n, P->lam[ri], P->lsin,
                                  P->lcos, P->lbin[ri], P->kap, P->gtab, HA, HB,
                                  r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
@@ -503,6 +539,7 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *
     }
     for (int k = 0; k < P->nslice; ++k) {
         const int s = P->slice_spin[k];
+        TIMED(S2_STAGE_FINISH);
         HIPCHK(launch_finish_fwd(st, L, P->fwd_nblk, s, s, Q0 + k * nQ, wl[k],
                                  hpole0 ? hpole0 + k * (2 * L - 1) : nullptr, flm + k * slab), "forward finish");
     }
@@ -524,8 +561,12 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
     else q = 4.0 * M_PI / (double)P->nsamp;
     for (int k = 0; k < P->nslice; ++k) {
         double *F = F0 + k * nF;
+        {
+        TIMED(S2_STAGE_PHI_FWD);
         HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, L, q, slice_maps[k], P->ring_nphi,
                               P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F), "forward phi-DFT");
+        }
+        TIMED(S2_STAGE_MW_THETA);
         if (mw && !adjoint)
             HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->slice_spin[k], P->ffts, P->wq, P->ph, F,
                                     hp0 + k * (2 * L - 1)), "MW theta filter");
@@ -596,7 +637,10 @@ int so3_inverse(s2_plan_t P, const void *flmn, void *f, int batch, void *workspa
         for (int k = 0; k < S; ++k) maps[k] = tmp + (size_t)k * P->nsamp;
         if ((rc = run_inverse(P, (const double2 *)flmn + (size_t)b * S * slab, maps.data(), P->w_so3i,
                               (char *)workspace, st))) return rc;
-        if (S > 1) HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, +1, 1.0, P->groots, tmp, out), "gamma DFT");
+        if (S > 1) {
+            TIMED(S2_STAGE_GAMMA);
+            HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, +1, 1.0, P->groots, tmp, out), "gamma DFT");
+        }
     }
     return S2_OK;
 }
@@ -614,12 +658,40 @@ int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspa
         std::vector<const double2 *> maps(S);
         double2 *tmp = (double2 *)((char *)workspace + P->off_maps);
         // f_n = 2pi/(2N-1) sum_k f(gamma_k) e^{-i n gamma_k}  (Eq. 16, exact equispaced rule)
+        {
+        TIMED(S2_STAGE_GAMMA);
         HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, -1, 2.0 * M_PI / (double)S, P->groots, in, tmp), "gamma DFT");
+        }
         for (int k = 0; k < S; ++k) maps[k] = tmp + (size_t)k * P->nsamp;
         if ((rc = run_forward(P, maps.data(), (double2 *)flmn + (size_t)b * S * slab, P->w_so3f, (char *)workspace,
                               st, false))) return rc;
     }
     return S2_OK;
+}
+
+int s2_plan_set_timing(s2_plan_t P, int enable)
+{
+    if (!P) return fail(S2_ERR_INVALID_ARG, "s2_plan_set_timing: plan is NULL");
+    P->timing = enable != 0;
+    return S2_OK;
+}
+
+int s2_plan_read_timing(s2_plan_t P, s2_timing_t *out)
+{
+    if (!P || !out) return fail(S2_ERR_INVALID_ARG, "s2_plan_read_timing: null argument");
+    for (int s = 0; s < S2_NSTAGES; ++s) { out->ms[s] = 0.0; out->launches[s] = 0; }
+    int rc = S2_OK;
+    for (auto &t : P->tl) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess && rc == S2_OK) rc = hipfail(e, "stage timing");
+        if (t.stage >= 0 && t.stage < S2_NSTAGES) { out->ms[t.stage] += ms; out->launches[t.stage] += 1; }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    P->tl.clear();
+    return rc;
 }
 
 int s2_debug_wigner_d(s2_plan_t P, int n, void *out, void *hip_stream)

@@ -72,7 +72,8 @@ struct s2_plan_s {
     // recursion tables
     double *kap = nullptr, *gtab = nullptr;
     std::vector<double *> lbin;   // per run
-    std::vector<double *> lam;    // per run [L][nreg]
+    std::vector<double *> lam;    // per run [L][hstride]
+    std::vector<double2 *> init;  // per run [nreg][L]: start values of Eq. 27
     // per-slice weights: SHT (Eqs. 30, 33), SO(3) inverse (Eq. 13), SO(3) forward (Eq. 14)
     std::vector<double *> w_sht, w_so3i, w_so3f;
     // FFT
@@ -85,9 +86,9 @@ struct s2_plan_s {
     double *groots = nullptr;              // e^{-2 pi i k/(2N-1)}
     // d-stage work assignment
     int inv_nblk = 1, inv_waves = 4;
-    int *lslot = nullptr, *mtop = nullptr;
+    int *lslot = nullptr, *lchunk = nullptr, *mtop = nullptr;
     int fwd_nblk = 1, fwd_waves = 4, G = 1;
-    int *rslot = nullptr;
+    int hstride = 0;                       // ring stride of the forward spectra (padded to the sweep's slots)
     // workspace layout (bytes)
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
     size_t szC = 0, szP = 0, szF = 0, szQ = 0;
@@ -189,18 +190,28 @@ int build_fft(s2_plan_s *P, int n, Staging &stg, hipStream_t st, FftArgs *out)
 
 int fft_threads_for(int len) { return std::min(1024, std::max(64, ((len / 8 + 63) / 64) * 64)); }
 
-// Inverse d-stage: deal l = L-1, L-2, ... over (block, wave) bins in snake order
-// so every wave's work sum_l (l + 1) is balanced; slots in a wave descend in l.
-void assign_inverse(int L, int nblk, int W, std::vector<int> &lslot, std::vector<int> &mtop)
+// Inverse d-stage: l is cut into chunks of 8 consecutive degrees; chunks are
+// dealt in decreasing order of work (work of chunk c ~ c) over the (block,
+// wave) bins in snake order, two per wave, so every wave's sum_l (l + 1) is
+// balanced.  lchunk[bin] = {base of chunk A, base of chunk B} (or -1);
+// lslot[bin][16] = the degree of each slot (slot j of a chunk: base + 7 - j),
+// -1 where the chunk runs past L-1.
+void assign_inverse(int L, int nblk, int W, std::vector<int> &lchunk, std::vector<int> &lslot, std::vector<int> &mtop)
 {
     const int nbin = nblk * W;
+    const int nch = (L + 7) / 8;
+    lchunk.assign((size_t)nbin * INV_NCH, -1);
     lslot.assign((size_t)nbin * INV_J, -1);
     std::vector<int> fill(nbin, 0);
-    int idx = 0;
-    for (int l = L - 1; l >= 0; --l, ++idx) {
+    for (int idx = 0, c = nch - 1; c >= 0; --c, ++idx) {
         const int round = idx / nbin, pos = idx % nbin;
         const int bin = (round % 2 == 0) ? pos : nbin - 1 - pos;
-        lslot[(size_t)bin * INV_J + fill[bin]++] = l;
+        const int g = fill[bin]++;
+        lchunk[(size_t)bin * INV_NCH + g] = 8 * c;
+        for (int j = 0; j < 8; ++j) {
+            const int l = 8 * c + 7 - j;
+            lslot[(size_t)bin * INV_J + g * 8 + j] = l < L ? l : -1;
+        }
     }
     mtop.assign(nblk, 0);
     for (int b = 0; b < nblk; ++b)
@@ -370,12 +381,9 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     for (const Run &r : P->runs) {
         stg.d.emplace_back();
         host_log2_binom(L, r.n, &stg.d.back());
-        double *lb, *lam;
+        double *lb;
         if ((rc = upload(P, &lb, stg.d.back(), st, "log2 binomials"))) return bail(rc);
-        if ((rc = P->dalloc(&lam, (size_t)L * P->nreg, "lambda table"))) return bail(rc);
-        HIPCHK(launch_lambda_table(st, L, P->nreg, r.n, P->cot, P->csc, lam), "lambda table");
         P->lbin.push_back(lb);
-        P->lam.push_back(lam);
     }
     for (int k = 0; k < P->nslice; ++k) {
         for (int kind = 0; kind < 3; ++kind) {
@@ -387,27 +395,46 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         }
     }
 
-    // inverse d-stage assignment
+    // inverse d-stage assignment: waves of INV_NCH 8-degree chunks, W a multiple of 4
     {
-        P->inv_nblk = (L + 16 * INV_J - 1) / (16 * INV_J);
-        P->inv_waves = std::min(16, std::max(4, (L + P->inv_nblk * INV_J - 1) / (P->inv_nblk * INV_J)));
+        const int nch = (L + 7) / 8;
+        const int per_blk = DSTAGE_MAX_WAVES * INV_NCH;
+        P->inv_nblk = (nch + per_blk - 1) / per_blk;
+        const int wneed = (nch + INV_NCH * P->inv_nblk - 1) / (INV_NCH * P->inv_nblk);
+        P->inv_waves = std::min(DSTAGE_MAX_WAVES, std::max(4, (wneed + 3) / 4 * 4));
+        stg.i.emplace_back(); std::vector<int> &lch = stg.i.back();
         stg.i.emplace_back(); std::vector<int> &ls = stg.i.back();
         stg.i.emplace_back(); std::vector<int> &mt = stg.i.back();
-        assign_inverse(L, P->inv_nblk, P->inv_waves, ls, mt);
+        assign_inverse(L, P->inv_nblk, P->inv_waves, lch, ls, mt);
+        if ((rc = upload(P, &P->lchunk, lch, st, "inverse chunks"))) return bail(rc);
         if ((rc = upload(P, &P->lslot, ls, st, "inverse slots"))) return bail(rc);
         if ((rc = upload(P, &P->mtop, mt, st, "inverse mtop"))) return bail(rc);
     }
-    // forward d-stage assignment: rings in contiguous chunks of waves x FWD_R
+    // forward d-stage assignment: wave w of block b sweeps rings (b W + w) FWD_R ..
+    // + FWD_R - 1; rings past the last regular ring are inert padding.  W is a
+    // multiple of 4 (rotating reducers).
     {
         P->G = (L + 63) / 64;
         const int pairs = (P->G + 1) / 2;
         int nb = std::max(1, std::min(256 / pairs, (P->nreg + 4 * FWD_R - 1) / (4 * FWD_R)));
         int W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R);
-        while (W > 16) { ++nb; W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R); }
-        W = std::max(W, 4);
+        while (W > DSTAGE_MAX_WAVES) { ++nb; W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R); }
+        W = std::max(4, (W + 3) / 4 * 4);
         P->fwd_nblk = nb;
         P->fwd_waves = W;
-        // wave w of block b sweeps rings (b W + w) FWD_R .. + FWD_R - 1 (clipped at nreg)
+        P->hstride = std::max(nb * W * FWD_R, P->nring);
+    }
+
+    for (size_t ri = 0; ri < P->runs.size(); ++ri) {
+        const Run &r = P->runs[ri];
+        double *lam;
+        double2 *ini;
+        if ((rc = P->dalloc(&lam, (size_t)L * P->hstride, "lambda table"))) return bail(rc);
+        HIPCHK(launch_lambda_table(st, L, P->nreg, P->hstride, r.n, P->cot, P->csc, lam), "lambda table");
+        if ((rc = P->dalloc(&ini, (size_t)L * P->nreg, "start values"))) return bail(rc);
+        HIPCHK(launch_init_table(st, L, P->nreg, r.n, P->lsin, P->lcos, P->lbin[ri], ini), "start values");
+        P->lam.push_back(lam);
+        P->init.push_back(ini);
     }
 
     // workspace layout
@@ -415,7 +442,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         const size_t S = P->nslice;
         P->szC = (size_t)P->inv_nblk * P->inv_waves * INV_J * L * 5 * sizeof(double);
         P->szP = (size_t)P->inv_nblk * P->nreg * L * 4 * sizeof(double);
-        P->szF = (size_t)L * P->nring * 4 * sizeof(double);
+        P->szF = (size_t)L * P->hstride * 4 * sizeof(double);
         P->szQ = (size_t)P->fwd_nblk * L * L * 4 * sizeof(double);
         size_t o = 0;
         P->off_C = o; o += align256(P->szC * P->runs.size());
@@ -505,8 +532,8 @@ int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, con
                                P->gtab, C), "pack");
         }
         TIMED(S2_STAGE_DSTAGE_INV);
-        HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nreg, r.n, P->cot, P->csc, P->lsin, P->lcos,
-                                 P->lbin[ri], C, P->lslot, P->mtop,
+        HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nreg, r.n, P->cot, P->csc, P->init[ri], C,
+                                 P->lchunk, P->mtop,
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
                                  r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr), "inverse d-stage");
     }
@@ -532,8 +559,8 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *
         const double *HA = r.sliceA >= 0 ? H0 + r.sliceA * nF : H0 + r.sliceB * nF;
         const double *HB = r.sliceB >= 0 ? H0 + r.sliceB * nF : HA;
         TIMED(S2_STAGE_DSTAGE_FWD);
-        HIPCHK(launch_dstage_fwd(st, P->fwd_waves, P->fwd_nblk, P->G, L, P->nreg, P->nring, r.n, P->lam[ri], P->lsin,
-                                 P->lcos, P->lbin[ri], P->kap, P->gtab, HA, HB,
+        HIPCHK(launch_dstage_fwd(st, P->fwd_waves, P->fwd_nblk, P->G, L, P->nreg, P->hstride, P->hstride, r.n,
+                                 P->lam[ri], P->init[ri], P->kap, P->gtab, HA, HB,
                                  r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
                                  r.sliceB >= 0 ? Q0 + r.sliceB * nQ : nullptr), "forward d-stage");
     }
@@ -563,15 +590,15 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
         double *F = F0 + k * nF;
         {
         TIMED(S2_STAGE_PHI_FWD);
-        HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, L, q, slice_maps[k], P->ring_nphi,
+        HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L, q, slice_maps[k], P->ring_nphi,
                               P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F), "forward phi-DFT");
         }
         TIMED(S2_STAGE_MW_THETA);
         if (mw && !adjoint)
-            HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->slice_spin[k], P->ffts, P->wq, P->ph, F,
+            HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, P->slice_spin[k], P->ffts, P->wq, P->ph, F,
                                     hp0 + k * (2 * L - 1)), "MW theta filter");
         else if (mw)
-            HIPCHK(launch_pole_from_F(st, L, P->nring, L - 1, F, hp0 + k * (2 * L - 1)), "pole line");
+            HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp0 + k * (2 * L - 1)), "pole line");
     }
     return run_forward_dstage(P, F0, mw ? hp0 : nullptr, flm, wl, ws, st);
 }

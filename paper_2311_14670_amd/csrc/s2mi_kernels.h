@@ -11,22 +11,24 @@ hipError_t launch_pack_inv(hipStream_t st, int L, int n, int nblk, int slots_per
                            const double2 *flmA, const double2 *flmB, const double *wA, const double *wB,
                            const double *kap, const double *gtab, double *C);
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nreg, int n, const double *cot,
-                             const double *csc, const double *lsin, const double *lcos, const double *lbin,
-                             const double *C, const int *lslot, const int *mtop, double *partA, double *partB);
-hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nreg, int hstride, int n,
-                             const double *lam, const double *lsin, const double *lcos, const double *lbin,
-                             const double *kap, const double *gtab, const double *HA, const double *HB,
-                             double *QA, double *QB);
-hipError_t launch_lambda_table(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
-                               double *lam);
+                             const double *csc, const double2 *init, const double *C, const int *lchunk,
+                             const int *mtop, double *partA, double *partB);
+hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const double *lsin, const double *lcos,
+                             const double *lbin, double2 *init);
+hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nreg, int hstride, int lstride,
+                             int n, const double *lam, const double2 *init, const double *kap, const double *gtab,
+                             const double *HA, const double *HB, double *QA, double *QB);
+hipError_t launch_lambda_table(hipStream_t st, int L, int nreg, int lstride, int n, const double *cot,
+                               const double *csc, double *lam);
 hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk, int spin,
                           const double *part, const int *mtop, const double2 *flm, const double *wl,
                           const int *ring_nphi, const long long *ring_start, const int *ring_shift,
                           const int *ring_fft, const FftArgs *ffts, double2 *map);
-hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, int L, double q, const double2 *map,
+hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
+                          const double2 *map,
                           const int *ring_nphi, const long long *ring_start, const int *ring_shift,
                           const int *ring_fft, const FftArgs *ffts, double *F);
-hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int spin, const FftArgs *fN,
+hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int hstride, int spin, const FftArgs *fN,
                             const double *wq, const double *ph, double *F, double2 *hpole);
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *wl,
                              const double2 *hpole, double2 *flm);
@@ -36,7 +38,7 @@ hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *
                           const double *lsin, const double *lcos, const double *lbin, const double *kap,
                           const double *gtab, double *out);
 hipError_t launch_bluestein_filter(hipStream_t st, int nfft, const FftArgs *ffts, int nthreads, size_t lds);
-hipError_t launch_pole_from_F(hipStream_t st, int L, int nring, int ring, const double *F, double2 *pole);
+hipError_t launch_pole_from_F(hipStream_t st, int L, int hstride, int ring, const double *F, double2 *pole);
 hipError_t set_kernel_lds_limits(size_t max_dyn);
 
 }  // namespace s2mi

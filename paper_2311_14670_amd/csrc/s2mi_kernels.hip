@@ -92,6 +92,23 @@ __device__ __forceinline__ void renorm(double &e, double &ep, int &E)
     E = real ? 0 : E + k;
 }
 
+// ------------------------------------------------------------------ start values
+// init[r][l] = {mantissa, exponent} of d^l_{l,n}(theta_r) (Eq. 27) for every
+// swept ring and l >= |n| (zeros below): computed once per plan so the sweeps
+// only load them when a degree starts.
+__global__ void k_init_table(int L, int nreg, int n, const double *__restrict__ lsin, const double *__restrict__ lcos,
+                             const double *__restrict__ lbin, double2 *__restrict__ init)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)nreg * L) return;
+    const int r = (int)(i / L), l = (int)(i % L);
+    const int an = n < 0 ? -n : n;
+    double e = 0.0;
+    int E = 0;
+    if (l >= an) d_init(l, n, dd_from(lbin + 2 * l), dd_from(lsin + 2 * r), dd_from(lcos + 2 * r), e, E);
+    init[i] = make_double2(e, (double)E);
+}
+
 // ------------------------------------------------------------------ inverse pack
 // Records in the inverse sweep's slot order, C[blk][m][wave][slot] = 5 doubles
 //   {kappa_{m+1}^l, wA_l g_m^l flmA[l][m], wB_l g_m^l (-1)^{m-n} flmB[l][-m]}
@@ -135,54 +152,82 @@ __global__ void k_pack_inv(int L, int n, int nslot, int S, const int *__restrict
 }
 
 // ------------------------------------------------------------------ inverse d-stage
-// Lanes = 64 rings; each wave owns INV_J l-slots (wave-uniform, from lslot);
-// waves of a workgroup share the rings and split the l-range.  At order m:
-//   acc_A(ring) = sum_{slots} e g 2^E * C[m][l].A,  acc_B likewise,
-// reduced over the waves in LDS and written to partA/partB[blk][ring][m].
+// Lanes = 64 rings.  Each wave owns two chunks of SG = 8 consecutive l (a high
+// and a low chunk, for balance; slot j of a chunk holds l = base + SG-1-j),
+// waves of a workgroup share the rings and split the l-range.  A slot whose l
+// has not started (l < m) has zero state and zero records, so chunks need no
+// per-slot activity test: a chunk is skipped until its top l is reached, its
+// SG starts happen in SG consecutive "ramp" orders, and afterwards it runs the
+// branch-free step
+//   e_{m-1} = (kappa lambda) e_m - e_{m+1};  acc += e * C[m][slot].{A,B}.
 // The two state registers of a slot alternate roles between consecutive
-// orders (PAR = 0: X newest, Y older; the step overwrites Y), so the recursion
-// needs no register moves.
-template <int J, int PAR>
+// orders (PAR), so the recursion needs no register moves.  Per order, each
+// wave's partial sums are reduced over the waves in LDS by a rotating group of
+// four waves and written to partA/partB[blk][ring][m].
+constexpr int SG = 8;
+
+template <int PAR, bool SLOW>
+__device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ rec,
+                                          double lam, int jin, double e0, int E0, double &aAr, double &aAi,
+                                          double &aBr, double &aBi)
+{
+#pragma unroll
+    for (int j = 0; j < SG; ++j) {
+        double &nw = PAR == 0 ? Y[j] : X[j];              // receives order m
+        double &od = PAR == 0 ? X[j] : Y[j];              // holds order m+1
+        const double *c = rec + j * 5;
+        nw = fma(c[0] * lam, od, -nw);
+        double t = nw;
+        if constexpr (SLOW) {
+            if (j == jin) {                               // this slot's l == m starts here
+                nw = e0;
+                od = 0.0;
+                E[j] = E0;
+            }
+            renorm(nw, od, E[j]);
+            t = nw * ldexp(1.0, E[j]);
+        }
+        aAr = fma(t, c[1], aAr);
+        aAi = fma(t, c[2], aAi);
+        aBr = fma(t, c[3], aBr);
+        aBi = fma(t, c[4], aBi);
+    }
+}
+
+template <int NCH, int PAR>
 __device__ __forceinline__ void inv_step(int m, int L, int n, int an, int ring0, int nreg, int lane, int w, int W,
-                                         const int (&lsl)[J], double (&X)[J], double (&Y)[J], int (&E)[J],
-                                         uint32_t &fast, double ct, double ncs, DD ls, DD lc,
-                                         const double *__restrict__ lbin, const double *__restrict__ C, double *red,
+                                         const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
+                                         int (&E)[NCH][SG], uint32_t &fast, double ct, double ncs,
+                                         const double2 *__restrict__ initr, const double *__restrict__ C, double *red,
                                          int blk, double *__restrict__ partA, double *__restrict__ partB)
 {
     const double lam = fma(-(double)(m + 1), ct, ncs);   // lambda_{m+1}: produces order m
     double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
-    const double *Cw = C + (((size_t)blk * L + m) * W + w) * J * 5;   // this wave's records at order m
-    // at most one slot starts at this order (distinct l per wave): initialise it once
-    int jin = -1;
+    const double *Cw = C + (((size_t)blk * L + m) * W + w) * (NCH * SG) * 5;   // this wave's records at order m
 #pragma unroll
-    for (int j = 0; j < J; ++j) if (lsl[j] == m && m >= an) jin = j;
-    double e0 = 0.0;
-    int E0 = 0;
-    if (jin >= 0) d_init(m, n, dd_from(lbin + 2 * m), ls, lc, e0, E0);
+    for (int g = 0; g < NCH; ++g) {
+        const int base = lb[g];
+        if (base < 0 || m > base + SG - 1) continue;     // chunk not started
+        const double *rec = Cw + g * SG * 5;
+        if (m >= base) {                                  // ramp: slot jin starts at this order
+            const int jin = base + SG - 1 - m;
+            const double2 iv = initr[m];                 // d^m_{m,n}(theta_ring), zero if m < |n|
+            const double e0 = iv.x;
+            const int E0 = (int)iv.y;
+            inv_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, e0, E0, aAr, aAi, aBr, aBi);
+            bool z = true;
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int l = lsl[j];
-        if (l < m || l < an) continue;                    // slot not started, empty (-1), or below |n|
-        double &nw = PAR == 0 ? Y[j] : X[j];              // receives order m
-        double &od = PAR == 0 ? X[j] : Y[j];              // holds order m+1
-        if (j == jin) {
-            nw = e0;
-            od = 0.0;
-            E[j] = E0;
-            fast = __all(E0 == 0) ? (fast | (1u << j)) : (fast & ~(1u << j));
+            for (int j = 0; j < SG; ++j) z = z && (E[g][j] == 0);
+            fast = __all(z) ? (fast | (1u << g)) : (fast & ~(1u << g));
+        } else if ((fast >> g) & 1u) {
+            inv_chunk<PAR, false>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
         } else {
-            nw = fma(Cw[j * 5] * lam, od, -nw);
-            if (!((fast >> j) & 1u)) {
-                renorm(nw, od, E[j]);
-                if (__all(E[j] == 0)) fast |= (1u << j);
-            }
+            inv_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
+            bool z = true;
+#pragma unroll
+            for (int j = 0; j < SG; ++j) z = z && (E[g][j] == 0);
+            if (__all(z)) fast |= (1u << g);
         }
-        const double t = ((fast >> j) & 1u) ? nw : nw * ldexp(1.0, E[j]);
-        const double *c = Cw + j * 5 + 1;
-        aAr = fma(t, c[0], aAr);
-        aAi = fma(t, c[1], aAi);
-        aBr = fma(t, c[2], aBr);
-        aBi = fma(t, c[3], aBi);
     }
     double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr;
@@ -190,8 +235,11 @@ __device__ __forceinline__ void inv_step(int m, int L, int n, int an, int ring0,
     rb[(w * 4 + 2) * 64 + lane] = aBr;
     rb[(w * 4 + 3) * 64 + lane] = aBi;
     __syncthreads();
-    if (threadIdx.x < 256) {
-        const int rl = threadIdx.x & 63, comp = threadIdx.x >> 6;
+    // four waves, rotating with the order, reduce the 4 x 64 outputs over the waves
+    const int grp = m % (W / 4);
+    const int tr = (int)threadIdx.x - 256 * grp;
+    if (tr >= 0 && tr < 256) {
+        const int rl = tr & 63, comp = tr >> 6;
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
         double *dst = comp < 2 ? partA : partB;
@@ -199,12 +247,11 @@ __device__ __forceinline__ void inv_step(int m, int L, int n, int an, int ring0,
     }
 }
 
-template <int J>
-__global__ __launch_bounds__(1024) void k_dstage_inv(
+template <int NCH>
+__global__ __launch_bounds__(512) void k_dstage_inv(
     int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
-    const double *__restrict__ lsin, const double *__restrict__ lcos, const double *__restrict__ lbin,
-    const double *__restrict__ C, const int *__restrict__ lslot, const int *__restrict__ mtop,
-    double *__restrict__ partA, double *__restrict__ partB)
+    const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
+    const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
 {
     __shared__ double red[2 * MAX_WAVES * 4 * 64];
     const int an = n < 0 ? -n : n;
@@ -216,97 +263,127 @@ __global__ __launch_bounds__(1024) void k_dstage_inv(
     const int ring = min(ring0 + lane, nreg - 1);
     const double ct = cot[ring], cs = csc[ring];
     const double ncs = (double)n * cs;
-    const DD ls = dd_from(lsin + 2 * ring), lc = dd_from(lcos + 2 * ring);
+    const double2 *initr = init + (size_t)ring * L;
 
-    int lsl[J];
+    int lb[NCH];
 #pragma unroll
-    for (int j = 0; j < J; ++j) lsl[j] = ufl(lslot[((size_t)blk * W + w) * J + j]);
-    double X[J], Y[J];
-    int E[J];
+    for (int g = 0; g < NCH; ++g) lb[g] = ufl(lchunk[((size_t)blk * W + w) * NCH + g]);
+    double X[NCH][SG], Y[NCH][SG];
+    int E[NCH][SG];
 #pragma unroll
-    for (int j = 0; j < J; ++j) { X[j] = 0.0; Y[j] = 0.0; E[j] = 0; }
+    for (int g = 0; g < NCH; ++g)
+#pragma unroll
+        for (int j = 0; j < SG; ++j) { X[g][j] = 0.0; Y[g][j] = 0.0; E[g][j] = 0; }
     uint32_t fast = 0;
 
     const int mt = ufl(mtop[blk]);
     for (int m = mt; m >= 0; m -= 2) {
-        inv_step<J, 0>(m, L, n, an, ring0, nreg, lane, w, W, lsl, X, Y, E, fast, ct, ncs, ls, lc, lbin, C, red,
-                       blk, partA, partB);
+        inv_step<NCH, 0>(m, L, n, an, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red, blk, partA,
+                    partB);
         if (m >= 1)
-            inv_step<J, 1>(m - 1, L, n, an, ring0, nreg, lane, w, W, lsl, X, Y, E, fast, ct, ncs, ls, lc, lbin, C,
-                           red, blk, partA, partB);
+            inv_step<NCH, 1>(m - 1, L, n, an, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red, blk,
+                             partA, partB);
     }
 }
 
 // ------------------------------------------------------------------ forward d-stage
-// Lanes = 64 consecutive l (group g); each wave owns FWD_R ring slots; waves of
-// a workgroup share the l-group and split the rings.  A workgroup runs group p
-// then group G-1-p so all workgroups carry equal work.  At order m:
+// Lanes = 64 consecutive l (group g); each wave owns 2 x SG contiguous ring
+// slots (ring rbase + k; rings past the last regular ring are inert: zero
+// lambda, zero H, never initialised); waves of a workgroup share the l-group
+// and split the rings.  A workgroup runs group p then group G-1-p so all
+// workgroups carry equal work.  At order m:
 //   acc(l) = g_m^l sum_{slots} e 2^E * H[m][ring],
-// reduced over the waves in LDS and written to QA/QB[blk][l][m].  Register
-// roles alternate between orders as in the inverse sweep.
-template <int R, int PAR, bool HEAD>
-__device__ __forceinline__ void fwd_step(int m, int g, int l, int lc, int L, int n, int an, int lane, int w, int W,
-                                         int hstride, int my_ring, int rbase, int rcnt, double (&X)[R],
-                                         double (&Y)[R], int (&E)[R], uint32_t &fast,
-                                         const double *__restrict__ lam, const double *__restrict__ lsin,
-                                         const double *__restrict__ lcos, const double *__restrict__ lbin,
-                                         const double *__restrict__ kap, const double *__restrict__ gtab,
-                                         const double *__restrict__ HA, const double *__restrict__ HB,
-                                         double (*ini_e)[R], int (*ini_E)[R], double *red, int blk,
-                                         double *__restrict__ QA, double *__restrict__ QB)
+// reduced over the waves in LDS (rotating reducers) and written to
+// QA/QB[blk][l][m].  kappa and g of the next order are loaded one step ahead.
+__device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int r0, int m, int L)
 {
-    if constexpr (HEAD) {
-        // some lane may initialise at this order: d^m_{m,n}(theta_slot) for every
-        // slot of this wave, one slot per lane, broadcast through LDS
-        if (my_ring >= 0 && m >= an) {
-            double v;
-            int ex;
-            d_init(m, n, dd_from(lbin + 2 * m), dd_from(lsin + 2 * my_ring), dd_from(lcos + 2 * my_ring), v, ex);
-            ini_e[w][lane] = v;
-            ini_E[w][lane] = ex;
-        }
-        __syncthreads();
-    }
-    const double kk = (l > m && l < L) ? kap[(size_t)m * L + lc] : 0.0;
-    double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
-    const double *HAm = HA + ((size_t)m * hstride + rbase) * 4;    // slot k = ring rbase + k
-    const double *HBm = HB + ((size_t)m * hstride + rbase) * 4 + 2;
-    const double *Lm = lam + rbase;
+    return init + (size_t)r0 * L + m;
+}
+
+template <int PAR, bool SLOW, bool HEAD>
+__device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ Lm,
+                                          const double *__restrict__ HA, const double *__restrict__ HB, double kk,
+                                          bool init, const double2 *__restrict__ iv, int istride, double &aAr,
+                                          double &aAi, double &aBr, double &aBi)
+{
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        if (k >= rcnt) continue;
+    for (int k = 0; k < SG; ++k) {
         double &nw = PAR == 0 ? Y[k] : X[k];
         double &od = PAR == 0 ? X[k] : Y[k];
         nw = fma(kk * Lm[k], od, -nw);
-        if constexpr (HEAD) {
-            if (l == m && l >= an) {
-                nw = ini_e[w][k];
-                E[k] = ini_E[w][k];
-                od = 0.0;
+        double t = nw;
+        if constexpr (SLOW) {
+            if constexpr (HEAD) {
+                if (init) {                                  // this lane's l == m starts at slot k's ring
+                    const double2 v = iv[(size_t)k * istride];
+                    nw = v.x;
+                    E[k] = (int)v.y;
+                    od = 0.0;
+                }
             }
-            if (!((fast >> k) & 1u)) renorm(nw, od, E[k]);
-            fast = __all(E[k] == 0) ? (fast | (1u << k)) : (fast & ~(1u << k));
-        } else if (!((fast >> k) & 1u)) {
             renorm(nw, od, E[k]);
-            if (__all(E[k] == 0)) fast |= (1u << k);
+            t = nw * ldexp(1.0, E[k]);
         }
-        const double t = ((fast >> k) & 1u) ? nw : nw * ldexp(1.0, E[k]);
-        const double *ha = HAm + k * 4;
-        const double *hb = HBm + k * 4;
+        const double *ha = HA + k * 4;
+        const double *hb = HB + k * 4;
         aAr = fma(t, ha[0], aAr);
         aAi = fma(t, ha[1], aAi);
-        aBr = fma(t, hb[0], aBr);
-        aBi = fma(t, hb[1], aBi);
+        aBr = fma(t, hb[2], aBr);
+        aBi = fma(t, hb[3], aBi);
     }
-    const double gm = (l >= m && l < L) ? gtab[(size_t)m * L + lc] : 0.0;
+}
+
+template <int NCH, int PAR, bool HEAD>
+__device__ __forceinline__ void fwd_step(int m, int g, int l, int L, int n, int an, int lane, int w, int W,
+                                         int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
+                                         double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &fast, double &kk, double &gm,
+                                         const double *__restrict__ lam, const double2 *__restrict__ init,
+                                         const double *__restrict__ kap, const double *__restrict__ gtab,
+                                         const double *__restrict__ HA, const double *__restrict__ HB, double *red,
+                                         int blk, double *__restrict__ QA, double *__restrict__ QB)
+{
+    // kappa / g of this order were loaded one step ahead; fetch the next order's now
+    const double kcur = kk, gcur = gm;
+    if (m >= 1) {
+        const int mn = m - 1;
+        const int lc = min(l, L - 1);
+        kk = (l > mn && l < L) ? kap[(size_t)mn * L + lc] : 0.0;
+        gm = (l >= mn && l < L) ? gtab[(size_t)mn * L + lc] : 0.0;
+    }
+    const bool starts = HEAD && (l == m) && (l >= an);
+    // start values of slot k: init[rbase + k][m] (rings past nreg stay zero)
+    double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
+    const double *Lm = lam + (size_t)m * lstride + rbase;
+    const double *HAm = HA + ((size_t)m * hstride + rbase) * 4;    // slot k = ring rbase + k
+    const double *HBm = HB + ((size_t)m * hstride + rbase) * 4;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const double *Lc = Lm + c * SG;
+        const double *Ac = HAm + c * SG * 4;
+        const double *Bc = HBm + c * SG * 4;
+        if (HEAD || !((fast >> c) & 1u)) {
+            const int r0 = min(rbase + c * SG, nreg - 1);
+            const bool ok = starts && (rbase + c * SG < nreg);
+            fwd_chunk<PAR, true, HEAD>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, init_tab_ptr(init, r0, m, L), L, aAr,
+                                       aAi, aBr, aBi);
+            bool z = true;
+#pragma unroll
+            for (int k = 0; k < SG; ++k) z = z && (E[c][k] == 0);
+            fast = __all(z) ? (fast | (1u << c)) : (fast & ~(1u << c));
+        } else {
+            fwd_chunk<PAR, false, false>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, nullptr, 0, aAr, aAi, aBr, aBi);
+        }
+    }
     double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
-    rb[(w * 4 + 0) * 64 + lane] = aAr * gm;
-    rb[(w * 4 + 1) * 64 + lane] = aAi * gm;
-    rb[(w * 4 + 2) * 64 + lane] = aBr * gm;
-    rb[(w * 4 + 3) * 64 + lane] = aBi * gm;
+    rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
+    rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
+    rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
+    rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
     __syncthreads();
-    if (threadIdx.x < 256) {
-        const int ll = threadIdx.x & 63, comp = threadIdx.x >> 6;
+    const int grp = m % (W / 4);
+    const int tr = (int)threadIdx.x - 256 * grp;
+    if (tr >= 0 && tr < 256) {
+        const int ll = tr & 63, comp = tr >> 6;
         const int lo = 64 * g + ll;
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + ll];
@@ -315,59 +392,54 @@ __device__ __forceinline__ void fwd_step(int m, int g, int l, int lc, int L, int
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(1024) void k_dstage_fwd(
-    int L, int nreg, int hstride, int n, int G, const double *__restrict__ lam, const double *__restrict__ lsin,
-    const double *__restrict__ lcos, const double *__restrict__ lbin, const double *__restrict__ kap,
-    const double *__restrict__ gtab, const double *__restrict__ HA, const double *__restrict__ HB,
-    double *__restrict__ QA, double *__restrict__ QB)
+template <int NCH>
+__global__ __launch_bounds__(512) void k_dstage_fwd(
+    int L, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
+    const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
+    const double *__restrict__ HA, const double *__restrict__ HB, double *__restrict__ QA, double *__restrict__ QB)
 {
     __shared__ double red[2 * MAX_WAVES * 4 * 64];
-    __shared__ double ini_e[MAX_WAVES][R];
-    __shared__ int ini_E[MAX_WAVES][R];
     const int an = n < 0 ? -n : n;
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
     const int W = blockDim.x >> 6;
     const int blk = blockIdx.y;
     const int p = blockIdx.x;
-    // this wave's rings: rbase .. rbase + rcnt - 1 (contiguous)
-    const int rbase = (blk * W + w) * R;
-    const int rcnt = ufl(max(0, min(R, nreg - rbase)));
-    const int my_ring = lane < rcnt ? rbase + lane : -1;   // slot 'lane'
+    // this wave's rings: rbase .. rbase + NCH SG - 1 (contiguous; >= nreg inert)
+    const int rbase = (blk * W + w) * NCH * SG;
 
     for (int pass = 0; pass < 2; ++pass) {
         const int g = pass == 0 ? p : G - 1 - p;
         if (pass == 1 && g == p) break;
         const int l = 64 * g + lane;
-        const int lc = min(l, L - 1);
-        double X[R], Y[R];
-        int E[R];
+        double X[NCH][SG], Y[NCH][SG];
+        int E[NCH][SG];
 #pragma unroll
-        for (int k = 0; k < R; ++k) { X[k] = 0.0; Y[k] = 0.0; E[k] = 0; }
-        uint32_t fast = (1u << R) - 1u;
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int k = 0; k < SG; ++k) { X[c][k] = 0.0; Y[c][k] = 0.0; E[c][k] = 0; }
+        uint32_t fast = (1u << NCH) - 1u;
         const int mstart = min(64 * g + 63, L - 1);
+        const int lc = min(l, L - 1);
+        double kk = (l > mstart && l < L) ? kap[(size_t)mstart * L + lc] : 0.0;
+        double gm = (l >= mstart && l < L) ? gtab[(size_t)mstart * L + lc] : 0.0;
         // head: the orders at which lanes of this group start (an even number of
         // steps so the register roles line up with the main loop)
         const int hend = ((mstart - 64 * g + 1) % 2 == 0) ? 64 * g : 64 * g - 1;
         int m = mstart;
         for (; m >= hend && m >= 0; m -= 2) {
-            fwd_step<R, 0, true>(m, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
-                                 lam + (size_t)m * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E, red, blk,
-                                 QA, QB);
+            fwd_step<NCH, 0, true>(m, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast, kk, gm,
+                              lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
             if (m >= 1)
-                fwd_step<R, 1, true>(m - 1, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
-                                     lam + (size_t)(m - 1) * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E,
-                                     red, blk, QA, QB);
+                fwd_step<NCH, 1, true>(m - 1, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast,
+                                  kk, gm, lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
         }
         for (; m >= 0; m -= 2) {
-            fwd_step<R, 0, false>(m, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
-                                  lam + (size_t)m * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E, red, blk,
-                                  QA, QB);
+            fwd_step<NCH, 0, false>(m, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast, kk, gm,
+                               lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
             if (m >= 1)
-                fwd_step<R, 1, false>(m - 1, g, l, lc, L, n, an, lane, w, W, hstride, my_ring, rbase, rcnt, X, Y, E, fast,
-                                      lam + (size_t)(m - 1) * nreg, lsin, lcos, lbin, kap, gtab, HA, HB, ini_e, ini_E,
-                                      red, blk, QA, QB);
+                fwd_step<NCH, 1, false>(m - 1, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast,
+                                   kk, gm, lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
         }
         __syncthreads();   // the LDS buffers are reused by the next pass
     }
@@ -375,13 +447,14 @@ __global__ __launch_bounds__(1024) void k_dstage_fwd(
 
 // 2 lambda table for the forward sweep: lam[m][r] = n csc_r - (m+1) cot_r
 // (the same FMA the inverse sweep evaluates inline).
-__global__ void k_lambda_table(int L, int nreg, int n, const double *__restrict__ cot,
+// Rows are padded to lstride rings; padding rings get lambda = 0 (inert).
+__global__ void k_lambda_table(int L, int nreg, int lstride, int n, const double *__restrict__ cot,
                                const double *__restrict__ csc, double *__restrict__ lam)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)L * nreg) return;
-    const int m = (int)(i / nreg), r = (int)(i % nreg);
-    lam[i] = fma(-(double)(m + 1), cot[r], (double)n * csc[r]);
+    if (i >= (size_t)L * lstride) return;
+    const int m = (int)(i / lstride), r = (int)(i % lstride);
+    lam[i] = r < nreg ? fma(-(double)(m + 1), cot[r], (double)n * csc[r]) : 0.0;
 }
 
 // ------------------------------------------------------------------ phi-DFT: inverse
@@ -464,13 +537,21 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
 // for |m| < L (the periodic repeat of Sec. 4.2 for short HEALPix rings), written
 // to F[m][ring] = {ftilde_m, ftilde_-m}.
 __global__ __launch_bounds__(1024) void k_phi_fwd(
-    int L, int nring, double q, const double2 *__restrict__ map, const int *__restrict__ ring_nphi,
+    int L, int nring, int hstride, double q, const double2 *__restrict__ map, const int *__restrict__ ring_nphi,
     const long long *__restrict__ ring_start, const int *__restrict__ ring_shift,
     const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, double *__restrict__ F)
 {
     extern __shared__ double2 buf[];
     const int r = blockIdx.x;
     const int T = blockDim.x, tid = threadIdx.x;
+    if (r >= nring) {                       // padding rings of the forward sweep: zeros
+        for (int m = tid; m < L; m += T) {
+            double *o = F + ((size_t)m * hstride + r) * 4;
+            *reinterpret_cast<double2 *>(o) = make_double2(0.0, 0.0);
+            *reinterpret_cast<double2 *>(o + 2) = make_double2(0.0, 0.0);
+        }
+        return;
+    }
     const int nphi = ring_nphi[r];
     const FftArgs *f = ffts + ring_fft[r];
     const int shift = ring_shift[r];
@@ -487,7 +568,7 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
             a = cmul(a, make_double2(c, -s));
             b = cmul(b, make_double2(c, s));
         }
-        double *o = F + ((size_t)m * nring + r) * 4;
+        double *o = F + ((size_t)m * hstride + r) * 4;
         *reinterpret_cast<double2 *>(o) = make_double2(q * a.x, q * a.y);
         *reinterpret_cast<double2 *>(o + 2) = make_double2(q * b.x, q * b.y);
     }
@@ -504,7 +585,7 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
 //   h = (g w'_theta + S-[w'_mu S+ g]) / 2,
 // S+-: band-limited half-sample shifts (DFT, phase e^{+-i k pi/N}/N, inverse DFT).
 // In place: F[m][t] -> H[m][t]; the south-pole value goes to hpole[m].
-__global__ __launch_bounds__(1024) void k_mw_filter(int L, int spin, const FftArgs *__restrict__ fN,
+__global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin, const FftArgs *__restrict__ fN,
                                                     const double *__restrict__ wq, const double *__restrict__ ph,
                                                     double *__restrict__ F, double2 *__restrict__ hpole)
 {
@@ -519,7 +600,7 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int spin, const FftAr
         // torus samples
         for (int t = tid; t < N; t += T) {
             const int tt = t < L ? t : N - 1 - t;
-            const double *src = F + ((size_t)m * L + tt) * 4 + 2 * side;
+            const double *src = F + ((size_t)m * hstride + tt) * 4 + 2 * side;
             double2 g = make_double2(src[0], src[1]);
             if (t >= L) { g.x *= par; g.y *= par; }
             buf[t] = g;
@@ -537,7 +618,7 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int spin, const FftAr
         dft_lds(buf, fN, +1);
         for (int t = tid; t < N; t += T) {          // + g w'_theta (g re-read: F is rewritten only below)
             const int tt = t < L ? t : N - 1 - t;
-            const double *src = F + ((size_t)m * L + tt) * 4 + 2 * side;
+            const double *src = F + ((size_t)m * hstride + tt) * 4 + 2 * side;
             const double wv = (t >= L ? par : 1.0) * wq[t];
             buf[t] = make_double2(0.5 * fma(src[0], wv, buf[t].x), 0.5 * fma(src[1], wv, buf[t].y));
         }
@@ -553,7 +634,7 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int spin, const FftAr
             h.x *= sc;
             h.y *= sc;
             if (t < L - 1) {
-                double *dst = F + ((size_t)m * L + t) * 4 + 2 * side;
+                double *dst = F + ((size_t)m * hstride + t) * 4 + 2 * side;
                 dst[0] = h.x;
                 dst[1] = h.y;
             } else {
@@ -675,12 +756,12 @@ __global__ __launch_bounds__(1024) void k_bluestein_prep(const FftArgs *__restri
 }
 
 // pole[(L-1) + m] = F[|m|][ring].side(m): the MW south-pole ring's Fourier line
-__global__ void k_pole_from_F(int L, int nring, int ring, const double *__restrict__ F, double2 *__restrict__ pole)
+__global__ void k_pole_from_F(int L, int hstride, int ring, const double *__restrict__ F, double2 *__restrict__ pole)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 2 * L - 1) return;
     const int m = i - (L - 1), am = m < 0 ? -m : m;
-    const double *src = F + ((size_t)am * nring + ring) * 4 + (m < 0 ? 2 : 0);
+    const double *src = F + ((size_t)am * hstride + ring) * 4 + (m < 0 ? 2 : 0);
     pole[i] = make_double2(src[0], src[1]);
 }
 
@@ -700,34 +781,43 @@ hipError_t launch_pack_inv(hipStream_t st, int L, int n, int nblk, int slots_per
 }
 
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nreg, int n, const double *cot,
-                             const double *csc, const double *lsin, const double *lcos, const double *lbin,
-                             const double *C, const int *lslot, const int *mtop, double *partA, double *partB)
+                             const double *csc, const double2 *init, const double *C, const int *lchunk,
+                             const int *mtop, double *partA, double *partB)
 {
     dim3 grid((nreg + 63) / 64, nblk);
-    hipLaunchKernelGGL(k_dstage_inv<INV_J>, grid, dim3(64 * nwaves), 0, st, L, nreg, n, cot, csc, lsin, lcos,
-                       lbin, C, lslot, mtop, partA, partB);
+    hipLaunchKernelGGL(k_dstage_inv<INV_NCH>, grid, dim3(64 * nwaves), 0, st, L, nreg, n, cot, csc, init, C, lchunk,
+                       mtop, partA, partB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nreg, int hstride, int n,
-                             const double *lam, const double *lsin, const double *lcos, const double *lbin,
-                             const double *kap, const double *gtab, const double *HA, const double *HB,
-                             double *QA, double *QB)
+hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nreg, int hstride, int lstride,
+                             int n, const double *lam, const double2 *init, const double *kap, const double *gtab,
+                             const double *HA, const double *HB, double *QA, double *QB)
 {
     dim3 grid((G + 1) / 2, nblk);
-    hipLaunchKernelGGL(k_dstage_fwd<FWD_R>, grid, dim3(64 * nwaves), 0, st, L, nreg, hstride, n, G, lam, lsin,
-                       lcos, lbin, kap, gtab, HA, HB, QA, QB);
+    hipLaunchKernelGGL(k_dstage_fwd<FWD_NCH>, grid, dim3(64 * nwaves), 0, st, L, nreg, hstride, lstride, n, G, lam, init,
+                       kap, gtab, HA, HB, QA, QB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_lambda_table(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
-                               double *lam)
+hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const double *lsin, const double *lcos,
+                             const double *lbin, double2 *init)
 {
     const size_t tot = (size_t)L * nreg;
-    hipLaunchKernelGGL(k_lambda_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nreg, n, cot,
-                       csc, lam);
+    hipLaunchKernelGGL(k_init_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nreg, n, lsin, lcos,
+                       lbin, init);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_lambda_table(hipStream_t st, int L, int nreg, int lstride, int n, const double *cot,
+                               const double *csc, double *lam)
+{
+    const size_t tot = (size_t)L * lstride;
+    hipLaunchKernelGGL(k_lambda_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nreg, lstride, n,
+                       cot, csc, lam);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -743,20 +833,20 @@ hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, i
     return hipSuccess;
 }
 
-hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, int L, double q, const double2 *map,
-                          const int *ring_nphi, const long long *ring_start, const int *ring_shift,
+hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
+                          const double2 *map, const int *ring_nphi, const long long *ring_start, const int *ring_shift,
                           const int *ring_fft, const FftArgs *ffts, double *F)
 {
-    hipLaunchKernelGGL(k_phi_fwd, dim3(nring), dim3(nthreads), lds, st, L, nring, q, map, ring_nphi, ring_start,
-                       ring_shift, ring_fft, ffts, F);
+    hipLaunchKernelGGL(k_phi_fwd, dim3(hstride), dim3(nthreads), lds, st, L, nring, hstride, q, map, ring_nphi,
+                       ring_start, ring_shift, ring_fft, ffts, F);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int spin, const FftArgs *fN,
+hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int hstride, int spin, const FftArgs *fN,
                             const double *wq, const double *ph, double *F, double2 *hpole)
 {
-    hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, spin, fN, wq, ph, F, hpole);
+    hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, hstride, spin, fN, wq, ph, F, hpole);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -797,9 +887,9 @@ hipError_t launch_bluestein_filter(hipStream_t st, int nfft, const FftArgs *ffts
     return hipSuccess;
 }
 
-hipError_t launch_pole_from_F(hipStream_t st, int L, int nring, int ring, const double *F, double2 *pole)
+hipError_t launch_pole_from_F(hipStream_t st, int L, int hstride, int ring, const double *F, double2 *pole)
 {
-    hipLaunchKernelGGL(k_pole_from_F, dim3((2 * L - 1 + 255) / 256), dim3(256), 0, st, L, nring, ring, F, pole);
+    hipLaunchKernelGGL(k_pole_from_F, dim3((2 * L - 1 + 255) / 256), dim3(256), 0, st, L, hstride, ring, F, pole);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -59,6 +59,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rings", type=int, default=64)
     ap.add_argument("--cpu-orders", type=int, default=64)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run plain device copies of MIB MiB (a reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the transform is not sharded "
@@ -137,6 +140,14 @@ def main():
         "stage_ms_per_step": {s: v[0] / args.steps for s, v in stages.items()},
         "roofline": roof,
     }
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 17                      # float64 elements in MIB MiB
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = n * 8
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, spin, flm, args.cpu_rings, args.cpu_orders)
     print(json.dumps(out), flush=True)

@@ -70,7 +70,16 @@ typedef enum { S2_MW = 0, S2_HEALPIX = 1 } s2_sampling_t;
 
 /* Arithmetic of the l/theta contraction.  The Wigner-d recursion, its
  * renormalisation, the quadrature weights and the phi-DFT are FP64 in every
- * mode; inputs and outputs are always complex128. */
+ * mode; inputs and outputs are always complex128.
+ *   S2_FP64                 fused FP64 sweeps, one map at a time.
+ *   S2_CONTRACT_FP32        all maps of a call together: per order m the
+ *                           contraction is a matrix product on the matrix
+ *                           cores with fp32 operands and fp32 accumulation.
+ *   S2_CONTRACT_SPLIT_BF16  as above with x = hi + lo (hi = bf16(x),
+ *                           lo = bf16(x - hi)) and three products
+ *                           hi*hi + hi*lo + lo*hi, fp32 accumulation.
+ * The reduced-precision modes trade accuracy (relative errors of order 1e-6
+ * and 1e-5) for throughput on large batches. */
 typedef enum { S2_FP64 = 0, S2_CONTRACT_FP32 = 1, S2_CONTRACT_SPLIT_BF16 = 2 } s2_precision_t;
 
 typedef struct {
@@ -182,7 +191,9 @@ int s2_debug_wigner_d(s2_plan_t plan, int n, void *out, void *hip_stream);
 #define S2_STAGE_DSTAGE_FWD  5   /* forward Wigner-d sweep (Eq. 30)     */
 #define S2_STAGE_FINISH      6   /* forward weights and layout          */
 #define S2_STAGE_GAMMA       7   /* SO(3) gamma DFT                     */
-#define S2_NSTAGES           8
+#define S2_STAGE_DGEN        8   /* d-tile generation (matrix-core path) */
+#define S2_STAGE_MFMA        9   /* batched MFMA contraction            */
+#define S2_NSTAGES          10
 typedef struct { double ms[S2_NSTAGES]; long long launches[S2_NSTAGES]; } s2_timing_t;
 int s2_plan_set_timing(s2_plan_t plan, int enable);
 int s2_plan_read_timing(s2_plan_t plan, s2_timing_t *out);

@@ -29,11 +29,11 @@ class S2Error(RuntimeError):
         self.code = code
 
 
-STAGES = ["pack", "dstage_inv", "phi_inv", "phi_fwd", "mw_theta", "dstage_fwd", "finish", "gamma"]
+STAGES = ["pack", "dstage_inv", "phi_inv", "phi_fwd", "mw_theta", "dstage_fwd", "finish", "gamma", "dgen", "mfma"]
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_longlong * 8)]
+    _fields_ = [("ms", ctypes.c_double * len(STAGES)), ("launches", ctypes.c_longlong * len(STAGES))]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -155,36 +155,48 @@ class Plan:
             raise ValueError(f"{what}: shape {tuple(x.shape)} does not end in {tuple(tail)}")
         return x.contiguous(), (x.shape[0] if batched else 1), batched
 
-    def _call(self, fn, x, in_tail, out_tail, what):
+    def new_workspace(self):
+        """A fresh workspace tensor for calls issued concurrently on another stream."""
+        return torch.empty(max(int(self.info["workspace_bytes"]), 256), dtype=torch.uint8, device=self.device)
+
+    def _call(self, fn, x, in_tail, out_tail, what, workspace=None, out=None):
         x, B, batched = self._prep(x, in_tail, what)
-        out = torch.empty(((B,) if batched else ()) + tuple(out_tail), dtype=torch.complex128, device=self.device)
+        shape = ((B,) if batched else ()) + tuple(out_tail)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        elif (out.dtype != torch.complex128 or out.device != self.device or tuple(out.shape) != shape
+              or not out.is_contiguous()):
+            raise ValueError(f"{what}: out must be a contiguous complex128 tensor of shape {shape} on {self.device}")
+        ws = self.workspace if workspace is None else workspace
+        if ws.device != self.device or ws.numel() * ws.element_size() < self.info["workspace_bytes"]:
+            raise ValueError(f"{what}: workspace too small or on the wrong device")
         with torch.cuda.device(self.device):
             _check(fn(self._handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), int(B),
-                      ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(self.device)))
+                      ctypes.c_void_p(ws.data_ptr()), _stream_handle(self.device)))
         return out
 
     # ------------------------------------------------------------ transforms
-    def inverse(self, flm):
+    def inverse(self, flm, workspace=None, out=None):
         """Inverse spin SHT: flm [B?, L, 2L-1] -> map."""
-        return self._call(self._lib.s2_inverse, flm, self.coeff_shape, self.map_shape, "inverse")
+        return self._call(self._lib.s2_inverse, flm, self.coeff_shape, self.map_shape, "inverse", workspace, out)
 
-    def forward(self, f):
+    def forward(self, f, workspace=None, out=None):
         """Forward spin SHT: map -> flm [B?, L, 2L-1]."""
-        return self._call(self._lib.s2_forward, f, self.map_shape, self.coeff_shape, "forward")
+        return self._call(self._lib.s2_forward, f, self.map_shape, self.coeff_shape, "forward", workspace, out)
 
-    def inverse_adjoint(self, g):
+    def inverse_adjoint(self, g, workspace=None, out=None):
         """Hermitian adjoint of the inverse SHT: map-space cotangent -> coefficients."""
-        return self._call(self._lib.s2_inverse_adjoint, g, self.map_shape, self.coeff_shape, "inverse_adjoint")
+        return self._call(self._lib.s2_inverse_adjoint, g, self.map_shape, self.coeff_shape, "inverse_adjoint", workspace, out)
 
-    def so3_inverse(self, flmn):
+    def so3_inverse(self, flmn, workspace=None, out=None):
         """Inverse Wigner transform: flmn [B?, 2N-1, L, 2L-1] -> f [B?, 2N-1, L, 2L-1]."""
         shp = (2 * self.N - 1,) + self.coeff_shape
-        return self._call(self._lib.so3_inverse, flmn, shp, shp, "so3_inverse")
+        return self._call(self._lib.so3_inverse, flmn, shp, shp, "so3_inverse", workspace, out)
 
-    def so3_forward(self, f):
+    def so3_forward(self, f, workspace=None, out=None):
         """Forward Wigner transform: f [B?, 2N-1, L, 2L-1] -> flmn."""
         shp = (2 * self.N - 1,) + self.coeff_shape
-        return self._call(self._lib.so3_forward, f, shp, shp, "so3_forward")
+        return self._call(self._lib.so3_forward, f, shp, shp, "so3_forward", workspace, out)
 
     def set_timing(self, enable=True):
         """Record HIP events around every kernel launch of this plan's transforms."""

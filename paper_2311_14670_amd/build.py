@@ -28,7 +28,7 @@ def _run(cmd):
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ["s2mi_kernels.hip", "s2mi_capi.hip"]:
+    for src in ["s2mi_kernels.hip", "s2mi_mfma.hip", "s2mi_capi.hip"]:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run(["hipcc", "-c", "-x", "hip"] + HIP_FLAGS + [os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

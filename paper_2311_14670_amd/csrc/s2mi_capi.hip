@@ -19,6 +19,7 @@
 #include "../../include/s2mi.h"
 #include "s2mi_internal.h"
 #include "s2mi_kernels.h"
+#include "s2mi_mfma.h"
 
 using namespace s2mi;
 
@@ -92,6 +93,17 @@ struct s2_plan_s {
     // workspace layout (bytes)
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
     size_t szC = 0, szP = 0, szF = 0, szQ = 0;
+
+    // matrix-core contraction path (precision FP32 / split BF16): batched over maps
+    bool mfma = false;
+    MfmaGeom mg{};
+    int mch = 1;                           // orders per generated d chunk
+    int gen_nblk = 1, gen_waves = 1;
+    int *gen_lchunk = nullptr, *gen_mtop = nullptr, *mtop1 = nullptr;
+    double2 *kg = nullptr;                 // [m][lrow] {kappa, g}
+    size_t nslots = 0;                     // recursion state slots (l) of the generator
+    size_t off_D = 0, off_S = 0, off_AH = 0, off_mP = 0, off_mF = 0, off_mQ = 0, off_mhp = 0, off_mmaps = 0;
+    size_t state_bytes = 0;
 
     // stage timing
     bool timing = false;
@@ -196,26 +208,28 @@ int fft_threads_for(int len) { return std::min(1024, std::max(64, ((len / 8 + 63
 // balanced.  lchunk[bin] = {base of chunk A, base of chunk B} (or -1);
 // lslot[bin][16] = the degree of each slot (slot j of a chunk: base + 7 - j),
 // -1 where the chunk runs past L-1.
-void assign_inverse(int L, int nblk, int W, std::vector<int> &lchunk, std::vector<int> &lslot, std::vector<int> &mtop)
+void assign_inverse(int L, int nblk, int W, int nchw, std::vector<int> &lchunk, std::vector<int> &lslot,
+                    std::vector<int> &mtop)
 {
     const int nbin = nblk * W;
+    const int jw = 8 * nchw;
     const int nch = (L + 7) / 8;
-    lchunk.assign((size_t)nbin * INV_NCH, -1);
-    lslot.assign((size_t)nbin * INV_J, -1);
+    lchunk.assign((size_t)nbin * nchw, -1);
+    lslot.assign((size_t)nbin * jw, -1);
     std::vector<int> fill(nbin, 0);
     for (int idx = 0, c = nch - 1; c >= 0; --c, ++idx) {
         const int round = idx / nbin, pos = idx % nbin;
         const int bin = (round % 2 == 0) ? pos : nbin - 1 - pos;
         const int g = fill[bin]++;
-        lchunk[(size_t)bin * INV_NCH + g] = 8 * c;
+        lchunk[(size_t)bin * nchw + g] = 8 * c;
         for (int j = 0; j < 8; ++j) {
             const int l = 8 * c + 7 - j;
-            lslot[(size_t)bin * INV_J + g * 8 + j] = l < L ? l : -1;
+            lslot[(size_t)bin * jw + g * 8 + j] = l < L ? l : -1;
         }
     }
     mtop.assign(nblk, 0);
     for (int b = 0; b < nblk; ++b)
-        for (int k = 0; k < W * INV_J; ++k) mtop[b] = std::max(mtop[b], lslot[(size_t)b * W * INV_J + k]);
+        for (int k = 0; k < W * jw; ++k) mtop[b] = std::max(mtop[b], lslot[(size_t)b * W * jw + k]);
 }
 
 }  // namespace
@@ -276,7 +290,8 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     if (sampling == S2_HEALPIX && (nside < 1 || nside > 2048)) return fail(S2_ERR_INVALID_ARG, "nside=%d outside [1, 2048]", nside);
     if (sampling == S2_HEALPIX && N > 1) return fail(S2_ERR_UNSUPPORTED, "SO(3) plans need MW sampling");
     if (max_batch < 1) return fail(S2_ERR_INVALID_ARG, "max_batch=%d < 1", max_batch);
-    if (prec != S2_FP64) return fail(S2_ERR_UNSUPPORTED, "precision mode %d not available in this build", (int)prec);
+    if (prec != S2_FP64 && prec != S2_CONTRACT_FP32 && prec != S2_CONTRACT_SPLIT_BF16)
+        return fail(S2_ERR_INVALID_ARG, "unknown precision mode %d", (int)prec);
     hipStream_t st = (hipStream_t)hip_stream;
 
     s2_plan_s *P = new (std::nothrow) s2_plan_s();
@@ -405,7 +420,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         stg.i.emplace_back(); std::vector<int> &lch = stg.i.back();
         stg.i.emplace_back(); std::vector<int> &ls = stg.i.back();
         stg.i.emplace_back(); std::vector<int> &mt = stg.i.back();
-        assign_inverse(L, P->inv_nblk, P->inv_waves, lch, ls, mt);
+        assign_inverse(L, P->inv_nblk, P->inv_waves, INV_NCH, lch, ls, mt);
         if ((rc = upload(P, &P->lchunk, lch, st, "inverse chunks"))) return bail(rc);
         if ((rc = upload(P, &P->lslot, ls, st, "inverse slots"))) return bail(rc);
         if ((rc = upload(P, &P->mtop, mt, st, "inverse mtop"))) return bail(rc);
@@ -451,6 +466,52 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->off_F = o; o += align256(P->szF * S);
         P->off_Q = o; o += align256(P->szQ * S);
         P->off_hpole = o; o += align256((size_t)(2 * L - 1) * S * sizeof(double2));
+        P->ws_bytes = o;
+    }
+
+    // matrix-core path: generator assignment, {kappa, g} table, batched workspace
+    if (prec != S2_FP64) {
+        P->mfma = true;
+        MfmaGeom &g = P->mg;
+        g.L = L;
+        g.nreg = P->nreg;
+        g.rpad = (P->nreg + 63) / 64 * 64;
+        g.lp = (L + 63) / 64 * 64;
+        g.kc = (L + 7) / 8;
+        g.lrow = 8 * g.kc;
+        g.rows = (4 * max_batch + 31) / 32 * 32;
+        {
+            const int nch = g.kc;
+            const int per_blk = DSTAGE_MAX_WAVES * GEN_NCH;
+            P->gen_nblk = (nch + per_blk - 1) / per_blk;
+            P->gen_waves = std::max(1, (nch + GEN_NCH * P->gen_nblk - 1) / (GEN_NCH * P->gen_nblk));
+            stg.i.emplace_back(); std::vector<int> &lch = stg.i.back();
+            stg.i.emplace_back(); std::vector<int> &ls = stg.i.back();
+            stg.i.emplace_back(); std::vector<int> &mt = stg.i.back();
+            assign_inverse(L, P->gen_nblk, P->gen_waves, GEN_NCH, lch, ls, mt);
+            if ((rc = upload(P, &P->gen_lchunk, lch, st, "generator chunks"))) return bail(rc);
+            if ((rc = upload(P, &P->gen_mtop, mt, st, "generator mtop"))) return bail(rc);
+            stg.i.emplace_back(1, L - 1);
+            if ((rc = upload(P, &P->mtop1, stg.i.back(), st, "single-block mtop"))) return bail(rc);
+            P->nslots = (size_t)P->gen_nblk * P->gen_waves * GEN_NCH * 8;
+        }
+        if ((rc = P->dalloc(&P->kg, (size_t)L * g.lrow, "kappa/g table"))) return bail(rc);
+        HIPCHK(launch_kg_table(st, L, g.lrow, P->kap, P->gtab, P->kg), "kappa/g table");
+        const size_t per_m_d = std::max((size_t)g.kc * g.rpad, (size_t)(g.rpad / 8) * g.lp) * 32;
+        P->mch = (int)std::max<size_t>(4, std::min<size_t>((size_t)L, ((size_t)512 << 20) / per_m_d));
+        const size_t per_m_ah = (size_t)std::max(g.kc, g.rpad / 8) * g.rows * 32;
+        const size_t S = P->nslice, B = max_batch;
+        const size_t nP1 = (size_t)P->nreg * L * 4, nQ1 = (size_t)L * L * 4;
+        P->state_bytes = P->nslots * g.rpad * (2 * sizeof(double) + sizeof(int));
+        size_t o = P->ws_bytes;
+        P->off_D = o; o += align256(per_m_d * P->mch);
+        P->off_S = o; o += align256(P->state_bytes);
+        P->off_AH = o; o += align256(per_m_ah * P->mch);
+        P->off_mP = o; o += align256(B * S * nP1 * sizeof(double));
+        P->off_mF = o; o += align256(B * S * P->szF);
+        P->off_mQ = o; o += align256(B * S * nQ1 * sizeof(double));
+        P->off_mhp = o; o += align256(B * S * (2 * L - 1) * sizeof(double2));
+        P->off_mmaps = o; o += (S > 1) ? align256(B * S * (size_t)P->nsamp * sizeof(double2)) : 0;
         P->ws_bytes = o;
     }
     HIPCHK(hipStreamSynchronize(st), "plan upload");
@@ -603,6 +664,128 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
     return run_forward_dstage(P, F0, mw ? hp0 : nullptr, flm, wl, ws, st);
 }
 
+// ---------------------------------------------------------------- matrix-core path
+// Batched inverse: flm [B][S][L][2L-1] -> slice maps [B][S][nsamp].
+int run_inverse_mfma(s2_plan_t P, const double2 *flm, int B, double2 *maps, const std::vector<double *> &wl, char *ws,
+                     hipStream_t st)
+{
+    const int L = P->L, S = P->nslice, fmt = P->prec;
+    const MfmaGeom &g = P->mg;
+    const size_t slab = (size_t)L * (2 * L - 1);
+    const size_t nP1 = (size_t)P->nreg * L * 4;
+    uint4 *D = (uint4 *)(ws + P->off_D);
+    uint4 *A = (uint4 *)(ws + P->off_AH);
+    double *SX = (double *)(ws + P->off_S);
+    double *SY = SX + P->nslots * g.rpad;
+    int *SE = (int *)(SY + P->nslots * g.rpad);
+    double *Pm = (double *)(ws + P->off_mP);
+    for (size_t ri = 0; ri < P->runs.size(); ++ri) {
+        const Run &r = P->runs[ri];
+        const double2 *fa = r.sliceA >= 0 ? flm + r.sliceA * slab : nullptr;
+        const double2 *fb = r.sliceB >= 0 ? flm + r.sliceB * slab : nullptr;
+        double *PA = r.sliceA >= 0 ? Pm + r.sliceA * nP1 : nullptr;
+        double *PB = r.sliceB >= 0 ? Pm + r.sliceB * nP1 : nullptr;
+        HIPCHK(launch_zero(st, SX, P->state_bytes), "recursion state clear");
+        for (int mhi = L - 1; mhi >= 0; mhi -= P->mch) {
+            const int mlo = std::max(0, mhi - P->mch + 1), mcn = mhi - mlo + 1;
+            {
+            TIMED(S2_STAGE_DGEN);
+            HIPCHK(launch_dgen(st, 0, fmt, P->gen_waves, P->gen_nblk, g, r.n, mhi, mlo, P->cot, P->csc, P->init[ri],
+                               P->kg, P->gen_lchunk, P->gen_mtop, SX, SY, SE, D), "d-tile generator");
+            }
+            {
+            TIMED(S2_STAGE_PACK);
+            HIPCHK(launch_pack_a(st, fmt, g, r.n, mlo, mcn, B, (long long)(S * slab), fa, fb,
+                                 r.sliceA >= 0 ? wl[r.sliceA] : nullptr, r.sliceB >= 0 ? wl[r.sliceB] : nullptr, A),
+                   "coefficient pack");
+            }
+            TIMED(S2_STAGE_MFMA);
+            HIPCHK(launch_mfma_inv(st, fmt, g, r.n, mlo, mcn, B, A, D, PA, PB, (long long)(S * nP1)),
+                   "inverse contraction");
+        }
+    }
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < S; ++k) {
+            TIMED(S2_STAGE_PHI_INV);
+            HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, P->nreg, 1, P->slice_spin[k],
+                                  Pm + ((size_t)b * S + k) * nP1, P->mtop1, flm + ((size_t)b * S + k) * slab, wl[k],
+                                  P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts,
+                                  maps + ((size_t)b * S + k) * P->nsamp), "inverse phi-DFT");
+        }
+    return S2_OK;
+}
+
+// Batched forward (adjoint: unit phi weight, no theta filter): slice maps [B][S][nsamp] -> flm [B][S][L][2L-1].
+int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, const std::vector<double *> &wl, char *ws,
+                     hipStream_t st, bool adjoint)
+{
+    const int L = P->L, S = P->nslice, fmt = P->prec;
+    const MfmaGeom &g = P->mg;
+    const size_t slab = (size_t)L * (2 * L - 1);
+    const size_t nF = P->szF / sizeof(double), nQ1 = (size_t)L * L * 4;
+    const bool mw = P->sampling == S2_MW;
+    uint4 *D = (uint4 *)(ws + P->off_D);
+    uint4 *H = (uint4 *)(ws + P->off_AH);
+    double *SX = (double *)(ws + P->off_S);
+    double *SY = SX + P->nslots * g.rpad;
+    int *SE = (int *)(SY + P->nslots * g.rpad);
+    double *Fm = (double *)(ws + P->off_mF);
+    double *Qm = (double *)(ws + P->off_mQ);
+    double2 *hp = (double2 *)(ws + P->off_mhp);
+    double q;
+    if (adjoint) q = 1.0;
+    else if (mw) q = 2.0 * M_PI / (double)(2 * L - 1);
+    else q = 4.0 * M_PI / (double)P->nsamp;
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < S; ++k) {
+            const size_t bk = (size_t)b * S + k;
+            double *F = Fm + bk * nF;
+            {
+            TIMED(S2_STAGE_PHI_FWD);
+            HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L, q, maps + bk * P->nsamp,
+                                  P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F),
+                   "forward phi-DFT");
+            }
+            TIMED(S2_STAGE_MW_THETA);
+            if (mw && !adjoint)
+                HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, P->slice_spin[k], P->ffts,
+                                        P->wq, P->ph, F, hp + bk * (2 * L - 1)), "MW theta filter");
+            else if (mw)
+                HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp + bk * (2 * L - 1)), "pole line");
+        }
+    for (size_t ri = 0; ri < P->runs.size(); ++ri) {
+        const Run &r = P->runs[ri];
+        const double *FA = r.sliceA >= 0 ? Fm + r.sliceA * nF : Fm + r.sliceB * nF;
+        const double *FB = r.sliceB >= 0 ? Fm + r.sliceB * nF : FA;
+        double *QA = r.sliceA >= 0 ? Qm + r.sliceA * nQ1 : nullptr;
+        double *QB = r.sliceB >= 0 ? Qm + r.sliceB * nQ1 : nullptr;
+        HIPCHK(launch_zero(st, SX, P->state_bytes), "recursion state clear");
+        for (int mhi = L - 1; mhi >= 0; mhi -= P->mch) {
+            const int mlo = std::max(0, mhi - P->mch + 1), mcn = mhi - mlo + 1;
+            {
+            TIMED(S2_STAGE_DGEN);
+            HIPCHK(launch_dgen(st, 1, fmt, P->gen_waves, P->gen_nblk, g, r.n, mhi, mlo, P->cot, P->csc, P->init[ri],
+                               P->kg, P->gen_lchunk, P->gen_mtop, SX, SY, SE, D), "d-tile generator");
+            }
+            {
+            TIMED(S2_STAGE_PACK);
+            HIPCHK(launch_pack_h(st, fmt, g, P->hstride, mlo, mcn, B, (long long)(S * nF), FA, FB, H), "spectra pack");
+            }
+            TIMED(S2_STAGE_MFMA);
+            HIPCHK(launch_mfma_fwd(st, fmt, g, mlo, mcn, B, H, D, QA, QB, (long long)(S * nQ1)), "forward contraction");
+        }
+    }
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < S; ++k) {
+            const size_t bk = (size_t)b * S + k;
+            const int s = P->slice_spin[k];
+            TIMED(S2_STAGE_FINISH);
+            HIPCHK(launch_finish_fwd(st, L, 1, s, s, Qm + bk * nQ1, wl[k], mw ? hp + bk * (2 * L - 1) : nullptr,
+                                     flm + bk * slab), "forward finish");
+        }
+    return S2_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -614,6 +797,7 @@ int s2_inverse(s2_plan_t P, const void *flm, void *f, int batch, void *workspace
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_inverse: plan was created for SO(3) (N=%d)", P->N);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    if (P->mfma) return run_inverse_mfma(P, (const double2 *)flm, batch, (double2 *)f, P->w_sht, (char *)workspace, st);
     for (int b = 0; b < batch; ++b) {
         double2 *out = (double2 *)f + (size_t)b * P->nsamp;
         if ((rc = run_inverse(P, (const double2 *)flm + b * slab, &out, P->w_sht, (char *)workspace, st))) return rc;
@@ -628,6 +812,8 @@ int s2_forward(s2_plan_t P, const void *f, void *flm, int batch, void *workspace
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_forward: plan was created for SO(3) (N=%d)", P->N);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    if (P->mfma)
+        return run_forward_mfma(P, (const double2 *)f, batch, (double2 *)flm, P->w_sht, (char *)workspace, st, false);
     for (int b = 0; b < batch; ++b) {
         const double2 *in = (const double2 *)f + (size_t)b * P->nsamp;
         if ((rc = run_forward(P, &in, (double2 *)flm + b * slab, P->w_sht, (char *)workspace, st, false))) return rc;
@@ -642,6 +828,8 @@ int s2_inverse_adjoint(s2_plan_t P, const void *g, void *g_flm, int batch, void 
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_inverse_adjoint: plan was created for SO(3) (N=%d)", P->N);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    if (P->mfma)
+        return run_forward_mfma(P, (const double2 *)g, batch, (double2 *)g_flm, P->w_sht, (char *)workspace, st, true);
     for (int b = 0; b < batch; ++b) {
         const double2 *in = (const double2 *)g + (size_t)b * P->nsamp;
         if ((rc = run_forward(P, &in, (double2 *)g_flm + b * slab, P->w_sht, (char *)workspace, st, true))) return rc;
@@ -657,6 +845,17 @@ int so3_inverse(s2_plan_t P, const void *flmn, void *f, int batch, void *workspa
     hipStream_t st = (hipStream_t)hip_stream;
     const int S = P->nslice;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    if (P->mfma) {
+        double2 *tmp = (S > 1) ? (double2 *)((char *)workspace + P->off_mmaps) : (double2 *)f;
+        if ((rc = run_inverse_mfma(P, (const double2 *)flmn, batch, tmp, P->w_so3i, (char *)workspace, st))) return rc;
+        if (S > 1)
+            for (int b = 0; b < batch; ++b) {
+                TIMED(S2_STAGE_GAMMA);
+                HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, +1, 1.0, P->groots, tmp + (size_t)b * S * P->nsamp,
+                                        (double2 *)f + (size_t)b * S * P->nsamp), "gamma DFT");
+            }
+        return S2_OK;
+    }
     for (int b = 0; b < batch; ++b) {
         double2 *out = (double2 *)f + (size_t)b * S * P->nsamp;
         std::vector<double2 *> maps(S);
@@ -680,6 +879,20 @@ int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspa
     hipStream_t st = (hipStream_t)hip_stream;
     const int S = P->nslice;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    if (P->mfma) {
+        const double2 *src = (const double2 *)f;
+        if (S > 1) {
+            double2 *tmp = (double2 *)((char *)workspace + P->off_mmaps);
+            for (int b = 0; b < batch; ++b) {
+                TIMED(S2_STAGE_GAMMA);
+                HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, -1, 2.0 * M_PI / (double)S, P->groots,
+                                        (const double2 *)f + (size_t)b * S * P->nsamp, tmp + (size_t)b * S * P->nsamp),
+                       "gamma DFT");
+            }
+            src = tmp;
+        }
+        return run_forward_mfma(P, src, batch, (double2 *)flmn, P->w_so3f, (char *)workspace, st, false);
+    }
     for (int b = 0; b < batch; ++b) {
         const double2 *in = (const double2 *)f + (size_t)b * S * P->nsamp;
         std::vector<const double2 *> maps(S);

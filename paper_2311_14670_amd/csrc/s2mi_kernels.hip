@@ -26,14 +26,11 @@
 #include "s2mi_fft.h"
 #include "s2mi_internal.h"
 #include "s2mi_kernels.h"
+#include "s2mi_recur.h"
 
 namespace s2mi {
 
-constexpr int RT = 600;   // realise once the scale exponent is above -RT
-
 // ------------------------------------------------------------------ helpers
-__device__ __forceinline__ int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
 struct DD {
     double hi, lo;
 };
@@ -78,18 +75,6 @@ __device__ __forceinline__ void d_init(int l, int n, DD lbin, DD ls, DD lc, doub
     if (ex >= -RT) { v = ldexp(v, ex); ex = 0; }
     e = v;
     E = ex;
-}
-
-// exact power-of-two renormalisation of the pair (e, ep) carrying exponent E
-__device__ __forceinline__ void renorm(double &e, double &ep, int &E)
-{
-    const double mx = fmax(fabs(e), fabs(ep));
-    const int k = mx > 0.0 ? ilogb(mx) : 0;          // a not-yet-started (zero) state keeps E
-    const bool real = (E + k >= -RT);
-    const int sh = real ? E : -k;
-    e = ldexp(e, sh);
-    ep = ldexp(ep, sh);
-    E = real ? 0 : E + k;
 }
 
 // ------------------------------------------------------------------ start values
@@ -164,8 +149,6 @@ __global__ void k_pack_inv(int L, int n, int nslot, int S, const int *__restrict
 // orders (PAR), so the recursion needs no register moves.  Per order, each
 // wave's partial sums are reduced over the waves in LDS by a rotating group of
 // four waves and written to partA/partB[blk][ring][m].
-constexpr int SG = 8;
-
 template <int PAR, bool SLOW>
 __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ rec,
                                           double lam, int jin, double e0, int E0, double &aAr, double &aAi,

@@ -1,0 +1,141 @@
+"""GPU parity beyond the small cases: sizes spanning several workgroups with
+ragged tails (full oracle comparison), and the benchmark's full sizes in the
+benchmark's launch configuration (oracle on sampled rings / orders, plus the
+round-trip property that holds at any size)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_14670_amd.synth import flm_gaussian, flmn_gaussian, map_gaussian, coeff_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(x):
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_2311_14670_amd import binding as b
+    b.load_library()
+    return b
+
+
+# --------------------------------------------------------------- several tiles, full oracle
+@pytest.mark.parametrize("L,spin", [(200, 0), (131, 2), (97, -3)])
+def test_mw_multi_tile(binding, L, spin):
+    flm = flm_gaussian(L, spin, seed=10, scale="inv1pl")
+    plan = binding.Plan(L, spin=spin)
+    f = host(plan.inverse(dev(flm)))
+    assert rel_l2(f, oracle.s2_inverse(flm, L, spin)) < 1e-12
+    g = map_gaussian((L, 2 * L - 1), seed=11)
+    a = host(plan.forward(dev(g)))
+    assert rel_l2(a, oracle.s2_forward(g, L, spin)) < 1e-12
+    adj = host(plan.inverse_adjoint(dev(g)))
+    assert rel_l2(adj, oracle.s2_inverse_adjoint(g, L, spin)) < 1e-12
+
+
+@pytest.mark.parametrize("nside,L,spin", [(32, 64, 0), (24, 50, 2)])
+def test_healpix_multi_tile(binding, nside, L, spin):
+    flm = flm_gaussian(L, spin, seed=12)
+    plan = binding.Plan(L, spin=spin, sampling="healpix", nside=nside)
+    f = host(plan.inverse(dev(flm)))
+    assert rel_l2(f, oracle.s2_inverse(flm, L, spin, oracle.HEALPIX, nside)) < 1e-12
+    g = map_gaussian(12 * nside * nside, seed=13)
+    a = host(plan.forward(dev(g)))
+    assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < 1e-12
+
+
+def test_so3_multi_tile(binding):
+    L, N = 72, 4
+    flmn = flmn_gaussian(L, N, seed=14)
+    plan = binding.Plan(L, N=N)
+    f = host(plan.so3_inverse(dev(flmn)))
+    assert rel_l2(f, oracle.so3_inverse(flmn, L, N)) < 1e-12
+    back = host(plan.so3_forward(dev(f)))
+    assert rel_l2(back, flmn) < 1e-12
+
+
+def test_batch_with_ragged_sizes(binding):
+    """Batch 5 through a plan sized for 8, against per-map oracle results."""
+    L, spin = 70, 1
+    flm = flm_gaussian(L, spin, seed=15, batch=5)
+    plan = binding.Plan(L, spin=spin, max_batch=8)
+    f = host(plan.inverse(dev(flm)))
+    for b in range(5):
+        assert rel_l2(f[b], oracle.s2_inverse(flm[b], L, spin)) < 1e-12
+    a = host(plan.forward(dev(f)))
+    assert rel_l2(a, flm) < 1e-12
+
+
+@pytest.mark.parametrize("L", [2, 3, 9])
+def test_smallest_bandlimits(binding, L):
+    for spin in range(-(L - 1), L):
+        flm = flm_gaussian(L, spin, seed=16)
+        plan = binding.Plan(L, spin=spin)
+        f = host(plan.inverse(dev(flm)))
+        assert rel_l2(f, oracle.s2_inverse(flm, L, spin)) < 1e-13
+        assert rel_l2(host(plan.forward(dev(f))), flm) < 1e-13
+
+
+def test_batch_larger_than_plan_is_rejected(binding):
+    plan = binding.Plan(16, max_batch=2)
+    x = torch.zeros((3, 16, 31), dtype=torch.complex128, device="cuda")
+    with pytest.raises(binding.S2Error):
+        plan.inverse(x)
+
+
+# --------------------------------------------------------------- full sizes, sampled
+def _sample_rings(L):
+    return np.array(sorted({0, 1, L // 3, L // 2, L - 3, L - 2, L - 1}))
+
+
+def _sample_orders(L):
+    return np.array(sorted({0, 1, -1, 2, L // 2, -(L // 3), L - 2, -(L - 1), L - 1}))
+
+
+@pytest.mark.parametrize("L,spin", [(2048, 0), (1024, 2)])
+def test_mw_full_size_sampled(binding, L, spin):
+    flm = flm_gaussian(L, spin, seed=1, scale="inv1pl")
+    plan = binding.Plan(L, spin=spin)                # benchmark configuration: batch 1
+    x = dev(flm)
+    f = plan.inverse(x)
+    rings = _sample_rings(L)
+    fr = host(f)[rings].ravel()
+    assert rel_l2(fr, oracle.s2_inverse(flm, L, spin, rings=rings)) < 1e-11
+    back = host(plan.forward(f))
+    assert rel_l2(back, flm) < 1e-11                 # holds at any size
+    g = map_gaussian((L, 2 * L - 1), seed=17)
+    a = host(plan.forward(dev(g)))
+    ms = _sample_orders(L)
+    ref = oracle.s2_forward(g, L, spin, ms=ms)
+    cols = ms + L - 1
+    assert rel_l2(a[:, cols], ref[:, cols]) < 1e-11
+    assert np.all(a[~coeff_mask(L, spin)] == 0)
+
+
+def test_healpix_full_size_sampled(binding):
+    nside, L, spin = 1024, 2048, 0
+    flm = flm_gaussian(L, spin, seed=18, scale="inv1pl")
+    plan = binding.Plan(L, spin=spin, sampling="healpix", nside=nside)
+    f = host(plan.inverse(dev(flm)))
+    theta, nphi, start, _ = oracle.healpix_rings(nside)
+    rings = np.array([0, 1, nside - 1, nside, 2 * nside - 1, 3 * nside, 4 * nside - 2])
+    fr = np.concatenate([f[start[r]:start[r] + nphi[r]] for r in rings])
+    assert rel_l2(fr, oracle.s2_inverse(flm, L, spin, oracle.HEALPIX, nside, rings=rings)) < 1e-11
+    a = host(plan.forward(dev(f)))
+    ms = _sample_orders(L)
+    ref = oracle.s2_forward(f, L, spin, oracle.HEALPIX, nside, ms=ms)
+    cols = ms + L - 1
+    assert rel_l2(a[:, cols], ref[:, cols]) < 1e-11

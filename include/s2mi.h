@@ -152,6 +152,22 @@ int s2_inverse_adjoint(s2_plan_t plan, const void *g, void *g_flm, int batch, vo
                        void *hip_stream);
 
 /*
+ * Hermitian adjoint of the forward spin SHT (for gradients through s2_forward;
+ * the conjugate convention PyTorch uses for complex tensors):
+ *   g = F^H g_flm, with <F f, g_flm> = <f, g> for every map f.
+ *   MW: the inverse-type d-stage sweep with the SHT weights (Eqs. 30, 33),
+ *       the MW theta filter (which is Hermitian) and the adjoint phi-DFT
+ *       (Eq. 31) times 2 pi/(2L-1); the south pole follows Eq. 29.
+ *   HEALPix: (4 pi / Npix) times the inverse SHT (the forward is the
+ *       quadrature of Eq. 19).
+ *   g_flm  [batch][L][2L-1] complex128 (device, read)
+ *   g      [batch][nsamples] complex128 (device, written)
+ * FP64 plans only (S2_ERR_UNSUPPORTED otherwise).
+ */
+int s2_forward_adjoint(s2_plan_t plan, const void *g_flm, void *g, int batch, void *workspace,
+                       void *hip_stream);
+
+/*
  * Inverse Wigner transform (Eq. 13 with Eq. 10):
  *   f(alpha_p, beta_t, gamma_k) = sum_n e^{i n gamma_k} sum_m e^{i m alpha_p}
  *                                 sum_l (2l+1)/(8 pi^2) flmn[n][l][m] d^l_{mn}(beta_t)

@@ -66,7 +66,8 @@ def load_library():
         lib.s2_plan_create.argtypes = [ctypes.POINTER(P), i, i, i, i, i, i, i, vp]
         lib.s2_plan_destroy.argtypes = [P]
         lib.s2_plan_info.argtypes = [P, ctypes.POINTER(_PlanInfo)]
-        for name in ["s2_inverse", "s2_forward", "s2_inverse_adjoint", "so3_inverse", "so3_forward"]:
+        for name in ["s2_inverse", "s2_forward", "s2_inverse_adjoint", "s2_forward_adjoint", "so3_inverse",
+                     "so3_forward"]:
             getattr(lib, name).argtypes = [P, vp, vp, i, vp, vp]
             getattr(lib, name).restype = i
         lib.s2_debug_wigner_d.argtypes = [P, i, vp, vp]
@@ -187,6 +188,11 @@ class Plan:
     def inverse_adjoint(self, g, workspace=None, out=None):
         """Hermitian adjoint of the inverse SHT: map-space cotangent -> coefficients."""
         return self._call(self._lib.s2_inverse_adjoint, g, self.map_shape, self.coeff_shape, "inverse_adjoint", workspace, out)
+
+    def forward_adjoint(self, g_flm, workspace=None, out=None):
+        """Hermitian adjoint of the forward SHT: coefficient-space cotangent -> map (FP64 plans)."""
+        return self._call(self._lib.s2_forward_adjoint, g_flm, self.coeff_shape, self.map_shape, "forward_adjoint",
+                          workspace, out)
 
     def so3_inverse(self, flmn, workspace=None, out=None):
         """Inverse Wigner transform: flmn [B?, 2N-1, L, 2L-1] -> f [B?, 2N-1, L, 2L-1]."""

@@ -77,6 +77,7 @@ struct s2_plan_s {
     std::vector<double2 *> init;  // per run [nreg][L]: start values of Eq. 27
     // per-slice weights: SHT (Eqs. 30, 33), SO(3) inverse (Eq. 13), SO(3) forward (Eq. 14)
     std::vector<double *> w_sht, w_so3i, w_so3f;
+    std::vector<double *> w_fadj;         // HEALPix: (4 pi / Npix) w_l, the adjoint of the forward quadrature
     // FFT
     std::vector<FftArgs> ffts_h;
     FftArgs *ffts = nullptr;
@@ -469,6 +470,20 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->ws_bytes = o;
     }
 
+    {
+        stg.i.emplace_back(1, L - 1);
+        if ((rc = upload(P, &P->mtop1, stg.i.back(), st, "single-block mtop"))) return bail(rc);
+    }
+    // HEALPix forward = q x adjoint of the inverse, so its adjoint is the inverse with weights q w_l
+    if (sampling == S2_HEALPIX && !so3) {
+        stg.d.emplace_back();
+        host_weights(L, 0, spin, &stg.d.back());
+        for (double &v : stg.d.back()) v *= 4.0 * M_PI / (double)P->nsamp;
+        double *a;
+        if ((rc = upload(P, &a, stg.d.back(), st, "forward-adjoint weights"))) return bail(rc);
+        P->w_fadj.push_back(a);
+    }
+
     // matrix-core path: generator assignment, {kappa, g} table, batched workspace
     if (prec != S2_FP64) {
         P->mfma = true;
@@ -491,8 +506,6 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             assign_inverse(L, P->gen_nblk, P->gen_waves, GEN_NCH, lch, ls, mt);
             if ((rc = upload(P, &P->gen_lchunk, lch, st, "generator chunks"))) return bail(rc);
             if ((rc = upload(P, &P->gen_mtop, mt, st, "generator mtop"))) return bail(rc);
-            stg.i.emplace_back(1, L - 1);
-            if ((rc = upload(P, &P->mtop1, stg.i.back(), st, "single-block mtop"))) return bail(rc);
             P->nslots = (size_t)P->gen_nblk * P->gen_waves * GEN_NCH * 8;
         }
         if ((rc = P->dalloc(&P->kg, (size_t)L * g.lrow, "kappa/g table"))) return bail(rc);
@@ -572,9 +585,8 @@ int check_call(const char *fn, s2_plan_t P, const void *in, const void *out, int
     return S2_OK;
 }
 
-// inverse of one (map, all slices): flm slices [S][L][2L-1] -> slice maps
-int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, const std::vector<double *> &wl,
-                char *ws, hipStream_t st)
+// inverse d-stage of one (map, all slices): flm slices [S][L][2L-1] -> partials P[slice][blk][ring][m][4]
+int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double *> &wl, char *ws, hipStream_t st)
 {
     const int L = P->L;
     const size_t slab = (size_t)L * (2 * L - 1);
@@ -598,12 +610,49 @@ int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, con
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
                                  r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr), "inverse d-stage");
     }
+    return S2_OK;
+}
+
+// inverse of one (map, all slices): flm slices [S][L][2L-1] -> slice maps
+int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, const std::vector<double *> &wl,
+                char *ws, hipStream_t st)
+{
+    const int L = P->L;
+    const size_t slab = (size_t)L * (2 * L - 1);
+    double *P0 = (double *)(ws + P->off_P);
+    const size_t nP = P->szP / sizeof(double);
+    int rc = run_inverse_dstage(P, flm, wl, ws, st);
+    if (rc) return rc;
     for (int k = 0; k < P->nslice; ++k) {
         TIMED(S2_STAGE_PHI_INV);
         HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, P->nreg, P->inv_nblk, P->slice_spin[k],
                               P0 + k * nP, P->mtop, flm + k * slab, wl[k], P->ring_nphi, P->ring_start,
                               P->ring_shift, P->ring_fft, P->ffts, slice_maps[k]), "inverse phi-DFT");
     }
+    return S2_OK;
+}
+
+// adjoint of the MW forward SHT of one map (S2 plan): coefficient cotangent -> map
+int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *map, char *ws, hipStream_t st)
+{
+    const int L = P->L, s = P->spin;
+    int rc = run_inverse_dstage(P, G, P->w_sht, ws, st);
+    if (rc) return rc;
+    double *P0 = (double *)(ws + P->off_P);
+    double *F0 = (double *)(ws + P->off_F);
+    double2 *hp0 = (double2 *)(ws + P->off_hpole);
+    double *Q0 = (double *)(ws + P->off_Q);
+    const double q = 2.0 * M_PI / (double)(2 * L - 1);
+    {
+    TIMED(S2_STAGE_MW_THETA);
+    HIPCHK(launch_fadj_gather(st, L, P->inv_nblk, s, P0, P->mtop, G, P->w_sht[0], P->hstride, F0), "adjoint gather");
+    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0),
+           "MW theta filter");
+    HIPCHK(launch_fadj_scatter(st, L, P->hstride, q, F0, hp0, Q0), "adjoint scatter");
+    }
+    TIMED(S2_STAGE_PHI_INV);
+    HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, L, 1, s, Q0, P->mtop1, G, P->w_sht[0],
+                          P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, map), "adjoint phi-DFT");
     return S2_OK;
 }
 
@@ -833,6 +882,24 @@ int s2_inverse_adjoint(s2_plan_t P, const void *g, void *g_flm, int batch, void 
     for (int b = 0; b < batch; ++b) {
         const double2 *in = (const double2 *)g + (size_t)b * P->nsamp;
         if ((rc = run_forward(P, &in, (double2 *)g_flm + b * slab, P->w_sht, (char *)workspace, st, true))) return rc;
+    }
+    return S2_OK;
+}
+
+int s2_forward_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_forward_adjoint", P, g_flm, g, batch, workspace);
+    if (rc) return rc;
+    if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_forward_adjoint: plan was created for SO(3) (N=%d)", P->N);
+    if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "s2_forward_adjoint: available for FP64 plans");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b) {
+        const double2 *G = (const double2 *)g_flm + b * slab;
+        double2 *out = (double2 *)g + (size_t)b * P->nsamp;
+        if (P->sampling == S2_MW) rc = run_forward_adjoint_mw(P, G, out, (char *)workspace, st);
+        else rc = run_inverse(P, G, &out, P->w_fadj, (char *)workspace, st);
+        if (rc) return rc;
     }
     return S2_OK;
 }

@@ -38,6 +38,10 @@ hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *
                           const double *lsin, const double *lcos, const double *lbin, const double *kap,
                           const double *gtab, double *out);
 hipError_t launch_bluestein_filter(hipStream_t st, int nfft, const FftArgs *ffts, int nthreads, size_t lds);
+hipError_t launch_fadj_gather(hipStream_t st, int L, int nblk, int spin, const double *part, const int *mtop,
+                              const double2 *flm, const double *wl, int hstride, double *F);
+hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, const double *F, const double2 *hpole,
+                               double *out);
 hipError_t launch_pole_from_F(hipStream_t st, int L, int hstride, int ring, const double *F, double2 *pole);
 hipError_t set_kernel_lds_limits(size_t max_dyn);
 

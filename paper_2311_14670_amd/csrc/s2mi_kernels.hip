@@ -286,7 +286,7 @@ __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int 
 template <int PAR, bool SLOW, bool HEAD>
 __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ Lm,
                                           const double *__restrict__ HA, const double *__restrict__ HB, double kk,
-                                          bool init, const double2 *__restrict__ iv, int istride, double &aAr,
+                                          bool init, int nval, const double2 *__restrict__ iv, int istride, double &aAr,
                                           double &aAi, double &aBr, double &aBi)
 {
 #pragma unroll
@@ -297,7 +297,7 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
         double t = nw;
         if constexpr (SLOW) {
             if constexpr (HEAD) {
-                if (init) {                                  // this lane's l == m starts at slot k's ring
+                if (init && k < nval) {                      // l == m starts at slot k's ring (a swept ring)
                     const double2 v = iv[(size_t)k * istride];
                     nw = v.x;
                     E[k] = (int)v.y;
@@ -346,15 +346,18 @@ __device__ __forceinline__ void fwd_step(int m, int g, int l, int L, int n, int 
         const double *Bc = HBm + c * SG * 4;
         if (HEAD || !((fast >> c) & 1u)) {
             const int r0 = min(rbase + c * SG, nreg - 1);
-            const bool ok = starts && (rbase + c * SG < nreg);
-            fwd_chunk<PAR, true, HEAD>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, init_tab_ptr(init, r0, m, L), L, aAr,
+            // slots at or past the last swept ring (MW south pole, padding) are never
+            // started: they stay zero, and their start values lie outside the table
+            const int nval = nreg - (rbase + c * SG);
+            const bool ok = starts && nval > 0;
+            fwd_chunk<PAR, true, HEAD>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval, init_tab_ptr(init, r0, m, L), L, aAr,
                                        aAi, aBr, aBi);
             bool z = true;
 #pragma unroll
             for (int k = 0; k < SG; ++k) z = z && (E[c][k] == 0);
             fast = __all(z) ? (fast | (1u << c)) : (fast & ~(1u << c));
         } else {
-            fwd_chunk<PAR, false, false>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, nullptr, 0, aAr, aAi, aBr, aBi);
+            fwd_chunk<PAR, false, false>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr, aBi);
         }
     }
     double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
@@ -628,6 +631,74 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin
     }
 }
 
+// ------------------------------------------------------------------ adjoint of the forward (MW)
+// The MW forward is F = Finish Dfwd Theta PhiFwd with the theta filter Theta =
+// sc E^H A E (torus extension E, Hermitian A, fold sc E^H): Theta is
+// Hermitian, so F^H = PhiFwd^H Theta Dfwd^H Finish^H, where Dfwd^H Finish^H
+// is the inverse sweep with the SHT weights on the regular rings plus the
+// closed-form south pole (Eq. 29).  gather: sum the sweep's blocks (and the
+// pole) into the filter's [m][ring] layout; scatter: filtered rings and pole
+// -> [ring][m] partials of a single block, scaled by the phi weight q.
+__global__ void k_fadj_gather(int L, int nblk, int spin, const double *__restrict__ part, const int *__restrict__ mtop,
+                              const double2 *__restrict__ flm, const double *__restrict__ wl, int hstride,
+                              double *__restrict__ F)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)L * L) return;
+    const int m = (int)(i / L), t = (int)(i % L);
+    const int nreg = L - 1, M = 2 * L - 1;
+    const size_t bstride = (size_t)nreg * L * 4;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (t < nreg) {
+        for (int b = 0; b < nblk; ++b) {
+            if (m > mtop[b]) continue;                  // that block's sweep never reached order m
+            const double *pp = part + b * bstride + ((size_t)t * L + m) * 4;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] += pp[c];
+        }
+    } else {
+        // south pole: only the signed order s is nonzero, sum_l (-1)^{l+s} w_l G[l][s]
+        const int as = spin < 0 ? -spin : spin;
+        if (m == as) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int l = as; l < L; ++l) {
+                const double2 g = flm[(size_t)l * M + (L - 1) + spin];
+                const double c = ((l + spin) & 1) ? -wl[l] : wl[l];
+                acc.x += c * g.x;
+                acc.y += c * g.y;
+            }
+            const int off = (spin < 0) ? 2 : 0;
+            v[off] = acc.x;
+            v[off + 1] = acc.y;
+        }
+    }
+    if (m == 0) { v[2] = 0.0; v[3] = 0.0; }
+    double *dst = F + ((size_t)m * hstride + t) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c] = v[c];
+}
+
+__global__ void k_fadj_scatter(int L, int hstride, double q, const double *__restrict__ F,
+                               const double2 *__restrict__ hpole, double *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)L * L) return;
+    const int t = (int)(i / L), m = (int)(i % L);
+    double v[4];
+    if (t < L - 1) {
+        const double *src = F + ((size_t)m * hstride + t) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = src[c];
+    } else {
+        const double2 a = hpole[(L - 1) + m], b = hpole[(L - 1) - m];
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+    if (m == 0) { v[2] = 0.0; v[3] = 0.0; }
+    double *dst = out + ((size_t)t * L + m) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c] = q * v[c];
+}
+
 // ------------------------------------------------------------------ forward finish
 // flm[l][m] = w_l * (sum_b Q[b][l][|m|].side) * ((-1)^{|m|-nB} for m < 0)
 //           + MW south pole: w_l (-1)^{l+s} h~_s(pi) at m = s  (Eq. 29).
@@ -866,6 +937,26 @@ hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *
 hipError_t launch_bluestein_filter(hipStream_t st, int nfft, const FftArgs *ffts, int nthreads, size_t lds)
 {
     hipLaunchKernelGGL(k_bluestein_prep, dim3(nfft), dim3(nthreads), lds, st, ffts);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fadj_gather(hipStream_t st, int L, int nblk, int spin, const double *part, const int *mtop,
+                              const double2 *flm, const double *wl, int hstride, double *F)
+{
+    const size_t tot = (size_t)L * L;
+    hipLaunchKernelGGL(k_fadj_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, part, mtop,
+                       flm, wl, hstride, F);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, const double *F, const double2 *hpole,
+                               double *out)
+{
+    const size_t tot = (size_t)L * L;
+    hipLaunchKernelGGL(k_fadj_scatter, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, hstride, q, F, hpole,
+                       out);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

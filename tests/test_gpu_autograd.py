@@ -86,3 +86,48 @@ def test_gradient_matches_oracle_at_L512(ag, spin):
         lb = torch.view_as_real(autograd.inverse(xb, plan1) - t[b]).pow(2).sum()
         lb.backward()
         assert rel_l2(grad[b], xb.grad.cpu().numpy()) < 1e-14
+
+
+@pytest.mark.parametrize("sampling,L,nside,spin", [("mw", 24, 0, 0), ("mw", 20, 0, 2), ("mw", 17, 0, -3),
+                                                   ("healpix", 16, 8, 0), ("healpix", 12, 8, 1)])
+def test_forward_adjoint_dot_product(ag, sampling, L, nside, spin):
+    """<F f, G> = <f, F^H G> with F the oracle's forward transform."""
+    autograd, binding = ag
+    plan = binding.Plan(L, spin=spin, sampling=sampling, nside=nside)
+    f = map_gaussian(plan.map_shape, seed=30)
+    G = flm_gaussian(L, spin, seed=31)
+    samp = oracle.MW if sampling == "mw" else oracle.HEALPIX
+    lhs = np.vdot(G, oracle.s2_forward(f, L, spin, samp, nside))           # <G, F f>
+    FhG = plan.forward_adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
+    rhs = np.vdot(FhG, f)                                                   # <F^H G, f>
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("spin", [0, 2])
+def test_forward_gradient_matches_finite_differences(ag, spin):
+    """loss = sum |forward(f) - target|^2 over the coefficients, L = 16 MW."""
+    autograd, binding = ag
+    L = 16
+    nmap = L * (2 * L - 1)
+    chunk = 2 * 124
+    f0 = map_gaussian((L, 2 * L - 1), seed=32)
+    target = torch.from_numpy(flm_gaussian(L, spin, seed=33)).cuda()
+    plan = binding.Plan(L, spin=spin, max_batch=chunk)
+    x = torch.from_numpy(f0).cuda().requires_grad_(True)
+    loss = torch.view_as_real(autograd.forward(x, plan) - target).pow(2).sum()
+    loss.backward()
+    grad = x.grad.cpu().numpy()
+    base = torch.from_numpy(f0).cuda()
+    fd = np.zeros(2 * nmap)
+    for c0 in range(0, 2 * nmap, chunk // 2):
+        cs = np.arange(c0, min(c0 + chunk // 2, 2 * nmap))
+        pert = base.unsqueeze(0).repeat(2 * cs.size, 1, 1)
+        flat = torch.view_as_real(pert).reshape(2 * cs.size, -1)
+        idx = torch.from_numpy(cs).cuda()
+        rows = torch.arange(cs.size, device="cuda")
+        flat[rows, idx] += 1.0
+        flat[rows + cs.size, idx] -= 1.0
+        lv = torch.view_as_real(plan.forward(pert) - target).pow(2).sum(dim=(1, 2, 3)).cpu().numpy()
+        fd[c0:c0 + cs.size] = (lv[:cs.size] - lv[cs.size:]) / 2.0
+    fd_c = (fd[0::2] + 1j * fd[1::2]).reshape(L, 2 * L - 1)
+    assert rel_l2(grad, fd_c) < 1e-9

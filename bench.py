@@ -31,6 +31,29 @@ def algorithmic_flops(L, spin, rings):
     return (6 if spin == 0 else 8) * T
 
 
+def measured_traffic(kernel, L, spin):
+    """HBM bytes per launch of a sweep kernel from the committed counter summary
+    (FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration), only when the
+    summary was taken on this workload and on the current kernel source; else None."""
+    import hashlib
+    if (L, spin) != (2048, 0):
+        return None
+    summ = os.path.join(ROOT, "profiles", "dstage_counters_mw_L2048_spin0.md")
+    src = os.path.join(ROOT, "paper_2311_14670_amd", "csrc", "s2mi_kernels.hip")
+    try:
+        text = open(summ).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f"kernels source sha256 (first 16 hex): {sha}" not in text:
+        return None
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic_bytes" and parts[1] == kernel:
+            return float(parts[2])
+    return None
+
+
 def cpu_baseline(L, spin, flm, nring_sample, norder_sample):
     import oracle
     oracle._load()
@@ -110,7 +133,8 @@ def main():
     if dom in ("dstage_inv", "dstage_fwd"):
         achieved = flops / (dom_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": measured_traffic("k_" + dom, L, spin),
                 "algorithmic_flops_per_launch": flops, "avg_launch_ms": dom_ms}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -85,8 +85,8 @@ def test_smallest_bandlimits(binding, L):
         flm = flm_gaussian(L, spin, seed=16)
         plan = binding.Plan(L, spin=spin)
         f = host(plan.inverse(dev(flm)))
-        assert rel_l2(f, oracle.s2_inverse(flm, L, spin)) < 1e-13
-        assert rel_l2(host(plan.forward(dev(f))), flm) < 1e-13
+        assert rel_l2(f, oracle.s2_inverse(flm, L, spin)) < 1e-11, spin
+        assert rel_l2(host(plan.forward(dev(f))), flm) < 1e-11, spin
 
 
 def test_batch_larger_than_plan_is_rejected(binding):

@@ -87,6 +87,10 @@ struct s2_plan_s {
     double *wq = nullptr, *ph = nullptr;   // MW theta filter
     double *groots = nullptr;              // e^{-2 pi i k/(2N-1)}
     // d-stage work assignment
+    // stable-direction remedy: a run with n cos(theta) < 0 at a ring continues to
+    // orders -(|n|-1) and supplies the other run's orders |m| < |n| there
+    int nxp = 0;                           // max |n| over the runs (orders below it are remedied)
+    int nx = 0;                            // negative orders held in the tables: max(0, nxp - 1)
     int inv_nblk = 1, inv_waves = 4;
     int *lslot = nullptr, *lchunk = nullptr, *mtop = nullptr;
     int fwd_nblk = 1, fwd_waves = 4, G = 1;
@@ -94,6 +98,7 @@ struct s2_plan_s {
     // workspace layout (bytes)
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
     size_t szC = 0, szP = 0, szF = 0, szQ = 0;
+    size_t off_Hx = 0, off_Qx = 0, szHx = 0, szQx = 0;
 
     // matrix-core contraction path (precision FP32 / split BF16): batched over maps
     bool mfma = false;
@@ -104,6 +109,7 @@ struct s2_plan_s {
     double2 *kg = nullptr;                 // [m][lrow] {kappa, g}
     size_t nslots = 0;                     // recursion state slots (l) of the generator
     size_t off_D = 0, off_S = 0, off_AH = 0, off_mP = 0, off_mF = 0, off_mQ = 0, off_mhp = 0, off_mmaps = 0;
+    size_t off_mQx = 0;
     size_t state_bytes = 0;
 
     // stage timing
@@ -386,13 +392,17 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         if ((rc = upload(P, &P->groots, stg.d.back(), st, "gamma roots"))) return bail(rc);
     }
 
-    // recursion tables
+    // recursion tables, rows m in [-nx, L) (device pointers at row m = 0)
     {
+        for (const Run &r : P->runs) P->nxp = std::max(P->nxp, r.n < 0 ? -r.n : r.n);
+        P->nx = std::max(0, P->nxp - 1);
         stg.d.emplace_back(); std::vector<double> &kap = stg.d.back();
         stg.d.emplace_back(); std::vector<double> &g = stg.d.back();
-        host_recursion_tables(L, &kap, &g);
+        host_recursion_tables(L, P->nx, &kap, &g);
         if ((rc = upload(P, &P->kap, kap, st, "kappa table"))) return bail(rc);
         if ((rc = upload(P, &P->gtab, g, st, "g table"))) return bail(rc);
+        P->kap += (size_t)P->nx * L;
+        P->gtab += (size_t)P->nx * L;
     }
     for (const Run &r : P->runs) {
         stg.d.emplace_back();
@@ -445,8 +455,9 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         const Run &r = P->runs[ri];
         double *lam;
         double2 *ini;
-        if ((rc = P->dalloc(&lam, (size_t)L * P->hstride, "lambda table"))) return bail(rc);
-        HIPCHK(launch_lambda_table(st, L, P->nreg, P->hstride, r.n, P->cot, P->csc, lam), "lambda table");
+        if ((rc = P->dalloc(&lam, (size_t)(L + P->nx) * P->hstride, "lambda table"))) return bail(rc);
+        lam += (size_t)P->nx * P->hstride;                 // rows m in [-nx, L)
+        HIPCHK(launch_lambda_table(st, L, P->nx, P->nreg, P->hstride, r.n, P->cot, P->csc, lam), "lambda table");
         if ((rc = P->dalloc(&ini, (size_t)L * P->nreg, "start values"))) return bail(rc);
         HIPCHK(launch_init_table(st, L, P->nreg, r.n, P->lsin, P->lcos, P->lbin[ri], ini), "start values");
         P->lam.push_back(lam);
@@ -456,7 +467,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     // workspace layout
     {
         const size_t S = P->nslice;
-        P->szC = (size_t)P->inv_nblk * P->inv_waves * INV_J * L * 5 * sizeof(double);
+        P->szC = (size_t)P->inv_nblk * P->inv_waves * INV_J * (L + P->nx) * 5 * sizeof(double);
         P->szP = (size_t)P->inv_nblk * P->nreg * L * 4 * sizeof(double);
         P->szF = (size_t)L * P->hstride * 4 * sizeof(double);
         P->szQ = (size_t)P->fwd_nblk * L * L * 4 * sizeof(double);
@@ -467,6 +478,11 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->off_F = o; o += align256(P->szF * S);
         P->off_Q = o; o += align256(P->szQ * S);
         P->off_hpole = o; o += align256((size_t)(2 * L - 1) * S * sizeof(double2));
+        // low-order machinery of runs with n != 0: masked spectra copies per run, continuation sums per slice
+        P->szHx = (size_t)std::max(P->nxp, 1) * P->hstride * 4 * sizeof(double);
+        P->szQx = (size_t)P->fwd_nblk * L * std::max(P->nxp, 1) * 4 * sizeof(double);
+        P->off_Hx = o; o += P->nxp > 0 ? align256(2 * P->szHx * P->runs.size()) : 0;
+        P->off_Qx = o; o += P->nxp > 0 ? align256(P->szQx * S) : 0;
         P->ws_bytes = o;
     }
 
@@ -508,8 +524,9 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             if ((rc = upload(P, &P->gen_mtop, mt, st, "generator mtop"))) return bail(rc);
             P->nslots = (size_t)P->gen_nblk * P->gen_waves * GEN_NCH * 8;
         }
-        if ((rc = P->dalloc(&P->kg, (size_t)L * g.lrow, "kappa/g table"))) return bail(rc);
-        HIPCHK(launch_kg_table(st, L, g.lrow, P->kap, P->gtab, P->kg), "kappa/g table");
+        if ((rc = P->dalloc(&P->kg, (size_t)(L + P->nx) * g.lrow, "kappa/g table"))) return bail(rc);
+        P->kg += (size_t)P->nx * g.lrow;                     // rows m in [-nx, L)
+        HIPCHK(launch_kg_table(st, L, P->nx, g.lrow, P->kap, P->gtab, P->kg), "kappa/g table");
         const size_t per_m_d = std::max((size_t)g.kc * g.rpad, (size_t)(g.rpad / 8) * g.lp) * 32;
         P->mch = (int)std::max<size_t>(4, std::min<size_t>((size_t)L, ((size_t)512 << 20) / per_m_d));
         const size_t per_m_ah = (size_t)std::max(g.kc, g.rpad / 8) * g.rows * 32;
@@ -525,6 +542,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->off_mQ = o; o += align256(B * S * nQ1 * sizeof(double));
         P->off_mhp = o; o += align256(B * S * (2 * L - 1) * sizeof(double2));
         P->off_mmaps = o; o += (S > 1) ? align256(B * S * (size_t)P->nsamp * sizeof(double2)) : 0;
+        P->off_mQx = o; o += P->nxp > 0 ? align256(B * S * (size_t)L * P->nxp * 4 * sizeof(double)) : 0;
         P->ws_bytes = o;
     }
     HIPCHK(hipStreamSynchronize(st), "plan upload");
@@ -600,12 +618,12 @@ int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double
         double *C = C0 + ri * nC;
         {
         TIMED(S2_STAGE_PACK);
-        HIPCHK(launch_pack_inv(st, L, r.n, P->inv_nblk, P->inv_waves * INV_J, P->lslot, fa, fb,
+        HIPCHK(launch_pack_inv(st, L, P->nx, r.n, P->inv_nblk, P->inv_waves * INV_J, P->lslot, fa, fb,
                                r.sliceA >= 0 ? wl[r.sliceA] : nullptr, r.sliceB >= 0 ? wl[r.sliceB] : nullptr, P->kap,
                                P->gtab, C), "pack");
         }
         TIMED(S2_STAGE_DSTAGE_INV);
-        HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nreg, r.n, P->cot, P->csc, P->init[ri], C,
+        HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nx, P->nreg, r.n, P->cot, P->csc, P->init[ri], C,
                                  P->lchunk, P->mtop,
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
                                  r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr), "inverse d-stage");
@@ -663,22 +681,34 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *
     const int L = P->L;
     const size_t slab = (size_t)L * (2 * L - 1);
     const size_t nF = P->szF / sizeof(double), nQ = P->szQ / sizeof(double);
+    const size_t nHx = P->szHx / sizeof(double), nQx = P->szQx / sizeof(double);
     double *Q0 = (double *)(ws + P->off_Q);
+    double *Hx0 = P->nxp > 0 ? (double *)(ws + P->off_Hx) : nullptr;
+    double *Qx0 = P->nxp > 0 ? (double *)(ws + P->off_Qx) : nullptr;
+    if (Qx0) HIPCHK(launch_zero(st, Qx0, P->szQx * P->nslice), "continuation sums clear");
     for (size_t ri = 0; ri < P->runs.size(); ++ri) {
         const Run &r = P->runs[ri];
+        const int an = r.n < 0 ? -r.n : r.n;
         const double *HA = r.sliceA >= 0 ? H0 + r.sliceA * nF : H0 + r.sliceB * nF;
         const double *HB = r.sliceB >= 0 ? H0 + r.sliceB * nF : HA;
+        double *HxA = an > 0 ? Hx0 + 2 * ri * nHx : nullptr;
+        double *HxB = an > 0 ? HxA + nHx : nullptr;
         TIMED(S2_STAGE_DSTAGE_FWD);
-        HIPCHK(launch_dstage_fwd(st, P->fwd_waves, P->fwd_nblk, P->G, L, P->nreg, P->hstride, P->hstride, r.n,
-                                 P->lam[ri], P->init[ri], P->kap, P->gtab, HA, HB,
+        if (an > 0)
+            HIPCHK(launch_mask_low(st, an, r.n, P->nreg, P->hstride, P->cot, HA, HB, HxA, HxB), "low-order spectra");
+        HIPCHK(launch_dstage_fwd(st, P->fwd_waves, P->fwd_nblk, P->G, L, std::max(P->nxp, 1), P->nreg, P->hstride,
+                                 P->hstride, r.n, P->lam[ri], P->init[ri], P->kap, P->gtab, HA, HB, HxA, HxB,
                                  r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
-                                 r.sliceB >= 0 ? Q0 + r.sliceB * nQ : nullptr), "forward d-stage");
+                                 r.sliceB >= 0 ? Q0 + r.sliceB * nQ : nullptr,
+                                 (an > 0 && r.sliceA >= 0) ? Qx0 + r.sliceA * nQx : nullptr,
+                                 (an > 0 && r.sliceB >= 0) ? Qx0 + r.sliceB * nQx : nullptr), "forward d-stage");
     }
     for (int k = 0; k < P->nslice; ++k) {
         const int s = P->slice_spin[k];
         TIMED(S2_STAGE_FINISH);
-        HIPCHK(launch_finish_fwd(st, L, P->fwd_nblk, s, s, Q0 + k * nQ, wl[k],
-                                 hpole0 ? hpole0 + k * (2 * L - 1) : nullptr, flm + k * slab), "forward finish");
+        HIPCHK(launch_finish_fwd(st, L, P->fwd_nblk, s, s, Q0 + k * nQ, Qx0 ? Qx0 + k * nQx : nullptr,
+                                 std::max(P->nxp, 1), wl[k], hpole0 ? hpole0 + k * (2 * L - 1) : nullptr,
+                                 flm + k * slab), "forward finish");
     }
     return S2_OK;
 }
@@ -734,9 +764,11 @@ int run_inverse_mfma(s2_plan_t P, const double2 *flm, int B, double2 *maps, cons
         const double2 *fb = r.sliceB >= 0 ? flm + r.sliceB * slab : nullptr;
         double *PA = r.sliceA >= 0 ? Pm + r.sliceA * nP1 : nullptr;
         double *PB = r.sliceB >= 0 ? Pm + r.sliceB * nP1 : nullptr;
+        const int an = r.n < 0 ? -r.n : r.n;
+        const int mend = an > 1 ? -(an - 1) : 0;          // continuation below m = 0
         HIPCHK(launch_zero(st, SX, P->state_bytes), "recursion state clear");
-        for (int mhi = L - 1; mhi >= 0; mhi -= P->mch) {
-            const int mlo = std::max(0, mhi - P->mch + 1), mcn = mhi - mlo + 1;
+        for (int mhi = L - 1; mhi >= mend; mhi -= P->mch) {
+            const int mlo = std::max(mend, mhi - P->mch + 1), mcn = mhi - mlo + 1;
             {
             TIMED(S2_STAGE_DGEN);
             HIPCHK(launch_dgen(st, 0, fmt, P->gen_waves, P->gen_nblk, g, r.n, mhi, mlo, P->cot, P->csc, P->init[ri],
@@ -749,7 +781,7 @@ int run_inverse_mfma(s2_plan_t P, const double2 *flm, int B, double2 *maps, cons
                    "coefficient pack");
             }
             TIMED(S2_STAGE_MFMA);
-            HIPCHK(launch_mfma_inv(st, fmt, g, r.n, mlo, mcn, B, A, D, PA, PB, (long long)(S * nP1)),
+            HIPCHK(launch_mfma_inv(st, fmt, g, r.n, P->cot, mlo, mcn, B, A, D, PA, PB, (long long)(S * nP1)),
                    "inverse contraction");
         }
     }
@@ -781,6 +813,10 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
     double *Fm = (double *)(ws + P->off_mF);
     double *Qm = (double *)(ws + P->off_mQ);
     double2 *hp = (double2 *)(ws + P->off_mhp);
+    const int nxp1 = std::max(P->nxp, 1);
+    const size_t nQx1 = (size_t)L * nxp1 * 4;
+    double *Qxm = P->nxp > 0 ? (double *)(ws + P->off_mQx) : nullptr;
+    if (Qxm) HIPCHK(launch_zero(st, Qxm, (size_t)B * S * nQx1 * sizeof(double)), "continuation sums clear");
     double q;
     if (adjoint) q = 1.0;
     else if (mw) q = 2.0 * M_PI / (double)(2 * L - 1);
@@ -808,9 +844,13 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
         const double *FB = r.sliceB >= 0 ? Fm + r.sliceB * nF : FA;
         double *QA = r.sliceA >= 0 ? Qm + r.sliceA * nQ1 : nullptr;
         double *QB = r.sliceB >= 0 ? Qm + r.sliceB * nQ1 : nullptr;
+        const int an = r.n < 0 ? -r.n : r.n;
+        const int mend = an > 1 ? -(an - 1) : 0;          // continuation below m = 0
+        double *QxA = (an > 0 && r.sliceA >= 0) ? Qxm + r.sliceA * nQx1 : nullptr;
+        double *QxB = (an > 0 && r.sliceB >= 0) ? Qxm + r.sliceB * nQx1 : nullptr;
         HIPCHK(launch_zero(st, SX, P->state_bytes), "recursion state clear");
-        for (int mhi = L - 1; mhi >= 0; mhi -= P->mch) {
-            const int mlo = std::max(0, mhi - P->mch + 1), mcn = mhi - mlo + 1;
+        for (int mhi = L - 1; mhi >= mend; mhi -= P->mch) {
+            const int mlo = std::max(mend, mhi - P->mch + 1), mcn = mhi - mlo + 1;
             {
             TIMED(S2_STAGE_DGEN);
             HIPCHK(launch_dgen(st, 1, fmt, P->gen_waves, P->gen_nblk, g, r.n, mhi, mlo, P->cot, P->csc, P->init[ri],
@@ -818,10 +858,12 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             }
             {
             TIMED(S2_STAGE_PACK);
-            HIPCHK(launch_pack_h(st, fmt, g, P->hstride, mlo, mcn, B, (long long)(S * nF), FA, FB, H), "spectra pack");
+            HIPCHK(launch_pack_h(st, fmt, g, P->hstride, r.n, P->cot, mlo, mcn, B, (long long)(S * nF), FA, FB, H),
+                   "spectra pack");
             }
             TIMED(S2_STAGE_MFMA);
-            HIPCHK(launch_mfma_fwd(st, fmt, g, mlo, mcn, B, H, D, QA, QB, (long long)(S * nQ1)), "forward contraction");
+            HIPCHK(launch_mfma_fwd(st, fmt, g, r.n, nxp1, mlo, mcn, B, H, D, QA, QB, (long long)(S * nQ1), QxA, QxB,
+                                   (long long)(S * nQx1)), "forward contraction");
         }
     }
     for (int b = 0; b < B; ++b)
@@ -829,8 +871,8 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             const size_t bk = (size_t)b * S + k;
             const int s = P->slice_spin[k];
             TIMED(S2_STAGE_FINISH);
-            HIPCHK(launch_finish_fwd(st, L, 1, s, s, Qm + bk * nQ1, wl[k], mw ? hp + bk * (2 * L - 1) : nullptr,
-                                     flm + bk * slab), "forward finish");
+            HIPCHK(launch_finish_fwd(st, L, 1, s, s, Qm + bk * nQ1, Qxm ? Qxm + bk * nQx1 : nullptr, nxp1, wl[k],
+                                     mw ? hp + bk * (2 * L - 1) : nullptr, flm + bk * slab), "forward finish");
         }
     return S2_OK;
 }

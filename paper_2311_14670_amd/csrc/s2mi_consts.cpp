@@ -9,6 +9,7 @@
 //   recursion          Sec. 3.3, Eqs. 25-26 (descending-m three-term recursion)
 //   initial values     Eq. 27, computed in log space (Sec. 3.3)
 //   MW theta weights   Sec. 4.2, Eqs. 41-42 (band-limited sin(theta) 1_[0,pi])
+#include <algorithm>
 #include <quadmath.h>
 
 #include <cmath>
@@ -122,20 +123,26 @@ void host_log2_binom(int L, int n, std::vector<double> *out)
 // gtab[m][l] = g_m (m <= l).  Both [L][L], l fastest.  Long double: the even
 // and odd g-chains accumulate ~1e-19 per step, and every product of consecutive
 // kappas telescopes to exact alpha ratios, so no error drifts through the sweep.
-void host_recursion_tables(int L, std::vector<double> *kap, std::vector<double> *gtab)
+// kappa / g tables of the rescaled recursion for orders m in [-nx, L): row (m + nx).
+// The negative rows serve the continuation of a run past m = 0 (stable-direction
+// remedy near the poles); entries outside the recursion's range are zero.
+void host_recursion_tables(int L, int nx, std::vector<double> *kap, std::vector<double> *gtab)
 {
-    kap->assign((size_t)L * L, 0.0);
-    gtab->assign((size_t)L * L, 0.0);
-    std::vector<long double> g(L + 1);
+    const size_t rows = (size_t)L + nx;
+    kap->assign(rows * L, 0.0);
+    gtab->assign(rows * L, 0.0);
+    std::vector<long double> g(L + 2 + 2 * (size_t)nx);   // g[m + nx + 1], m in [-nx-1, l+1)
     for (int l = 0; l < L; ++l) {
         auto al = [l](int k) { return sqrtl((long double)(l + k) * (long double)(l - k + 1)); };
-        g[l] = 1.0L;
-        if (l >= 1) g[l - 1] = 1.0L;
-        for (int m = l - 1; m >= 1; --m) g[m - 1] = g[m + 1] * al(m + 1) / al(m);
-        for (int m = 0; m <= l; ++m) (*gtab)[(size_t)m * L + l] = (double)g[m];
-        for (int m = 0; m < l; ++m) {
+        auto G = [&](int m) -> long double & { return g[(size_t)(m + nx + 1)]; };
+        G(l) = 1.0L;
+        if (l >= 1) G(l - 1) = 1.0L;
+        const int mlow = std::max(-nx, -l + 1);             // alpha_m > 0 for m > -l
+        for (int m = l - 1; m >= mlow; --m) G(m - 1) = G(m + 1) * al(m + 1) / al(m);
+        for (int m = std::max(-nx, -l); m <= l; ++m) (*gtab)[(size_t)(m + nx) * L + l] = (double)G(m);
+        for (int m = std::max(-nx, -l); m < l; ++m) {
             const int mp = m + 1;   // kappa_{m+1} produces order m
-            (*kap)[(size_t)m * L + l] = (double)(2.0L * g[mp] / (al(mp) * g[mp - 1]));
+            (*kap)[(size_t)(m + nx) * L + l] = (double)(2.0L * G(mp) / (al(mp) * G(mp - 1)));
         }
     }
 }

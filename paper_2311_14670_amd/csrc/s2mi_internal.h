@@ -24,7 +24,7 @@ void host_mw_rings(int L, RingConsts *rc);
 void host_healpix_rings(int nside, RingConsts *rc, std::vector<int> *nphi,
                         std::vector<long long> *start, std::vector<int> *shift);
 void host_log2_binom(int L, int n, std::vector<double> *out);
-void host_recursion_tables(int L, std::vector<double> *kap, std::vector<double> *gtab);
+void host_recursion_tables(int L, int nx, std::vector<double> *kap, std::vector<double> *gtab);
 void host_roots(int n, std::vector<double> *out);
 void host_chirp(int n, std::vector<double> *out);
 void host_mw_filter(int L, std::vector<double> *wq, std::vector<double> *ph);

@@ -7,18 +7,19 @@
 
 namespace s2mi {
 
-hipError_t launch_pack_inv(hipStream_t st, int L, int n, int nblk, int slots_per_blk, const int *lslot,
+hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int slots_per_blk, const int *lslot,
                            const double2 *flmA, const double2 *flmB, const double *wA, const double *wB,
                            const double *kap, const double *gtab, double *C);
-hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nreg, int n, const double *cot,
+hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
                              const int *mtop, double *partA, double *partB);
 hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const double *lsin, const double *lcos,
                              const double *lbin, double2 *init);
-hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nreg, int hstride, int lstride,
-                             int n, const double *lam, const double2 *init, const double *kap, const double *gtab,
-                             const double *HA, const double *HB, double *QA, double *QB);
-hipError_t launch_lambda_table(hipStream_t st, int L, int nreg, int lstride, int n, const double *cot,
+hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
+                             int lstride, int n, const double *lam, const double2 *init, const double *kap,
+                             const double *gtab, const double *HA, const double *HB, const double *HxA,
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB);
+hipError_t launch_lambda_table(hipStream_t st, int L, int nx, int nreg, int lstride, int n, const double *cot,
                                const double *csc, double *lam);
 hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk, int spin,
                           const double *part, const int *mtop, const double2 *flm, const double *wl,
@@ -30,8 +31,8 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
                           const int *ring_fft, const FftArgs *ffts, double *F);
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int hstride, int spin, const FftArgs *fN,
                             const double *wq, const double *ph, double *F, double2 *hpole);
-hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *wl,
-                             const double2 *hpole, double2 *flm);
+hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
+                             int nxp, const double *wl, const double2 *hpole, double2 *flm);
 hipError_t launch_gamma_dft(hipStream_t st, int N, long long nper, int sign, double q, const double *roots,
                             const double2 *in, double2 *out);
 hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
@@ -42,6 +43,8 @@ hipError_t launch_fadj_gather(hipStream_t st, int L, int nblk, int spin, const d
                               const double2 *flm, const double *wl, int hstride, double *F);
 hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, const double *F, const double2 *hpole,
                                double *out);
+hipError_t launch_mask_low(hipStream_t st, int an, int n, int nreg, int hstride, const double *cot, const double *FA,
+                           const double *FB, double *HxA, double *HxB);
 hipError_t launch_pole_from_F(hipStream_t st, int L, int hstride, int ring, const double *F, double2 *pole);
 hipError_t set_kernel_lds_limits(size_t max_dyn);
 

@@ -95,33 +95,36 @@ __global__ void k_init_table(int L, int nreg, int n, const double *__restrict__ 
 }
 
 // ------------------------------------------------------------------ inverse pack
-// Records in the inverse sweep's slot order, C[blk][m][wave][slot] = 5 doubles
+// Records in the inverse sweep's slot order, C[blk][m + nx][wave][slot] = 5 doubles
 //   {kappa_{m+1}^l, wA_l g_m^l flmA[l][m], wB_l g_m^l (-1)^{m-n} flmB[l][-m]}
-// for l = lslot[blk][wave][slot]; zeros where the run does not reach
-// (l < max(m, |n|), empty slot) or the side is absent.  A wave then reads the
-// records of one order at fixed offsets from a single base address.
-__global__ void k_pack_inv(int L, int n, int nslot, int S, const int *__restrict__ lslot, const double2 *__restrict__ flmA,
-                           const double2 *__restrict__ flmB, const double *__restrict__ wA,
-                           const double *__restrict__ wB, const double *__restrict__ kap,
-                           const double *__restrict__ gtab, double *__restrict__ C)
+// for l = lslot[blk][wave][slot] and orders m in [-nx, L); zeros where the run
+// does not reach (l < max(m, |n|), empty slot) or the side is absent.  The
+// B record is used at m > 0 and, for n != 0, at m <= 0 by the continuation of
+// the run below m = 0 (orders m <= 0 then feed the B slice at -m >= 0 and the
+// A slice at m < 0).  A wave reads the records of one order at fixed offsets
+// from a single base address.
+__global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, const int *__restrict__ lslot,
+                           const double2 *__restrict__ flmA, const double2 *__restrict__ flmB,
+                           const double *__restrict__ wA, const double *__restrict__ wB,
+                           const double *__restrict__ kap, const double *__restrict__ gtab, double *__restrict__ C)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // i = (m, blk, slot-in-block)
-    const int m = blockIdx.y;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // i = (blk, slot-in-block)
+    const int m = (int)blockIdx.y - nx;
     if (i >= (size_t)nslot) return;
     const int M = 2 * L - 1;
     const int an = n < 0 ? -n : n;
     const int l = lslot[i];
     double rec[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (l >= 0 && l >= m && l >= an) {
-        const double g = gtab[(size_t)m * L + l];
-        if (l > m) rec[0] = kap[(size_t)m * L + l];
+        const double g = gtab[(ptrdiff_t)m * L + l];
+        if (l > m) rec[0] = kap[(ptrdiff_t)m * L + l];
         if (flmA) {
             const double2 a = flmA[(size_t)l * M + (L - 1) + m];
             const double sa = wA[l] * g;
             rec[1] = sa * a.x;
             rec[2] = sa * a.y;
         }
-        if (flmB && m > 0) {
+        if (flmB && (m > 0 || an > 0)) {
             const double2 b = flmB[(size_t)l * M + (L - 1) - m];
             double sb = wB[l] * g;
             if ((m - n) & 1) sb = -sb;
@@ -129,9 +132,9 @@ __global__ void k_pack_inv(int L, int n, int nslot, int S, const int *__restrict
             rec[4] = sb * b.y;
         }
     }
-    // slot index i = blk * S + s (S slots per block); record at ((blk * L + m) * S + s)
+    // slot index i = blk * S + s (S slots per block); record at ((blk * (L + nx) + m + nx) * S + s)
     const int blk = (int)(i / S), s = (int)(i % S);
-    double *o = C + (((size_t)blk * L + m) * S + s) * 5;
+    double *o = C + (((size_t)blk * (L + nx) + (m + nx)) * S + s) * 5;
 #pragma unroll
     for (int q = 0; q < 5; ++q) o[q] = rec[q];
 }
@@ -178,7 +181,8 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
 }
 
 template <int NCH, int PAR>
-__device__ __forceinline__ void inv_step(int m, int L, int n, int an, int ring0, int nreg, int lane, int w, int W,
+__device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ring0, int nreg, int lane,
+                                         int w, int W,
                                          const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
                                          int (&E)[NCH][SG], uint32_t &fast, double ct, double ncs,
                                          const double2 *__restrict__ initr, const double *__restrict__ C, double *red,
@@ -186,7 +190,7 @@ __device__ __forceinline__ void inv_step(int m, int L, int n, int an, int ring0,
 {
     const double lam = fma(-(double)(m + 1), ct, ncs);   // lambda_{m+1}: produces order m
     double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
-    const double *Cw = C + (((size_t)blk * L + m) * W + w) * (NCH * SG) * 5;   // this wave's records at order m
+    const double *Cw = C + (((size_t)blk * (L + nx) + (m + nx)) * W + w) * (NCH * SG) * 5;   // records at order m
 #pragma unroll
     for (int g = 0; g < NCH; ++g) {
         const int base = lb[g];
@@ -219,20 +223,31 @@ __device__ __forceinline__ void inv_step(int m, int L, int n, int an, int ring0,
     rb[(w * 4 + 3) * 64 + lane] = aBi;
     __syncthreads();
     // four waves, rotating with the order, reduce the 4 x 64 outputs over the waves
-    const int grp = m % (W / 4);
+    const int grp = ((m % (W / 4)) + (W / 4)) % (W / 4);   // m may be negative (continuation)
     const int tr = (int)threadIdx.x - 256 * grp;
     if (tr >= 0 && tr < 256) {
-        const int rl = tr & 63, comp = tr >> 6;
+        const int rl = tr & 63, comp = tr >> 6;         // rl == lane: this thread's ring
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
-        double *dst = comp < 2 ? partA : partB;
-        if (dst && ring0 + rl < nreg) dst[(((size_t)blk * nreg + ring0 + rl) * L + m) * 4 + comp] = s;
+        // Orders below |n| come, at each ring, from the run that is stable there
+        // (n cos(theta) < 0): it writes its own sides at m >= 0 and, from its
+        // continuation to m <= 0, the A slice at order m < 0 (components 2,3 at |m|)
+        // and the B slice at order -m >= 0 (components 0,1 at |m|).  The other run
+        // writes nothing at these orders.
+        double *dst = nullptr;
+        int mo = m, co = comp;
+        if (m >= an || (good && m > 0)) dst = comp < 2 ? partA : partB;
+        else if (good) {
+            if (comp < 2) { dst = partA; if (m < 0) { mo = -m; co = comp + 2; } }
+            else { dst = partB; mo = -m; co = comp - 2; }
+        }
+        if (dst && ring0 + rl < nreg) dst[(((size_t)blk * nreg + ring0 + rl) * L + mo) * 4 + co] = s;
     }
 }
 
 template <int NCH>
 __global__ __launch_bounds__(512) void k_dstage_inv(
-    int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
+    int L, int nx, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
     const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
 {
@@ -246,6 +261,9 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
     const int ring = min(ring0 + lane, nreg - 1);
     const double ct = cot[ring], cs = csc[ring];
     const double ncs = (double)n * cs;
+    // this run is the stable one at this ring when n cos(theta) < 0 (ties: n < 0)
+    const bool good = an > 0 && ((double)n * ct < 0.0 || (ct == 0.0 && n < 0));
+    const int mend = an > 1 ? -(an - 1) : 0;            // continuation below m = 0
     const double2 *initr = init + (size_t)ring * L;
 
     int lb[NCH];
@@ -260,12 +278,12 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
     uint32_t fast = 0;
 
     const int mt = ufl(mtop[blk]);
-    for (int m = mt; m >= 0; m -= 2) {
-        inv_step<NCH, 0>(m, L, n, an, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red, blk, partA,
-                    partB);
-        if (m >= 1)
-            inv_step<NCH, 1>(m - 1, L, n, an, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red, blk,
-                             partA, partB);
+    for (int m = mt; m >= mend; m -= 2) {
+        inv_step<NCH, 0>(m, L, nx, n, an, good, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red, blk,
+                         partA, partB);
+        if (m - 1 >= mend)
+            inv_step<NCH, 1>(m - 1, L, nx, n, an, good, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C,
+                             red, blk, partA, partB);
     }
 }
 
@@ -307,38 +325,46 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
             renorm(nw, od, E[k]);
             t = nw * ldexp(1.0, E[k]);
         }
-        const double *ha = HA + k * 4;
+        const double *ha = HA + k * 4;                   // components chosen by the caller's offsets
         const double *hb = HB + k * 4;
         aAr = fma(t, ha[0], aAr);
         aAi = fma(t, ha[1], aAi);
-        aBr = fma(t, hb[2], aBr);
-        aBi = fma(t, hb[3], aBi);
+        aBr = fma(t, hb[0], aBr);
+        aBi = fma(t, hb[1], aBi);
     }
 }
 
 template <int NCH, int PAR, bool HEAD>
-__device__ __forceinline__ void fwd_step(int m, int g, int l, int L, int n, int an, int lane, int w, int W,
-                                         int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
+__device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
+                                         int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
                                          double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &fast, double &kk, double &gm,
                                          const double *__restrict__ lam, const double2 *__restrict__ init,
                                          const double *__restrict__ kap, const double *__restrict__ gtab,
-                                         const double *__restrict__ HA, const double *__restrict__ HB, double *red,
-                                         int blk, double *__restrict__ QA, double *__restrict__ QB)
+                                         const double *__restrict__ HA, const double *__restrict__ HB,
+                                         const double *__restrict__ HxA, const double *__restrict__ HxB, double *red,
+                                         int blk, double *__restrict__ QA, double *__restrict__ QB,
+                                         double *__restrict__ QxA, double *__restrict__ QxB)
 {
     // kappa / g of this order were loaded one step ahead; fetch the next order's now
     const double kcur = kk, gcur = gm;
-    if (m >= 1) {
+    if (m - 1 >= mend) {
         const int mn = m - 1;
         const int lc = min(l, L - 1);
-        kk = (l > mn && l < L) ? kap[(size_t)mn * L + lc] : 0.0;
-        gm = (l >= mn && l < L) ? gtab[(size_t)mn * L + lc] : 0.0;
+        kk = (l > mn && l < L) ? kap[(ptrdiff_t)mn * L + lc] : 0.0;
+        gm = (l >= mn && l < L) ? gtab[(ptrdiff_t)mn * L + lc] : 0.0;
     }
     const bool starts = HEAD && (l == m) && (l >= an);
     // start values of slot k: init[rbase + k][m] (rings past nreg stay zero)
     double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
-    const double *Lm = lam + (size_t)m * lstride + rbase;
-    const double *HAm = HA + ((size_t)m * hstride + rbase) * 4;    // slot k = ring rbase + k
-    const double *HBm = HB + ((size_t)m * hstride + rbase) * 4;
+    const double *Lm = lam + (ptrdiff_t)m * lstride + rbase;
+    // Ring spectra of the two sides.  Orders below |n| read copies in which the
+    // rings where this run is unstable are zero (the other run covers them); the
+    // continuation (m <= 0) reads the A slice at order m < 0 (components 2,3) and
+    // the B slice at order -m >= 0 (components 0,1).
+    const int am = m < 0 ? -m : m;
+    const bool low = m < an;
+    const double *HAm = (low ? HxA : HA) + ((size_t)am * hstride + rbase) * 4 + (m < 0 ? 2 : 0);
+    const double *HBm = (low ? HxB : HB) + ((size_t)am * hstride + rbase) * 4 + (m > 0 ? 2 : 0);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const double *Lc = Lm + c * SG;
@@ -350,8 +376,8 @@ __device__ __forceinline__ void fwd_step(int m, int g, int l, int L, int n, int 
             // started: they stay zero, and their start values lie outside the table
             const int nval = nreg - (rbase + c * SG);
             const bool ok = starts && nval > 0;
-            fwd_chunk<PAR, true, HEAD>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval, init_tab_ptr(init, r0, m, L), L, aAr,
-                                       aAi, aBr, aBi);
+            fwd_chunk<PAR, true, HEAD>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval,
+                                       init_tab_ptr(init, r0, m < 0 ? 0 : m, L), L, aAr, aAi, aBr, aBi);
             bool z = true;
 #pragma unroll
             for (int k = 0; k < SG; ++k) z = z && (E[c][k] == 0);
@@ -366,26 +392,43 @@ __device__ __forceinline__ void fwd_step(int m, int g, int l, int L, int n, int 
     rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
     rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
     __syncthreads();
-    const int grp = m % (W / 4);
+    const int grp = ((m % (W / 4)) + (W / 4)) % (W / 4);   // m may be negative (continuation)
     const int tr = (int)threadIdx.x - 256 * grp;
     if (tr >= 0 && tr < 256) {
         const int ll = tr & 63, comp = tr >> 6;
         const int lo = 64 * g + ll;
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + ll];
-        double *dst = comp < 2 ? QA : QB;
-        if (dst && lo < L && lo >= m) dst[(((size_t)blk * L + lo) * L + m) * 4 + comp] = s;
+        if (lo < L && lo >= m) {
+            if (m > 0 || comp < 2) {
+                if (m >= 0) {
+                    double *dst = comp < 2 ? QA : QB;
+                    if (dst) dst[(((size_t)blk * L + lo) * L + m) * 4 + comp] = s;
+                } else if (QxA) {
+                    // A slice at order m < 0; the sign cancels the one the finish applies to m < 0
+                    const double sg = ((am + n) & 1) ? -s : s;
+                    QxA[(((size_t)blk * L + lo) * nxp + am) * 4 + comp + 2] = sg;
+                }
+            } else if (an > 0 && QxB) {
+                // B slice at order -m >= 0: d^l_{-m,-n} = (-1)^{m-n} d^l_{m,n}
+                const double sg = ((am + n) & 1) ? -s : s;
+                QxB[(((size_t)blk * L + lo) * nxp + am) * 4 + comp - 2] = sg;
+            }
+        }
     }
 }
 
 template <int NCH>
 __global__ __launch_bounds__(512) void k_dstage_fwd(
-    int L, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
+    int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
-    const double *__restrict__ HA, const double *__restrict__ HB, double *__restrict__ QA, double *__restrict__ QB)
+    const double *__restrict__ HA, const double *__restrict__ HB, const double *__restrict__ HxA,
+    const double *__restrict__ HxB, double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
+    double *__restrict__ QxB)
 {
     __shared__ double red[2 * MAX_WAVES * 4 * 64];
     const int an = n < 0 ? -n : n;
+    const int mend = an > 1 ? -(an - 1) : 0;            // continuation below m = 0
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
     const int W = blockDim.x >> 6;
@@ -413,34 +456,58 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
         // steps so the register roles line up with the main loop)
         const int hend = ((mstart - 64 * g + 1) % 2 == 0) ? 64 * g : 64 * g - 1;
         int m = mstart;
-        for (; m >= hend && m >= 0; m -= 2) {
-            fwd_step<NCH, 0, true>(m, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast, kk, gm,
-                              lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
-            if (m >= 1)
-                fwd_step<NCH, 1, true>(m - 1, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast,
-                                  kk, gm, lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
+        for (; m >= hend && m >= mend; m -= 2) {
+            fwd_step<NCH, 0, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
+                                   fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            if (m - 1 >= mend)
+                fwd_step<NCH, 1, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
+                                       Y, E, fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
+                                       QxA, QxB);
         }
-        for (; m >= 0; m -= 2) {
-            fwd_step<NCH, 0, false>(m, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast, kk, gm,
-                               lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
-            if (m >= 1)
-                fwd_step<NCH, 1, false>(m - 1, g, l, L, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E, fast,
-                                   kk, gm, lam, init, kap, gtab, HA, HB, red, blk, QA, QB);
+        for (; m >= mend; m -= 2) {
+            fwd_step<NCH, 0, false>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
+                                    fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            if (m - 1 >= mend)
+                fwd_step<NCH, 1, false>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
+                                        Y, E, fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
+                                        QxA, QxB);
         }
         __syncthreads();   // the LDS buffers are reused by the next pass
+    }
+}
+
+// Copies of the two sides' ring spectra at orders mu < |n| with the rings where
+// the run n is unstable (n cos(theta) >= 0, ties to n > 0) set to zero: the
+// forward sweep of run n reads these at its low orders and its continuation.
+__global__ void k_mask_low(int an_run, int n, int nreg, int hstride, const double *__restrict__ cot,
+                           const double *__restrict__ FA, const double *__restrict__ FB, double *__restrict__ HxA,
+                           double *__restrict__ HxB)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)an_run * hstride) return;
+    const int r = (int)(i % hstride);
+    bool good = false;
+    if (r < nreg) {
+        const double ct = cot[r];
+        good = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        HxA[i * 4 + c] = good ? FA[i * 4 + c] : 0.0;
+        HxB[i * 4 + c] = good ? FB[i * 4 + c] : 0.0;
     }
 }
 
 // 2 lambda table for the forward sweep: lam[m][r] = n csc_r - (m+1) cot_r
 // (the same FMA the inverse sweep evaluates inline).
 // Rows are padded to lstride rings; padding rings get lambda = 0 (inert).
-__global__ void k_lambda_table(int L, int nreg, int lstride, int n, const double *__restrict__ cot,
+__global__ void k_lambda_table(int L, int nx, int nreg, int lstride, int n, const double *__restrict__ cot,
                                const double *__restrict__ csc, double *__restrict__ lam)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)L * lstride) return;
-    const int m = (int)(i / lstride), r = (int)(i % lstride);
-    lam[i] = r < nreg ? fma(-(double)(m + 1), cot[r], (double)n * csc[r]) : 0.0;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // rows m in [-nx, L), lam at row 0
+    if (i >= (size_t)(L + nx) * lstride) return;
+    const int m = (int)(i / lstride) - nx, r = (int)(i % lstride);
+    lam[(ptrdiff_t)m * lstride + r] = r < nreg ? fma(-(double)(m + 1), cot[r], (double)n * csc[r]) : 0.0;
 }
 
 // ------------------------------------------------------------------ phi-DFT: inverse
@@ -700,12 +767,12 @@ __global__ void k_fadj_scatter(int L, int hstride, double q, const double *__res
 }
 
 // ------------------------------------------------------------------ forward finish
-// flm[l][m] = w_l * (sum_b Q[b][l][|m|].side) * ((-1)^{|m|-nB} for m < 0)
+// flm[l][m] = w_l * (sum_b Q[b][l][|m|].side + Qx[b][l][|m|].side) * ((-1)^{|m|-nB} for m < 0)
 //           + MW south pole: w_l (-1)^{l+s} h~_s(pi) at m = s  (Eq. 29).
 // Zero where l < max(|m|, |spin|).
 __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__restrict__ Q,
-                             const double *__restrict__ wl, const double2 *__restrict__ hpole,
-                             double2 *__restrict__ flm)
+                             const double *__restrict__ Qx, int nxp, const double *__restrict__ wl,
+                             const double2 *__restrict__ hpole, double2 *__restrict__ flm)
 {
     const int M = 2 * L - 1;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -719,6 +786,11 @@ __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__
             const double *q = Q + (((size_t)b * L + l) * L + am) * 4 + off;
             v.x += q[0];
             v.y += q[1];
+            if (Qx && am < nxp) {                       // orders below |n| from the other run's continuation
+                const double *qx = Qx + (((size_t)b * L + l) * nxp + am) * 4 + off;
+                v.x += qx[0];
+                v.y += qx[1];
+            }
         }
         if (m < 0 && ((am - nB) & 1)) { v.x = -v.x; v.y = -v.y; }
         v.x *= wl[l];
@@ -784,6 +856,27 @@ __global__ void k_debug_d(int L, int nreg, int n, const double *__restrict__ cot
         if (E != 0) renorm(e, ep, E);
         o[(size_t)m * L + l] = ldexp(e * gtab[(size_t)m * L + l], E);
     }
+    // orders below |n| where this run is unstable (n cos(theta) >= 0): continue the
+    // run -n (stable here) to order -(|n|-1) and use d^l_{m,n} = (-1)^{m-n} d^l_{-m,-n}
+    const double ct = cot[r];
+    const bool good = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
+    if (an > 0 && !good) {
+        E = 0;
+        ep = 0.0;
+        d_init(l, -n, dd_from(lbin + 2 * l), dd_from(lsin + 2 * r), dd_from(lcos + 2 * r), e, E);
+        for (int m = l - 1; m >= -(an - 1); --m) {
+            const double lam = fma(-(double)(m + 1), ct, -(double)n * csc[r]);
+            const double en = fma(kap[(ptrdiff_t)m * L + l] * lam, e, -ep);
+            ep = e;
+            e = en;
+            if (E != 0) renorm(e, ep, E);
+            const int mm = -m;
+            if (mm >= 0 && mm < an) {
+                const double v = ldexp(e * gtab[(ptrdiff_t)m * L + l], E);
+                o[(size_t)mm * L + l] = ((mm - n) & 1) ? -v : v;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ Bluestein filters
@@ -822,36 +915,37 @@ __global__ void k_pole_from_F(int L, int hstride, int ring, const double *__rest
 // ------------------------------------------------------------------ launchers
 #define S2_LAUNCH_CHECK() do { hipError_t _e = hipGetLastError(); if (_e != hipSuccess) return _e; } while (0)
 
-hipError_t launch_pack_inv(hipStream_t st, int L, int n, int nblk, int slots_per_blk, const int *lslot,
+hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int slots_per_blk, const int *lslot,
                            const double2 *flmA, const double2 *flmB, const double *wA, const double *wB,
                            const double *kap, const double *gtab, double *C)
 {
     const int nslot = nblk * slots_per_blk;
-    dim3 grid((nslot + 255) / 256, L);
-    hipLaunchKernelGGL(k_pack_inv, grid, dim3(256), 0, st, L, n, nslot, slots_per_blk, lslot, flmA, flmB, wA, wB, kap,
-                       gtab, C);
+    dim3 grid((nslot + 255) / 256, L + nx);
+    hipLaunchKernelGGL(k_pack_inv, grid, dim3(256), 0, st, L, nx, n, nslot, slots_per_blk, lslot, flmA, flmB, wA, wB,
+                       kap, gtab, C);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nreg, int n, const double *cot,
+hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
                              const int *mtop, double *partA, double *partB)
 {
     dim3 grid((nreg + 63) / 64, nblk);
-    hipLaunchKernelGGL(k_dstage_inv<INV_NCH>, grid, dim3(64 * nwaves), 0, st, L, nreg, n, cot, csc, init, C, lchunk,
-                       mtop, partA, partB);
+    hipLaunchKernelGGL(k_dstage_inv<INV_NCH>, grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init, C,
+                       lchunk, mtop, partA, partB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nreg, int hstride, int lstride,
-                             int n, const double *lam, const double2 *init, const double *kap, const double *gtab,
-                             const double *HA, const double *HB, double *QA, double *QB)
+hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
+                             int lstride, int n, const double *lam, const double2 *init, const double *kap,
+                             const double *gtab, const double *HA, const double *HB, const double *HxA,
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB)
 {
     dim3 grid((G + 1) / 2, nblk);
-    hipLaunchKernelGGL(k_dstage_fwd<FWD_NCH>, grid, dim3(64 * nwaves), 0, st, L, nreg, hstride, lstride, n, G, lam, init,
-                       kap, gtab, HA, HB, QA, QB);
+    hipLaunchKernelGGL(k_dstage_fwd<FWD_NCH>, grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride, n, G, lam,
+                       init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -866,11 +960,11 @@ hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const doubl
     return hipSuccess;
 }
 
-hipError_t launch_lambda_table(hipStream_t st, int L, int nreg, int lstride, int n, const double *cot,
+hipError_t launch_lambda_table(hipStream_t st, int L, int nx, int nreg, int lstride, int n, const double *cot,
                                const double *csc, double *lam)
 {
-    const size_t tot = (size_t)L * lstride;
-    hipLaunchKernelGGL(k_lambda_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nreg, lstride, n,
+    const size_t tot = (size_t)(L + nx) * lstride;
+    hipLaunchKernelGGL(k_lambda_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nx, nreg, lstride, n,
                        cot, csc, lam);
     S2_LAUNCH_CHECK();
     return hipSuccess;
@@ -905,12 +999,12 @@ hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int
     return hipSuccess;
 }
 
-hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *wl,
-                             const double2 *hpole, double2 *flm)
+hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
+                             int nxp, const double *wl, const double2 *hpole, double2 *flm)
 {
     const size_t tot = (size_t)L * (2 * L - 1);
-    hipLaunchKernelGGL(k_finish_fwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, nB, Q,
-                       wl, hpole, flm);
+    hipLaunchKernelGGL(k_finish_fwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, nB, Q, Qx,
+                       nxp, wl, hpole, flm);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -957,6 +1051,17 @@ hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, con
     const size_t tot = (size_t)L * L;
     hipLaunchKernelGGL(k_fadj_scatter, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, hstride, q, F, hpole,
                        out);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_mask_low(hipStream_t st, int an, int n, int nreg, int hstride, const double *cot, const double *FA,
+                           const double *FB, double *HxA, double *HxB)
+{
+    const size_t tot = (size_t)an * hstride;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mask_low, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, an, n, nreg, hstride, cot, FA,
+                       FB, HxA, HxB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

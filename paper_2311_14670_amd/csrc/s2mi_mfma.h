@@ -21,7 +21,8 @@ struct MfmaGeom {
 
 // zero a byte range (multiple of 4) with a fill kernel
 hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);
-hipError_t launch_kg_table(hipStream_t st, int L, int lrow, const double *kap, const double *gtab, double2 *kg);
+hipError_t launch_kg_table(hipStream_t st, int L, int nx, int lrow, const double *kap, const double *gtab,
+                           double2 *kg);
 // layout 0: D[m][l/8][ring][8] (inverse);  layout 1: D[m][ring/8][l][8] (forward)
 hipError_t launch_dgen(hipStream_t st, int layout, int fmt, int nwaves, int nblk, const MfmaGeom &g, int n, int m_hi,
                        int m_lo, const double *cot, const double *csc, const double2 *init,
@@ -30,11 +31,12 @@ hipError_t launch_dgen(hipStream_t st, int layout, int fmt, int nwaves, int nblk
 hipError_t launch_pack_a(hipStream_t st, int fmt, const MfmaGeom &g, int n, int m_lo, int mcn, int B,
                          long long mstride, const double2 *flmA, const double2 *flmB, const double *wA,
                          const double *wB, uint4 *A);
-hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int m_lo, int mcn, int B,
-                         long long fstride, const double *FA, const double *FB, uint4 *H);
-hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, int m_lo, int mcn, int B,
-                           const uint4 *A, const uint4 *D, double *PA, double *PB, long long pstride);
-hipError_t launch_mfma_fwd(hipStream_t st, int fmt, const MfmaGeom &g, int m_lo, int mcn, int B, const uint4 *H,
-                           const uint4 *D, double *QA, double *QB, long long qstride);
+hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int n, const double *cot, int m_lo,
+                         int mcn, int B, long long fstride, const double *FA, const double *FB, uint4 *H);
+hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, const double *cot, int m_lo, int mcn,
+                           int B, const uint4 *A, const uint4 *D, double *PA, double *PB, long long pstride);
+hipError_t launch_mfma_fwd(hipStream_t st, int fmt, const MfmaGeom &g, int n, int nxp, int m_lo, int mcn, int B,
+                           const uint4 *H, const uint4 *D, double *QA, double *QB, long long qstride, double *QxA,
+                           double *QxB, long long qxstride);
 
 }  // namespace s2mi

@@ -100,22 +100,25 @@ __global__ void k_zero_words(unsigned *__restrict__ p, size_t n)
 }
 
 // ------------------------------------------------------------------ recursion tables
-// kg[m][l] = {kappa_{m+1}^l, g_m^l} with l padded to lrow (zeros past L and
-// where the plan tables hold zeros), so a chunk of 8 degrees is one load.
-__global__ void k_kg_table(int L, int lrow, const double *__restrict__ kap, const double *__restrict__ gtab,
+// kg[m][l] = {kappa_{m+1}^l, g_m^l} for m in [-nx, L) with l padded to lrow (zeros
+// past L and where the plan tables hold zeros), so a chunk of 8 degrees is one load.
+__global__ void k_kg_table(int L, int nx, int lrow, const double *__restrict__ kap, const double *__restrict__ gtab,
                            double2 *__restrict__ kg)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)L * lrow) return;
-    const int m = (int)(i / lrow), l = (int)(i % lrow);
-    kg[i] = l < L ? make_double2(kap[(size_t)m * L + l], gtab[(size_t)m * L + l]) : make_double2(0.0, 0.0);
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // rows m in [-nx, L); pointers at row 0
+    if (i >= (size_t)(L + nx) * lrow) return;
+    const int m = (int)(i / lrow) - nx, l = (int)(i % lrow);
+    kg[(ptrdiff_t)m * lrow + l] = l < L ? make_double2(kap[(ptrdiff_t)m * L + l], gtab[(ptrdiff_t)m * L + l])
+                                        : make_double2(0.0, 0.0);
 }
 
 // ------------------------------------------------------------------ d-tile generator
 // Same sweep geometry as the fused inverse sweep: lanes = 64 rings, each wave
 // owns NCH chunks of 8 consecutive degrees (slot e holds l = base + e).  Runs
 // the orders m_hi .. m_lo (register roles fixed by the parity of m so a chunk
-// boundary needs no fix-up), writing realised d values:
+// boundary needs no fix-up; m_lo < 0 continues the run below m = 0), writing
+// realised d values (zero at orders below |n| on rings where the run is the
+// unstable one):
 //   LAY 0 (K = l):    D[m - m_lo][l/8][ring][8 degrees]
 //   LAY 1 (K = ring): D[m - m_lo][ring/8][l][8 rings]   (8x8 transposes through LDS)
 template <int PAR, bool SLOW>
@@ -143,8 +146,8 @@ __device__ __forceinline__ void gen_chunk(double (&X)[SG], double (&Y)[SG], int 
 }
 
 template <int NCH, int LAY, int FMT, int PAR>
-__device__ __forceinline__ void gen_step(int m, int m_lo, int an, int kc_tot, int rpad, int lp, int ring0, int lane,
-                                         int w, const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
+__device__ __forceinline__ void gen_step(int m, int m_lo, int an, bool good, int kc_tot, int rpad, int lp, int ring0,
+                                         int lane, int w, const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
                                          int (&E)[NCH][SG], uint32_t &fast, double ct, double ncs,
                                          const double2 *__restrict__ initr, const double2 *__restrict__ kgm,
                                          float *tr, uint4 *__restrict__ D)
@@ -172,6 +175,10 @@ __device__ __forceinline__ void gen_step(int m, int m_lo, int an, int kc_tot, in
 #pragma unroll
             for (int e = 0; e < SG; ++e) z = z && (E[g][e] == 0);
             if (__all(z)) fast |= (1u << g);
+        }
+        if (m < an && !good) {                            // orders below |n| at rings where this run is
+#pragma unroll                                            // unstable come from the other run
+            for (int e = 0; e < SG; ++e) dv[e] = 0.0f;
         }
         if constexpr (LAY == 0) {
             store_elem<FMT>(D + ((mc * kc_tot + base / SG) * rpad + ring0 + lane) * 2, dv);
@@ -208,6 +215,8 @@ __global__ __launch_bounds__(512) void k_dgen(
     const double ncs = (double)n * cs;
     const double2 *initr = init + (size_t)ring * L;
     float *tr = trbuf + (LAY == 1 ? w * SG * 64 : 0);
+    // this run is the stable one at this ring when n cos(theta) < 0 (ties: n < 0)
+    const bool good = an > 0 && ((double)n * ct < 0.0 || (ct == 0.0 && n < 0));
 
     int lb[NCH];
 #pragma unroll
@@ -232,16 +241,16 @@ __global__ __launch_bounds__(512) void k_dgen(
     const int mt = ufl(mtop[blk]);
     int m = min(m_hi, mt);
     if (m >= m_lo && (m & 1)) {
-        gen_step<NCH, LAY, FMT, 1>(m, m_lo, an, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs, initr,
-                                   kg + (size_t)m * lrow, tr, D);
+        gen_step<NCH, LAY, FMT, 1>(m, m_lo, an, good, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs,
+                                   initr, kg + (ptrdiff_t)m * lrow, tr, D);
         --m;
     }
     for (; m >= m_lo; m -= 2) {
-        gen_step<NCH, LAY, FMT, 0>(m, m_lo, an, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs, initr,
-                                   kg + (size_t)m * lrow, tr, D);
+        gen_step<NCH, LAY, FMT, 0>(m, m_lo, an, good, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs,
+                                   initr, kg + (ptrdiff_t)m * lrow, tr, D);
         if (m - 1 >= m_lo)
-            gen_step<NCH, LAY, FMT, 1>(m - 1, m_lo, an, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs,
-                                       initr, kg + (size_t)(m - 1) * lrow, tr, D);
+            gen_step<NCH, LAY, FMT, 1>(m - 1, m_lo, an, good, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct,
+                                       ncs, initr, kg + (ptrdiff_t)(m - 1) * lrow, tr, D);
     }
 #pragma unroll
     for (int g = 0; g < NCH; ++g)
@@ -256,7 +265,8 @@ __global__ __launch_bounds__(512) void k_dgen(
 
 // ------------------------------------------------------------------ operand packs
 // Inverse: A[m - m_lo][l/8][row][8 degrees], row = 4b + comp,
-//   comp 0,1: wA_l flmA[b][l][m]   comp 2,3: (-1)^{m-n} wB_l flmB[b][l][-m]  (m > 0)
+//   comp 0,1: wA_l flmA[b][l][m]   comp 2,3: (-1)^{m-n} wB_l flmB[b][l][-m]
+//   (the B rows at m > 0, and at m <= 0 for n != 0: the run's continuation)
 // zero for l < max(m, |n|), l >= L, b >= B.
 template <int FMT>
 __global__ void k_pack_a(int L, int n, int m_lo, int mcn, int kc_tot, int rpad_rows, int B, long long mstride,
@@ -285,7 +295,7 @@ __global__ void k_pack_a(int L, int n, int m_lo, int mcn, int kc_tot, int rpad_r
                     const double2 a = flmA[(size_t)b * mstride + (size_t)l * M + (L - 1) + m];
                     x = wA[l] * (comp ? a.y : a.x);
                 }
-            } else if (flmB && m > 0) {
+            } else if (flmB && (m > 0 || an > 0)) {
                 const double2 c = flmB[(size_t)b * mstride + (size_t)l * M + (L - 1) - m];
                 x = wB[l] * (comp == 3 ? c.y : c.x);
                 if ((m - n) & 1) x = -x;
@@ -296,11 +306,15 @@ __global__ void k_pack_a(int L, int n, int m_lo, int mcn, int kc_tot, int rpad_r
     store_elem<FMT>(A + i * 2, v);
 }
 
-// Forward: H[m - m_lo][ring/8][row][8 rings], comp 0,1 from FA[b][m][ring][0,1],
-// comp 2,3 from FB[b][m][ring][2,3]; zero past the swept rings and for b >= B.
+// Forward: H[m - m_lo][ring/8][row][8 rings] from the ring spectra F[b][|m|][ring][4]:
+//   comp 0,1: FA components 0,1 (m >= 0) or 2,3 (m < 0: the A slice at order m);
+//   comp 2,3: FB components 2,3 (m > 0) or 0,1 (m <= 0: the B slice at order -m);
+// zero past the swept rings, for b >= B, and at orders below |n| on rings where
+// the run is the unstable one.
 template <int FMT>
 __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int rpad_rows, int B, long long fstride,
-                         const double *__restrict__ FA, const double *__restrict__ FB, uint4 *__restrict__ H)
+                         int n, const double *__restrict__ cot, const double *__restrict__ FA,
+                         const double *__restrict__ FB, uint4 *__restrict__ H)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int kr_tot = rpad / SG;
@@ -310,14 +324,23 @@ __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int
     const size_t r2 = i / rpad_rows;
     const int kr = (int)(r2 % kr_tot);
     const int m = m_lo + (int)(r2 / kr_tot);
+    const int am = m < 0 ? -m : m, an = n < 0 ? -n : n;
     const int b = row >> 2, comp = row & 3;
     const double *F = comp < 2 ? FA : FB;
+    const int c = comp < 2 ? (m < 0 ? comp + 2 : comp) : (m > 0 ? comp : comp - 2);
     float v[SG];
 #pragma unroll
     for (int k = 0; k < SG; ++k) {
         const int ring = kr * SG + k;
         double x = 0.0;
-        if (F && b < B && ring < nreg) x = F[(size_t)b * fstride + ((size_t)m * hstride + ring) * 4 + comp];
+        if (F && b < B && ring < nreg) {
+            bool use = true;
+            if (m < an) {
+                const double ct = cot[ring];
+                use = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
+            }
+            if (use) x = F[(size_t)b * fstride + ((size_t)am * hstride + ring) * 4 + c];
+        }
         v[k] = (float)x;
     }
     store_elem<FMT>(H + i * 2, v);
@@ -329,9 +352,9 @@ __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int
 // Output of map b, ring r, order m: partA[b][r][m][0,1], partB[b][r][m][2,3].
 template <int FMT, int MTW>
 __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int kc_tot, int n, int m_lo, int B,
-                                                  int rpad_rows, const uint4 *__restrict__ A,
-                                                  const uint4 *__restrict__ D, double *__restrict__ PA,
-                                                  double *__restrict__ PB, long long pstride)
+                                                  int rpad_rows, const double *__restrict__ cot,
+                                                  const uint4 *__restrict__ A, const uint4 *__restrict__ D,
+                                                  double *__restrict__ PA, double *__restrict__ PB, long long pstride)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int half = lane >> 5, li = lane & 31;
@@ -388,15 +411,28 @@ __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int ring = ring0 + t * 32 + li;
+            // orders below |n|: only the run that is stable at this ring writes; its
+            // continuation (m <= 0) feeds the A slice at m < 0 (components 2,3 at |m|)
+            // and the B slice at -m >= 0 (components 0,1 at |m|)
+            bool good = false;
+            if (an > 0 && ring < nreg) {
+                const double ct = cot[ring];
+                good = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
+            }
+            const bool wa = m >= an || (good && m >= 0), wa_x = !wa && good;
+            const bool wb = m >= an || (good && m > 0), wb_x = !wb && good;
+            const int am = m < 0 ? -m : m;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int b = mts[i] * 8 + 2 * q + half;
                 if (b < B && ring < nreg) {
-                    const size_t o = ((size_t)ring * L + m) * 4;
-                    if (PA) *(double2 *)(PA + (size_t)b * pstride + o) =
-                        make_double2((double)acc[i][t][4 * q + 0], (double)acc[i][t][4 * q + 1]);
-                    if (PB) *(double2 *)(PB + (size_t)b * pstride + o + 2) =
-                        make_double2((double)acc[i][t][4 * q + 2], (double)acc[i][t][4 * q + 3]);
+                    const size_t o = ((size_t)ring * L + am) * 4;
+                    const double2 va = make_double2((double)acc[i][t][4 * q + 0], (double)acc[i][t][4 * q + 1]);
+                    const double2 vb = make_double2((double)acc[i][t][4 * q + 2], (double)acc[i][t][4 * q + 3]);
+                    if (PA && wa) *(double2 *)(PA + (size_t)b * pstride + o) = va;
+                    if (PA && wa_x) *(double2 *)(PA + (size_t)b * pstride + o + 2) = va;
+                    if (PB && wb) *(double2 *)(PB + (size_t)b * pstride + o + 2) = vb;
+                    if (PB && wb_x) *(double2 *)(PB + (size_t)b * pstride + o) = vb;
                 }
             }
         }
@@ -406,15 +442,17 @@ __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int
 // Forward: columns = 64 degrees l, K = rings.  Output Q[b][l][m][comp] for
 // l >= m (degrees below max(m, |n|) carry zero d and give zero).
 template <int FMT, int MTW>
-__global__ __launch_bounds__(256) void k_mfma_fwd(int L, int rpad, int lp, int m_lo, int B, int rpad_rows,
-                                                  const uint4 *__restrict__ H, const uint4 *__restrict__ D,
+__global__ __launch_bounds__(256) void k_mfma_fwd(int L, int rpad, int lp, int n, int m_lo, int B, int rpad_rows,
+                                                  int nxp, const uint4 *__restrict__ H, const uint4 *__restrict__ D,
                                                   double *__restrict__ QA, double *__restrict__ QB,
-                                                  long long qstride)
+                                                  long long qstride, double *__restrict__ QxA,
+                                                  double *__restrict__ QxB, long long qxstride)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int half = lane >> 5, li = lane & 31;
     const int l0 = blockIdx.x * 64;
     const int mc = blockIdx.y, m = m_lo + mc;
+    const int an = n < 0 ? -n : n, am = m < 0 ? -m : m;
     if (l0 + 63 < m) return;
     const int MT = rpad_rows / 32;
     int mts[MTW];
@@ -468,11 +506,23 @@ __global__ __launch_bounds__(256) void k_mfma_fwd(int L, int rpad, int lp, int m
             for (int q = 0; q < 4; ++q) {
                 const int b = mts[i] * 8 + 2 * q + half;
                 if (b < B && l < L && l >= m) {
-                    const size_t o = ((size_t)l * L + m) * 4;
-                    if (QA) *(double2 *)(QA + (size_t)b * qstride + o) =
-                        make_double2((double)acc[i][t][4 * q + 0], (double)acc[i][t][4 * q + 1]);
-                    if (QB) *(double2 *)(QB + (size_t)b * qstride + o + 2) =
-                        make_double2((double)acc[i][t][4 * q + 2], (double)acc[i][t][4 * q + 3]);
+                    const double2 va = make_double2((double)acc[i][t][4 * q + 0], (double)acc[i][t][4 * q + 1]);
+                    const double2 vb = make_double2((double)acc[i][t][4 * q + 2], (double)acc[i][t][4 * q + 3]);
+                    // continuation sums (orders m <= 0 of a run with n != 0): the A slice at
+                    // order m < 0 and the B slice at order -m, signed to cancel the finish's
+                    // (-1)^{|m| - spin} on negative orders / give d^l_{-m,-n} = (-1)^{m-n} d^l_{m,n}
+                    const double sg = ((am + n) & 1) ? -1.0 : 1.0;
+                    if (m >= 0) {
+                        const size_t o = ((size_t)l * L + m) * 4;
+                        if (QA) *(double2 *)(QA + (size_t)b * qstride + o) = va;
+                        if (QB && m > 0) *(double2 *)(QB + (size_t)b * qstride + o + 2) = vb;
+                    } else if (QxA) {
+                        *(double2 *)(QxA + (size_t)b * qxstride + ((size_t)l * nxp + am) * 4 + 2) =
+                            make_double2(sg * va.x, sg * va.y);
+                    }
+                    if (m <= 0 && an > 0 && QxB)
+                        *(double2 *)(QxB + (size_t)b * qxstride + ((size_t)l * nxp + am) * 4) =
+                            make_double2(sg * vb.x, sg * vb.y);
                 }
             }
         }
@@ -495,10 +545,11 @@ hipError_t launch_zero(hipStream_t st, void *p, size_t bytes)
     return hipSuccess;
 }
 
-hipError_t launch_kg_table(hipStream_t st, int L, int lrow, const double *kap, const double *gtab, double2 *kg)
+hipError_t launch_kg_table(hipStream_t st, int L, int nx, int lrow, const double *kap, const double *gtab,
+                           double2 *kg)
 {
-    const size_t tot = (size_t)L * lrow;
-    hipLaunchKernelGGL(k_kg_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, lrow, kap, gtab, kg);
+    const size_t tot = (size_t)(L + nx) * lrow;
+    hipLaunchKernelGGL(k_kg_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nx, lrow, kap, gtab, kg);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -508,7 +559,7 @@ hipError_t launch_dgen(hipStream_t st, int layout, int fmt, int nwaves, int nblk
                        const double2 *kg, const int *lchunk, const int *mtop, double *SX, double *SY, int *SE,
                        uint4 *D)
 {
-    if (nwaves < 1 || nwaves > DSTAGE_MAX_WAVES || g.rpad % 64 || m_lo < 0 || m_hi >= g.L || m_lo > m_hi)
+    if (nwaves < 1 || nwaves > DSTAGE_MAX_WAVES || g.rpad % 64 || m_lo <= -g.L || m_hi >= g.L || m_lo > m_hi)
         return hipErrorInvalidValue;
     dim3 grid((unsigned)(g.rpad / 64), (unsigned)nblk), block((unsigned)(64 * nwaves));
 #define S2_DGEN(LAY, FMT)                                                                                   \
@@ -539,30 +590,30 @@ hipError_t launch_pack_a(hipStream_t st, int fmt, const MfmaGeom &g, int n, int 
     return hipSuccess;
 }
 
-hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int m_lo, int mcn, int B,
-                         long long fstride, const double *FA, const double *FB, uint4 *H)
+hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int n, const double *cot, int m_lo,
+                         int mcn, int B, long long fstride, const double *FA, const double *FB, uint4 *H)
 {
     const size_t tot = (size_t)mcn * (g.rpad / SG) * g.rows;
     const dim3 grid((unsigned)((tot + 255) / 256)), block(256);
     if (fmt == S2_CONTRACT_FP32)
         hipLaunchKernelGGL(k_pack_h<S2_CONTRACT_FP32>, grid, block, 0, st, m_lo, mcn, g.rpad, g.nreg, hstride, g.rows,
-                           B, fstride, FA, FB, H);
+                           B, fstride, n, cot, FA, FB, H);
     else
         hipLaunchKernelGGL(k_pack_h<S2_CONTRACT_SPLIT_BF16>, grid, block, 0, st, m_lo, mcn, g.rpad, g.nreg, hstride,
-                           g.rows, B, fstride, FA, FB, H);
+                           g.rows, B, fstride, n, cot, FA, FB, H);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, int m_lo, int mcn, int B,
-                           const uint4 *A, const uint4 *D, double *PA, double *PB, long long pstride)
+hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, const double *cot, int m_lo, int mcn,
+                           int B, const uint4 *A, const uint4 *D, double *PA, double *PB, long long pstride)
 {
     const int MT = g.rows / 32;
     const int mtw = MT <= 4 ? 1 : 2;
     const dim3 grid((unsigned)(g.rpad / 64), (unsigned)mcn, (unsigned)((MT + 4 * mtw - 1) / (4 * mtw))), block(256);
 #define S2_MI(FMT, MTW)                                                                                    \
     hipLaunchKernelGGL((k_mfma_inv<FMT, MTW>), grid, block, 0, st, g.L, g.nreg, g.rpad, g.kc, n, m_lo, B, \
-                       g.rows, A, D, PA, PB, pstride)
+                       g.rows, cot, A, D, PA, PB, pstride)
     if (fmt == S2_CONTRACT_FP32) { if (mtw == 1) S2_MI(S2_CONTRACT_FP32, 1); else S2_MI(S2_CONTRACT_FP32, 2); }
     else { if (mtw == 1) S2_MI(S2_CONTRACT_SPLIT_BF16, 1); else S2_MI(S2_CONTRACT_SPLIT_BF16, 2); }
 #undef S2_MI
@@ -570,15 +621,16 @@ hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, in
     return hipSuccess;
 }
 
-hipError_t launch_mfma_fwd(hipStream_t st, int fmt, const MfmaGeom &g, int m_lo, int mcn, int B, const uint4 *H,
-                           const uint4 *D, double *QA, double *QB, long long qstride)
+hipError_t launch_mfma_fwd(hipStream_t st, int fmt, const MfmaGeom &g, int n, int nxp, int m_lo, int mcn, int B,
+                           const uint4 *H, const uint4 *D, double *QA, double *QB, long long qstride, double *QxA,
+                           double *QxB, long long qxstride)
 {
     const int MT = g.rows / 32;
     const int mtw = MT <= 4 ? 1 : 2;
     const dim3 grid((unsigned)(g.lp / 64), (unsigned)mcn, (unsigned)((MT + 4 * mtw - 1) / (4 * mtw))), block(256);
 #define S2_MF(FMT, MTW)                                                                                     \
-    hipLaunchKernelGGL((k_mfma_fwd<FMT, MTW>), grid, block, 0, st, g.L, g.rpad, g.lp, m_lo, B, g.rows, H, D, \
-                       QA, QB, qstride)
+    hipLaunchKernelGGL((k_mfma_fwd<FMT, MTW>), grid, block, 0, st, g.L, g.rpad, g.lp, n, m_lo, B, g.rows, nxp, H, \
+                       D, QA, QB, qstride, QxA, QxB, qxstride)
     if (fmt == S2_CONTRACT_FP32) { if (mtw == 1) S2_MF(S2_CONTRACT_FP32, 1); else S2_MF(S2_CONTRACT_FP32, 2); }
     else { if (mtw == 1) S2_MF(S2_CONTRACT_SPLIT_BF16, 1); else S2_MF(S2_CONTRACT_SPLIT_BF16, 2); }
 #undef S2_MF

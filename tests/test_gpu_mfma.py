@@ -56,7 +56,7 @@ def _check(name, prec, got, ref):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("L,spin,B", [(64, 0, 5), (48, 2, 3), (41, -1, 2), (130, 0, 9)])
+@pytest.mark.parametrize("L,spin,B", [(64, 0, 5), (48, 2, 3), (41, -1, 2), (130, 0, 9), (40, 13, 2)])
 def test_mw_batched(binding, prec, L, spin, B):
     flm = flm_gaussian(L, spin, seed=20, batch=B, scale="inv1pl")
     plan = binding.Plan(L, spin=spin, max_batch=B, precision=prec)
@@ -86,7 +86,7 @@ def test_healpix_batched(binding, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_so3_batched(binding, prec):
-    L, N, B = 24, 3, 2
+    L, N, B = 40, 8, 2
     flmn = flmn_gaussian(L, N, seed=24, batch=B)
     plan = binding.Plan(L, N=N, max_batch=B, precision=prec)
     f = host(plan.so3_inverse(dev(flmn)))

@@ -32,7 +32,7 @@ def binding():
     return b
 
 
-@pytest.mark.parametrize("L,n", [(32, 0), (64, 0), (40, 2), (40, -2), (33, 3)])
+@pytest.mark.parametrize("L,n", [(32, 0), (64, 0), (40, 2), (40, -2), (33, 3), (33, 16), (64, -7), (24, 23)])
 def test_recursion_matches_oracle_d(binding, L, n):
     plan = binding.Plan(L, spin=-n if n else 0)
     d = host(plan.debug_wigner_d(n))                     # [ring][m][l]
@@ -43,59 +43,63 @@ def test_recursion_matches_oracle_d(binding, L, n):
             ref[r, m, :] = oracle.wigner_d(L, m, n, t)
     for m in range(L):
         ref[:, m, :m] = 0.0
-    # n != 0: near a pole the run with n cos(theta) > 0 crosses its lower turning
-    # point in its last <= |n| steps (the unstable direction of Eq. 25), where
-    # absolute errors reach ~1e-12; elsewhere the recursion is at ~1e-15.
-    assert np.max(np.abs(d - ref)) < (1e-13 if n == 0 else 1e-11)
+    # n != 0: near a pole the descending recursion of the run with n cos(theta) > 0
+    # is unstable at orders below |n|; those values come from the run -n continued
+    # to negative orders (d^l_{m,n} = (-1)^{m-n} d^l_{-m,-n}).
+    assert np.max(np.abs(d - ref)) < (1e-13 if n == 0 else 1e-12)
 
 
-@pytest.mark.parametrize("L,spin", [(64, 0), (32, 2), (31, -1), (16, 3)])
+@pytest.mark.parametrize("L,spin", [(64, 0), (32, 2), (31, -1), (16, 3), (48, 17), (40, -39)])
 def test_mw_inverse_and_forward(binding, L, spin):
+    tol = 1e-13 if abs(spin) <= 3 else 1e-12      # high spins: extra error of the low-order continuation
     flm = flm_gaussian(L, spin, seed=0)
     plan = binding.Plan(L, spin=spin)
     f = host(plan.inverse(dev(flm)))
     fref = oracle.s2_inverse(flm, L, spin)
-    assert rel_l2(f, fref) < 1e-13
+    assert rel_l2(f, fref) < tol
     # forward of an arbitrary (not band-limited) map
     g = map_gaussian((L, 2 * L - 1), seed=1)
     a = host(plan.forward(dev(g)))
     aref = oracle.s2_forward(g, L, spin)
-    assert rel_l2(a, aref) < 1e-13
+    assert rel_l2(a, aref) < tol
     assert np.all(a[~coeff_mask(L, spin)] == 0)
     # round trip
     back = host(plan.forward(plan.inverse(dev(flm))))
-    assert rel_l2(back, flm) < 1e-13
+    assert rel_l2(back, flm) < tol
 
 
-@pytest.mark.parametrize("nside,L,spin", [(4, 8, 0), (8, 16, 0), (8, 16, 2)])
+@pytest.mark.parametrize("nside,L,spin", [(4, 8, 0), (8, 16, 0), (8, 16, 2), (16, 32, -9)])
 def test_healpix_inverse_and_forward(binding, nside, L, spin):
+    tol = 1e-13 if abs(spin) <= 3 else 1e-12
     flm = flm_gaussian(L, spin, seed=2)
     plan = binding.Plan(L, spin=spin, sampling="healpix", nside=nside)
     f = host(plan.inverse(dev(flm)))
-    assert rel_l2(f, oracle.s2_inverse(flm, L, spin, oracle.HEALPIX, nside)) < 1e-13
+    assert rel_l2(f, oracle.s2_inverse(flm, L, spin, oracle.HEALPIX, nside)) < tol
     g = map_gaussian(12 * nside * nside, seed=3)
     a = host(plan.forward(dev(g)))
-    assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < 1e-13
+    assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < tol
 
 
-@pytest.mark.parametrize("sampling,L,nside,spin", [("mw", 24, 0, 0), ("mw", 24, 0, 2), ("healpix", 16, 8, 2)])
+@pytest.mark.parametrize("sampling,L,nside,spin", [("mw", 24, 0, 0), ("mw", 24, 0, 2), ("healpix", 16, 8, 2),
+                                                   ("mw", 30, 0, -11)])
 def test_inverse_adjoint(binding, sampling, L, nside, spin):
     plan = binding.Plan(L, spin=spin, sampling=sampling, nside=nside)
     g = map_gaussian(plan.map_shape, seed=4)
     a = host(plan.inverse_adjoint(dev(g)))
     ref = oracle.s2_inverse_adjoint(g, L, spin, 0 if sampling == "mw" else 1, nside)
-    assert rel_l2(a, ref) < 1e-13
+    assert rel_l2(a, ref) < (1e-13 if abs(spin) <= 3 else 1e-12)
 
 
-@pytest.mark.parametrize("L,N", [(8, 1), (12, 3), (16, 5)])
+@pytest.mark.parametrize("L,N", [(8, 1), (12, 3), (16, 5), (96, 8)])
 def test_so3(binding, L, N):
+    tol = 1e-13 if N <= 4 else 1e-12
     flmn = flmn_gaussian(L, N, seed=5)
     plan = binding.Plan(L, N=N)
     f = host(plan.so3_inverse(dev(flmn)))
-    assert rel_l2(f, oracle.so3_inverse(flmn, L, N)) < 1e-13
+    assert rel_l2(f, oracle.so3_inverse(flmn, L, N)) < tol
     g = map_gaussian((2 * N - 1, L, 2 * L - 1), seed=6)
     a = host(plan.so3_forward(dev(g)))
-    assert rel_l2(a, oracle.so3_forward(g, L, N)) < 1e-13
+    assert rel_l2(a, oracle.so3_forward(g, L, N)) < tol
 
 
 def test_batched_inverse_matches_single(binding):

@@ -54,6 +54,52 @@ def measured_traffic(kernel, L, spin):
     return None
 
 
+def mixed_precision(L, batch, steps, dev, fp64_plan):
+    """Batched MW spin-0 pairs with the contraction on the matrix cores (FP32 and
+    split BF16): maps/s and the max relative coefficient error of map 0 against the
+    FP64 path (itself checked against the oracle) and against the oracle on sampled
+    rings of the inverse."""
+    import torch
+    import oracle
+    from paper_2311_14670_amd import binding
+    from paper_2311_14670_amd.synth import flm_gaussian
+    flm = flm_gaussian(L, 0, seed=2, batch=batch, scale="inv1pl")
+    x = torch.from_numpy(flm).to(dev)
+    f64_inv = fp64_plan.inverse(x[0]).cpu().numpy()
+    f64_pair = fp64_plan.forward(fp64_plan.inverse(x[0])).cpu().numpy()
+    rings = np.array([0, L // 2, L - 2])
+    ref_rings = oracle.s2_inverse(flm[0], L, 0, rings=rings).reshape(rings.size, -1)
+    res = {"workload": f"MW L={L} spin 0, batch {batch} maps, Gaussian coefficients x 1/(1+l), seed 2",
+           "batch": batch}
+    for prec in ("fp32", "split_bf16"):
+        plan = binding.Plan(L, spin=0, max_batch=batch, precision=prec, device=dev)
+        _ = plan.workspace
+        y = plan.forward(plan.inverse(x))          # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            finv = plan.inverse(x)
+            y = plan.forward(finv)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        fi = finv[0].cpu().numpy()
+        y0 = y[0].cpu().numpy()
+
+        def err(a, b):
+            return {"max_rel": float(np.max(np.abs(a - b)) / np.max(np.abs(b))),
+                    "rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b))}
+        res[prec] = {"ms_per_batch_pair": ms, "maps_per_s": batch * 1e3 / ms,
+                     "inverse_vs_fp64": err(fi, f64_inv), "pair_vs_fp64": err(y0, f64_pair),
+                     "inverse_vs_oracle_rings": err(fi[rings], ref_rings),
+                     "pair_vs_input": err(y0, flm[0])}
+        plan.close()
+        del y, finv
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(L, spin, flm, nring_sample, norder_sample):
     import oracle
     oracle._load()
@@ -82,6 +128,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rings", type=int, default=64)
     ap.add_argument("--cpu-orders", type=int, default=64)
+    ap.add_argument("--mixed-batch", type=int, default=64,
+                    help="maps per call of the matrix-core (FP32 / split-BF16) comparison; 0 skips it")
+    ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run plain device copies of MIB MiB (a reference for "
                          "hardware byte counters)")
@@ -172,6 +221,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = n * 8
+    if args.mixed_batch > 0 and spin == 0:
+        out["mixed_precision"] = mixed_precision(L, args.mixed_batch, args.mixed_steps, dev, plan)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, spin, flm, args.cpu_rings, args.cpu_orders)
     print(json.dumps(out), flush=True)

@@ -695,7 +695,8 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *
         double *HxB = an > 0 ? HxA + nHx : nullptr;
         TIMED(S2_STAGE_DSTAGE_FWD);
         if (an > 0)
-            HIPCHK(launch_mask_low(st, an, r.n, P->nreg, P->hstride, P->cot, HA, HB, HxA, HxB), "low-order spectra");
+            HIPCHK(launch_mask_low(st, an, r.n, P->nreg, P->hstride, P->cot, P->csc, HA, HB, HxA, HxB),
+                   "low-order spectra");
         HIPCHK(launch_dstage_fwd(st, P->fwd_waves, P->fwd_nblk, P->G, L, std::max(P->nxp, 1), P->nreg, P->hstride,
                                  P->hstride, r.n, P->lam[ri], P->init[ri], P->kap, P->gtab, HA, HB, HxA, HxB,
                                  r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
@@ -781,7 +782,7 @@ int run_inverse_mfma(s2_plan_t P, const double2 *flm, int B, double2 *maps, cons
                    "coefficient pack");
             }
             TIMED(S2_STAGE_MFMA);
-            HIPCHK(launch_mfma_inv(st, fmt, g, r.n, P->cot, mlo, mcn, B, A, D, PA, PB, (long long)(S * nP1)),
+            HIPCHK(launch_mfma_inv(st, fmt, g, r.n, P->cot, P->csc, mlo, mcn, B, A, D, PA, PB, (long long)(S * nP1)),
                    "inverse contraction");
         }
     }
@@ -858,7 +859,7 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             }
             {
             TIMED(S2_STAGE_PACK);
-            HIPCHK(launch_pack_h(st, fmt, g, P->hstride, r.n, P->cot, mlo, mcn, B, (long long)(S * nF), FA, FB, H),
+            HIPCHK(launch_pack_h(st, fmt, g, P->hstride, r.n, P->cot, P->csc, mlo, mcn, B, (long long)(S * nF), FA, FB, H),
                    "spectra pack");
             }
             TIMED(S2_STAGE_MFMA);

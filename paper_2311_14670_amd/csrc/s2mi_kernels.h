@@ -43,8 +43,8 @@ hipError_t launch_fadj_gather(hipStream_t st, int L, int nblk, int spin, const d
                               const double2 *flm, const double *wl, int hstride, double *F);
 hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, const double *F, const double2 *hpole,
                                double *out);
-hipError_t launch_mask_low(hipStream_t st, int an, int n, int nreg, int hstride, const double *cot, const double *FA,
-                           const double *FB, double *HxA, double *HxB);
+hipError_t launch_mask_low(hipStream_t st, int an, int n, int nreg, int hstride, const double *cot, const double *csc,
+                           const double *FA, const double *FB, double *HxA, double *HxB);
 hipError_t launch_pole_from_F(hipStream_t st, int L, int hstride, int ring, const double *F, double2 *pole);
 hipError_t set_kernel_lds_limits(size_t max_dyn);
 

@@ -181,7 +181,8 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
 }
 
 template <int NCH, int PAR>
-__device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ring0, int nreg, int lane,
+__device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ms, int ring0, int nreg,
+                                         int lane,
                                          int w, int W,
                                          const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
                                          int (&E)[NCH][SG], uint32_t &fast, double ct, double ncs,
@@ -229,17 +230,20 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
         const int rl = tr & 63, comp = tr >> 6;         // rl == lane: this thread's ring
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
-        // Orders below |n| come, at each ring, from the run that is stable there
-        // (n cos(theta) < 0): it writes its own sides at m >= 0 and, from its
-        // continuation to m <= 0, the A slice at order m < 0 (components 2,3 at |m|)
+        // Orders below the ring's switch order ms come from the run that is stable
+        // there (n cos(theta) < 0): it writes its own sides at m >= 0 and, from its
+        // continuation to m > -ms, the A slice at order m < 0 (components 2,3 at |m|)
         // and the B slice at order -m >= 0 (components 0,1 at |m|).  The other run
-        // writes nothing at these orders.
+        // writes nothing below ms.
         double *dst = nullptr;
         int mo = m, co = comp;
-        if (m >= an || (good && m > 0)) dst = comp < 2 ? partA : partB;
-        else if (good) {
-            if (comp < 2) { dst = partA; if (m < 0) { mo = -m; co = comp + 2; } }
-            else { dst = partB; mo = -m; co = comp - 2; }
+        const bool ext_ok = good && m <= 0 && -m < ms;   // continuation output of the stable run
+        if (comp < 2) {
+            if (m >= 0 && (good || m >= ms)) dst = partA;                      // A slice at order m
+            else if (m < 0 && ext_ok) { dst = partA; mo = -m; co = comp + 2; }  // A slice at order m < 0
+        } else {
+            if (m > 0 && (good || m >= ms)) dst = partB;                       // B slice at order -m
+            else if (ext_ok) { dst = partB; mo = -m; co = comp - 2; }          // B slice at order -m >= 0
         }
         if (dst && ring0 + rl < nreg) dst[(((size_t)blk * nreg + ring0 + rl) * L + mo) * 4 + co] = s;
     }
@@ -261,8 +265,8 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
     const int ring = min(ring0 + lane, nreg - 1);
     const double ct = cot[ring], cs = csc[ring];
     const double ncs = (double)n * cs;
-    // this run is the stable one at this ring when n cos(theta) < 0 (ties: n < 0)
-    const bool good = an > 0 && ((double)n * ct < 0.0 || (ct == 0.0 && n < 0));
+    const bool good = ring_good(n, ct);                 // this run is the stable one at this ring
+    const int ms = switch_order(n, ct, cs);
     const int mend = an > 1 ? -(an - 1) : 0;            // continuation below m = 0
     const double2 *initr = init + (size_t)ring * L;
 
@@ -279,11 +283,11 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
 
     const int mt = ufl(mtop[blk]);
     for (int m = mt; m >= mend; m -= 2) {
-        inv_step<NCH, 0>(m, L, nx, n, an, good, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red, blk,
-                         partA, partB);
+        inv_step<NCH, 0>(m, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red,
+                         blk, partA, partB);
         if (m - 1 >= mend)
-            inv_step<NCH, 1>(m - 1, L, nx, n, an, good, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C,
-                             red, blk, partA, partB);
+            inv_step<NCH, 1>(m - 1, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr,
+                             C, red, blk, partA, partB);
     }
 }
 
@@ -476,26 +480,35 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
     }
 }
 
-// Copies of the two sides' ring spectra at orders mu < |n| with the rings where
-// the run n is unstable (n cos(theta) >= 0, ties to n > 0) set to zero: the
-// forward sweep of run n reads these at its low orders and its continuation.
+// Copies of the two sides' ring spectra at orders mu < |n| for the forward sweep
+// of run n, restricted to the rings whose values this run supplies (switch
+// order ms of the ring): the own orders (A components 0,1 at mu >= 0, B
+// components 2,3 at mu > 0) where the run is stable or mu >= ms, and the
+// continuation orders (A components 2,3 = A slice at -mu, B components 0,1 = B
+// slice at +mu) where the run is the stable one and mu < ms.  Other entries 0.
 __global__ void k_mask_low(int an_run, int n, int nreg, int hstride, const double *__restrict__ cot,
-                           const double *__restrict__ FA, const double *__restrict__ FB, double *__restrict__ HxA,
-                           double *__restrict__ HxB)
+                           const double *__restrict__ csc, const double *__restrict__ FA,
+                           const double *__restrict__ FB, double *__restrict__ HxA, double *__restrict__ HxB)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)an_run * hstride) return;
-    const int r = (int)(i % hstride);
-    bool good = false;
+    const int r = (int)(i % hstride), mu = (int)(i / hstride);
+    bool own = false, ext = false;
     if (r < nreg) {
         const double ct = cot[r];
-        good = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
+        const bool good = ring_good(n, ct);
+        const int ms = switch_order(n, ct, csc[r]);
+        own = good || mu >= ms;
+        ext = good && mu < ms;
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        HxA[i * 4 + c] = good ? FA[i * 4 + c] : 0.0;
-        HxB[i * 4 + c] = good ? FB[i * 4 + c] : 0.0;
-    }
+    HxA[i * 4 + 0] = own ? FA[i * 4 + 0] : 0.0;
+    HxA[i * 4 + 1] = own ? FA[i * 4 + 1] : 0.0;
+    HxA[i * 4 + 2] = ext ? FA[i * 4 + 2] : 0.0;
+    HxA[i * 4 + 3] = ext ? FA[i * 4 + 3] : 0.0;
+    HxB[i * 4 + 0] = ext ? FB[i * 4 + 0] : 0.0;
+    HxB[i * 4 + 1] = ext ? FB[i * 4 + 1] : 0.0;
+    HxB[i * 4 + 2] = own ? FB[i * 4 + 2] : 0.0;
+    HxB[i * 4 + 3] = own ? FB[i * 4 + 3] : 0.0;
 }
 
 // 2 lambda table for the forward sweep: lam[m][r] = n csc_r - (m+1) cot_r
@@ -856,22 +869,22 @@ __global__ void k_debug_d(int L, int nreg, int n, const double *__restrict__ cot
         if (E != 0) renorm(e, ep, E);
         o[(size_t)m * L + l] = ldexp(e * gtab[(size_t)m * L + l], E);
     }
-    // orders below |n| where this run is unstable (n cos(theta) >= 0): continue the
-    // run -n (stable here) to order -(|n|-1) and use d^l_{m,n} = (-1)^{m-n} d^l_{-m,-n}
+    // orders below the switch order ms where this run is the unstable one: continue
+    // the run -n (stable there) to order -(ms-1) and use d^l_{m,n} = (-1)^{m-n} d^l_{-m,-n}
     const double ct = cot[r];
-    const bool good = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
-    if (an > 0 && !good) {
+    const int ms = switch_order(n, ct, csc[r]);
+    if (an > 0 && !ring_good(n, ct) && ms > 0) {
         E = 0;
         ep = 0.0;
         d_init(l, -n, dd_from(lbin + 2 * l), dd_from(lsin + 2 * r), dd_from(lcos + 2 * r), e, E);
-        for (int m = l - 1; m >= -(an - 1); --m) {
+        for (int m = l - 1; m >= -(ms - 1); --m) {
             const double lam = fma(-(double)(m + 1), ct, -(double)n * csc[r]);
             const double en = fma(kap[(ptrdiff_t)m * L + l] * lam, e, -ep);
             ep = e;
             e = en;
             if (E != 0) renorm(e, ep, E);
             const int mm = -m;
-            if (mm >= 0 && mm < an) {
+            if (mm >= 0 && mm < ms) {
                 const double v = ldexp(e * gtab[(ptrdiff_t)m * L + l], E);
                 o[(size_t)mm * L + l] = ((mm - n) & 1) ? -v : v;
             }
@@ -1055,13 +1068,13 @@ hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, con
     return hipSuccess;
 }
 
-hipError_t launch_mask_low(hipStream_t st, int an, int n, int nreg, int hstride, const double *cot, const double *FA,
-                           const double *FB, double *HxA, double *HxB)
+hipError_t launch_mask_low(hipStream_t st, int an, int n, int nreg, int hstride, const double *cot, const double *csc,
+                           const double *FA, const double *FB, double *HxA, double *HxB)
 {
     const size_t tot = (size_t)an * hstride;
     if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mask_low, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, an, n, nreg, hstride, cot, FA,
-                       FB, HxA, HxB);
+    hipLaunchKernelGGL(k_mask_low, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, an, n, nreg, hstride, cot, csc,
+                       FA, FB, HxA, HxB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -31,10 +31,12 @@ hipError_t launch_dgen(hipStream_t st, int layout, int fmt, int nwaves, int nblk
 hipError_t launch_pack_a(hipStream_t st, int fmt, const MfmaGeom &g, int n, int m_lo, int mcn, int B,
                          long long mstride, const double2 *flmA, const double2 *flmB, const double *wA,
                          const double *wB, uint4 *A);
-hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int n, const double *cot, int m_lo,
-                         int mcn, int B, long long fstride, const double *FA, const double *FB, uint4 *H);
-hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, const double *cot, int m_lo, int mcn,
-                           int B, const uint4 *A, const uint4 *D, double *PA, double *PB, long long pstride);
+hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int n, const double *cot,
+                         const double *csc, int m_lo, int mcn, int B, long long fstride, const double *FA,
+                         const double *FB, uint4 *H);
+hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, const double *cot, const double *csc,
+                           int m_lo, int mcn, int B, const uint4 *A, const uint4 *D, double *PA, double *PB,
+                           long long pstride);
 hipError_t launch_mfma_fwd(hipStream_t st, int fmt, const MfmaGeom &g, int n, int nxp, int m_lo, int mcn, int B,
                            const uint4 *H, const uint4 *D, double *QA, double *QB, long long qstride, double *QxA,
                            double *QxB, long long qxstride);

@@ -146,8 +146,8 @@ __device__ __forceinline__ void gen_chunk(double (&X)[SG], double (&Y)[SG], int 
 }
 
 template <int NCH, int LAY, int FMT, int PAR>
-__device__ __forceinline__ void gen_step(int m, int m_lo, int an, bool good, int kc_tot, int rpad, int lp, int ring0,
-                                         int lane, int w, const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
+__device__ __forceinline__ void gen_step(int m, int m_lo, int an, bool good, int ms, int kc_tot, int rpad, int lp,
+                                         int ring0, int lane, int w, const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
                                          int (&E)[NCH][SG], uint32_t &fast, double ct, double ncs,
                                          const double2 *__restrict__ initr, const double2 *__restrict__ kgm,
                                          float *tr, uint4 *__restrict__ D)
@@ -176,8 +176,8 @@ __device__ __forceinline__ void gen_step(int m, int m_lo, int an, bool good, int
             for (int e = 0; e < SG; ++e) z = z && (E[g][e] == 0);
             if (__all(z)) fast |= (1u << g);
         }
-        if (m < an && !good) {                            // orders below |n| at rings where this run is
-#pragma unroll                                            // unstable come from the other run
+        if (good ? (m < 0 && -m >= ms) : (m < ms)) {      // values this run does not supply at this ring
+#pragma unroll                                            // (the other run covers them): emitted as 0
             for (int e = 0; e < SG; ++e) dv[e] = 0.0f;
         }
         if constexpr (LAY == 0) {
@@ -215,8 +215,8 @@ __global__ __launch_bounds__(512) void k_dgen(
     const double ncs = (double)n * cs;
     const double2 *initr = init + (size_t)ring * L;
     float *tr = trbuf + (LAY == 1 ? w * SG * 64 : 0);
-    // this run is the stable one at this ring when n cos(theta) < 0 (ties: n < 0)
-    const bool good = an > 0 && ((double)n * ct < 0.0 || (ct == 0.0 && n < 0));
+    const bool good = ring_good(n, ct);                 // this run is the stable one at this ring
+    const int ms = switch_order(n, ct, cs);
 
     int lb[NCH];
 #pragma unroll
@@ -241,15 +241,15 @@ __global__ __launch_bounds__(512) void k_dgen(
     const int mt = ufl(mtop[blk]);
     int m = min(m_hi, mt);
     if (m >= m_lo && (m & 1)) {
-        gen_step<NCH, LAY, FMT, 1>(m, m_lo, an, good, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs,
+        gen_step<NCH, LAY, FMT, 1>(m, m_lo, an, good, ms, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs,
                                    initr, kg + (ptrdiff_t)m * lrow, tr, D);
         --m;
     }
     for (; m >= m_lo; m -= 2) {
-        gen_step<NCH, LAY, FMT, 0>(m, m_lo, an, good, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs,
+        gen_step<NCH, LAY, FMT, 0>(m, m_lo, an, good, ms, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct, ncs,
                                    initr, kg + (ptrdiff_t)m * lrow, tr, D);
         if (m - 1 >= m_lo)
-            gen_step<NCH, LAY, FMT, 1>(m - 1, m_lo, an, good, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct,
+            gen_step<NCH, LAY, FMT, 1>(m - 1, m_lo, an, good, ms, kc_tot, rpad, lp, ring0, lane, w, lb, X, Y, E, fast, ct,
                                        ncs, initr, kg + (ptrdiff_t)(m - 1) * lrow, tr, D);
     }
 #pragma unroll
@@ -309,12 +309,12 @@ __global__ void k_pack_a(int L, int n, int m_lo, int mcn, int kc_tot, int rpad_r
 // Forward: H[m - m_lo][ring/8][row][8 rings] from the ring spectra F[b][|m|][ring][4]:
 //   comp 0,1: FA components 0,1 (m >= 0) or 2,3 (m < 0: the A slice at order m);
 //   comp 2,3: FB components 2,3 (m > 0) or 0,1 (m <= 0: the B slice at order -m);
-// zero past the swept rings, for b >= B, and at orders below |n| on rings where
-// the run is the unstable one.
+// zero past the swept rings, for b >= B, and at orders below |n| where the ring's
+// values come from the other run (see the switch order in s2mi_recur.h).
 template <int FMT>
 __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int rpad_rows, int B, long long fstride,
-                         int n, const double *__restrict__ cot, const double *__restrict__ FA,
-                         const double *__restrict__ FB, uint4 *__restrict__ H)
+                         int n, const double *__restrict__ cot, const double *__restrict__ csc,
+                         const double *__restrict__ FA, const double *__restrict__ FB, uint4 *__restrict__ H)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int kr_tot = rpad / SG;
@@ -335,9 +335,12 @@ __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int
         double x = 0.0;
         if (F && b < B && ring < nreg) {
             bool use = true;
-            if (m < an) {
+            if (m < an) {                                 // low orders: own values or continuation
                 const double ct = cot[ring];
-                use = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
+                const bool good = ring_good(n, ct);
+                const int ms = switch_order(n, ct, csc[ring]);
+                const bool cont = (comp < 2) ? (m < 0) : (m <= 0);
+                use = cont ? (good && am < ms) : (good || m >= ms);
             }
             if (use) x = F[(size_t)b * fstride + ((size_t)am * hstride + ring) * 4 + c];
         }
@@ -353,7 +356,8 @@ __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int
 template <int FMT, int MTW>
 __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int kc_tot, int n, int m_lo, int B,
                                                   int rpad_rows, const double *__restrict__ cot,
-                                                  const uint4 *__restrict__ A, const uint4 *__restrict__ D,
+                                                  const double *__restrict__ csc, const uint4 *__restrict__ A,
+                                                  const uint4 *__restrict__ D,
                                                   double *__restrict__ PA, double *__restrict__ PB, long long pstride)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -415,12 +419,15 @@ __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int
             // continuation (m <= 0) feeds the A slice at m < 0 (components 2,3 at |m|)
             // and the B slice at -m >= 0 (components 0,1 at |m|)
             bool good = false;
+            int ms = 0;
             if (an > 0 && ring < nreg) {
                 const double ct = cot[ring];
-                good = (double)n * ct < 0.0 || (ct == 0.0 && n < 0);
+                good = ring_good(n, ct);
+                ms = switch_order(n, ct, csc[ring]);
             }
-            const bool wa = m >= an || (good && m >= 0), wa_x = !wa && good;
-            const bool wb = m >= an || (good && m > 0), wb_x = !wb && good;
+            const bool ext_ok = good && m <= 0 && -m < ms;
+            const bool wa = m >= 0 && (good || m >= ms), wa_x = m < 0 && ext_ok;
+            const bool wb = m > 0 && (good || m >= ms), wb_x = ext_ok;
             const int am = m < 0 ? -m : m;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -590,30 +597,32 @@ hipError_t launch_pack_a(hipStream_t st, int fmt, const MfmaGeom &g, int n, int 
     return hipSuccess;
 }
 
-hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int n, const double *cot, int m_lo,
-                         int mcn, int B, long long fstride, const double *FA, const double *FB, uint4 *H)
+hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride, int n, const double *cot,
+                         const double *csc, int m_lo, int mcn, int B, long long fstride, const double *FA,
+                         const double *FB, uint4 *H)
 {
     const size_t tot = (size_t)mcn * (g.rpad / SG) * g.rows;
     const dim3 grid((unsigned)((tot + 255) / 256)), block(256);
     if (fmt == S2_CONTRACT_FP32)
         hipLaunchKernelGGL(k_pack_h<S2_CONTRACT_FP32>, grid, block, 0, st, m_lo, mcn, g.rpad, g.nreg, hstride, g.rows,
-                           B, fstride, n, cot, FA, FB, H);
+                           B, fstride, n, cot, csc, FA, FB, H);
     else
         hipLaunchKernelGGL(k_pack_h<S2_CONTRACT_SPLIT_BF16>, grid, block, 0, st, m_lo, mcn, g.rpad, g.nreg, hstride,
-                           g.rows, B, fstride, n, cot, FA, FB, H);
+                           g.rows, B, fstride, n, cot, csc, FA, FB, H);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, const double *cot, int m_lo, int mcn,
-                           int B, const uint4 *A, const uint4 *D, double *PA, double *PB, long long pstride)
+hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, const double *cot, const double *csc,
+                           int m_lo, int mcn, int B, const uint4 *A, const uint4 *D, double *PA, double *PB,
+                           long long pstride)
 {
     const int MT = g.rows / 32;
     const int mtw = MT <= 4 ? 1 : 2;
     const dim3 grid((unsigned)(g.rpad / 64), (unsigned)mcn, (unsigned)((MT + 4 * mtw - 1) / (4 * mtw))), block(256);
 #define S2_MI(FMT, MTW)                                                                                    \
     hipLaunchKernelGGL((k_mfma_inv<FMT, MTW>), grid, block, 0, st, g.L, g.nreg, g.rpad, g.kc, n, m_lo, B, \
-                       g.rows, cot, A, D, PA, PB, pstride)
+                       g.rows, cot, csc, A, D, PA, PB, pstride)
     if (fmt == S2_CONTRACT_FP32) { if (mtw == 1) S2_MI(S2_CONTRACT_FP32, 1); else S2_MI(S2_CONTRACT_FP32, 2); }
     else { if (mtw == 1) S2_MI(S2_CONTRACT_SPLIT_BF16, 1); else S2_MI(S2_CONTRACT_SPLIT_BF16, 2); }
 #undef S2_MI

@@ -27,4 +27,23 @@ __device__ __forceinline__ void renorm(double &e, double &ep, int &E)
     E = real ? 0 : E + k;
 }
 
+// Stable-direction switch for runs with n != 0.  At a ring the descending
+// recursion of d^l_{m,n} grows (is stable) down to about m = n cos(theta); for
+// the run with n cos(theta) > 0 the orders m < ms = ceil(|n cos(theta)|) are
+// taken instead from the run -n (which is stable down to m = -ms) via
+// d^l_{m,n} = (-1)^{m-n} d^l_{-m,-n}.  ring_good: this run is the one with
+// n cos(theta) < 0 (ties: n < 0) at the ring; switch_order: ms in [0, |n|].
+__device__ __forceinline__ bool ring_good(int n, double ct)
+{
+    return n != 0 && ((double)n * ct < 0.0 || (ct == 0.0 && n < 0));
+}
+
+__device__ __forceinline__ int switch_order(int n, double ct, double cs)
+{
+    const int an = n < 0 ? -n : n;
+    if (an == 0) return 0;
+    const int ms = (int)ceil(fabs((double)n * ct / cs) - 1e-9);   // |n cos(theta)|, cos = cot / csc
+    return ms < 0 ? 0 : (ms > an ? an : ms);
+}
+
 }  // namespace s2mi

@@ -14,10 +14,12 @@
 // d_m = e_m g_m (g from the plan tables), Eq. 25 becomes
 //     e_{m-1} = kappa_m lambda_m e_m - e_{m+1},  lambda_m = (n - m cos th)/sin th,
 // two FP64 operations per step.  Each (ring, l) carries (e_m, e_{m+1}, E) with
-// d = e g 2^E.  While E < 0 the pair is renormalised every step by an exact
-// power of two; once the value is within 2^-600 of unity scale it is held
-// unscaled (E = 0): |d| <= 1 and the recursion runs downhill in m, so it can
-// no longer overflow or meaningfully underflow.  A wave switches a slot to the
+// d = e g 2^E.  While E < 0 the pair is renormalised by an exact power of two
+// (every step in the inverse sweep; every RN orders in the forward sweep, which
+// then uses the contribution e 2^E, an exact scaling that is zero once below the
+// double range); once the value is within 2^-600 of unit scale it is realised
+// (E = 0): |d| <= 1 and the recursion runs downhill in m, so it can no longer
+// overflow or meaningfully underflow.  A wave switches an inverse chunk to the
 // unscaled fast path when all its lanes have E = 0.
 #include <hip/hip_runtime.h>
 
@@ -305,7 +307,30 @@ __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int 
     return init + (size_t)r0 * L + m;
 }
 
-template <int PAR, bool SLOW, bool HEAD>
+// Renormalisation pass of the forward sweep over chunks that are not yet
+// realised: the state grows by at most ~2^28 per order (L <= 4096), so a pass
+// every RN orders keeps it far from overflow; a chunk whose lanes all reached
+// E = 0 stays realised while no degree starts in it.
+constexpr int RN = 8;
+
+template <int NCH>
+__device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[NCH][SG], int (&E)[NCH][SG], int p,
+                                              uint32_t &real)
+{
+#pragma unroll
+    for (int g = 0; g < NCH; ++g) {
+        if (g >= p || ((real >> g) & 1u)) continue;
+        bool z = true;
+#pragma unroll
+        for (int j = 0; j < SG; ++j) {
+            renorm(X[g][j], Y[g][j], E[g][j]);
+            z = z && (E[g][j] == 0);
+        }
+        if (__all(z)) real |= (1u << g);
+    }
+}
+
+template <int PAR, bool HEAD>
 __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ Lm,
                                           const double *__restrict__ HA, const double *__restrict__ HB, double kk,
                                           bool init, int nval, const double2 *__restrict__ iv, int istride, double &aAr,
@@ -316,19 +341,15 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
         double &nw = PAR == 0 ? Y[k] : X[k];
         double &od = PAR == 0 ? X[k] : Y[k];
         nw = fma(kk * Lm[k], od, -nw);
-        double t = nw;
-        if constexpr (SLOW) {
-            if constexpr (HEAD) {
-                if (init && k < nval) {                      // l == m starts at slot k's ring (a swept ring)
-                    const double2 v = iv[(size_t)k * istride];
-                    nw = v.x;
-                    E[k] = (int)v.y;
-                    od = 0.0;
-                }
+        if constexpr (HEAD) {
+            if (init && k < nval) {                      // l == m starts at slot k's ring (a swept ring)
+                const double2 v = iv[(size_t)k * istride];
+                nw = v.x;
+                E[k] = (int)v.y;
+                od = 0.0;
             }
-            renorm(nw, od, E[k]);
-            t = nw * ldexp(1.0, E[k]);
         }
+        const double t = ldexp(nw, E[k]);               // exact scaling; 0 below the double range
         const double *ha = HA + k * 4;                   // components chosen by the caller's offsets
         const double *hb = HB + k * 4;
         aAr = fma(t, ha[0], aAr);
@@ -341,7 +362,7 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
 template <int NCH, int PAR, bool HEAD>
 __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
                                          int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
-                                         double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &fast, double &kk, double &gm,
+                                         double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk, double &gm,
                                          const double *__restrict__ lam, const double2 *__restrict__ init,
                                          const double *__restrict__ kap, const double *__restrict__ gtab,
                                          const double *__restrict__ HA, const double *__restrict__ HB,
@@ -374,22 +395,20 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
         const double *Lc = Lm + c * SG;
         const double *Ac = HAm + c * SG * 4;
         const double *Bc = HBm + c * SG * 4;
-        if (HEAD || !((fast >> c) & 1u)) {
+        if (HEAD) {
             const int r0 = min(rbase + c * SG, nreg - 1);
             // slots at or past the last swept ring (MW south pole, padding) are never
             // started: they stay zero, and their start values lie outside the table
             const int nval = nreg - (rbase + c * SG);
             const bool ok = starts && nval > 0;
-            fwd_chunk<PAR, true, HEAD>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval,
-                                       init_tab_ptr(init, r0, m < 0 ? 0 : m, L), L, aAr, aAi, aBr, aBi);
-            bool z = true;
-#pragma unroll
-            for (int k = 0; k < SG; ++k) z = z && (E[c][k] == 0);
-            fast = __all(z) ? (fast | (1u << c)) : (fast & ~(1u << c));
+            fwd_chunk<PAR, true>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval, init_tab_ptr(init, r0, m < 0 ? 0 : m, L),
+                                 L, aAr, aAi, aBr, aBi);
         } else {
-            fwd_chunk<PAR, false, false>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr, aBi);
+            fwd_chunk<PAR, false>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr, aBi);
         }
     }
+    if (HEAD) real = 0u;                                  // degrees start in this group: not realised
+    if ((m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
     double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
     rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
@@ -451,7 +470,7 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
         for (int c = 0; c < NCH; ++c)
 #pragma unroll
             for (int k = 0; k < SG; ++k) { X[c][k] = 0.0; Y[c][k] = 0.0; E[c][k] = 0; }
-        uint32_t fast = (1u << NCH) - 1u;
+        uint32_t real = 0u;
         const int mstart = min(64 * g + 63, L - 1);
         const int lc = min(l, L - 1);
         double kk = (l > mstart && l < L) ? kap[(size_t)mstart * L + lc] : 0.0;
@@ -462,18 +481,18 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
         int m = mstart;
         for (; m >= hend && m >= mend; m -= 2) {
             fwd_step<NCH, 0, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
-                                   fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+                                   real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
                 fwd_step<NCH, 1, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
-                                       Y, E, fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
+                                       Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
                                        QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             fwd_step<NCH, 0, false>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
-                                    fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+                                    real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
                 fwd_step<NCH, 1, false>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
-                                        Y, E, fast, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
+                                        Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
                                         QxA, QxB);
         }
         __syncthreads();   // the LDS buffers are reused by the next pass

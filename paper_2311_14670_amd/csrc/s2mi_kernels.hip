@@ -14,13 +14,12 @@
 // d_m = e_m g_m (g from the plan tables), Eq. 25 becomes
 //     e_{m-1} = kappa_m lambda_m e_m - e_{m+1},  lambda_m = (n - m cos th)/sin th,
 // two FP64 operations per step.  Each (ring, l) carries (e_m, e_{m+1}, E) with
-// d = e g 2^E.  While E < 0 the pair is renormalised by an exact power of two
-// (every step in the inverse sweep; every RN orders in the forward sweep, which
-// then uses the contribution e 2^E, an exact scaling that is zero once below the
-// double range); once the value is within 2^-600 of unit scale it is realised
-// (E = 0): |d| <= 1 and the recursion runs downhill in m, so it can no longer
-// overflow or meaningfully underflow.  A wave switches an inverse chunk to the
-// unscaled fast path when all its lanes have E = 0.
+// d = e g 2^E.  While E < 0 the contribution is e 2^E (exact scaling, zero once
+// below the double range) and every RN orders the pair is renormalised by an
+// exact power of two; once the value is within 2^-600 of unit scale it is
+// realised (E = 0): |d| <= 1 and the recursion runs downhill in m, so it can no
+// longer overflow or meaningfully underflow.  A chunk whose lanes are all
+// realised runs the plain step.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -154,6 +153,33 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, const int *__
 // orders (PAR), so the recursion needs no register moves.  Per order, each
 // wave's partial sums are reduced over the waves in LDS by a rotating group of
 // four waves and written to partA/partB[blk][ring][m].
+// Renormalisation pass over chunks that are not yet
+// realised: the state grows by at most ~2^28 per order (L <= 4096), so a pass
+// every RN orders keeps it far from overflow; a chunk whose lanes all reached
+// E = 0 stays realised while no degree starts in it.
+constexpr int RN = 8;
+
+template <int NCH>
+__device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[NCH][SG], int (&E)[NCH][SG], int p,
+                                              uint32_t &real)
+{
+#pragma unroll
+    for (int g = 0; g < NCH; ++g) {
+        if (g >= p || ((real >> g) & 1u)) continue;
+        bool z = true;
+#pragma unroll
+        for (int j = 0; j < SG; ++j) {
+            renorm(X[g][j], Y[g][j], E[g][j]);
+            z = z && (E[g][j] == 0);
+        }
+        if (__all(z)) real |= (1u << g);
+    }
+}
+
+// One order of one chunk: e_{m-1} = (kappa lambda) e_m - e_{m+1}, plus the
+// contribution times the records.  SLOW: the contribution is e 2^E (exact
+// scaling, zero once below the double range) and slot jin may start here
+// (l == m) from its start value; otherwise the chunk is realised (E = 0).
 template <int PAR, bool SLOW>
 __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ rec,
                                           double lam, int jin, double e0, int E0, double &aAr, double &aAi,
@@ -172,8 +198,7 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
                 od = 0.0;
                 E[j] = E0;
             }
-            renorm(nw, od, E[j]);
-            t = nw * ldexp(1.0, E[j]);
+            t = ldexp(nw, E[j]);
         }
         aAr = fma(t, c[1], aAr);
         aAi = fma(t, c[2], aAi);
@@ -202,20 +227,26 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
         if (m >= base) {                                  // ramp: slot jin starts at this order
             const int jin = base + SG - 1 - m;
             const double2 iv = initr[m];                 // d^m_{m,n}(theta_ring), zero if m < |n|
-            const double e0 = iv.x;
-            const int E0 = (int)iv.y;
-            inv_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, e0, E0, aAr, aAi, aBr, aBi);
-            bool z = true;
-#pragma unroll
-            for (int j = 0; j < SG; ++j) z = z && (E[g][j] == 0);
-            fast = __all(z) ? (fast | (1u << g)) : (fast & ~(1u << g));
+            inv_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, aAr, aAi, aBr, aBi);
+            fast &= ~(1u << g);
         } else if ((fast >> g) & 1u) {
             inv_chunk<PAR, false>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
         } else {
             inv_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
+        }
+    }
+    // renormalisation pass every RN orders over the started chunks not yet realised
+    if ((m & (RN - 1)) == 0) {
+#pragma unroll
+        for (int g = 0; g < NCH; ++g) {
+            const int base = lb[g];
+            if (base < 0 || m > base + SG - 1 || ((fast >> g) & 1u)) continue;
             bool z = true;
 #pragma unroll
-            for (int j = 0; j < SG; ++j) z = z && (E[g][j] == 0);
+            for (int j = 0; j < SG; ++j) {
+                renorm(X[g][j], Y[g][j], E[g][j]);
+                z = z && (E[g][j] == 0);
+            }
             if (__all(z)) fast |= (1u << g);
         }
     }
@@ -305,29 +336,6 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
 __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int r0, int m, int L)
 {
     return init + (size_t)r0 * L + m;
-}
-
-// Renormalisation pass of the forward sweep over chunks that are not yet
-// realised: the state grows by at most ~2^28 per order (L <= 4096), so a pass
-// every RN orders keeps it far from overflow; a chunk whose lanes all reached
-// E = 0 stays realised while no degree starts in it.
-constexpr int RN = 8;
-
-template <int NCH>
-__device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[NCH][SG], int (&E)[NCH][SG], int p,
-                                              uint32_t &real)
-{
-#pragma unroll
-    for (int g = 0; g < NCH; ++g) {
-        if (g >= p || ((real >> g) & 1u)) continue;
-        bool z = true;
-#pragma unroll
-        for (int j = 0; j < SG; ++j) {
-            renorm(X[g][j], Y[g][j], E[g][j]);
-            z = z && (E[g][j] == 0);
-        }
-        if (__all(z)) real |= (1u << g);
-    }
 }
 
 template <int PAR, bool HEAD>

@@ -158,6 +158,7 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, const int *__
 // every RN orders keeps it far from overflow; a chunk whose lanes all reached
 // E = 0 stays realised while no degree starts in it.
 constexpr int RN = 8;
+constexpr int PFD = 3;   // orders of record prefetch ahead of use (inverse sweep)
 
 template <int NCH>
 __device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[NCH][SG], int (&E)[NCH][SG], int p,
@@ -219,6 +220,7 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
     const double lam = fma(-(double)(m + 1), ct, ncs);   // lambda_{m+1}: produces order m
     double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
     const double *Cw = C + (((size_t)blk * (L + nx) + (m + nx)) * W + w) * (NCH * SG) * 5;   // records at order m
+
 #pragma unroll
     for (int g = 0; g < NCH; ++g) {
         const int base = lb[g];
@@ -315,13 +317,26 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
     uint32_t fast = 0;
 
     const int mt = ufl(mtop[blk]);
+    int pf = 0;
+    constexpr int ROWB = NCH * SG * 5 * 8;               // bytes of one wave's records per order
     for (int m = mt; m >= mend; m -= 2) {
+        // Pull the records of orders m - PFD and m - PFD - 1 toward the caches (one
+        // dword per 128-byte line); the result is consumed only at the next pair of
+        // orders, so the load latency overlaps this pair's work.
+        asm volatile("" ::"v"(pf));
+        if (m - PFD - 1 >= -nx && lane < 2 * ROWB / 128) {
+            const int row = m - PFD - (lane >= ROWB / 128 ? 1 : 0);
+            const int *Cp = reinterpret_cast<const int *>(C + (((size_t)blk * (L + nx) + (row + nx)) * W + w) *
+                                                                  (NCH * SG) * 5);
+            pf = Cp[(lane % (ROWB / 128)) * 32];
+        }
         inv_step<NCH, 0>(m, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red,
                          blk, partA, partB);
         if (m - 1 >= mend)
             inv_step<NCH, 1>(m - 1, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr,
                              C, red, blk, partA, partB);
     }
+    asm volatile("" ::"v"(pf));
 }
 
 // ------------------------------------------------------------------ forward d-stage
@@ -487,7 +502,25 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
         // steps so the register roles line up with the main loop)
         const int hend = ((mstart - 64 * g + 1) % 2 == 0) ? 64 * g : 64 * g - 1;
         int m = mstart;
+        // Pull the wave's lambda and spectra rows of orders m - PFD, m - PFD - 1 toward
+        // the caches (one dword per 128-byte line, lanes 0..8 and 10..18); the result is
+        // consumed only at the next pair of orders, so the latency overlaps their work.
+        int pf = 0;
+        auto prefetch = [&](int mm) {
+            asm volatile("" ::"v"(pf));
+            const int mp = mm - PFD - (lane >= 10 ? 1 : 0);
+            const int q = lane % 10;
+            if (lane < 20 && q < 9 && mp >= an) {
+                // q = 0: the 16 lambdas; q = 1..4 / 5..8: the 512-byte spectra rows of the two sides
+                const int *a;
+                if (q == 0) a = reinterpret_cast<const int *>(lam + (ptrdiff_t)mp * lstride + rbase);
+                else if (q < 5) a = reinterpret_cast<const int *>(HA + ((size_t)mp * hstride + rbase) * 4) + (q - 1) * 32;
+                else a = reinterpret_cast<const int *>(HB + ((size_t)mp * hstride + rbase) * 4) + (q - 5) * 32;
+                pf = *a;
+            }
+        };
         for (; m >= hend && m >= mend; m -= 2) {
+            prefetch(m);
             fwd_step<NCH, 0, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
                                    real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
@@ -496,6 +529,7 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
                                        QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
+            prefetch(m);
             fwd_step<NCH, 0, false>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
                                     real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
@@ -503,6 +537,7 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
                                         Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
                                         QxA, QxB);
         }
+        asm volatile("" ::"v"(pf));
         __syncthreads();   // the LDS buffers are reused by the next pass
     }
 }

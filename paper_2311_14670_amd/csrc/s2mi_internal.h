@@ -50,10 +50,9 @@ struct FftArgs {
 // ----------------------------------------------------------------- d-stage geometry
 constexpr int INV_NCH = 4;              // 8-degree chunks per wave, inverse d-stage
 constexpr int INV_J = 8 * INV_NCH;      // l-slots per wave
-constexpr int FWD_NCH = 2;              // 8-ring chunks per wave, forward d-stage
+constexpr int FWD_NCH = 1;              // 8-ring chunks per wave, forward d-stage
 constexpr int FWD_R = 8 * FWD_NCH;      // ring-slots per wave
 constexpr int GEN_NCH = 2;              // 8-degree chunks per wave, d-tile generator (matrix-core path)
-constexpr int MAX_WAVES = 16;
 constexpr int DSTAGE_MAX_WAVES = 8;     // d-stage workgroups: at most 512 threads
 
 // One recursion run: fixed second index n of d^l_{m,n}; its A side feeds the

@@ -160,6 +160,28 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, const int *__
 constexpr int RN = 8;
 constexpr int PFD = 3;   // orders of record prefetch ahead of use (inverse sweep)
 
+// Workgroups of the sweeps hold W = 4 or 8 waves; the 4 x 64 outputs of an order
+// are reduced by one group of four waves, rotating with the order.
+static_assert(DSTAGE_MAX_WAVES == 8, "reducer rotation assumes at most two groups of four waves");
+__device__ __forceinline__ int reducer_group(int m, int W)
+{
+    return W == 8 ? (m & 1) : 0;                          // m & 1 is the positive residue, also for m < 0
+}
+
+// Sum over the W waves of one output's partials in LDS.  The reads of all
+// DSTAGE_MAX_WAVES slots are issued together; slots of absent waves are read
+// (inside the buffer) but selected away, so stale contents never enter the sum.
+__device__ __forceinline__ double wave_sum(const double *rb, int comp, int i, int W)
+{
+    double v[DSTAGE_MAX_WAVES];
+#pragma unroll
+    for (int ww = 0; ww < DSTAGE_MAX_WAVES; ++ww) v[ww] = rb[(ww * 4 + comp) * 64 + i];
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < DSTAGE_MAX_WAVES; ++ww) s += ww < W ? v[ww] : 0.0;
+    return s;
+}
+
 template <int NCH>
 __device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[NCH][SG], int (&E)[NCH][SG], int p,
                                               uint32_t &real)
@@ -252,19 +274,17 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
             if (__all(z)) fast |= (1u << g);
         }
     }
-    double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
+    double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr;
     rb[(w * 4 + 1) * 64 + lane] = aAi;
     rb[(w * 4 + 2) * 64 + lane] = aBr;
     rb[(w * 4 + 3) * 64 + lane] = aBi;
     __syncthreads();
     // four waves, rotating with the order, reduce the 4 x 64 outputs over the waves
-    const int grp = ((m % (W / 4)) + (W / 4)) % (W / 4);   // m may be negative (continuation)
-    const int tr = (int)threadIdx.x - 256 * grp;
+    const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
     if (tr >= 0 && tr < 256) {
         const int rl = tr & 63, comp = tr >> 6;         // rl == lane: this thread's ring
-        double s = 0.0;
-        for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
+        const double s = wave_sum(rb, comp, rl, W);
         // Orders below the ring's switch order ms come from the run that is stable
         // there (n cos(theta) < 0): it writes its own sides at m >= 0 and, from its
         // continuation to m > -ms, the A slice at order m < 0 (components 2,3 at |m|)
@@ -290,7 +310,7 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
     const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
 {
-    __shared__ double red[2 * MAX_WAVES * 4 * 64];
+    __shared__ double red[2 * DSTAGE_MAX_WAVES * 4 * 64];
     const int an = n < 0 ? -n : n;
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
@@ -382,7 +402,9 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
     }
 }
 
-template <int NCH, int PAR, bool HEAD>
+// HEAD: degrees of the group start in this pair of orders.  MAIN: m >= |n|
+// (no low-order copies, no continuation outputs).
+template <int NCH, int PAR, bool HEAD, bool MAIN = false>
 __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
                                          int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
                                          double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk, double &gm,
@@ -409,9 +431,9 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     // rings where this run is unstable are zero (the other run covers them); the
     // continuation (m <= 0) reads the A slice at order m < 0 (components 2,3) and
     // the B slice at order -m >= 0 (components 0,1).
-    const int am = m < 0 ? -m : m;
-    const bool low = m < an;
-    const double *HAm = (low ? HxA : HA) + ((size_t)am * hstride + rbase) * 4 + (m < 0 ? 2 : 0);
+    const int am = MAIN ? m : (m < 0 ? -m : m);
+    const bool low = !MAIN && m < an;
+    const double *HAm = (low ? HxA : HA) + ((size_t)am * hstride + rbase) * 4 + (!MAIN && m < 0 ? 2 : 0);
     const double *HBm = (low ? HxB : HB) + ((size_t)am * hstride + rbase) * 4 + (m > 0 ? 2 : 0);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -432,20 +454,23 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
     if (HEAD) real = 0u;                                  // degrees start in this group: not realised
     if ((m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
-    double *rb = red + (size_t)(m & 1) * MAX_WAVES * 4 * 64;
+    double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
     rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
     rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
     rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
     __syncthreads();
-    const int grp = ((m % (W / 4)) + (W / 4)) % (W / 4);   // m may be negative (continuation)
-    const int tr = (int)threadIdx.x - 256 * grp;
+    const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
     if (tr >= 0 && tr < 256) {
         const int ll = tr & 63, comp = tr >> 6;
         const int lo = 64 * g + ll;
-        double s = 0.0;
-        for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + ll];
-        if (lo < L && lo >= m) {
+        const double s = wave_sum(rb, comp, ll, W);
+        if (MAIN) {
+            if (lo < L && lo >= m && (m > 0 || comp < 2)) {
+                double *dst = comp < 2 ? QA : QB;
+                if (dst) dst[(((size_t)blk * L + lo) * L + m) * 4 + comp] = s;
+            }
+        } else if (lo < L && lo >= m) {
             if (m > 0 || comp < 2) {
                 if (m >= 0) {
                     double *dst = comp < 2 ? QA : QB;
@@ -472,7 +497,7 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
     const double *__restrict__ HxB, double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
     double *__restrict__ QxB)
 {
-    __shared__ double red[2 * MAX_WAVES * 4 * 64];
+    __shared__ double red[2 * DSTAGE_MAX_WAVES * 4 * 64];
     const int an = n < 0 ? -n : n;
     const int mend = an > 1 ? -(an - 1) : 0;            // continuation below m = 0
     const int lane = threadIdx.x & 63;
@@ -503,19 +528,21 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
         const int hend = ((mstart - 64 * g + 1) % 2 == 0) ? 64 * g : 64 * g - 1;
         int m = mstart;
         // Pull the wave's lambda and spectra rows of orders m - PFD, m - PFD - 1 toward
-        // the caches (one dword per 128-byte line, lanes 0..8 and 10..18); the result is
+        // the caches (one dword per 128-byte line, PQ lanes per order); the result is
         // consumed only at the next pair of orders, so the latency overlaps their work.
+        constexpr int HL = NCH * SG * 4 * 8 / 128;           // 128-byte lines of one side's spectra row
+        constexpr int PQ = 1 + 2 * HL;
         int pf = 0;
         auto prefetch = [&](int mm) {
             asm volatile("" ::"v"(pf));
-            const int mp = mm - PFD - (lane >= 10 ? 1 : 0);
-            const int q = lane % 10;
-            if (lane < 20 && q < 9 && mp >= an) {
-                // q = 0: the 16 lambdas; q = 1..4 / 5..8: the 512-byte spectra rows of the two sides
+            const int mp = mm - PFD - (lane >= PQ ? 1 : 0);
+            const int q = lane % PQ;
+            if (lane < 2 * PQ && mp >= an) {
+                // q = 0: the wave's lambdas; q = 1..HL / HL+1..2HL: the spectra rows of the two sides
                 const int *a;
                 if (q == 0) a = reinterpret_cast<const int *>(lam + (ptrdiff_t)mp * lstride + rbase);
-                else if (q < 5) a = reinterpret_cast<const int *>(HA + ((size_t)mp * hstride + rbase) * 4) + (q - 1) * 32;
-                else a = reinterpret_cast<const int *>(HB + ((size_t)mp * hstride + rbase) * 4) + (q - 5) * 32;
+                else if (q <= HL) a = reinterpret_cast<const int *>(HA + ((size_t)mp * hstride + rbase) * 4) + (q - 1) * 32;
+                else a = reinterpret_cast<const int *>(HB + ((size_t)mp * hstride + rbase) * 4) + (q - 1 - HL) * 32;
                 pf = *a;
             }
         };
@@ -527,6 +554,15 @@ __global__ __launch_bounds__(512) void k_dstage_fwd(
                 fwd_step<NCH, 1, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
                                        Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
                                        QxA, QxB);
+        }
+        for (; m - 1 >= an; m -= 2) {                     // both orders of the pair >= |n|
+            prefetch(m);
+            fwd_step<NCH, 0, false, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y,
+                                          E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA,
+                                          QxB);
+            fwd_step<NCH, 1, false, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
+                                          Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
+                                          QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             prefetch(m);
@@ -1006,6 +1042,7 @@ hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
                              const int *mtop, double *partA, double *partB)
 {
+    if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
     dim3 grid((nreg + 63) / 64, nblk);
     hipLaunchKernelGGL(k_dstage_inv<INV_NCH>, grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init, C,
                        lchunk, mtop, partA, partB);
@@ -1018,6 +1055,7 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
                              const double *HxB, double *QA, double *QB, double *QxA, double *QxB)
 {
+    if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
     dim3 grid((G + 1) / 2, nblk);
     hipLaunchKernelGGL(k_dstage_fwd<FWD_NCH>, grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride, n, G, lam,
                        init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);

@@ -437,15 +437,17 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         if ((rc = upload(P, &P->mtop, mt, st, "inverse mtop"))) return bail(rc);
     }
     // forward d-stage assignment: wave w of block b sweeps rings (b W + w) FWD_R ..
-    // + FWD_R - 1; rings past the last regular ring are inert padding.  W is a
-    // multiple of 4 (rotating reducers).
+    // + FWD_R - 1; rings past the last regular ring are inert padding.  W is 4, 8
+    // or 16 (rotating groups of four reducer waves); larger workgroups mean fewer
+    // ring blocks and so fewer partial sums to write and add up in the finish.
     {
         P->G = (L + 63) / 64;
         const int pairs = (P->G + 1) / 2;
         int nb = std::max(1, std::min(256 / pairs, (P->nreg + 4 * FWD_R - 1) / (4 * FWD_R)));
         int W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R);
-        while (W > DSTAGE_MAX_WAVES) { ++nb; W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R); }
-        W = std::max(4, (W + 3) / 4 * 4);
+        while (W > FWD_MAX_WAVES) { ++nb; W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R); }
+        W = W <= 4 ? 4 : W <= 8 ? 8 : 16;                    // 1, 2 or 4 groups of four waves
+        if (W > FWD_MAX_WAVES) W = FWD_MAX_WAVES;
         P->fwd_nblk = nb;
         P->fwd_waves = W;
         P->hstride = std::max(nb * W * FWD_R, P->nring);

@@ -53,7 +53,8 @@ constexpr int INV_J = 8 * INV_NCH;      // l-slots per wave
 constexpr int FWD_NCH = 1;              // 8-ring chunks per wave, forward d-stage
 constexpr int FWD_R = 8 * FWD_NCH;      // ring-slots per wave
 constexpr int GEN_NCH = 2;              // 8-degree chunks per wave, d-tile generator (matrix-core path)
-constexpr int DSTAGE_MAX_WAVES = 8;     // d-stage workgroups: at most 512 threads
+constexpr int DSTAGE_MAX_WAVES = 8;     // inverse sweep / d-tile generator workgroups: at most 512 threads
+constexpr int FWD_MAX_WAVES = 16;       // forward sweep workgroups: at most 1024 threads (4, 8 or 16 waves)
 
 // One recursion run: fixed second index n of d^l_{m,n}; its A side feeds the
 // slice of spin -n at orders +m, its B side the slice of spin +n at orders -m.

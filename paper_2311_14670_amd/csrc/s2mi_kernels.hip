@@ -160,25 +160,25 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, const int *__
 constexpr int RN = 8;
 constexpr int PFD = 3;   // orders of record prefetch ahead of use (inverse sweep)
 
-// Workgroups of the sweeps hold W = 4 or 8 waves; the 4 x 64 outputs of an order
-// are reduced by one group of four waves, rotating with the order.
-static_assert(DSTAGE_MAX_WAVES == 8, "reducer rotation assumes at most two groups of four waves");
+// Workgroups of the sweeps hold W = 4, 8 or 16 waves; the 4 x 64 outputs of an
+// order are reduced by one group of four waves, rotating with the order.
 __device__ __forceinline__ int reducer_group(int m, int W)
 {
-    return W == 8 ? (m & 1) : 0;                          // m & 1 is the positive residue, also for m < 0
+    return m & ((W >> 2) - 1);                            // positive residue, also for m < 0
 }
 
-// Sum over the W waves of one output's partials in LDS.  The reads of all
-// DSTAGE_MAX_WAVES slots are issued together; slots of absent waves are read
-// (inside the buffer) but selected away, so stale contents never enter the sum.
+// Sum over the W waves of one output's partials in LDS.  The reads of all MAXW
+// slots are issued together; slots of absent waves are read (inside the
+// buffer) but selected away, so stale contents never enter the sum.
+template <int MAXW>
 __device__ __forceinline__ double wave_sum(const double *rb, int comp, int i, int W)
 {
-    double v[DSTAGE_MAX_WAVES];
+    double v[MAXW];
 #pragma unroll
-    for (int ww = 0; ww < DSTAGE_MAX_WAVES; ++ww) v[ww] = rb[(ww * 4 + comp) * 64 + i];
+    for (int ww = 0; ww < MAXW; ++ww) v[ww] = rb[(ww * 4 + comp) * 64 + i];
     double s = 0.0;
 #pragma unroll
-    for (int ww = 0; ww < DSTAGE_MAX_WAVES; ++ww) s += ww < W ? v[ww] : 0.0;
+    for (int ww = 0; ww < MAXW; ++ww) s += ww < W ? v[ww] : 0.0;
     return s;
 }
 
@@ -284,7 +284,8 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
     if (tr >= 0 && tr < 256) {
         const int rl = tr & 63, comp = tr >> 6;         // rl == lane: this thread's ring
-        const double s = wave_sum(rb, comp, rl, W);
+        double s = 0.0;                                 // a plain loop: fewer scalar registers than wave_sum
+        for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
         // Orders below the ring's switch order ms come from the run that is stable
         // there (n cos(theta) < 0): it writes its own sides at m >= 0 and, from its
         // continuation to m > -ms, the A slice at order m < 0 (components 2,3 at |m|)
@@ -454,7 +455,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
     if (HEAD) real = 0u;                                  // degrees start in this group: not realised
     if ((m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
-    double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * 4 * 64;
+    double *rb = red + (size_t)(m & 1) * FWD_MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
     rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
     rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
@@ -464,7 +465,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     if (tr >= 0 && tr < 256) {
         const int ll = tr & 63, comp = tr >> 6;
         const int lo = 64 * g + ll;
-        const double s = wave_sum(rb, comp, ll, W);
+        const double s = wave_sum<FWD_MAX_WAVES>(rb, comp, ll, W);
         if (MAIN) {
             if (lo < L && lo >= m && (m > 0 || comp < 2)) {
                 double *dst = comp < 2 ? QA : QB;
@@ -490,14 +491,14 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
 }
 
 template <int NCH>
-__global__ __launch_bounds__(512) void k_dstage_fwd(
+__global__ __launch_bounds__(64 * FWD_MAX_WAVES) void k_dstage_fwd(
     int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
     const double *__restrict__ HA, const double *__restrict__ HB, const double *__restrict__ HxA,
     const double *__restrict__ HxB, double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
     double *__restrict__ QxB)
 {
-    __shared__ double red[2 * DSTAGE_MAX_WAVES * 4 * 64];
+    __shared__ double red[2 * FWD_MAX_WAVES * 4 * 64];
     const int an = n < 0 ? -n : n;
     const int mend = an > 1 ? -(an - 1) : 0;            // continuation below m = 0
     const int lane = threadIdx.x & 63;
@@ -1055,7 +1056,8 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
                              const double *HxB, double *QA, double *QB, double *QxA, double *QxB)
 {
-    if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
+    if ((nwaves != 4 && nwaves != 8 && nwaves != 16) || nwaves > FWD_MAX_WAVES)
+        return hipErrorInvalidValue;                                // reducer rotation: 1, 2 or 4 groups of 4
     dim3 grid((G + 1) / 2, nblk);
     hipLaunchKernelGGL(k_dstage_fwd<FWD_NCH>, grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride, n, G, lam,
                        init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);

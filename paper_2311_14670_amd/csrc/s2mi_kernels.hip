@@ -404,8 +404,10 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
 }
 
 // HEAD: degrees of the group start in this pair of orders.  MAIN: m >= |n|
-// (no low-order copies, no continuation outputs).
-template <int NCH, int PAR, bool HEAD, bool MAIN = false>
+// (no low-order copies, no continuation outputs).  SAME (with MAIN, m > 0): both
+// sides read one spectra array (run n = 0), so a ring's four components form one
+// contiguous record and the wave's row is fetched with wide scalar loads.
+template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false>
 __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
                                          int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
                                          double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk, double &gm,
@@ -435,7 +437,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     const int am = MAIN ? m : (m < 0 ? -m : m);
     const bool low = !MAIN && m < an;
     const double *HAm = (low ? HxA : HA) + ((size_t)am * hstride + rbase) * 4 + (!MAIN && m < 0 ? 2 : 0);
-    const double *HBm = (low ? HxB : HB) + ((size_t)am * hstride + rbase) * 4 + (m > 0 ? 2 : 0);
+    const double *HBm = SAME ? HAm + 2 : (low ? HxB : HB) + ((size_t)am * hstride + rbase) * 4 + (m > 0 ? 2 : 0);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const double *Lc = Lm + c * SG;
@@ -490,7 +492,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
 }
 
-template <int NCH>
+template <int NCH, bool SAME>
 __global__ __launch_bounds__(64 * FWD_MAX_WAVES) void k_dstage_fwd(
     int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
@@ -556,14 +558,15 @@ __global__ __launch_bounds__(64 * FWD_MAX_WAVES) void k_dstage_fwd(
                                        Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
                                        QxA, QxB);
         }
-        for (; m - 1 >= an; m -= 2) {                     // both orders of the pair >= |n|
+        // both orders of the pair >= |n| (and > 0 when the sides share one array)
+        for (; m - 1 >= (SAME ? max(an, 1) : an); m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, false, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y,
-                                          E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA,
-                                          QxB);
-            fwd_step<NCH, 1, false, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
-                                          Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
-                                          QxA, QxB);
+            fwd_step<NCH, 0, false, true, SAME>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase,
+                                                X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk,
+                                                QA, QB, QxA, QxB);
+            fwd_step<NCH, 1, false, true, SAME>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg,
+                                                rbase, X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
+                                                blk, QA, QB, QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             prefetch(m);
@@ -1059,8 +1062,12 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
     if ((nwaves != 4 && nwaves != 8 && nwaves != 16) || nwaves > FWD_MAX_WAVES)
         return hipErrorInvalidValue;                                // reducer rotation: 1, 2 or 4 groups of 4
     dim3 grid((G + 1) / 2, nblk);
-    hipLaunchKernelGGL(k_dstage_fwd<FWD_NCH>, grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride, n, G, lam,
-                       init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
+    if (HA == HB)                                                   // run n = 0: one spectra array
+        hipLaunchKernelGGL((k_dstage_fwd<FWD_NCH, true>), grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride,
+                           n, G, lam, init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
+    else
+        hipLaunchKernelGGL((k_dstage_fwd<FWD_NCH, false>), grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride,
+                           lstride, n, G, lam, init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

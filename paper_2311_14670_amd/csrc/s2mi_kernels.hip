@@ -492,8 +492,8 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
 }
 
-template <int NCH, bool SAME>
-__global__ __launch_bounds__(64 * FWD_MAX_WAVES) void k_dstage_fwd(
+template <int NCH, bool SAME, int WT>
+__global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
     const double *__restrict__ HA, const double *__restrict__ HB, const double *__restrict__ HxA,
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(64 * FWD_MAX_WAVES) void k_dstage_fwd(
     const int mend = an > 1 ? -(an - 1) : 0;            // continuation below m = 0
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
-    const int W = blockDim.x >> 6;
+    constexpr int W = WT;                                // waves per workgroup (== blockDim.x / 64)
     const int blk = blockIdx.y;
     const int p = blockIdx.x;
     // this wave's rings: rbase .. rbase + NCH SG - 1 (contiguous; >= nreg inert)
@@ -1062,12 +1062,16 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
     if ((nwaves != 4 && nwaves != 8 && nwaves != 16) || nwaves > FWD_MAX_WAVES)
         return hipErrorInvalidValue;                                // reducer rotation: 1, 2 or 4 groups of 4
     dim3 grid((G + 1) / 2, nblk);
-    if (HA == HB)                                                   // run n = 0: one spectra array
-        hipLaunchKernelGGL((k_dstage_fwd<FWD_NCH, true>), grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride,
-                           n, G, lam, init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
-    else
-        hipLaunchKernelGGL((k_dstage_fwd<FWD_NCH, false>), grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride,
-                           lstride, n, G, lam, init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
+    // the wave count is a template argument: the reducer rotation and the wave sum
+    // then compile to fixed code; HA == HB (run n = 0) selects the one-array path
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride, n, G, lam, init, kap,
+                           gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
+    };
+    const bool same = HA == HB;
+    if (nwaves == 16) same ? go(k_dstage_fwd<FWD_NCH, true, 16>) : go(k_dstage_fwd<FWD_NCH, false, 16>);
+    else if (nwaves == 8) same ? go(k_dstage_fwd<FWD_NCH, true, 8>) : go(k_dstage_fwd<FWD_NCH, false, 8>);
+    else same ? go(k_dstage_fwd<FWD_NCH, true, 4>) : go(k_dstage_fwd<FWD_NCH, false, 4>);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -305,8 +305,8 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
     }
 }
 
-template <int NCH>
-__global__ __launch_bounds__(512) void k_dstage_inv(
+template <int NCH, int WT>
+__global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     int L, int nx, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
     const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(512) void k_dstage_inv(
     const int an = n < 0 ? -n : n;
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
-    const int W = blockDim.x >> 6;
+    constexpr int W = WT;                                // waves per workgroup (== blockDim.x / 64)
     const int blk = blockIdx.y;
     const int ring0 = blockIdx.x * 64;
     const int ring = min(ring0 + lane, nreg - 1);
@@ -1048,8 +1048,12 @@ hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx
 {
     if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
     dim3 grid((nreg + 63) / 64, nblk);
-    hipLaunchKernelGGL(k_dstage_inv<INV_NCH>, grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init, C,
-                       lchunk, mtop, partA, partB);
+    if (nwaves == 8)                                                // wave count as a template argument
+        hipLaunchKernelGGL((k_dstage_inv<INV_NCH, 8>), grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init,
+                           C, lchunk, mtop, partA, partB);
+    else
+        hipLaunchKernelGGL((k_dstage_inv<INV_NCH, 4>), grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init,
+                           C, lchunk, mtop, partA, partB);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -374,7 +374,7 @@ __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int 
     return init + (size_t)r0 * L + m;
 }
 
-template <int PAR, bool HEAD>
+template <int PAR, bool HEAD, bool REAL = false>
 __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ Lm,
                                           const double *__restrict__ HA, const double *__restrict__ HB, double kk,
                                           bool init, int nval, const double2 *__restrict__ iv, int istride, double &aAr,
@@ -393,7 +393,7 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
                 od = 0.0;
             }
         }
-        const double t = ldexp(nw, E[k]);               // exact scaling; 0 below the double range
+        const double t = REAL ? nw : ldexp(nw, E[k]);   // exact scaling; 0 below the double range
         const double *ha = HA + k * 4;                   // components chosen by the caller's offsets
         const double *hb = HB + k * 4;
         aAr = fma(t, ha[0], aAr);
@@ -407,7 +407,9 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
 // (no low-order copies, no continuation outputs).  SAME (with MAIN, m > 0): both
 // sides read one spectra array (run n = 0), so a ring's four components form one
 // contiguous record and the wave's row is fetched with wide scalar loads.
-template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false>
+// REAL (with MAIN): every chunk is realised (all E == 0), which stays so in the
+// main loop since no degree starts there: no scaling and no renormalisation.
+template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false, bool REAL = false>
 __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
                                          int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
                                          double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk, double &gm,
@@ -452,11 +454,11 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
             fwd_chunk<PAR, true>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval, init_tab_ptr(init, r0, m < 0 ? 0 : m, L),
                                  L, aAr, aAi, aBr, aBi);
         } else {
-            fwd_chunk<PAR, false>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr, aBi);
+            fwd_chunk<PAR, false, REAL>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr, aBi);
         }
     }
     if (HEAD) real = 0u;                                  // degrees start in this group: not realised
-    if ((m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
+    if (!REAL && (m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
     double *rb = red + (size_t)(m & 1) * FWD_MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
     rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
@@ -559,7 +561,9 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
                                        QxA, QxB);
         }
         // both orders of the pair >= |n| (and > 0 when the sides share one array)
-        for (; m - 1 >= (SAME ? max(an, 1) : an); m -= 2) {
+        constexpr uint32_t ALL = (1u << NCH) - 1u;
+        const int mlo = SAME ? max(an, 1) : an;
+        for (; m - 1 >= mlo && real != ALL; m -= 2) {
             prefetch(m);
             fwd_step<NCH, 0, false, true, SAME>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase,
                                                 X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk,
@@ -567,6 +571,15 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             fwd_step<NCH, 1, false, true, SAME>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg,
                                                 rbase, X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
                                                 blk, QA, QB, QxA, QxB);
+        }
+        for (; m - 1 >= mlo; m -= 2) {                   // realised: plain contributions
+            prefetch(m);
+            fwd_step<NCH, 0, false, true, SAME, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg,
+                                                      rbase, X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA,
+                                                      HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_step<NCH, 1, false, true, SAME, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride,
+                                                      nreg, rbase, X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB,
+                                                      HxA, HxB, red, blk, QA, QB, QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             prefetch(m);

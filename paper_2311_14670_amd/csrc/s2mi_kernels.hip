@@ -169,17 +169,19 @@ __device__ __forceinline__ int reducer_group(int m, int W)
 
 // Sum over the W waves of one output's partials in LDS.  The reads of all MAXW
 // slots are issued together; slots of absent waves are read (inside the
-// buffer) but selected away, so stale contents never enter the sum.
+// buffer) but selected away, so stale contents never enter the sum.  The sum is
+// a pairwise tree (depth log2 MAXW instead of a chain of MAXW dependent adds).
 template <int MAXW>
 __device__ __forceinline__ double wave_sum(const double *rb, int comp, int i, int W)
 {
     double v[MAXW];
 #pragma unroll
-    for (int ww = 0; ww < MAXW; ++ww) v[ww] = rb[(ww * 4 + comp) * 64 + i];
-    double s = 0.0;
+    for (int ww = 0; ww < MAXW; ++ww) v[ww] = ww < W ? rb[(ww * 4 + comp) * 64 + i] : 0.0;
 #pragma unroll
-    for (int ww = 0; ww < MAXW; ++ww) s += ww < W ? v[ww] : 0.0;
-    return s;
+    for (int h = MAXW / 2; h >= 1; h /= 2)
+#pragma unroll
+        for (int ww = 0; ww < h; ++ww) v[ww] += v[ww + h];
+    return v[0];
 }
 
 template <int NCH>

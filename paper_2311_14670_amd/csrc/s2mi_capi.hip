@@ -97,6 +97,7 @@ struct s2_plan_s {
     int hstride = 0;                       // ring stride of the forward spectra (padded to the sweep's slots)
     // workspace layout (bytes)
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
+    size_t off_fscr = 0, sz_fscr = 0;      // split-Bluestein scratch: FFT_SCRATCH complex per FFT workgroup
     size_t szC = 0, szP = 0, szF = 0, szQ = 0;
     size_t off_Hx = 0, off_Qx = 0, szHx = 0, szQx = 0;
 
@@ -181,7 +182,11 @@ int build_fft(s2_plan_s *P, int n, Staging &stg, hipStream_t st, FftArgs *out)
         int M = 1;
         while (M < 2 * n - 1) M *= 2;
         f.len = M;
-        factor_radices(M, rad);
+        if (M > FFT_MAX_LEN && M / 2 <= FFT_MAX_LEN && n < M / 2) {
+            f.split = 1;                                   // two LDS-resident halves of length M/2
+            f.len = M / 2;
+        }
+        factor_radices(f.len, rad);
     }
     if (f.len > FFT_MAX_LEN)
         return fail(S2_ERR_UNSUPPORTED, "DFT length %d needs an engine of %d points (> %d)", n, f.len, FFT_MAX_LEN);
@@ -199,9 +204,18 @@ int build_fft(s2_plan_s *P, int n, Staging &stg, hipStream_t st, FftArgs *out)
         host_chirp(n, &stg.d.back());
         double *ch, *bf;
         if ((rc = upload(P, &ch, stg.d.back(), st, "bluestein chirp"))) return rc;
-        if ((rc = P->dalloc(&bf, 2 * (size_t)f.len, "bluestein filter"))) return rc;
+        const int conv = f.split ? 2 * f.len : f.len;    // convolution length
+        if ((rc = P->dalloc(&bf, 2 * (size_t)conv, "bluestein filter"))) return rc;
         f.chirp = ch;
         f.bflt = bf;
+        if (f.split) {
+            stg.d.emplace_back();
+            host_roots(conv, &stg.d.back());
+            stg.d.back().resize(2 * (size_t)f.len);       // e^{-2 pi i k/conv}, k < len
+            double *wm;
+            if ((rc = upload(P, &wm, stg.d.back(), st, "bluestein split roots"))) return rc;
+            f.twm = wm;
+        }
     }
     *out = f;
     return S2_OK;
@@ -485,6 +499,12 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->szQx = (size_t)P->fwd_nblk * L * std::max(P->nxp, 1) * 4 * sizeof(double);
         P->off_Hx = o; o += P->nxp > 0 ? align256(2 * P->szHx * P->runs.size()) : 0;
         P->off_Qx = o; o += P->nxp > 0 ? align256(P->szQx * S) : 0;
+        bool split = false;
+        for (const FftArgs &f : P->ffts_h) split = split || (f.blue && f.split);
+        // one FFT_SCRATCH slice per workgroup of the phi-DFT (hstride), inverse phi-DFT
+        // (nring) and MW filter (L) launches
+        P->sz_fscr = split ? (size_t)std::max({P->hstride, P->nring, L}) * FFT_SCRATCH * sizeof(double2) : 0;
+        P->off_fscr = o; o += align256(P->sz_fscr);
         P->ws_bytes = o;
     }
 
@@ -605,6 +625,12 @@ int check_call(const char *fn, s2_plan_t P, const void *in, const void *out, int
     return S2_OK;
 }
 
+// the workspace's split-Bluestein scratch (nullptr when no DFT of the plan needs it)
+double2 *fft_scratch(const s2_plan_s *P, char *ws)
+{
+    return P->sz_fscr ? reinterpret_cast<double2 *>(ws + P->off_fscr) : nullptr;
+}
+
 // inverse d-stage of one (map, all slices): flm slices [S][L][2L-1] -> partials P[slice][blk][ring][m][4]
 int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double *> &wl, char *ws, hipStream_t st)
 {
@@ -647,7 +673,7 @@ int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, con
         TIMED(S2_STAGE_PHI_INV);
         HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, P->nreg, P->inv_nblk, P->slice_spin[k],
                               P0 + k * nP, P->mtop, flm + k * slab, wl[k], P->ring_nphi, P->ring_start,
-                              P->ring_shift, P->ring_fft, P->ffts, slice_maps[k]), "inverse phi-DFT");
+                              P->ring_shift, P->ring_fft, P->ffts, slice_maps[k], fft_scratch(P, ws)), "inverse phi-DFT");
     }
     return S2_OK;
 }
@@ -666,13 +692,14 @@ int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *map, char *ws
     {
     TIMED(S2_STAGE_MW_THETA);
     HIPCHK(launch_fadj_gather(st, L, P->inv_nblk, s, P0, P->mtop, G, P->w_sht[0], P->hstride, F0), "adjoint gather");
-    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0),
-           "MW theta filter");
+    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
+                            fft_scratch(P, ws)), "MW theta filter");
     HIPCHK(launch_fadj_scatter(st, L, P->hstride, q, F0, hp0, Q0), "adjoint scatter");
     }
     TIMED(S2_STAGE_PHI_INV);
     HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, L, 1, s, Q0, P->mtop1, G, P->w_sht[0],
-                          P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, map), "adjoint phi-DFT");
+                          P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, map, fft_scratch(P, ws)),
+           "adjoint phi-DFT");
     return S2_OK;
 }
 
@@ -734,12 +761,13 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
         {
         TIMED(S2_STAGE_PHI_FWD);
         HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L, q, slice_maps[k], P->ring_nphi,
-                              P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F), "forward phi-DFT");
+                              P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F, fft_scratch(P, ws)),
+                   "forward phi-DFT");
         }
         TIMED(S2_STAGE_MW_THETA);
         if (mw && !adjoint)
             HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, P->slice_spin[k], P->ffts, P->wq, P->ph, F,
-                                    hp0 + k * (2 * L - 1)), "MW theta filter");
+                                    hp0 + k * (2 * L - 1), fft_scratch(P, ws)), "MW theta filter");
         else if (mw)
             HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp0 + k * (2 * L - 1)), "pole line");
     }
@@ -794,7 +822,7 @@ int run_inverse_mfma(s2_plan_t P, const double2 *flm, int B, double2 *maps, cons
             HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, P->nreg, 1, P->slice_spin[k],
                                   Pm + ((size_t)b * S + k) * nP1, P->mtop1, flm + ((size_t)b * S + k) * slab, wl[k],
                                   P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts,
-                                  maps + ((size_t)b * S + k) * P->nsamp), "inverse phi-DFT");
+                                  maps + ((size_t)b * S + k) * P->nsamp, fft_scratch(P, ws)), "inverse phi-DFT");
         }
     return S2_OK;
 }
@@ -831,13 +859,14 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             {
             TIMED(S2_STAGE_PHI_FWD);
             HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L, q, maps + bk * P->nsamp,
-                                  P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F),
+                                  P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F, fft_scratch(P, ws)),
                    "forward phi-DFT");
             }
             TIMED(S2_STAGE_MW_THETA);
             if (mw && !adjoint)
                 HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, P->slice_spin[k], P->ffts,
-                                        P->wq, P->ph, F, hp + bk * (2 * L - 1)), "MW theta filter");
+                                        P->wq, P->ph, F, hp + bk * (2 * L - 1), fft_scratch(P, ws)),
+                   "MW theta filter");
             else if (mw)
                 HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp + bk * (2 * L - 1)), "pole line");
         }

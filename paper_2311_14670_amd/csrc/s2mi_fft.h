@@ -218,37 +218,67 @@ __device__ __forceinline__ void fft_engine(double2 *buf, const FftArgs *f, int s
 
 // Unnormalised DFT of length f.n of buf[0..n) in LDS (buf must hold f.len
 // entries).  sign = -1: forward, +1: inverse.  Leaves the result in buf[0..n).
-__device__ __forceinline__ void dft_lds(double2 *buf, const FftArgs *f, int sign)
+//
+// Bluestein (lengths with a prime factor above 13): the inverse is
+// conj(DFT(conj(x))); the chirped input u_j = x_j conj(c_j) is convolved with
+// the chirp by a forward FFT, a product with the filter spectrum and an inverse
+// FFT, then de-chirped.
+//
+// Split Bluestein (convolution length M = 2H, H = f.len the LDS engine length,
+// n < H): u is zero past n < H, so the even spectrum samples U[2k] are
+// DFT_H(u)[k] and the odd ones U[2k+1] are DFT_H(u w^j)[k], w = e^{-2 pi i/M}.
+// The inverse transform of V = U b~ is needed only at t < n < H, where it is
+// IDFT_H(V_even)[t] + conj(w)^t IDFT_H(V_odd)[t].  The halves run one after the
+// other in the same LDS buffer; u and the even result wait in scr (2H entries
+// of this workgroup's global scratch, each read back only by the thread that
+// wrote it).
+//
+// All forms run as one loop over engine passes, so the engine is inlined once
+// per call site.
+__device__ __forceinline__ void dft_lds(double2 *buf, const FftArgs *f, int sign, double2 *scr = nullptr)
 {
-    if (!f->blue) {
-        fft_engine(buf, f, sign);
-        return;
-    }
-    const double2 *ch = reinterpret_cast<const double2 *>(f->chirp);
-    const double2 *bf = reinterpret_cast<const double2 *>(f->bflt);
     const int T = blockDim.x, tid = threadIdx.x;
     const int n = f->n, len = f->len;
-    // the inverse is conj(DFT(conj(x)))
-    for (int i = tid; i < len; i += T) {
-        if (i < n) {
-            double2 x = buf[i];
-            if (sign > 0) x.y = -x.y;
-            buf[i] = cmulc(x, ch[i]);
-        } else {
-            buf[i] = make_double2(0.0, 0.0);
+    const int blue = f->blue, split = blue && f->split;
+    const double2 *ch = reinterpret_cast<const double2 *>(f->chirp);
+    const double2 *bf = reinterpret_cast<const double2 *>(f->bflt);
+    const double2 *wm = reinterpret_cast<const double2 *>(f->twm);
+    const int npass = !blue ? 1 : (split ? 4 : 2);
+#pragma unroll 1
+    for (int pass = 0; pass < npass; ++pass) {
+        if (blue) {
+            if (pass == 0) {                                 // chirp (zero-padded to len)
+                for (int i = tid; i < len; i += T) {
+                    double2 v = make_double2(0.0, 0.0);
+                    if (i < n) {
+                        double2 x = buf[i];
+                        if (sign > 0) x.y = -x.y;
+                        v = cmulc(x, ch[i]);
+                    }
+                    if (split) scr[i] = v;
+                    buf[i] = v;
+                }
+            } else if (pass == 2) {                          // split: odd half input u w^j
+                for (int i = tid; i < len; i += T) buf[i] = cmul(scr[i], wm[i]);
+            } else {                                         // filter spectrum (split: even / odd samples)
+                const int stp = split ? 2 : 1, off = pass == 3 ? 1 : 0;
+                for (int i = tid; i < len; i += T) buf[i] = cmul(buf[i], bf[stp * i + off]);
+            }
+            __syncthreads();
         }
+        fft_engine(buf, f, !blue ? sign : ((pass & 1) ? +1 : -1));
+        if (split && pass == 1)                              // keep the even half's result
+            for (int i = tid; i < len; i += T) scr[len + i] = buf[i];
     }
-    __syncthreads();
-    fft_engine(buf, f, -1);
-    for (int i = tid; i < len; i += T) buf[i] = cmul(buf[i], bf[i]);
-    __syncthreads();
-    fft_engine(buf, f, +1);
-    for (int i = tid; i < n; i += T) {
-        double2 y = cmulc(buf[i], ch[i]);
-        if (sign > 0) y.y = -y.y;
-        buf[i] = y;
+    if (blue) {                                              // (combine and) de-chirp
+        for (int i = tid; i < n; i += T) {
+            const double2 v = split ? cadd(scr[len + i], cmulc(buf[i], wm[i])) : buf[i];
+            double2 y = cmulc(v, ch[i]);
+            if (sign > 0) y.y = -y.y;
+            buf[i] = y;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 }  // namespace s2mi

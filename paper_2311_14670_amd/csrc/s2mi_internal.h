@@ -34,17 +34,21 @@ void host_weights(int L, int kind, int spin, std::vector<double> *w);
 constexpr int FFT_MAX_STAGES = 16;
 constexpr int FFT_MAX_LEN = 8192;        // LDS-resident engine length (complex doubles)
 constexpr int FFT_THREADS = 1024;
+constexpr size_t FFT_SCRATCH = 2 * (size_t)FFT_MAX_LEN;   // split Bluestein: complex scratch entries per workgroup
 
 // Everything a kernel needs to run one DFT of length n in LDS (passed by value).
 struct FftArgs {
     int n;            // logical DFT length
-    int len;          // engine length: n (mixed radix) or a power of two >= 2n-1 (Bluestein)
+    int len;          // engine length: n (mixed radix) or a power of two >= 2n-1 (Bluestein);
+                      // split Bluestein: half the convolution length M = 2 len
     int blue;         // 1: Bluestein
+    int split;        // 1: Bluestein convolution of length 2 len done as two LDS-resident halves
     int nst;          // engine stages
     int rad[FFT_MAX_STAGES];
     const double *tw;     // e^{-2 pi i k/len}, k < len (interleaved)
     const double *chirp;  // Bluestein: e^{+i pi k^2/n}, k < n
-    const double *bflt;   // Bluestein: FFT_len of the chirp filter, divided by len
+    const double *bflt;   // Bluestein: FFT of the chirp filter over the convolution length, divided by it
+    const double *twm;    // split: e^{-2 pi i k/(2 len)}, k < len
 };
 
 // ----------------------------------------------------------------- d-stage geometry

@@ -651,7 +651,7 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
     const double2 *__restrict__ flm,
     const double *__restrict__ wl, const int *__restrict__ ring_nphi, const long long *__restrict__ ring_start,
     const int *__restrict__ ring_shift, const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts,
-    double2 *__restrict__ map)
+    double2 *__restrict__ map, double2 *__restrict__ fscr)
 {
     extern __shared__ double2 buf[];
     __shared__ double2 red[1024];
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
         if (tid == 0) buf[((spin % nphi) + nphi) % nphi] = red[0];
     }
     __syncthreads();
-    dft_lds(buf, f, +1);
+    dft_lds(buf, f, +1, fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr);
     double2 *out = map + ring_start[r];
     for (int k = tid; k < nphi; k += T) out[k] = buf[k];
 }
@@ -722,7 +722,8 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
 __global__ __launch_bounds__(1024) void k_phi_fwd(
     int L, int nring, int hstride, double q, const double2 *__restrict__ map, const int *__restrict__ ring_nphi,
     const long long *__restrict__ ring_start, const int *__restrict__ ring_shift,
-    const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, double *__restrict__ F)
+    const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, double *__restrict__ F,
+    double2 *__restrict__ fscr)
 {
     extern __shared__ double2 buf[];
     const int r = blockIdx.x;
@@ -741,7 +742,7 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
     const double2 *in = map + ring_start[r];
     for (int k = tid; k < nphi; k += T) buf[k] = in[k];
     __syncthreads();
-    dft_lds(buf, f, -1);
+    dft_lds(buf, f, -1, fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr);
     for (int m = tid; m < L; m += T) {
         double2 a = buf[m % nphi];
         double2 b = buf[(nphi - (m % nphi)) % nphi];
@@ -770,7 +771,8 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
 // In place: F[m][t] -> H[m][t]; the south-pole value goes to hpole[m].
 __global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin, const FftArgs *__restrict__ fN,
                                                     const double *__restrict__ wq, const double *__restrict__ ph,
-                                                    double *__restrict__ F, double2 *__restrict__ hpole)
+                                                    double *__restrict__ F, double2 *__restrict__ hpole,
+                                                    double2 *__restrict__ fscr)
 {
     extern __shared__ double2 buf[];
     const int m = blockIdx.x;
@@ -778,6 +780,7 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin
     const int T = blockDim.x, tid = threadIdx.x;
     const double par = ((m + spin) & 1) ? -1.0 : 1.0;
     const double2 *phc = reinterpret_cast<const double2 *>(ph);
+    double2 *scr = fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr;
     for (int side = 0; side < 2; ++side) {
         if (side == 1 && m == 0) break;
         // torus samples
@@ -789,16 +792,16 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin
             buf[t] = g;
         }
         __syncthreads();
-        dft_lds(buf, fN, -1);
+        dft_lds(buf, fN, -1, scr);
         for (int k = tid; k < N; k += T) buf[k] = cmul(buf[k], phc[k]);              // shift +pi/N
         __syncthreads();
-        dft_lds(buf, fN, +1);
+        dft_lds(buf, fN, +1, scr);
         for (int t = tid; t < N; t += T) { const double wv = wq[N + t]; buf[t].x *= wv; buf[t].y *= wv; }
         __syncthreads();
-        dft_lds(buf, fN, -1);
+        dft_lds(buf, fN, -1, scr);
         for (int k = tid; k < N; k += T) buf[k] = cmulc(buf[k], phc[k]);             // shift -pi/N
         __syncthreads();
-        dft_lds(buf, fN, +1);
+        dft_lds(buf, fN, +1, scr);
         for (int t = tid; t < N; t += T) {          // + g w'_theta (g re-read: F is rewritten only below)
             const int tt = t < L ? t : N - 1 - t;
             const double *src = F + ((size_t)m * hstride + tt) * 4 + 2 * side;
@@ -1012,6 +1015,10 @@ __global__ void k_debug_d(int L, int nreg, int n, const double *__restrict__ cot
 // ------------------------------------------------------------------ Bluestein filters
 // For every Bluestein transform: bflt = DFT_len(b) / len with b_j = c_j (j < n),
 // b_{len-j} = c_j (0 < j < n), 0 elsewhere -- the circular form of the chirp.
+// Split form (convolution length M = 2H, H = f.len): by decimation in
+// frequency the even samples are DFT_H(b_j + b_{j+H}) and the odd ones
+// DFT_H((b_j - b_{j+H}) w^j), w = e^{-2 pi i/M}; with n < H, b_j = c_j for
+// j < n and b_{j+H} = c_{H-j} for j > H - n.
 __global__ __launch_bounds__(1024) void k_bluestein_prep(const FftArgs *__restrict__ ffts)
 {
     extern __shared__ double2 buf[];
@@ -1019,6 +1026,24 @@ __global__ __launch_bounds__(1024) void k_bluestein_prep(const FftArgs *__restri
     if (!f->blue) return;
     const int n = f->n, len = f->len;
     const double2 *ch = reinterpret_cast<const double2 *>(f->chirp);
+    if (f->split) {
+        const double2 *wm = reinterpret_cast<const double2 *>(f->twm);
+        double2 *out = reinterpret_cast<double2 *>(const_cast<double *>(f->bflt));
+        const double inv = 1.0 / (2.0 * (double)len);
+        for (int half = 0; half < 2; ++half) {
+            for (int j = threadIdx.x; j < len; j += blockDim.x) {
+                const double2 lo = j < n ? ch[j] : make_double2(0.0, 0.0);
+                const double2 hi = (j > len - n) ? ch[len - j] : make_double2(0.0, 0.0);
+                buf[j] = half == 0 ? cadd(lo, hi) : cmul(csub(lo, hi), wm[j]);
+            }
+            __syncthreads();
+            fft_engine(buf, f, -1);
+            for (int k = threadIdx.x; k < len; k += blockDim.x)
+                out[2 * k + half] = make_double2(buf[k].x * inv, buf[k].y * inv);
+            __syncthreads();
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < len; i += blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
         if (i < n) v = ch[i];
@@ -1118,28 +1143,28 @@ hipError_t launch_lambda_table(hipStream_t st, int L, int nx, int nreg, int lstr
 hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk, int spin,
                           const double *part, const int *mtop, const double2 *flm, const double *wl,
                           const int *ring_nphi, const long long *ring_start, const int *ring_shift,
-                          const int *ring_fft, const FftArgs *ffts, double2 *map)
+                          const int *ring_fft, const FftArgs *ffts, double2 *map, double2 *fscr)
 {
     hipLaunchKernelGGL(k_phi_inv, dim3(nring), dim3(nthreads), lds, st, L, nreg, nblk, spin, part, mtop, flm, wl,
-                       ring_nphi, ring_start, ring_shift, ring_fft, ffts, map);
+                       ring_nphi, ring_start, ring_shift, ring_fft, ffts, map, fscr);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
                           const double2 *map, const int *ring_nphi, const long long *ring_start, const int *ring_shift,
-                          const int *ring_fft, const FftArgs *ffts, double *F)
+                          const int *ring_fft, const FftArgs *ffts, double *F, double2 *fscr)
 {
     hipLaunchKernelGGL(k_phi_fwd, dim3(hstride), dim3(nthreads), lds, st, L, nring, hstride, q, map, ring_nphi,
-                       ring_start, ring_shift, ring_fft, ffts, F);
+                       ring_start, ring_shift, ring_fft, ffts, F, fscr);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int hstride, int spin, const FftArgs *fN,
-                            const double *wq, const double *ph, double *F, double2 *hpole)
+                            const double *wq, const double *ph, double *F, double2 *hpole, double2 *fscr)
 {
-    hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, hstride, spin, fN, wq, ph, F, hpole);
+    hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, hstride, spin, fN, wq, ph, F, hpole, fscr);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -105,7 +105,9 @@ def _sample_orders(L):
     return np.array(sorted({0, 1, -1, 2, L // 2, -(L // 3), L - 2, -(L - 1), L - 1}))
 
 
-@pytest.mark.parametrize("L,spin", [(2048, 0), (1024, 2)])
+# L = 2049 and 4096: the ring DFT length 2L - 1 (4097 = 17 x 241, 8191 prime) needs a
+# Bluestein convolution of 16384 points, run as two LDS-resident halves
+@pytest.mark.parametrize("L,spin", [(2048, 0), (1024, 2), (2049, 0), (4096, 0), (2100, 2)])
 def test_mw_full_size_sampled(binding, L, spin):
     flm = flm_gaussian(L, spin, seed=1, scale="inv1pl")
     plan = binding.Plan(L, spin=spin)                # benchmark configuration: batch 1
@@ -125,8 +127,9 @@ def test_mw_full_size_sampled(binding, L, spin):
     assert np.all(a[~coeff_mask(L, spin)] == 0)
 
 
-def test_healpix_full_size_sampled(binding):
-    nside, L, spin = 1024, 2048, 0
+@pytest.mark.parametrize("nside,L", [(1024, 2048), (1100, 2200)])
+def test_healpix_full_size_sampled(binding, nside, L):
+    spin = 0                                         # nside 1100: cap rings up to 4396 points (split Bluestein)
     flm = flm_gaussian(L, spin, seed=18, scale="inv1pl")
     plan = binding.Plan(L, spin=spin, sampling="healpix", nside=nside)
     f = host(plan.inverse(dev(flm)))

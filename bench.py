@@ -100,6 +100,32 @@ def mixed_precision(L, batch, steps, dev, fp64_plan):
     return res
 
 
+def largest_size(L, steps, dev):
+    """The paper's largest MW size (one spin-0 map, FP64): ms per inverse+forward
+    pair and the round-trip error, beside the headline figure."""
+    import torch
+    from paper_2311_14670_amd import binding
+    from paper_2311_14670_amd.synth import flm_gaussian
+    flm = flm_gaussian(L, 0, seed=1, scale="inv1pl")
+    x = torch.from_numpy(flm).to(dev)
+    plan = binding.Plan(L, device=dev)
+    y = plan.forward(plan.inverse(x))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        y = plan.forward(plan.inverse(x))
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    err = float(np.linalg.norm(y.cpu().numpy() - flm) / np.linalg.norm(flm))
+    del plan, x, y
+    torch.cuda.empty_cache()
+    return {"workload": f"MW L={L} spin-0 inverse+forward pair, one map, complex128 Gaussian coefficients "
+                        "x 1/(1+l), seed 1", "L": L, "steps": steps, "ms_per_pair": ms, "pairs_per_s": 1e3 / ms,
+            "roundtrip_rel_l2": err}
+
+
 def cpu_baseline(L, spin, flm, nring_sample, norder_sample):
     import oracle
     oracle._load()
@@ -131,6 +157,8 @@ def main():
     ap.add_argument("--mixed-batch", type=int, default=64,
                     help="maps per call of the matrix-core (FP32 / split-BF16) comparison; 0 skips it")
     ap.add_argument("--mixed-steps", type=int, default=3)
+    ap.add_argument("--large-L", type=int, default=4096, help="also time one MW spin-0 pair at this L (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run plain device copies of MIB MiB (a reference for "
                          "hardware byte counters)")
@@ -223,6 +251,8 @@ def main():
         out["copy_calibration_bytes"] = n * 8
     if args.mixed_batch > 0 and spin == 0:
         out["mixed_precision"] = mixed_precision(L, args.mixed_batch, args.mixed_steps, dev, plan)
+    if args.large_L > 0 and args.large_steps > 0:
+        out["large_L"] = largest_size(args.large_L, args.large_steps, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, spin, flm, args.cpu_rings, args.cpu_orders)
     print(json.dumps(out), flush=True)

@@ -158,6 +158,9 @@ def main():
                     help="maps per call of the matrix-core (FP32 / split-BF16) comparison; 0 skips it")
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--large-L", type=int, default=4096, help="also time one MW spin-0 pair at this L (0: skip)")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="also serve a seeded mixed request stream (L in [64, --serving-lmax]); 0: skip")
+    ap.add_argument("--serving-lmax", type=int, default=1024)
     ap.add_argument("--large-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run plain device copies of MIB MiB (a reference for "
@@ -253,6 +256,9 @@ def main():
         out["mixed_precision"] = mixed_precision(L, args.mixed_batch, args.mixed_steps, dev, plan)
     if args.large_L > 0 and args.large_steps > 0:
         out["large_L"] = largest_size(args.large_L, args.large_steps, dev)
+    if args.serving_requests > 0:
+        from paper_2311_14670_amd.serving import run_mix
+        out["serving"] = run_mix(n_requests=args.serving_requests, lmax=args.serving_lmax, device=str(dev))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, spin, flm, args.cpu_rings, args.cpu_orders)
     print(json.dumps(out), flush=True)

@@ -89,6 +89,7 @@ class Scheduler:
                                      if the next free stream has none)
       resident_bytes() -> int        bytes held by cached plans and workspaces
       free_streams() -> int          streams with no batch in flight
+      can_launch(key) -> bool        (optional) a batch of the key could start now
       launch(key, requests) -> handle     enqueue a batch (non-blocking)
       poll() -> finished handles (each keeps its .requests)
       evict(nbytes, busy_keys) -> int     drop cached plans (LRU) not in use
@@ -112,12 +113,25 @@ class Scheduler:
     def submit(self, req):
         self.queue.append(req)
 
+    def _can_launch(self, key):
+        f = getattr(self.ex, "can_launch", None)
+        return True if f is None else f(key)
+
     def _form_batch(self):
-        head = self.queue[0]
+        """The oldest waiting request whose key can launch now (a key whose only
+        workspace is busy waits), plus later requests with the same key."""
+        start = None
+        for idx, r in enumerate(self.queue):
+            if self._can_launch(r.key):
+                start = idx
+                break
+        if start is None:
+            return None, []
+        head = self.queue[start]
         key = head.key
         limit = max(1, int(self.ex.batch_limit(key)))
         batch = [head]
-        for r in itertools.islice(self.queue, 1, None):
+        for r in itertools.islice(self.queue, start + 1, None):
             if len(batch) >= limit:
                 break
             if r.key == key:
@@ -136,6 +150,8 @@ class Scheduler:
         launched = 0
         while self.queue and self.ex.free_streams() > 0:
             key, batch = self._form_batch()
+            if not batch:
+                break          # every waiting key is busy: wait for a completion
             n = len(batch)
             while n > 0 and not self._fits(key, n):
                 n -= 1
@@ -145,8 +161,9 @@ class Scheduler:
                 if self.ex.evict(short, busy) > 0 and self._fits(key, 1):
                     continue
                 if not self.inflight:
-                    # does not fit even alone on an idle device: reject the head request
-                    r = self.queue.popleft()
+                    # does not fit even alone on an idle device: reject the request
+                    r = batch[0]
+                    self.queue.remove(r)
                     r.error = "request does not fit the HBM budget"
                     self.rejected.append(r)
                     continue
@@ -216,18 +233,69 @@ def latency_stats(requests):
 
 
 # --------------------------------------------------------------------------- GPU executor
+class _DeviceBuffer:
+    """Workspace memory taken with hipMalloc and returned with hipFree, outside the
+    caching allocator: evicted workspaces go straight back to the device instead of
+    staying reserved (and fragmented) in torch's cache.  Duck-types the parts of a
+    uint8 tensor the binding uses (device, numel, element_size, data_ptr)."""
+    _hip = None
+
+    def __init__(self, nbytes, device):
+        import ctypes
+        import torch
+        if _DeviceBuffer._hip is None:
+            _DeviceBuffer._hip = ctypes.CDLL("libamdhip64.so")
+        self.device = device
+        self.nbytes = int(nbytes)
+        self._ptr = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            rc = _DeviceBuffer._hip.hipMalloc(ctypes.byref(self._ptr), ctypes.c_size_t(self.nbytes))
+        if rc != 0:
+            raise torch.OutOfMemoryError(f"hipMalloc of {self.nbytes} bytes failed (error {rc})")
+
+    def numel(self):
+        return self.nbytes
+
+    def element_size(self):
+        return 1
+
+    def data_ptr(self):
+        return self._ptr.value
+
+    def free(self):
+        if self._ptr is not None and self._ptr.value:
+            import torch
+            with torch.cuda.device(self.device):
+                _DeviceBuffer._hip.hipFree(self._ptr)
+        self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 class _Handle:
     __slots__ = ("requests", "event", "stream_idx", "out_host", "footprint", "key", "keep")
 
 
 class GpuExecutor:
     """Runs batches through the C ABI on ``n_streams`` HIP streams (default
-    priority), with an LRU cache of plans and one workspace per (plan, stream).
+    priority), with an LRU cache of plans and their workspaces.
+
+    A workspace serves one batch at a time.  A key gets up to one workspace per
+    stream while its workspace is small (<= small_ws bytes), so batches of a hot
+    small key overlap; a key with a large workspace (tens of GB at L = 4096) gets
+    one, and its batches run one after the other.  Under memory pressure idle
+    workspaces are dropped first (cheap to re-create), then idle plans (their
+    host-side tables take ~1 s to rebuild at L = 4096).
 
     batch_bytes: target device bytes of one batch's buffers; the batch limit of
     a key is the number of its requests that fit (at least 1, at most max_batch)."""
 
-    def __init__(self, device="cuda:0", n_streams=4, max_batch=8, batch_bytes=2 << 30, keep_results=True):
+    def __init__(self, device="cuda:0", n_streams=4, max_batch=8, batch_bytes=2 << 30, keep_results=True,
+                 small_ws=2 << 30):
         import torch
         from . import binding
         self.torch, self.binding = torch, binding
@@ -236,8 +304,11 @@ class GpuExecutor:
         self.busy = [False] * n_streams
         self.max_batch = int(max_batch)
         self.batch_bytes = int(batch_bytes)
+        self.small_ws = int(small_ws)
         self.plans = collections.OrderedDict()      # key -> Plan (LRU order)
-        self.ws = {}                                # (key, stream) -> workspace tensor
+        self.ws = {}                                # key -> list of workspaces
+        self.ws_busy = set()                        # id() of workspaces with a batch in flight
+        self.ws_lru = collections.OrderedDict()     # id(workspace) -> (key, workspace), LRU order
         self.pending = []
         self.keep_results = keep_results
 
@@ -257,46 +328,80 @@ class GpuExecutor:
         self.plans.move_to_end(key)
         return p
 
-    def _next_stream(self):
-        return self.busy.index(False)
+    def _ws_bytes(self, key):
+        return max(int(self.plans[key].info["workspace_bytes"]), 256)
+
+    def _idle_ws(self, key):
+        for w in self.ws.get(key, []):
+            if id(w) not in self.ws_busy:
+                return w
+        return None
+
+    def _ws_slots(self, key):
+        return len(self.streams) if self._ws_bytes(key) <= self.small_ws else 1
+
+    def can_launch(self, key):
+        """A stream is free and the key has (or may add) an idle workspace."""
+        if self.free_streams() == 0:
+            return False
+        if key not in self.plans:
+            return True
+        return self._idle_ws(key) is not None or len(self.ws.get(key, [])) < self._ws_slots(key)
 
     def new_bytes(self, key):
-        p = self.plans.get(key)
-        if p is None:
+        if key not in self.plans:
             # create the plan now (host tables + constant upload) to learn its sizes; the
-            # bytes are reported here once and are resident from then on
-            p = self._plan(key)
-            return 0 if (key, 0) in self.ws else int(p.info["workspace_bytes"])
-        if False not in self.busy:
-            return 0
-        return 0 if (key, self._next_stream()) in self.ws else int(p.info["workspace_bytes"])
+            # plan's bytes are resident from then on, its first workspace is new
+            self._plan(key)
+            return self._ws_bytes(key)
+        return 0 if self._idle_ws(key) is not None else self._ws_bytes(key)
 
     def resident_bytes(self):
         tot = sum(int(p.info["plan_device_bytes"]) for p in self.plans.values())
-        return tot + sum(int(w.numel()) for w in self.ws.values())
+        return tot + sum(int(w.numel()) for ws in self.ws.values() for w in ws)
 
     def free_streams(self):
         return sum(1 for b in self.busy if not b)
 
+    def _drop_ws(self, key, w):
+        self.ws[key].remove(w)
+        if not self.ws[key]:
+            del self.ws[key]
+        self.ws_lru.pop(id(w), None)
+        n = int(w.numel())
+        w.free()
+        return n
+
     def evict(self, nbytes, busy_keys):
         freed = 0
-        for key in list(self.plans):
+        for wid, (key, w) in list(self.ws_lru.items()):            # idle workspaces, LRU first
             if freed >= nbytes:
                 break
-            if key in busy_keys:
+            if wid in self.ws_busy:
                 continue
-            p = self.plans.pop(key)
-            freed += int(p.info["plan_device_bytes"])
-            for s in range(len(self.streams)):
-                w = self.ws.pop((key, s), None)
-                if w is not None:
-                    freed += int(w.numel())
-            p.close()
+            freed += self._drop_ws(key, w)
+        for key in list(self.plans):                                  # then idle plans, LRU first
+            if freed >= nbytes:
+                break
+            if key in busy_keys or self.ws.get(key):
+                continue
+            freed += int(self.plans.pop(key).info["plan_device_bytes"])
+        if freed:
+            # hand freed torch blocks back to the device as well
+            self.torch.cuda.empty_cache()
         return freed
+
+    def _alloc(self, make):
+        """Allocate; on out-of-memory return cached blocks and retry once."""
+        try:
+            return make()
+        except self.torch.OutOfMemoryError:
+            self.torch.cuda.empty_cache()
+            return make()
 
     def launch(self, key, requests):
         torch = self.torch
-        s = self._next_stream()
+        s = self.busy.index(False)
         self.busy[s] = True
         plan = self._plan(key)
         stream = self.streams[s]
@@ -304,22 +409,26 @@ class GpuExecutor:
         h.requests, h.stream_idx = requests, s
         x_host = torch.from_numpy(np.stack([r.data for r in requests])).pin_memory()
         with torch.cuda.stream(stream):
-            ws = self.ws.get((key, s))
+            ws = self._idle_ws(key)
             if ws is None:
-                ws = plan.new_workspace()
-                self.ws[(key, s)] = ws
-            x = x_host.to(self.device, non_blocking=True)
+                nb = self._ws_bytes(key)
+                ws = self._alloc(lambda: _DeviceBuffer(nb, self.device))
+                self.ws.setdefault(key, []).append(ws)
+            self.ws_busy.add(id(ws))
+            self.ws_lru[id(ws)] = (key, ws)
+            self.ws_lru.move_to_end(id(ws))
+            x = self._alloc(lambda: x_host.to(self.device, non_blocking=True))
             if key.kind == "so3":
-                y = plan.so3_forward(plan.so3_inverse(x, workspace=ws), workspace=ws)
+                y = self._alloc(lambda: plan.so3_forward(plan.so3_inverse(x, workspace=ws), workspace=ws))
             else:
-                y = plan.forward(plan.inverse(x, workspace=ws), workspace=ws)
+                y = self._alloc(lambda: plan.forward(plan.inverse(x, workspace=ws), workspace=ws))
             out = torch.empty(y.shape, dtype=y.dtype, pin_memory=True) if self.keep_results else None
             if out is not None:
                 out.copy_(y, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
         h.event, h.out_host = ev, out
-        h.keep = (x_host, x, y)        # buffers stay referenced until the stream passes the event
+        h.keep = (x_host, x, y, ws)    # buffers stay referenced until the stream passes the event
         self.pending.append(h)
         return h
 
@@ -328,6 +437,7 @@ class GpuExecutor:
         for h in fin:
             self.pending.remove(h)
             self.busy[h.stream_idx] = False
+            self.ws_busy.discard(id(h.keep[3]))
             if h.out_host is not None:
                 res = h.out_host.numpy()
                 for i, r in enumerate(h.requests):
@@ -340,7 +450,12 @@ class GpuExecutor:
         for p in self.plans.values():
             p.close()
         self.plans.clear()
+        for ws in self.ws.values():
+            for w in ws:
+                w.free()
         self.ws.clear()
+        self.ws_busy.clear()
+        self.ws_lru.clear()
 
 
 def build_requests(trace, seed=3):
@@ -370,9 +485,10 @@ def run_mix(n_requests=200, seed=3, lmin=64, lmax=1024, so3_lmax=256, n_streams=
     out = {"requests": n_requests, "seed": seed, "L_range": [lmin, lmax], "so3_L_max": so3_lmax,
            "streams": n_streams, "max_batch": max_batch}
     try:
-        # warm pass builds every plan once, then the saturation pass
+        # warm pass over the whole trace builds every plan (host tables take up to ~1 s
+        # each) and workspace once, so the saturation pass measures steady-state serving
         sched = Scheduler(ex, hbm_budget=budget_frac * total)
-        serve(sched, build_requests(trace[: min(len(trace), 4 * n_streams)], seed), realtime=False)
+        serve(sched, build_requests(trace, seed), realtime=False)
         reqs = build_requests(trace, seed)
         sched = Scheduler(ex, hbm_budget=budget_frac * total)
         wall = serve(sched, reqs, realtime=False)

@@ -151,3 +151,20 @@ def test_trace_keys():
     assert hp and all(k.nside == k.L // 2 for k in hp)
     ts = [t["t"] for t in tr]
     assert ts == sorted(ts)
+
+
+def test_busy_key_waits_while_other_keys_launch():
+    """A key whose single workspace is in flight waits; later requests of other
+    keys take the free stream meanwhile (executor with one workspace per key)."""
+    clk = Clock()
+
+    class OneWorkspace(FakeExecutor):
+        def can_launch(self, key):
+            return self.free_streams() > 0 and all(h.requests[0].key != key for h in self.pending)
+
+    ex = OneWorkspace(clk, n_streams=2, max_batch=1)
+    s = Scheduler(ex, hbm_budget=1 << 40)
+    reqs = [_req(0, 8), _req(1, 8), _req(2, 16)]
+    serve(s, reqs, clock=clk, realtime=False, sleep=clk.sleep)
+    assert [ids for _, ids in ex.launches] == [[0], [2], [1]]
+    assert len(s.done) == 3 and not s.rejected

@@ -661,7 +661,29 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
     const FftArgs *f = ffts + ring_fft[r];
     const int shift = ring_shift[r];
     const int M = 2 * L - 1;
-    if (r < nreg) {
+    if (r < nreg && nphi == M) {
+        // one bin per order (MW): a thread per |m| reads whole 32-byte records (order +|m|
+        // in components 0,1, order -|m| in 2,3) and fills bins |m| and nphi - |m|
+        const double *pr = part + (size_t)r * L * 4;
+        const size_t bstride = (size_t)nreg * L * 4;
+        for (int am = tid; am < L; am += T) {
+            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+            for (int b = 0; b < nblk; ++b) {
+                if (am > mtop[b]) continue;                  // that block's sweep never reached order am
+                const double2 *pp = reinterpret_cast<const double2 *>(pr + b * bstride + am * 4);
+                va = cadd(va, pp[0]);
+                vb = cadd(vb, pp[1]);
+            }
+            if (shift) {
+                double s, c;   // e^{+- i pi am / nphi}
+                sincospi((double)(am % (2 * nphi)) / (double)nphi, &s, &c);
+                va = cmul(va, make_double2(c, s));
+                vb = cmul(vb, make_double2(c, -s));
+            }
+            buf[am] = va;
+            if (am > 0) buf[nphi - am] = vb;
+        }
+    } else if (r < nreg) {
         const double *pr = part + (size_t)r * L * 4;
         const size_t bstride = (size_t)nreg * L * 4;
         for (int k = tid; k < nphi; k += T) {
@@ -902,40 +924,50 @@ __global__ void k_fadj_scatter(int L, int hstride, double q, const double *__res
 // ------------------------------------------------------------------ forward finish
 // flm[l][m] = w_l * (sum_b Q[b][l][|m|].side + Qx[b][l][|m|].side) * ((-1)^{|m|-nB} for m < 0)
 //           + MW south pole: w_l (-1)^{l+s} h~_s(pi) at m = s  (Eq. 29).
-// Zero where l < max(|m|, |spin|).
+// Zero where l < max(|m|, |spin|).  One thread per (l, |m|) reads whole 32-byte
+// records (side A = order +|m| in components 0,1, side B = order -|m| in 2,3) and
+// writes both orders.
 __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__restrict__ Q,
                              const double *__restrict__ Qx, int nxp, const double *__restrict__ wl,
                              const double2 *__restrict__ hpole, double2 *__restrict__ flm)
 {
     const int M = 2 * L - 1;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)L * M) return;
-    const int l = (int)(i / M), m = (int)(i % M) - (L - 1);
-    const int am = m < 0 ? -m : m, as = spin < 0 ? -spin : spin;
-    double2 v = make_double2(0.0, 0.0);
+    if (i >= (size_t)L * L) return;
+    const int l = (int)(i / L), am = (int)(i % L);
+    const int as = spin < 0 ? -spin : spin;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
     if (l >= am && l >= as) {
-        const int off = m < 0 ? 2 : 0;
-        for (int b = 0; b < nblk; ++b) {
-            const double *q = Q + (((size_t)b * L + l) * L + am) * 4 + off;
-            v.x += q[0];
-            v.y += q[1];
-            if (Qx && am < nxp) {                       // orders below |n| from the other run's continuation
-                const double *qx = Qx + (((size_t)b * L + l) * nxp + am) * 4 + off;
-                v.x += qx[0];
-                v.y += qx[1];
+        for (int bb = 0; bb < nblk; ++bb) {
+            const double2 *q = reinterpret_cast<const double2 *>(Q + (((size_t)bb * L + l) * L + am) * 4);
+            const double2 qa = q[0], qb = q[1];
+            a = cadd(a, qa);
+            b = cadd(b, qb);
+            if (Qx && am < nxp) {                      // orders below |n| from the other run's continuation
+                const double2 *qx = reinterpret_cast<const double2 *>(Qx + (((size_t)bb * L + l) * nxp + am) * 4);
+                a = cadd(a, qx[0]);
+                b = cadd(b, qx[1]);
             }
         }
-        if (m < 0 && ((am - nB) & 1)) { v.x = -v.x; v.y = -v.y; }
-        v.x *= wl[l];
-        v.y *= wl[l];
-        if (hpole && m == spin) {
-            const double2 hp = hpole[(L - 1) + m];
-            const double c = ((l + spin) & 1) ? -wl[l] : wl[l];
-            v.x += c * hp.x;
-            v.y += c * hp.y;
+        const double w = wl[l];
+        const double wb = ((am - nB) & 1) ? -w : w;
+        a = make_double2(a.x * w, a.y * w);
+        b = make_double2(b.x * wb, b.y * wb);
+        if (hpole) {
+            const double c = ((l + spin) & 1) ? -w : w;
+            if (am == spin) {
+                const double2 hp = hpole[(L - 1) + am];
+                a = make_double2(fma(c, hp.x, a.x), fma(c, hp.y, a.y));
+            }
+            if (am > 0 && -am == spin) {
+                const double2 hp = hpole[(L - 1) - am];
+                b = make_double2(fma(c, hp.x, b.x), fma(c, hp.y, b.y));
+            }
         }
     }
-    flm[i] = v;
+    double2 *row = flm + (size_t)l * M + (L - 1);
+    row[am] = a;
+    if (am > 0) row[-am] = b;
 }
 
 // ------------------------------------------------------------------ SO(3) gamma DFT
@@ -1172,7 +1204,7 @@ hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
                              int nxp, const double *wl, const double2 *hpole, double2 *flm)
 {
-    const size_t tot = (size_t)L * (2 * L - 1);
+    const size_t tot = (size_t)L * L;
     hipLaunchKernelGGL(k_finish_fwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, nB, Q, Qx,
                        nxp, wl, hpole, flm);
     S2_LAUNCH_CHECK();

@@ -12,6 +12,9 @@ Arrays are numpy ``complex128``.  Layouts:
   * MW maps ``f[t, p]`` with ``theta_t = (2t+1) pi/(2L-1)``,
     ``phi_p = 2 pi p/(2L-1)`` (paper Sec. 4.2, MW);
   * HEALPix maps as the RING-ordered pixel vector;
+  * DH maps ``f[t, p]`` with ``theta_t = (2t+1) pi/(4L)``, t < 2L, and GL maps
+    ``f[t, p]`` with ``cos(theta_t)`` the roots of P_L (theta ascending), both
+    with ``phi_p = 2 pi p/(2L-1)`` (Sec. 4.2, DH and GL sampling theorems);
   * Wigner coefficients ``flmn[n + N - 1, l, m + L - 1]`` and SO(3) maps
     ``f[k, t, p]`` with ``gamma_k = 2 pi k/(2N-1)`` (Sec. 4.5).
 """
@@ -26,7 +29,7 @@ _SRC = os.path.join(_HERE, "s2oracle.c")
 _LIB = os.path.join(_HERE, "_s2oracle.so")
 _lib = None
 
-MW, HEALPIX = 0, 1
+MW, HEALPIX, DH, GL = 0, 1, 2, 3
 
 
 def build(force=True):
@@ -117,12 +120,29 @@ def gauss_legendre(n):
     return x, w
 
 
+def dh_nodes(L):
+    """DH colatitudes (2t+1) pi/(4L), t < 2L, and theta weights w_t with
+    sum_t w_t g(theta_t) = int_0^pi g sin(theta) for g of degree < 2L in cos(theta)."""
+    th, w = np.empty(2 * L), np.empty(2 * L)
+    _load().or_dh_nodes(L, _dp(th), _dp(w))
+    return th, w
+
+
+def gl_nodes(L):
+    """GL colatitudes (cos(theta) = roots of P_L, theta ascending) and weights in cos(theta)."""
+    th, w = np.empty(L), np.empty(L)
+    _load().or_gl_nodes(L, _dp(th), _dp(w))
+    return th, w
+
+
 def num_rings(L, sampling, nside=0):
-    return L if sampling == MW else 4 * nside - 1
+    return {MW: L, DH: 2 * L, GL: L}.get(sampling, 4 * nside - 1)
 
 
 def map_size(L, sampling, nside=0):
-    return L * (2 * L - 1) if sampling == MW else 12 * nside * nside
+    if sampling == HEALPIX:
+        return 12 * nside * nside
+    return num_rings(L, sampling) * (2 * L - 1)
 
 
 # ----------------------------------------------------------------- Wigner d
@@ -137,27 +157,28 @@ def wigner_d(L, m, n, beta):
 def s2_inverse(flm, L, spin=0, sampling=MW, nside=0, rings=None):
     """Inverse spin SHT by direct summation (Eqs. 4, 32-33).
 
-    Returns the MW map [L, 2L-1] / HEALPix pixel vector, or, with ``rings``,
-    the concatenated samples of the selected rings."""
+    Returns the MW / DH / GL map [rings, 2L-1] or the HEALPix pixel vector, or,
+    with ``rings``, the concatenated samples of the selected rings."""
     flm = _c128(flm)
     assert flm.shape == (L, 2 * L - 1)
     lib = _load()
     nsel, sel = _sel(rings)
-    if sampling == MW:
-        nout = (L if nsel < 0 else nsel) * (2 * L - 1)
+    if sampling != HEALPIX:
+        nout = (num_rings(L, sampling) if nsel < 0 else nsel) * (2 * L - 1)
     else:
         _, nphi, _, _ = healpix_rings(nside)
         nout = int(nphi.sum()) if nsel < 0 else int(nphi[np.asarray(rings)].sum())
     f = np.empty(nout, dtype=np.complex128)
     lib.or_s2_inverse(L, spin, sampling, nside, _dp(flm.view(np.float64)), _dp(f.view(np.float64)),
                       nsel, _ip(sel) if sel is not None else None)
-    if sampling == MW and nsel < 0:
-        return f.reshape(L, 2 * L - 1)
+    if sampling != HEALPIX and nsel < 0:
+        return f.reshape(num_rings(L, sampling), 2 * L - 1)
     return f
 
 
 def s2_forward(f, L, spin=0, sampling=MW, nside=0, ms=None):
-    """Forward spin SHT: exact MW transform (GL route) or HEALPix quadrature.
+    """Forward spin SHT: exact MW transform (GL route), HEALPix quadrature, or the
+    DH / GL sampling theorems' quadratures (exact for band-limited maps).
 
     With ``ms`` only those order columns are computed (others are zero)."""
     f = _c128(f).reshape(-1)

@@ -19,9 +19,13 @@
  *   Coefficient layout: flm[l][m + L - 1], complex interleaved (re, im).
  *   Entries with l < max(|m|, |s|) are ignored on input, zero on output.
  *
- * Samplings (paper Sec. 4.2):
- *   MW:      theta_t = (2t+1) pi / (2L-1), t < L;  phi_p = 2 pi p / (2L-1).
- *   HEALPix: RING-ordered pixels, geometry of Gorski et al. (2005).
+ * Samplings (paper Sec. 4.2), codes 0..3:
+ *   0 MW:      theta_t = (2t+1) pi / (2L-1), t < L;  phi_p = 2 pi p / (2L-1).
+ *   1 HEALPix: RING-ordered pixels, geometry of Gorski et al. (2005).
+ *   2 DH:      theta_t = (2t+1) pi / (4L), t < 2L;   phi_p = 2 pi p / (2L-1);
+ *              forward by the explicit DH quadrature weights.
+ *   3 GL:      cos(theta_t) = roots of P_L (theta ascending), t < L;
+ *              phi_p = 2 pi p / (2L-1); forward by Gauss-Legendre weights.
  *   SO(3):   MW in (beta, alpha), gamma_k = 2 pi k / (2N-1) (Sec. 4.5).
  *
  * Every complex exponential whose phase is a rational multiple of pi is
@@ -159,6 +163,38 @@ static void gl_nodes_ld(int n, long double *theta, double *w)
         theta[i] = acosl(z);
         w[i] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
     }
+}
+
+/* DH colatitudes and theta weights (Sec. 4.2, DH sampling theorem):
+ *   theta_t = (2t+1) pi / (4L),  t < 2L,
+ *   w_t = (2/L) sin(theta_t) sum_{k<L} sin((2k+1) theta_t) / (2k+1),
+ * so that sum_t w_t g(theta_t) = int_0^pi g sin(theta) dtheta for g of degree
+ * < 2L in cos(theta); the paper's weight is (2 pi/(2L-1)) w_t.             */
+static void dh_nodes_ld(int L, long double *theta, double *w)
+{
+    for (int t = 0; t < 2 * L; ++t) {
+        const long double th = (2.0L * t + 1.0L) * OR_PI_L / (4.0L * L);
+        long double acc = 0.0L;
+        for (int k = 0; k < L; ++k) acc += sinl((2.0L * k + 1.0L) * th) / (2.0L * k + 1.0L);
+        theta[t] = th;
+        w[t] = (double)(2.0L / L * sinl(th) * acc);
+    }
+}
+
+void or_dh_nodes(int L, double *theta, double *w)
+{
+    long double *th = (long double *)malloc(sizeof(long double) * 2 * L);
+    dh_nodes_ld(L, th, w);
+    for (int t = 0; t < 2 * L; ++t) theta[t] = (double)th[t];
+    free(th);
+}
+
+void or_gl_nodes(int L, double *theta, double *w)
+{
+    long double *th = (long double *)malloc(sizeof(long double) * L);
+    gl_nodes_ld(L, th, w);
+    for (int t = 0; t < L; ++t) theta[t] = (double)th[t];
+    free(th);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -337,13 +373,29 @@ static void ring_inverse(int L, int s, long double theta, int nphi, int shift, i
     free(rt);
 }
 
-/* Ring list helper: number of rings, theta, nphi, shift, offset in the map. */
-typedef struct { int nring; double *theta; long double *thl; int *nphi; int *shift; long long *start; } rings_t;
+/* Ring list helper: number of rings, theta, nphi, shift, offset in the map;
+ * for DH and GL also the theta weights of the forward quadrature.          */
+typedef struct { int nring; double *theta; long double *thl; int *nphi; int *shift; long long *start; double *wq; } rings_t;
 
 static rings_t make_rings(int L, int sampling, int nside)
 {
     rings_t R;
-    if (sampling == 0) {
+    R.wq = NULL;
+    if (sampling == 2 || sampling == 3) {
+        R.nring = sampling == 2 ? 2 * L : L;
+        R.theta = (double *)malloc(sizeof(double) * R.nring);
+        R.nphi = (int *)malloc(sizeof(int) * R.nring);
+        R.shift = (int *)malloc(sizeof(int) * R.nring);
+        R.start = (long long *)malloc(sizeof(long long) * R.nring);
+        R.thl = (long double *)malloc(sizeof(long double) * R.nring);
+        R.wq = (double *)malloc(sizeof(double) * R.nring);
+        if (sampling == 2) dh_nodes_ld(L, R.thl, R.wq);
+        else gl_nodes_ld(L, R.thl, R.wq);
+        for (int t = 0; t < R.nring; ++t) {
+            R.theta[t] = (double)R.thl[t];
+            R.nphi[t] = 2 * L - 1; R.shift[t] = 0; R.start[t] = (long long)t * (2 * L - 1);
+        }
+    } else if (sampling == 0) {
         R.nring = L;
         R.theta = (double *)malloc(sizeof(double) * L);
         R.nphi = (int *)malloc(sizeof(int) * L);
@@ -368,7 +420,10 @@ static rings_t make_rings(int L, int sampling, int nside)
     return R;
 }
 
-static void free_rings(rings_t *R) { free(R->theta); free(R->thl); free(R->nphi); free(R->shift); free(R->start); }
+static void free_rings(rings_t *R)
+{
+    free(R->theta); free(R->thl); free(R->nphi); free(R->shift); free(R->start); free(R->wq);
+}
 
 
 /* e^{-i pi k / nphi} tables for every distinct HEALPix ring length (index nphi/4). */
@@ -392,7 +447,10 @@ static void free_hp_root_tables(const rings_t *R, double **tab)
     free(tab);
 }
 
-int or_num_rings(int L, int sampling, int nside) { return sampling == 0 ? L : 4 * nside - 1; }
+int or_num_rings(int L, int sampling, int nside)
+{
+    return sampling == 0 || sampling == 3 ? L : sampling == 2 ? 2 * L : 4 * nside - 1;
+}
 
 void or_s2_inverse(int L, int s, int sampling, int nside, const double *flm, double *f,
                    int nsel, const int *rings)
@@ -412,7 +470,7 @@ void or_s2_inverse(int L, int s, int sampling, int nside, const double *flm, dou
         #pragma omp for schedule(dynamic, 1)
         for (int i = 0; i < nr; ++i) {
             const int r = (nsel < 0) ? i : rings[i];
-            ring_inverse(L, s, R.thl[r], R.nphi[r], R.shift[r], sampling == 0,
+            ring_inverse(L, s, R.thl[r], R.nphi[r], R.shift[r], sampling != 1,
                          flm, f + 2 * off[i], dbuf, ft);
         }
         free(dbuf); free(ft);
@@ -535,6 +593,8 @@ static void mw_theta_forward(int L, int m, int n, int parity, const double *gt,
  * Forward spin SHT.  MW: the exact transform of Sec. 4.2 (torus extension of
  * the ring DFTs, computed here by GL quadrature of the interpolant).
  * HEALPix: the plain quadrature of Eq. 19 with q = 4 pi / Npix.
+ * DH, GL: the quadrature of Eq. 19 with the sampling theorem's weights
+ * q_t = (2 pi / (2L-1)) w_t (exact for band-limited maps).
  * Only the orders in msel (nsel >= 0) are computed; other columns are zero.
  */
 void or_s2_forward(int L, int s, int sampling, int nside, const double *f, double *flm,
@@ -551,7 +611,7 @@ void or_s2_forward(int L, int s, int sampling, int nside, const double *f, doubl
     if (sampling == 0) gl_nodes_ld(L, thgl, wgl);
     double *rt2N = root_table(2 * M, -1);          /* e^{-i pi k / M} */
     double *rtM = root_table(M, -1);
-    double **hpt = (sampling == 0) ? NULL : hp_root_tables(&R);
+    double **hpt = (sampling == 1) ? hp_root_tables(&R) : NULL;
     const long long npix = 12LL * nside * nside;
     #pragma omp parallel
     {
@@ -571,11 +631,17 @@ void or_s2_forward(int L, int s, int sampling, int nside, const double *f, doubl
                 mw_theta_forward(L, m, -s, parity, gt, wl, thgl, wgl, rt2N, col, dbuf);
             } else {
                 for (int l = 0; l < L; ++l) { col[2 * l] = 0.0; col[2 * l + 1] = 0.0; }
-                const double q = (double)(4.0L * OR_PI_L / (long double)npix);
                 for (int r = 0; r < R.nring; ++r) {
-                    const int P = 2 * R.nphi[r];
                     double fm[2];
-                    ring_dft(f + 2 * R.start[r], R.nphi[r], R.shift[r], 0, m, L, hpt[R.nphi[r] / 4], P, fm);
+                    double q;
+                    if (sampling == 1) {
+                        q = (double)(4.0L * OR_PI_L / (long double)npix);
+                        ring_dft(f + 2 * R.start[r], R.nphi[r], R.shift[r], 0, m, L, hpt[R.nphi[r] / 4],
+                                 2 * R.nphi[r], fm);
+                    } else {
+                        q = (double)(2.0L * OR_PI_L / M) * R.wq[r];
+                        ring_dft(f + 2 * R.start[r], M, 0, 1, m, L, rtM, M, fm);
+                    }
                     wigner_d_ld(L, m, -s, R.thl[r], dbuf);
                     for (int l = 0; l < L; ++l) {
                         const double c = q * wl[l] * dbuf[l];
@@ -609,7 +675,7 @@ void or_s2_inverse_adjoint(int L, int s, int sampling, int nside, const double *
     rings_t R = make_rings(L, sampling, nside);
     const int nm = (nsel < 0) ? M : nsel;
     double *rtM = root_table(M, -1);
-    double **hpt = (sampling == 0) ? NULL : hp_root_tables(&R);
+    double **hpt = (sampling == 1) ? hp_root_tables(&R) : NULL;
     #pragma omp parallel
     {
         double *dbuf = (double *)malloc(sizeof(double) * L);
@@ -620,7 +686,7 @@ void or_s2_inverse_adjoint(int L, int s, int sampling, int nside, const double *
             for (int l = 0; l < L; ++l) { col[2 * l] = 0.0; col[2 * l + 1] = 0.0; }
             for (int r = 0; r < R.nring; ++r) {
                 double fm[2];
-                if (sampling == 0) ring_dft(g + 2 * R.start[r], M, 0, 1, m, L, rtM, M, fm);
+                if (sampling != 1) ring_dft(g + 2 * R.start[r], M, 0, 1, m, L, rtM, M, fm);
                 else ring_dft(g + 2 * R.start[r], R.nphi[r], R.shift[r], 0, m, L,
                               hpt[R.nphi[r] / 4], 2 * R.nphi[r], fm);
                 wigner_d_ld(L, m, -s, R.thl[r], dbuf);

@@ -149,7 +149,7 @@ def test_spin_raising_relation(oracle, spin):
                 assert abs(eth - ref) < 1e-7
 
 
-@pytest.mark.parametrize("sampling,L,nside", [(0, 12, 0), (1, 12, 4)])
+@pytest.mark.parametrize("sampling,L,nside", [(0, 12, 0), (1, 12, 4), (2, 9, 0), (3, 9, 0)])
 @pytest.mark.parametrize("spin", [0, 2])
 def test_adjoint_dot_product(oracle, sampling, L, nside, spin):
     """<F^{-1} a, b> = <a, (F^{-1})^H b>."""
@@ -246,3 +246,53 @@ def test_selected_rings_and_orders_match_full(oracle):
     fsel = oracle.s2_forward(full, L, s, ms=[-5, 0, 19])
     for m in [-5, 0, 19]:
         assert np.array_equal(fsel[:, m + L - 1], fwd[:, m + L - 1])
+
+
+# ----------------------------------------------------------------- DH and GL sampling theorems (Sec. 4.2)
+@pytest.mark.parametrize("L", [1, 2, 5, 16, 40])
+def test_gl_nodes_match_numpy(oracle, L):
+    """GL sampling: cos(theta_t) are the roots of P_L, weights the Gauss-Legendre
+    weights (numpy's leggauss is an independent implementation)."""
+    th, w = oracle.gl_nodes(L)
+    x, wr = np.polynomial.legendre.leggauss(L)
+    assert np.all(np.diff(th) > 0)                         # theta ascending
+    assert np.max(np.abs(np.cos(th) - x[::-1])) < 1e-14
+    assert np.max(np.abs(w - wr[::-1])) < 1e-14
+
+
+@pytest.mark.parametrize("L", [1, 3, 8, 17])
+def test_dh_weights_integrate_legendre_exactly(oracle, L):
+    """DH sampling: theta_t = (2t+1) pi/(4L), t < 2L, and the explicit weights
+    integrate every P_l(cos theta) sin(theta) with l < 2L exactly."""
+    th, w = oracle.dh_nodes(L)
+    assert np.allclose(th, (2 * np.arange(2 * L) + 1) * np.pi / (4 * L), rtol=0, atol=1e-15)
+    for l in range(2 * L):
+        ref = 2.0 if l == 0 else 0.0
+        assert abs(np.dot(w, sp.eval_legendre(l, np.cos(th))) - ref) < 1e-14
+
+
+@pytest.mark.parametrize("sampling", [2, 3])
+@pytest.mark.parametrize("L,spin", [(5, 0), (8, 2), (7, -1), (12, 3)])
+def test_dh_gl_round_trip_exact(oracle, sampling, L, spin):
+    """Both sampling theorems: the forward quadrature inverts the inverse exactly."""
+    flm = flm_gaussian(L, spin, seed=30 + L + spin)
+    f = oracle.s2_inverse(flm, L, spin, sampling)
+    assert f.shape == (oracle.num_rings(L, sampling), 2 * L - 1)
+    back = oracle.s2_forward(f, L, spin, sampling)
+    assert np.max(np.abs(back - flm)) < 1e-13
+    assert np.all(back[~coeff_mask(L, spin)] == 0)
+
+
+def test_dh_inverse_brute_force(oracle):
+    """DH inverse at spin 0 against scipy's Y_lm summed term by term."""
+    L = 7
+    flm = flm_gaussian(L, 0, seed=12)
+    f = oracle.s2_inverse(flm, L, 0, oracle.DH)
+    th = (2 * np.arange(2 * L) + 1) * np.pi / (4 * L)
+    ph = 2 * np.pi * np.arange(2 * L - 1) / (2 * L - 1)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    ref = np.zeros_like(f)
+    for l in range(L):
+        for m in range(-l, l + 1):
+            ref += flm[l, m + L - 1] * sp.sph_harm_y(l, m, TH, PH)
+    assert np.max(np.abs(f - ref)) < 1e-13

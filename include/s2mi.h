@@ -66,7 +66,17 @@ extern "C" {
 
 typedef struct s2_plan_s *s2_plan_t;
 
-typedef enum { S2_MW = 0, S2_HEALPIX = 1 } s2_sampling_t;
+/* Sphere samplings (Sec. 4.2).  Maps are complex128, batch outermost:
+ *   S2_MW       theta_t = (2t+1) pi/(2L-1), t < L (t = L-1: south pole),
+ *               phi_p = 2 pi p/(2L-1): [L][2L-1]; exact transforms.
+ *   S2_HEALPIX  RING-ordered pixel vector of 12 nside^2 samples (nside given);
+ *               forward by the plain quadrature 4 pi/N_pix.
+ *   S2_DH       Driscoll & Healy: theta_t = (2t+1) pi/(4L), t < 2L,
+ *               phi_p = 2 pi p/(2L-1): [2L][2L-1]; exact transforms (DH weights).
+ *   S2_GL       Gauss-Legendre: cos(theta_t) the roots of P_L, theta ascending,
+ *               phi_p = 2 pi p/(2L-1): [L][2L-1]; exact transforms (GL weights).
+ * SO(3) plans (N > 1) need S2_MW; nside is ignored except for S2_HEALPIX. */
+typedef enum { S2_MW = 0, S2_HEALPIX = 1, S2_DH = 2, S2_GL = 3 } s2_sampling_t;
 
 /* Arithmetic of the l/theta contraction.  The Wigner-d recursion, its
  * renormalisation, the quadrature weights and the phi-DFT are FP64 in every

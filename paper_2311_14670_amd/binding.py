@@ -14,9 +14,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libs2mi.so"
 
-MW, HEALPIX = 0, 1
+MW, HEALPIX, DH, GL = 0, 1, 2, 3
 FP64, CONTRACT_FP32, CONTRACT_SPLIT_BF16 = 0, 1, 2
-_SAMPLING = {"mw": MW, "healpix": HEALPIX, MW: MW, HEALPIX: HEALPIX}
+_SAMPLING = {"mw": MW, "healpix": HEALPIX, "dh": DH, "gl": GL, MW: MW, HEALPIX: HEALPIX, DH: DH, GL: GL}
+_SAMPLING_NAME = {MW: "mw", HEALPIX: "healpix", DH: "dh", GL: "gl"}
 _PRECISION = {"fp64": FP64, "fp32": CONTRACT_FP32, "split_bf16": CONTRACT_SPLIT_BF16,
               FP64: FP64, CONTRACT_FP32: CONTRACT_FP32, CONTRACT_SPLIT_BF16: CONTRACT_SPLIT_BF16}
 
@@ -93,7 +94,7 @@ def _stream_handle(device):
 
 class Plan:
     """A transform plan: bandlimit L, spin, azimuthal band N (SO(3) when N > 1),
-    sampling 'mw' or 'healpix' (nside), max_batch, contraction precision.
+    sampling 'mw', 'healpix' (nside), 'dh' or 'gl', max_batch, contraction precision.
 
     Holds its device constants (freed with the plan) and one workspace tensor;
     calls on one Plan object are therefore serialised on the stream they are
@@ -111,7 +112,7 @@ class Plan:
         _check(self._lib.s2_plan_info(self._handle, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
         self.L, self.spin, self.N = info.L, info.spin, info.N
-        self.sampling = "mw" if info.sampling == MW else "healpix"
+        self.sampling = _SAMPLING_NAME[info.sampling]
         self.nside, self.max_batch = info.nside, info.max_batch
         self.nsamples = info.nsamples
         self._ws = None
@@ -142,7 +143,9 @@ class Plan:
 
     @property
     def map_shape(self):
-        return (self.L, 2 * self.L - 1) if self.sampling == "mw" else (self.nsamples,)
+        if self.sampling == "healpix":
+            return (self.nsamples,)
+        return (self.info["nrings"], 2 * self.L - 1)
 
     def _prep(self, x, tail, what):
         if not isinstance(x, torch.Tensor):

@@ -85,6 +85,7 @@ struct s2_plan_s {
     size_t fft_lds = 0;
     FftArgs fN{};                          // MW ring / theta-torus length 2L-1
     double *wq = nullptr, *ph = nullptr;   // MW theta filter
+    double *ringq = nullptr;               // DH / GL: forward quadrature weight of each ring (phi rule included)
     double *groots = nullptr;              // e^{-2 pi i k/(2N-1)}
     // d-stage work assignment
     // stable-direction remedy: a run with n cos(theta) < 0 at a ring continues to
@@ -307,9 +308,11 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     if (N > 8) return fail(S2_ERR_UNSUPPORTED, "N=%d: SO(3) plans support N <= 8", N);
     if (N > 1 && spin != 0) return fail(S2_ERR_INVALID_ARG, "SO(3) plans (N > 1) take spin 0");
     if (spin <= -L || spin >= L) return fail(S2_ERR_INVALID_ARG, "|spin|=%d must be < L=%d", spin, L);
-    if (sampling != S2_MW && sampling != S2_HEALPIX) return fail(S2_ERR_INVALID_ARG, "unknown sampling %d", (int)sampling);
+    if (sampling != S2_MW && sampling != S2_HEALPIX && sampling != S2_DH && sampling != S2_GL)
+        return fail(S2_ERR_INVALID_ARG, "unknown sampling %d", (int)sampling);
     if (sampling == S2_HEALPIX && (nside < 1 || nside > 2048)) return fail(S2_ERR_INVALID_ARG, "nside=%d outside [1, 2048]", nside);
-    if (sampling == S2_HEALPIX && N > 1) return fail(S2_ERR_UNSUPPORTED, "SO(3) plans need MW sampling");
+    if (sampling != S2_MW && N > 1) return fail(S2_ERR_UNSUPPORTED, "SO(3) plans need MW sampling");
+    if (sampling != S2_HEALPIX) nside = 0;
     if (max_batch < 1) return fail(S2_ERR_INVALID_ARG, "max_batch=%d < 1", max_batch);
     if (prec != S2_FP64 && prec != S2_CONTRACT_FP32 && prec != S2_CONTRACT_SPLIT_BF16)
         return fail(S2_ERR_INVALID_ARG, "unknown precision mode %d", (int)prec);
@@ -354,6 +357,19 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         start.resize(L);
         for (int t = 0; t < L; ++t) start[t] = (long long)t * (2 * L - 1);
         P->nsamp = (long long)L * (2 * L - 1);
+    } else if (sampling == S2_DH || sampling == S2_GL) {
+        // equiangular-phi rings without poles, each ring swept; forward by quadrature
+        stg.d.emplace_back(); std::vector<double> &rq = stg.d.back();
+        if (sampling == S2_DH) host_dh_rings(L, &rc_h, &rq);
+        else host_gl_rings(L, &rc_h, &rq);
+        P->nring = (int)rq.size();
+        P->nreg = P->nring;
+        nphi.assign(P->nring, 2 * L - 1);
+        shift.assign(P->nring, 0);
+        start.resize(P->nring);
+        for (int t = 0; t < P->nring; ++t) start[t] = (long long)t * (2 * L - 1);
+        P->nsamp = (long long)P->nring * (2 * L - 1);
+        if ((rc = upload(P, &P->ringq, rq, st, "ring weights"))) return bail(rc);
     } else {
         host_healpix_rings(nside, &rc_h, &nphi, &start, &shift);
         P->nring = 4 * nside - 1;
@@ -512,11 +528,13 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         stg.i.emplace_back(1, L - 1);
         if ((rc = upload(P, &P->mtop1, stg.i.back(), st, "single-block mtop"))) return bail(rc);
     }
-    // HEALPix forward = q x adjoint of the inverse, so its adjoint is the inverse with weights q w_l
-    if (sampling == S2_HEALPIX && !so3) {
+    // HEALPix forward = q x adjoint of the inverse, so its adjoint is the inverse with weights q w_l;
+    // DH / GL: the inverse with weights w_l, then each ring scaled by its quadrature weight
+    if (sampling != S2_MW && !so3) {
         stg.d.emplace_back();
         host_weights(L, 0, spin, &stg.d.back());
-        for (double &v : stg.d.back()) v *= 4.0 * M_PI / (double)P->nsamp;
+        if (sampling == S2_HEALPIX)
+            for (double &v : stg.d.back()) v *= 4.0 * M_PI / (double)P->nsamp;
         double *a;
         if ((rc = upload(P, &a, stg.d.back(), st, "forward-adjoint weights"))) return bail(rc);
         P->w_fadj.push_back(a);
@@ -761,7 +779,8 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
         {
         TIMED(S2_STAGE_PHI_FWD);
         HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L, q, slice_maps[k], P->ring_nphi,
-                              P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F, fft_scratch(P, ws)),
+                              P->ring_start, P->ring_shift, P->ring_fft, P->ffts, adjoint ? nullptr : P->ringq, F,
+                              fft_scratch(P, ws)),
                    "forward phi-DFT");
         }
         TIMED(S2_STAGE_MW_THETA);
@@ -859,7 +878,9 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             {
             TIMED(S2_STAGE_PHI_FWD);
             HIPCHK(launch_phi_fwd(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L, q, maps + bk * P->nsamp,
-                                  P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, F, fft_scratch(P, ws)),
+                                  P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts,
+                                  adjoint ? nullptr : P->ringq, F,
+                                  fft_scratch(P, ws)),
                    "forward phi-DFT");
             }
             TIMED(S2_STAGE_MW_THETA);
@@ -974,6 +995,8 @@ int s2_forward_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, void 
         if (P->sampling == S2_MW) rc = run_forward_adjoint_mw(P, G, out, (char *)workspace, st);
         else rc = run_inverse(P, G, &out, P->w_fadj, (char *)workspace, st);
         if (rc) return rc;
+        if (P->ringq)
+            HIPCHK(launch_ring_scale(st, P->nring, 2 * P->L - 1, P->ringq, out), "quadrature weights");
     }
     return S2_OK;
 }

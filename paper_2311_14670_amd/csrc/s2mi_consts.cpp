@@ -57,6 +57,82 @@ void fill_ring(RingConsts *rc, int r, __float128 th)
     split_dd(log2q(cosq(th / 2)), &rc->lcos[2 * r], &rc->lcos[2 * r + 1]);
 }
 
+// DH sampling theorem (Sec. 4.2): 2L rings theta_t = (2t+1) pi / (4L); the forward
+// weight of ring t (the phi rule 2 pi / (2L-1) included) is
+//   (4 pi / (L (2L-1))) sin(theta_t) sum_{k<L} sin((2k+1) theta_t) / (2k+1),
+// the sines by the recurrence s_{k+1} = 2 cos(2 theta) s_k - s_{k-1} in quad precision.
+void host_dh_rings(int L, RingConsts *rc, std::vector<double> *wq)
+{
+    const int nring = 2 * L;
+    rc->theta.resize(nring);
+    rc->cot.resize(nring);
+    rc->csc.resize(nring);
+    rc->lsin.resize(2 * nring);
+    rc->lcos.resize(2 * nring);
+    wq->resize(nring);
+    for (int t = 0; t < nring; ++t) {
+        const q th = (2 * (q)t + 1) * QPI / (4 * (q)L);
+        fill_ring(rc, t, th);
+        const q c2 = 2 * cosq(2 * th);
+        q sm = -sinq(th), sk = sinq(th), acc = 0;            // sin(-theta), sin(theta)
+        for (int k = 0; k < L; ++k) {
+            acc += sk / (2 * (q)k + 1);
+            const q sn = c2 * sk - sm;
+            sm = sk;
+            sk = sn;
+        }
+        (*wq)[t] = (double)(4 * QPI / ((q)L * (2 * (q)L - 1)) * sinq(th) * acc);
+    }
+}
+
+// GL sampling theorem (Sec. 4.2): L rings with cos(theta_t) the roots of P_L (theta
+// ascending), by Newton's method on the three-term Legendre recurrence in quad
+// precision; forward weight (phi rule included) (2 pi / (2L-1)) 2 / ((1 - x^2) P_L'(x)^2).
+void host_gl_rings(int L, RingConsts *rc, std::vector<double> *wq)
+{
+    rc->theta.resize(L);
+    rc->cot.resize(L);
+    rc->csc.resize(L);
+    rc->lsin.resize(2 * L);
+    rc->lcos.resize(2 * L);
+    wq->resize(L);
+    auto legendre = [L](q x, q *p, q *dp) {              // P_L(x) and P_L'(x)
+        q p0 = 1, p1 = x;
+        for (int k = 2; k <= L; ++k) {
+            const q p2 = ((2 * (q)k - 1) * x * p1 - ((q)k - 1) * p0) / (q)k;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (L == 1) { p1 = x; p0 = 1; }
+        *p = p1;
+        *dp = (q)L * (x * p1 - p0) / (x * x - 1);
+    };
+    for (int t = 0; t < L; ++t) {
+        long double xl = cosl(3.14159265358979323846264338327950288L * (t + 0.75L) / (L + 0.5L));
+        for (int it = 0; it < 60; ++it) {                  // long double Newton from the classical guess
+            long double p0 = 1, p1 = xl;
+            for (int k = 2; k <= L; ++k) {
+                const long double p2 = ((2.0L * k - 1) * xl * p1 - (k - 1.0L) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (L == 1) { p1 = xl; p0 = 1; }
+            const long double dpl = L * (xl * p1 - p0) / (xl * xl - 1);
+            const long double dx = p1 / dpl;
+            xl -= dx;
+            if (fabsl(dx) < 1e-19L) break;
+        }
+        q x = xl, p, dp;
+        for (int it = 0; it < 2; ++it) {                   // polish in quad precision
+            legendre(x, &p, &dp);
+            x -= p / dp;
+        }
+        legendre(x, &p, &dp);
+        fill_ring(rc, t, acosq(x));
+        (*wq)[t] = (double)(2 * QPI / (2 * (q)L - 1) * 2 / ((1 - x * x) * dp * dp));
+    }
+}
+
 // HEALPix RING geometry (Gorski et al. 2005), ring r = 0 .. 4 nside - 2, i = r + 1:
 //   i <  nside:          cos(theta) = 1 - i^2/(3 nside^2), 4i pixels, half-pixel shift
 //   nside <= i <= 3nside: cos(theta) = 4/3 - 2i/(3 nside), 4 nside pixels,

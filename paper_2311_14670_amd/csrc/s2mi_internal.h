@@ -21,6 +21,8 @@ void fill_ring(RingConsts *rc, int r, __float128 th);
 #endif
 #endif
 void host_mw_rings(int L, RingConsts *rc);
+void host_dh_rings(int L, RingConsts *rc, std::vector<double> *wq);
+void host_gl_rings(int L, RingConsts *rc, std::vector<double> *wq);
 void host_healpix_rings(int nside, RingConsts *rc, std::vector<int> *nphi,
                         std::vector<long long> *start, std::vector<int> *shift);
 void host_log2_binom(int L, int n, std::vector<double> *out);

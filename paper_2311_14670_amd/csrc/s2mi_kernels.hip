@@ -744,8 +744,8 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
 __global__ __launch_bounds__(1024) void k_phi_fwd(
     int L, int nring, int hstride, double q, const double2 *__restrict__ map, const int *__restrict__ ring_nphi,
     const long long *__restrict__ ring_start, const int *__restrict__ ring_shift,
-    const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, double *__restrict__ F,
-    double2 *__restrict__ fscr)
+    const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, const double *__restrict__ ringq,
+    double *__restrict__ F, double2 *__restrict__ fscr)
 {
     extern __shared__ double2 buf[];
     const int r = blockIdx.x;
@@ -761,6 +761,7 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
     const int nphi = ring_nphi[r];
     const FftArgs *f = ffts + ring_fft[r];
     const int shift = ring_shift[r];
+    if (ringq) q = ringq[r];                     // per-ring quadrature weight (DH, GL)
     const double2 *in = map + ring_start[r];
     for (int k = tid; k < nphi; k += T) buf[k] = in[k];
     __syncthreads();
@@ -968,6 +969,16 @@ __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__
     double2 *row = flm + (size_t)l * M + (L - 1);
     row[am] = a;
     if (am > 0) row[-am] = b;
+}
+
+// ------------------------------------------------------------------ ring scaling
+// map[t][p] *= w[t] for rings of nphi samples each (adjoint of a ring-weighted quadrature)
+__global__ void k_ring_scale(int nring, int nphi, const double *__restrict__ w, double2 *__restrict__ map)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)nring * nphi) return;
+    const double s = w[i / nphi];
+    map[i] = make_double2(map[i].x * s, map[i].y * s);
 }
 
 // ------------------------------------------------------------------ SO(3) gamma DFT
@@ -1185,10 +1196,11 @@ hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, i
 
 hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
                           const double2 *map, const int *ring_nphi, const long long *ring_start, const int *ring_shift,
-                          const int *ring_fft, const FftArgs *ffts, double *F, double2 *fscr)
+                          const int *ring_fft, const FftArgs *ffts, const double *ringq, double *F,
+                          double2 *fscr)
 {
     hipLaunchKernelGGL(k_phi_fwd, dim3(hstride), dim3(nthreads), lds, st, L, nring, hstride, q, map, ring_nphi,
-                       ring_start, ring_shift, ring_fft, ffts, F, fscr);
+                       ring_start, ring_shift, ring_fft, ffts, ringq, F, fscr);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1197,6 +1209,15 @@ hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int
                             const double *wq, const double *ph, double *F, double2 *hpole, double2 *fscr)
 {
     hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, hstride, spin, fN, wq, ph, F, hpole, fscr);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *w, double2 *map)
+{
+    const size_t tot = (size_t)nring * nphi;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ring_scale, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nring, nphi, w, map);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

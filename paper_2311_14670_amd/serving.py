@@ -36,7 +36,7 @@ class PlanKey:
     L: int
     spin: int
     N: int
-    sampling: str      # "mw" or "healpix"
+    sampling: str      # "mw", "healpix", "dh" or "gl"
     nside: int
     precision: str = "fp64"
 
@@ -74,9 +74,9 @@ def coeff_shape(key):
 def map_elems(key):
     if key.kind == "so3":
         return (2 * key.N - 1) * key.L * (2 * key.L - 1)
-    if key.sampling == "mw":
-        return key.L * (2 * key.L - 1)
-    return 12 * key.nside * key.nside
+    if key.sampling == "healpix":
+        return 12 * key.nside * key.nside
+    return (2 * key.L if key.sampling == "dh" else key.L) * (2 * key.L - 1)
 
 
 class Scheduler:

@@ -89,14 +89,15 @@ def test_gradient_matches_oracle_at_L512(ag, spin):
 
 
 @pytest.mark.parametrize("sampling,L,nside,spin", [("mw", 24, 0, 0), ("mw", 20, 0, 2), ("mw", 17, 0, -3),
-                                                   ("healpix", 16, 8, 0), ("healpix", 12, 8, 1)])
+                                                   ("healpix", 16, 8, 0), ("healpix", 12, 8, 1), ("dh", 14, 0, 2),
+                                                   ("gl", 15, 0, -1)])
 def test_forward_adjoint_dot_product(ag, sampling, L, nside, spin):
     """<F f, G> = <f, F^H G> with F the oracle's forward transform."""
     autograd, binding = ag
     plan = binding.Plan(L, spin=spin, sampling=sampling, nside=nside)
     f = map_gaussian(plan.map_shape, seed=30)
     G = flm_gaussian(L, spin, seed=31)
-    samp = oracle.MW if sampling == "mw" else oracle.HEALPIX
+    samp = {"mw": oracle.MW, "healpix": oracle.HEALPIX, "dh": oracle.DH, "gl": oracle.GL}[sampling]
     lhs = np.vdot(G, oracle.s2_forward(f, L, spin, samp, nside))           # <G, F f>
     FhG = plan.forward_adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
     rhs = np.vdot(FhG, f)                                                   # <F^H G, f>

@@ -85,6 +85,20 @@ def test_healpix_batched(binding, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("sampling", ["dh", "gl"])
+def test_dh_gl_batched(binding, prec, sampling):
+    L, spin, B = 40, 2, 3
+    samp = oracle.DH if sampling == "dh" else oracle.GL
+    flm = flm_gaussian(L, spin, seed=26, batch=B)
+    plan = binding.Plan(L, spin=spin, sampling=sampling, max_batch=B, precision=prec)
+    f = host(plan.inverse(dev(flm)))
+    _check(f"{sampling} inverse", prec, f[1], oracle.s2_inverse(flm[1], L, spin, samp))
+    g = map_gaussian((B,) + plan.map_shape, seed=27)
+    a = host(plan.forward(dev(g)))
+    _check(f"{sampling} forward", prec, a[2], oracle.s2_forward(g[2], L, spin, samp))
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_so3_batched(binding, prec):
     L, N, B = 40, 8, 2
     flmn = flmn_gaussian(L, N, seed=24, batch=B)

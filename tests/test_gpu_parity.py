@@ -80,13 +80,34 @@ def test_healpix_inverse_and_forward(binding, nside, L, spin):
     assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < tol
 
 
+_ORACLE_SAMPLING = {"mw": oracle.MW, "healpix": oracle.HEALPIX, "dh": oracle.DH, "gl": oracle.GL}
+
+
+@pytest.mark.parametrize("sampling", ["dh", "gl"])
+@pytest.mark.parametrize("L,spin", [(2, 0), (9, 0), (32, 0), (24, 2), (17, -1), (40, 5)])
+def test_dh_gl_inverse_and_forward(binding, sampling, L, spin):
+    """DH and GL sampling theorems (Sec. 4.2): inverse, forward quadrature and the
+    exact round trip."""
+    tol = 1e-13 if abs(spin) <= 3 else 1e-12
+    samp = _ORACLE_SAMPLING[sampling]
+    flm = flm_gaussian(L, spin, seed=5)
+    plan = binding.Plan(L, spin=spin, sampling=sampling)
+    assert plan.map_shape == (oracle.num_rings(L, samp), 2 * L - 1)
+    f = host(plan.inverse(dev(flm)))
+    assert rel_l2(f, oracle.s2_inverse(flm, L, spin, samp)) < tol
+    g = map_gaussian(plan.map_shape, seed=6)
+    a = host(plan.forward(dev(g)))
+    assert rel_l2(a, oracle.s2_forward(g, L, spin, samp)) < tol
+    assert rel_l2(host(plan.forward(dev(f))), flm) < tol
+
+
 @pytest.mark.parametrize("sampling,L,nside,spin", [("mw", 24, 0, 0), ("mw", 24, 0, 2), ("healpix", 16, 8, 2),
-                                                   ("mw", 30, 0, -11)])
+                                                   ("mw", 30, 0, -11), ("dh", 20, 0, 2), ("gl", 21, 0, 0)])
 def test_inverse_adjoint(binding, sampling, L, nside, spin):
     plan = binding.Plan(L, spin=spin, sampling=sampling, nside=nside)
     g = map_gaussian(plan.map_shape, seed=4)
     a = host(plan.inverse_adjoint(dev(g)))
-    ref = oracle.s2_inverse_adjoint(g, L, spin, 0 if sampling == "mw" else 1, nside)
+    ref = oracle.s2_inverse_adjoint(g, L, spin, _ORACLE_SAMPLING[sampling], nside)
     assert rel_l2(a, ref) < (1e-13 if abs(spin) <= 3 else 1e-12)
 
 

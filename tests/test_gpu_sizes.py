@@ -57,6 +57,29 @@ def test_healpix_multi_tile(binding, nside, L, spin):
     assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < 1e-12
 
 
+@pytest.mark.parametrize("sampling,L,spin", [("dh", 130, 0), ("gl", 150, 2)])
+def test_dh_gl_multi_tile(binding, sampling, L, spin):
+    samp = oracle.DH if sampling == "dh" else oracle.GL
+    flm = flm_gaussian(L, spin, seed=19, scale="inv1pl")
+    plan = binding.Plan(L, spin=spin, sampling=sampling)
+    f = host(plan.inverse(dev(flm)))
+    assert rel_l2(f, oracle.s2_inverse(flm, L, spin, samp)) < 1e-12
+    assert rel_l2(host(plan.forward(dev(f))), flm) < 1e-12     # sampling theorem: exact round trip
+
+
+@pytest.mark.parametrize("sampling,L", [("dh", 1024), ("gl", 2048)])
+def test_dh_gl_full_size_sampled(binding, sampling, L):
+    samp = oracle.DH if sampling == "dh" else oracle.GL
+    flm = flm_gaussian(L, 0, seed=20, scale="inv1pl")
+    plan = binding.Plan(L, sampling=sampling)
+    f = plan.inverse(dev(flm))
+    nr = oracle.num_rings(L, samp)
+    rings = np.array(sorted({0, 1, nr // 3, nr // 2, nr - 2, nr - 1}))
+    fr = host(f)[rings].ravel()
+    assert rel_l2(fr, oracle.s2_inverse(flm, L, 0, samp, rings=rings)) < 1e-11
+    assert rel_l2(host(plan.forward(f)), flm) < 1e-11
+
+
 def test_so3_multi_tile(binding):
     L, N = 72, 4
     flmn = flmn_gaussian(L, N, seed=14)

@@ -15,6 +15,8 @@ Arrays are numpy ``complex128``.  Layouts:
   * DH maps ``f[t, p]`` with ``theta_t = (2t+1) pi/(4L)``, t < 2L, and GL maps
     ``f[t, p]`` with ``cos(theta_t)`` the roots of P_L (theta ascending), both
     with ``phi_p = 2 pi p/(2L-1)`` (Sec. 4.2, DH and GL sampling theorems);
+  * MWSS maps ``f[t, p]`` with ``theta_t = pi t/L``, t = 0..L (both poles), and
+    ``phi_p = 2 pi p/(2L)`` (Sec. 4.2, MW with symmetric sampling);
   * Wigner coefficients ``flmn[n + N - 1, l, m + L - 1]`` and SO(3) maps
     ``f[k, t, p]`` with ``gamma_k = 2 pi k/(2N-1)`` (Sec. 4.5).
 """
@@ -29,7 +31,7 @@ _SRC = os.path.join(_HERE, "s2oracle.c")
 _LIB = os.path.join(_HERE, "_s2oracle.so")
 _lib = None
 
-MW, HEALPIX, DH, GL = 0, 1, 2, 3
+MW, HEALPIX, DH, GL, MWSS = 0, 1, 2, 3, 4
 
 
 def build(force=True):
@@ -136,13 +138,18 @@ def gl_nodes(L):
 
 
 def num_rings(L, sampling, nside=0):
-    return {MW: L, DH: 2 * L, GL: L}.get(sampling, 4 * nside - 1)
+    return {MW: L, DH: 2 * L, GL: L, MWSS: L + 1}.get(sampling, 4 * nside - 1)
+
+
+def ring_length(L, sampling):
+    """Samples per ring of the equiangular-phi samplings."""
+    return 2 * L if sampling == MWSS else 2 * L - 1
 
 
 def map_size(L, sampling, nside=0):
     if sampling == HEALPIX:
         return 12 * nside * nside
-    return num_rings(L, sampling) * (2 * L - 1)
+    return num_rings(L, sampling) * ring_length(L, sampling)
 
 
 # ----------------------------------------------------------------- Wigner d
@@ -164,7 +171,7 @@ def s2_inverse(flm, L, spin=0, sampling=MW, nside=0, rings=None):
     lib = _load()
     nsel, sel = _sel(rings)
     if sampling != HEALPIX:
-        nout = (num_rings(L, sampling) if nsel < 0 else nsel) * (2 * L - 1)
+        nout = (num_rings(L, sampling) if nsel < 0 else nsel) * ring_length(L, sampling)
     else:
         _, nphi, _, _ = healpix_rings(nside)
         nout = int(nphi.sum()) if nsel < 0 else int(nphi[np.asarray(rings)].sum())
@@ -172,7 +179,7 @@ def s2_inverse(flm, L, spin=0, sampling=MW, nside=0, rings=None):
     lib.or_s2_inverse(L, spin, sampling, nside, _dp(flm.view(np.float64)), _dp(f.view(np.float64)),
                       nsel, _ip(sel) if sel is not None else None)
     if sampling != HEALPIX and nsel < 0:
-        return f.reshape(num_rings(L, sampling), 2 * L - 1)
+        return f.reshape(num_rings(L, sampling), ring_length(L, sampling))
     return f
 
 

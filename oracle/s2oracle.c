@@ -26,6 +26,8 @@
  *              forward by the explicit DH quadrature weights.
  *   3 GL:      cos(theta_t) = roots of P_L (theta ascending), t < L;
  *              phi_p = 2 pi p / (2L-1); forward by Gauss-Legendre weights.
+ *   4 MWSS:    theta_t = pi t / L, t = 0..L (both poles); phi_p = 2 pi p / (2L);
+ *              forward exact like MW, on the 2L-point theta-torus.
  *   SO(3):   MW in (beta, alpha), gamma_k = 2 pi k / (2N-1) (Sec. 4.5).
  *
  * Every complex exponential whose phase is a rational multiple of pi is
@@ -381,7 +383,19 @@ static rings_t make_rings(int L, int sampling, int nside)
 {
     rings_t R;
     R.wq = NULL;
-    if (sampling == 2 || sampling == 3) {
+    if (sampling == 4) {
+        R.nring = L + 1;
+        R.theta = (double *)malloc(sizeof(double) * R.nring);
+        R.nphi = (int *)malloc(sizeof(int) * R.nring);
+        R.shift = (int *)malloc(sizeof(int) * R.nring);
+        R.start = (long long *)malloc(sizeof(long long) * R.nring);
+        R.thl = (long double *)malloc(sizeof(long double) * R.nring);
+        for (int t = 0; t <= L; ++t) {
+            R.thl[t] = (t == L) ? OR_PI_L : OR_PI_L * t / L;
+            R.theta[t] = (double)R.thl[t];
+            R.nphi[t] = 2 * L; R.shift[t] = 0; R.start[t] = (long long)t * 2 * L;
+        }
+    } else if (sampling == 2 || sampling == 3) {
         R.nring = sampling == 2 ? 2 * L : L;
         R.theta = (double *)malloc(sizeof(double) * R.nring);
         R.nphi = (int *)malloc(sizeof(int) * R.nring);
@@ -449,8 +463,11 @@ static void free_hp_root_tables(const rings_t *R, double **tab)
 
 int or_num_rings(int L, int sampling, int nside)
 {
-    return sampling == 0 || sampling == 3 ? L : sampling == 2 ? 2 * L : 4 * nside - 1;
+    return sampling == 0 || sampling == 3 ? L : sampling == 2 ? 2 * L : sampling == 4 ? L + 1 : 4 * nside - 1;
 }
+
+/* phi_p = 2 pi p / (2L-1) (MW, DH, GL) */
+static int phi_2l1(int sampling) { return sampling == 0 || sampling == 2 || sampling == 3; }
 
 void or_s2_inverse(int L, int s, int sampling, int nside, const double *flm, double *f,
                    int nsel, const int *rings)
@@ -470,7 +487,8 @@ void or_s2_inverse(int L, int s, int sampling, int nside, const double *flm, dou
         #pragma omp for schedule(dynamic, 1)
         for (int i = 0; i < nr; ++i) {
             const int r = (nsel < 0) ? i : rings[i];
-            ring_inverse(L, s, R.thl[r], R.nphi[r], R.shift[r], sampling != 1,
+            /* MWSS (phi_p = pi p / L) goes through the HEALPix-style phase index 2p / (2 nphi) */
+            ring_inverse(L, s, R.thl[r], R.nphi[r], R.shift[r], phi_2l1(sampling),
                          flm, f + 2 * off[i], dbuf, ft);
         }
         free(dbuf); free(ft);
@@ -522,9 +540,12 @@ static void eval_interp(int L, const double *gh, long double th, double *out)
  *  (1) extend to the 2L-1 torus samples with g(2pi - theta) = parity * g(theta),
  *      parity = (-1)^{m+s} (reflection with the pi phi-shift and the (-1)^s
  *      sign, Sec. 4.2 MW); the pole sample t = L-1 is its own mirror and is
- *      used as given;
+ *      used as given.  MWSS (ss = 1): the L+1 samples t = 0..L (theta_t = pi t/L)
+ *      extend to the 2L torus samples, mirror of t being 2L - t (both poles are
+ *      their own mirrors);
  *  (2) the torus interpolant of degree L-1, g(theta) = sum_k ghat_k e^{ik theta},
- *      ghat_k = (1/(2L-1)) sum_t g_t e^{-ik theta_t};
+ *      ghat_k = (1/N) sum_t g_t e^{-ik theta_t}, N = 2L-1 (MW) or 2L (MWSS; the
+ *      Nyquist frequency L is left out, it vanishes for band-limited samples);
  *  (3) out_l = wl[l] * int_0^pi g(theta) d^l_{mn}(theta) sin(theta) dtheta,
  *      evaluated exactly: with d(-theta) = parity d(theta), the integrand splits
  *      into G+ = d (g(th) + parity g(-th))/2, a polynomial of degree <= 2L-2 in
@@ -535,23 +556,25 @@ static void eval_interp(int L, const double *gh, long double th, double *out)
  */
 static void mw_theta_forward(int L, int m, int n, int parity, const double *gt,
                              const double *wl, const long double *thgl, const double *wgl,
-                             const double *rt2N, double *out, double *dbuf)
+                             const double *rt2N, double *out, double *dbuf, int ss)
 {
-    const int N = 2 * L - 1;
+    const int N = ss ? 2 * L : 2 * L - 1;
+    const int ngiven = ss ? L + 1 : L;
     double *g = (double *)malloc(sizeof(double) * 2 * N);
     for (int t = 0; t < N; ++t) {
-        if (t < L) { g[2 * t] = gt[2 * t]; g[2 * t + 1] = gt[2 * t + 1]; }
+        if (t < ngiven) { g[2 * t] = gt[2 * t]; g[2 * t + 1] = gt[2 * t + 1]; }
         else {
-            const int tr = N - 1 - t;
+            const int tr = ss ? N - t : N - 1 - t;
             g[2 * t] = parity * gt[2 * tr]; g[2 * t + 1] = parity * gt[2 * tr + 1];
         }
     }
-    /* ghat_k, k = -(L-1)..L-1; e^{-ik theta_t} = e^{-i pi k (2t+1) / N} -> index k(2t+1) mod 2N in rt2N */
+    /* ghat_k, k = -(L-1)..L-1; e^{-ik theta_t} = e^{-i pi idx / N} with idx = k(2t+1) (MW)
+     * or 2kt (MWSS), mod 2N, from rt2N */
     double *gh = (double *)malloc(sizeof(double) * 2 * N);
     for (int k = -(L - 1); k <= L - 1; ++k) {
         long double re = 0.0L, im = 0.0L;
         for (int t = 0; t < N; ++t) {
-            const long long idx = pmod((long long)k * (2 * t + 1), 2LL * N);
+            const long long idx = pmod((long long)k * (ss ? 2 * t : 2 * t + 1), 2LL * N);
             const long double cr = rt2N[2 * idx], ci = rt2N[2 * idx + 1];  /* e^{-i pi idx / N} */
             re += g[2 * t] * cr - g[2 * t + 1] * ci;
             im += g[2 * t] * ci + g[2 * t + 1] * cr;
@@ -608,8 +631,10 @@ void or_s2_forward(int L, int s, int sampling, int nside, const double *f, doubl
     for (int l = 0; l < L; ++l) wl[l] = w_sht(l, s);
     long double *thgl = (long double *)malloc(sizeof(long double) * L);
     double *wgl = (double *)malloc(sizeof(double) * L);
-    if (sampling == 0) gl_nodes_ld(L, thgl, wgl);
+    if (sampling == 0 || sampling == 4) gl_nodes_ld(L, thgl, wgl);
     double *rt2N = root_table(2 * M, -1);          /* e^{-i pi k / M} */
+    double *rt4L = root_table(4 * L, -1);          /* e^{-i pi k / (2L)}: MWSS torus */
+    double *rt2L = root_table(2 * L, -1);          /* e^{-2 pi i k / (2L)}: MWSS rings */
     double *rtM = root_table(M, -1);
     double **hpt = (sampling == 1) ? hp_root_tables(&R) : NULL;
     const long long npix = 12LL * nside * nside;
@@ -628,7 +653,15 @@ void or_s2_forward(int L, int s, int sampling, int nside, const double *f, doubl
                     gt[2 * t] *= q; gt[2 * t + 1] *= q;
                 }
                 const int parity = (iabs_(m + s) % 2) ? -1 : 1;
-                mw_theta_forward(L, m, -s, parity, gt, wl, thgl, wgl, rt2N, col, dbuf);
+                mw_theta_forward(L, m, -s, parity, gt, wl, thgl, wgl, rt2N, col, dbuf, 0);
+            } else if (sampling == 4) {
+                const double q = (double)(2.0L * OR_PI_L / (2 * L));   /* phi rule of 2L samples */
+                for (int t = 0; t <= L; ++t) {
+                    ring_dft(f + 2 * R.start[t], 2 * L, 0, 1, m, L, rt2L, 2 * L, gt + 2 * t);
+                    gt[2 * t] *= q; gt[2 * t + 1] *= q;
+                }
+                const int parity = (iabs_(m + s) % 2) ? -1 : 1;
+                mw_theta_forward(L, m, -s, parity, gt, wl, thgl, wgl, rt4L, col, dbuf, 1);
             } else {
                 for (int l = 0; l < L; ++l) { col[2 * l] = 0.0; col[2 * l + 1] = 0.0; }
                 for (int r = 0; r < R.nring; ++r) {
@@ -658,7 +691,7 @@ void or_s2_forward(int L, int s, int sampling, int nside, const double *f, doubl
         }
         free(dbuf); free(gt); free(col);
     }
-    free(wl); free(thgl); free(wgl); free(rt2N); free(rtM);
+    free(wl); free(thgl); free(wgl); free(rt2N); free(rtM); free(rt4L); free(rt2L);
     if (hpt) free_hp_root_tables(&R, hpt);
     free_rings(&R);
 }
@@ -675,6 +708,7 @@ void or_s2_inverse_adjoint(int L, int s, int sampling, int nside, const double *
     rings_t R = make_rings(L, sampling, nside);
     const int nm = (nsel < 0) ? M : nsel;
     double *rtM = root_table(M, -1);
+    double *rt2L = root_table(2 * L, -1);
     double **hpt = (sampling == 1) ? hp_root_tables(&R) : NULL;
     #pragma omp parallel
     {
@@ -686,7 +720,8 @@ void or_s2_inverse_adjoint(int L, int s, int sampling, int nside, const double *
             for (int l = 0; l < L; ++l) { col[2 * l] = 0.0; col[2 * l + 1] = 0.0; }
             for (int r = 0; r < R.nring; ++r) {
                 double fm[2];
-                if (sampling != 1) ring_dft(g + 2 * R.start[r], M, 0, 1, m, L, rtM, M, fm);
+                if (sampling == 4) ring_dft(g + 2 * R.start[r], 2 * L, 0, 1, m, L, rt2L, 2 * L, fm);
+                else if (sampling != 1) ring_dft(g + 2 * R.start[r], M, 0, 1, m, L, rtM, M, fm);
                 else ring_dft(g + 2 * R.start[r], R.nphi[r], R.shift[r], 0, m, L,
                               hpt[R.nphi[r] / 4], 2 * R.nphi[r], fm);
                 wigner_d_ld(L, m, -s, R.thl[r], dbuf);
@@ -703,7 +738,7 @@ void or_s2_inverse_adjoint(int L, int s, int sampling, int nside, const double *
         }
         free(dbuf); free(col);
     }
-    free(rtM);
+    free(rtM); free(rt2L);
     if (hpt) free_hp_root_tables(&R, hpt);
     free_rings(&R);
 }
@@ -819,7 +854,7 @@ void or_so3_forward(int L, int N, const double *f, double *flmn)
                     gt[2 * t] = re * qa * qg; gt[2 * t + 1] = im * qa * qg;
                 }
                 const int parity = (iabs_(m - n) % 2) ? -1 : 1;
-                mw_theta_forward(L, m, n, parity, gt, wl, thgl, wgl, rt2N, col, dbuf);
+                mw_theta_forward(L, m, n, parity, gt, wl, thgl, wgl, rt2N, col, dbuf, 0);
                 double *fl = flmn + 2 * (size_t)(n + N - 1) * slab;
                 for (int l = 0; l < L; ++l) {
                     fl[2 * ((size_t)l * M + m + L - 1)] = col[2 * l];

@@ -296,3 +296,41 @@ def test_dh_inverse_brute_force(oracle):
         for m in range(-l, l + 1):
             ref += flm[l, m + L - 1] * sp.sph_harm_y(l, m, TH, PH)
     assert np.max(np.abs(f - ref)) < 1e-13
+
+
+# ----------------------------------------------------------------- MWSS (MW with symmetric sampling, Sec. 4.2)
+@pytest.mark.parametrize("L,spin", [(2, 0), (5, 0), (8, 2), (7, -1), (12, 3), (16, 0)])
+def test_mwss_round_trip_exact(oracle, L, spin):
+    """MWSS sampling theorem: theta_t = pi t/L (t = 0..L, both poles), 2L longitudes;
+    the forward transform inverts the inverse exactly."""
+    flm = flm_gaussian(L, spin, seed=40 + L + spin)
+    f = oracle.s2_inverse(flm, L, spin, oracle.MWSS)
+    assert f.shape == (L + 1, 2 * L)
+    back = oracle.s2_forward(f, L, spin, oracle.MWSS)
+    assert np.max(np.abs(back - flm)) < 1e-14
+    assert np.all(back[~coeff_mask(L, spin)] == 0)
+
+
+def test_mwss_inverse_brute_force(oracle):
+    """MWSS inverse at spin 0, poles included, against scipy's Y_lm."""
+    L = 7
+    flm = flm_gaussian(L, 0, seed=13)
+    f = oracle.s2_inverse(flm, L, 0, oracle.MWSS)
+    th = np.pi * np.arange(L + 1) / L
+    ph = 2 * np.pi * np.arange(2 * L) / (2 * L)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    ref = np.zeros_like(f)
+    for l in range(L):
+        for m in range(-l, l + 1):
+            ref += flm[l, m + L - 1] * sp.sph_harm_y(l, m, TH, PH)
+    assert np.max(np.abs(f - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("spin", [0, 2, -3])
+def test_mwss_adjoint_dot_product(oracle, spin):
+    L = 10
+    a = flm_gaussian(L, spin, seed=5)
+    b = map_gaussian(oracle.map_size(L, oracle.MWSS), seed=6)
+    lhs = np.vdot(oracle.s2_inverse(a, L, spin, oracle.MWSS).reshape(-1), b)
+    rhs = np.vdot(a, oracle.s2_inverse_adjoint(b, L, spin, oracle.MWSS))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)

@@ -75,8 +75,11 @@ typedef struct s2_plan_s *s2_plan_t;
  *               phi_p = 2 pi p/(2L-1): [2L][2L-1]; exact transforms (DH weights).
  *   S2_GL       Gauss-Legendre: cos(theta_t) the roots of P_L, theta ascending,
  *               phi_p = 2 pi p/(2L-1): [L][2L-1]; exact transforms (GL weights).
+ *   S2_MWSS     MW with symmetric sampling: theta_t = pi t/L, t = 0..L (both poles),
+ *               phi_p = 2 pi p/(2L): [L+1][2L]; exact transforms (s2_forward_adjoint
+ *               is not built for it).
  * SO(3) plans (N > 1) need S2_MW; nside is ignored except for S2_HEALPIX. */
-typedef enum { S2_MW = 0, S2_HEALPIX = 1, S2_DH = 2, S2_GL = 3 } s2_sampling_t;
+typedef enum { S2_MW = 0, S2_HEALPIX = 1, S2_DH = 2, S2_GL = 3, S2_MWSS = 4 } s2_sampling_t;
 
 /* Arithmetic of the l/theta contraction.  The Wigner-d recursion, its
  * renormalisation, the quadrature weights and the phi-DFT are FP64 in every

@@ -14,10 +14,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libs2mi.so"
 
-MW, HEALPIX, DH, GL = 0, 1, 2, 3
+MW, HEALPIX, DH, GL, MWSS = 0, 1, 2, 3, 4
 FP64, CONTRACT_FP32, CONTRACT_SPLIT_BF16 = 0, 1, 2
-_SAMPLING = {"mw": MW, "healpix": HEALPIX, "dh": DH, "gl": GL, MW: MW, HEALPIX: HEALPIX, DH: DH, GL: GL}
-_SAMPLING_NAME = {MW: "mw", HEALPIX: "healpix", DH: "dh", GL: "gl"}
+_SAMPLING = {"mw": MW, "healpix": HEALPIX, "dh": DH, "gl": GL, "mwss": MWSS,
+             MW: MW, HEALPIX: HEALPIX, DH: DH, GL: GL, MWSS: MWSS}
+_SAMPLING_NAME = {MW: "mw", HEALPIX: "healpix", DH: "dh", GL: "gl", MWSS: "mwss"}
 _PRECISION = {"fp64": FP64, "fp32": CONTRACT_FP32, "split_bf16": CONTRACT_SPLIT_BF16,
               FP64: FP64, CONTRACT_FP32: CONTRACT_FP32, CONTRACT_SPLIT_BF16: CONTRACT_SPLIT_BF16}
 
@@ -94,7 +95,7 @@ def _stream_handle(device):
 
 class Plan:
     """A transform plan: bandlimit L, spin, azimuthal band N (SO(3) when N > 1),
-    sampling 'mw', 'healpix' (nside), 'dh' or 'gl', max_batch, contraction precision.
+    sampling 'mw', 'healpix' (nside), 'dh', 'gl' or 'mwss', max_batch, contraction precision.
 
     Holds its device constants (freed with the plan) and one workspace tensor;
     calls on one Plan object are therefore serialised on the stream they are
@@ -145,7 +146,7 @@ class Plan:
     def map_shape(self):
         if self.sampling == "healpix":
             return (self.nsamples,)
-        return (self.info["nrings"], 2 * self.L - 1)
+        return (self.info["nrings"], 2 * self.L if self.sampling == "mwss" else 2 * self.L - 1)
 
     def _prep(self, x, tail, what):
         if not isinstance(x, torch.Tensor):
@@ -219,7 +220,7 @@ class Plan:
 
     def debug_wigner_d(self, n):
         """d^l_{m,n}(theta_r) from the GPU recursion: [rings swept, m, l] (float64)."""
-        nreg = self.L - 1 if self.sampling == "mw" else self.info["nrings"]
+        nreg = self.L - 1 if self.sampling in ("mw", "mwss") else self.info["nrings"]
         out = torch.empty((nreg, self.L, self.L), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             _check(self._lib.s2_debug_wigner_d(self._handle, int(n), ctypes.c_void_p(out.data_ptr()),

@@ -308,7 +308,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     if (N > 8) return fail(S2_ERR_UNSUPPORTED, "N=%d: SO(3) plans support N <= 8", N);
     if (N > 1 && spin != 0) return fail(S2_ERR_INVALID_ARG, "SO(3) plans (N > 1) take spin 0");
     if (spin <= -L || spin >= L) return fail(S2_ERR_INVALID_ARG, "|spin|=%d must be < L=%d", spin, L);
-    if (sampling != S2_MW && sampling != S2_HEALPIX && sampling != S2_DH && sampling != S2_GL)
+    if (sampling != S2_MW && sampling != S2_HEALPIX && sampling != S2_DH && sampling != S2_GL && sampling != S2_MWSS)
         return fail(S2_ERR_INVALID_ARG, "unknown sampling %d", (int)sampling);
     if (sampling == S2_HEALPIX && (nside < 1 || nside > 2048)) return fail(S2_ERR_INVALID_ARG, "nside=%d outside [1, 2048]", nside);
     if (sampling != S2_MW && N > 1) return fail(S2_ERR_UNSUPPORTED, "SO(3) plans need MW sampling");
@@ -357,6 +357,18 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         start.resize(L);
         for (int t = 0; t < L; ++t) start[t] = (long long)t * (2 * L - 1);
         P->nsamp = (long long)L * (2 * L - 1);
+    } else if (sampling == S2_MWSS) {
+        // rings 0 .. L-2: theta = pi (r+1)/L; ring L-1: south pole; ring L: north pole
+        host_mwss_rings(L, &rc_h);
+        P->nreg = L - 1;
+        P->nring = L + 1;
+        nphi.assign(L + 1, 2 * L);
+        shift.assign(L + 1, 0);
+        start.resize(L + 1);
+        for (int r = 0; r < L - 1; ++r) start[r] = (long long)(r + 1) * 2 * L;
+        start[L - 1] = (long long)L * 2 * L;
+        start[L] = 0;
+        P->nsamp = (long long)(L + 1) * 2 * L;
     } else if (sampling == S2_DH || sampling == S2_GL) {
         // equiangular-phi rings without poles, each ring swept; forward by quadrature
         stg.d.emplace_back(); std::vector<double> &rq = stg.d.back();
@@ -399,7 +411,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             P->ffts_h.push_back(f);
             maxlen = std::max(maxlen, f.len);
         }
-        if (sampling == S2_MW) P->fN = P->ffts_h[0];
+        if (sampling == S2_MW || sampling == S2_MWSS) P->fN = P->ffts_h[0];
         P->fft_threads = fft_threads_for(maxlen);
         P->fft_lds = (size_t)maxlen * sizeof(double2);
         if ((rc = upload(P, &P->ring_fft, rf, st, "ring_fft"))) return bail(rc);
@@ -409,10 +421,10 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         for (auto &f : P->ffts_h) nblue += f.blue;
         if (nblue) HIPCHK(launch_bluestein_filter(st, (int)P->ffts_h.size(), P->ffts, P->fft_threads, P->fft_lds), "bluestein filters");
     }
-    if (sampling == S2_MW) {
+    if (sampling == S2_MW || sampling == S2_MWSS) {
         stg.d.emplace_back(); std::vector<double> &wq = stg.d.back();
         stg.d.emplace_back(); std::vector<double> &ph = stg.d.back();
-        host_mw_filter(L, &wq, &ph);
+        host_mw_filter(L, sampling == S2_MWSS, &wq, &ph);
         if ((rc = upload(P, &P->wq, wq, st, "mw filter weights"))) return bail(rc);
         if ((rc = upload(P, &P->ph, ph, st, "mw half-shift phases"))) return bail(rc);
     }
@@ -509,7 +521,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->off_maps = o; o += (sampling == S2_MW && spin == 0) ? align256((size_t)P->nsamp * S * sizeof(double2)) : 0;
         P->off_F = o; o += align256(P->szF * S);
         P->off_Q = o; o += align256(P->szQ * S);
-        P->off_hpole = o; o += align256((size_t)(2 * L - 1) * S * sizeof(double2));
+        P->off_hpole = o; o += align256((size_t)(2 * L - 1) * S * 2 * sizeof(double2));   // south, north
         // low-order machinery of runs with n != 0: masked spectra copies per run, continuation sums per slice
         P->szHx = (size_t)std::max(P->nxp, 1) * P->hstride * 4 * sizeof(double);
         P->szQx = (size_t)P->fwd_nblk * L * std::max(P->nxp, 1) * 4 * sizeof(double);
@@ -530,7 +542,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     }
     // HEALPix forward = q x adjoint of the inverse, so its adjoint is the inverse with weights q w_l;
     // DH / GL: the inverse with weights w_l, then each ring scaled by its quadrature weight
-    if (sampling != S2_MW && !so3) {
+    if (sampling != S2_MW && sampling != S2_MWSS && !so3) {
         stg.d.emplace_back();
         host_weights(L, 0, spin, &stg.d.back());
         if (sampling == S2_HEALPIX)
@@ -580,7 +592,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->off_mP = o; o += align256(B * S * nP1 * sizeof(double));
         P->off_mF = o; o += align256(B * S * P->szF);
         P->off_mQ = o; o += align256(B * S * nQ1 * sizeof(double));
-        P->off_mhp = o; o += align256(B * S * (2 * L - 1) * sizeof(double2));
+        P->off_mhp = o; o += align256(B * S * (2 * L - 1) * 2 * sizeof(double2));        // south, north
         P->off_mmaps = o; o += (S > 1) ? align256(B * S * (size_t)P->nsamp * sizeof(double2)) : 0;
         P->off_mQx = o; o += P->nxp > 0 ? align256(B * S * (size_t)L * P->nxp * 4 * sizeof(double)) : 0;
         P->ws_bytes = o;
@@ -710,8 +722,8 @@ int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *map, char *ws
     {
     TIMED(S2_STAGE_MW_THETA);
     HIPCHK(launch_fadj_gather(st, L, P->inv_nblk, s, P0, P->mtop, G, P->w_sht[0], P->hstride, F0), "adjoint gather");
-    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
-                            fft_scratch(P, ws)), "MW theta filter");
+    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, 0, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
+                            nullptr, fft_scratch(P, ws)), "MW theta filter");
     HIPCHK(launch_fadj_scatter(st, L, P->hstride, q, F0, hp0, Q0), "adjoint scatter");
     }
     TIMED(S2_STAGE_PHI_INV);
@@ -722,7 +734,8 @@ int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *map, char *ws
 }
 
 // forward d-stage of one map from the filtered ring spectra H (slices) -> flm slices
-int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *flm, const std::vector<double *> &wl,
+int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const double2 *hpoleN0, double2 *flm,
+                       const std::vector<double *> &wl,
                        char *ws, hipStream_t st)
 {
     const int L = P->L;
@@ -756,7 +769,7 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, double2 *
         TIMED(S2_STAGE_FINISH);
         HIPCHK(launch_finish_fwd(st, L, P->fwd_nblk, s, s, Q0 + k * nQ, Qx0 ? Qx0 + k * nQx : nullptr,
                                  std::max(P->nxp, 1), wl[k], hpole0 ? hpole0 + k * (2 * L - 1) : nullptr,
-                                 flm + k * slab), "forward finish");
+                                 hpoleN0 ? hpoleN0 + k * (2 * L - 1) : nullptr, flm + k * slab), "forward finish");
     }
     return S2_OK;
 }
@@ -769,10 +782,12 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
     const size_t nF = P->szF / sizeof(double);
     double *F0 = (double *)(ws + P->off_F);
     double2 *hp0 = (double2 *)(ws + P->off_hpole);
-    const bool mw = P->sampling == S2_MW;
+    const bool mw = P->sampling == S2_MW || P->sampling == S2_MWSS;   // theta-torus samplings
+    const int ss = P->sampling == S2_MWSS;
+    double2 *hpN0 = ss ? hp0 + (size_t)P->nslice * (2 * L - 1) : nullptr;
     double q;
     if (adjoint) q = 1.0;
-    else if (mw) q = 2.0 * M_PI / (double)(2 * L - 1);
+    else if (mw) q = 2.0 * M_PI / (double)(ss ? 2 * L : 2 * L - 1);
     else q = 4.0 * M_PI / (double)P->nsamp;
     for (int k = 0; k < P->nslice; ++k) {
         double *F = F0 + k * nF;
@@ -785,12 +800,15 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
         }
         TIMED(S2_STAGE_MW_THETA);
         if (mw && !adjoint)
-            HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, P->slice_spin[k], P->ffts, P->wq, P->ph, F,
-                                    hp0 + k * (2 * L - 1), fft_scratch(P, ws)), "MW theta filter");
-        else if (mw)
+            HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, P->slice_spin[k], P->ffts, P->wq,
+                                    P->ph, F, hp0 + k * (2 * L - 1), ss ? hpN0 + k * (2 * L - 1) : nullptr,
+                                    fft_scratch(P, ws)), "MW theta filter");
+        else if (mw) {
             HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp0 + k * (2 * L - 1)), "pole line");
+            if (ss) HIPCHK(launch_pole_from_F(st, L, P->hstride, L, F, hpN0 + k * (2 * L - 1)), "north pole line");
+        }
     }
-    return run_forward_dstage(P, F0, mw ? hp0 : nullptr, flm, wl, ws, st);
+    return run_forward_dstage(P, F0, mw ? hp0 : nullptr, hpN0, flm, wl, ws, st);
 }
 
 // ---------------------------------------------------------------- matrix-core path
@@ -854,7 +872,8 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
     const MfmaGeom &g = P->mg;
     const size_t slab = (size_t)L * (2 * L - 1);
     const size_t nF = P->szF / sizeof(double), nQ1 = (size_t)L * L * 4;
-    const bool mw = P->sampling == S2_MW;
+    const bool mw = P->sampling == S2_MW || P->sampling == S2_MWSS;   // theta-torus samplings
+    const int ss = P->sampling == S2_MWSS;
     uint4 *D = (uint4 *)(ws + P->off_D);
     uint4 *H = (uint4 *)(ws + P->off_AH);
     double *SX = (double *)(ws + P->off_S);
@@ -863,13 +882,14 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
     double *Fm = (double *)(ws + P->off_mF);
     double *Qm = (double *)(ws + P->off_mQ);
     double2 *hp = (double2 *)(ws + P->off_mhp);
+    double2 *hpN = ss ? hp + (size_t)B * S * (2 * L - 1) : nullptr;
     const int nxp1 = std::max(P->nxp, 1);
     const size_t nQx1 = (size_t)L * nxp1 * 4;
     double *Qxm = P->nxp > 0 ? (double *)(ws + P->off_mQx) : nullptr;
     if (Qxm) HIPCHK(launch_zero(st, Qxm, (size_t)B * S * nQx1 * sizeof(double)), "continuation sums clear");
     double q;
     if (adjoint) q = 1.0;
-    else if (mw) q = 2.0 * M_PI / (double)(2 * L - 1);
+    else if (mw) q = 2.0 * M_PI / (double)(ss ? 2 * L : 2 * L - 1);
     else q = 4.0 * M_PI / (double)P->nsamp;
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < S; ++k) {
@@ -885,11 +905,14 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             }
             TIMED(S2_STAGE_MW_THETA);
             if (mw && !adjoint)
-                HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, P->hstride, P->slice_spin[k], P->ffts,
-                                        P->wq, P->ph, F, hp + bk * (2 * L - 1), fft_scratch(P, ws)),
+                HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, P->slice_spin[k], P->ffts,
+                                        P->wq, P->ph, F, hp + bk * (2 * L - 1), ss ? hpN + bk * (2 * L - 1) : nullptr,
+                                        fft_scratch(P, ws)),
                    "MW theta filter");
-            else if (mw)
+            else if (mw) {
                 HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp + bk * (2 * L - 1)), "pole line");
+                if (ss) HIPCHK(launch_pole_from_F(st, L, P->hstride, L, F, hpN + bk * (2 * L - 1)), "north pole line");
+            }
         }
     for (size_t ri = 0; ri < P->runs.size(); ++ri) {
         const Run &r = P->runs[ri];
@@ -925,7 +948,8 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             const int s = P->slice_spin[k];
             TIMED(S2_STAGE_FINISH);
             HIPCHK(launch_finish_fwd(st, L, 1, s, s, Qm + bk * nQ1, Qxm ? Qxm + bk * nQx1 : nullptr, nxp1, wl[k],
-                                     mw ? hp + bk * (2 * L - 1) : nullptr, flm + bk * slab), "forward finish");
+                                     mw ? hp + bk * (2 * L - 1) : nullptr, ss ? hpN + bk * (2 * L - 1) : nullptr,
+                                     flm + bk * slab), "forward finish");
         }
     return S2_OK;
 }
@@ -987,6 +1011,7 @@ int s2_forward_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, void 
     if (rc) return rc;
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_forward_adjoint: plan was created for SO(3) (N=%d)", P->N);
     if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "s2_forward_adjoint: available for FP64 plans");
+    if (P->sampling == S2_MWSS) return fail(S2_ERR_UNSUPPORTED, "s2_forward_adjoint: not built for MWSS sampling");
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     for (int b = 0; b < batch; ++b) {

@@ -57,6 +57,19 @@ void fill_ring(RingConsts *rc, int r, __float128 th)
     split_dd(log2q(cosq(th / 2)), &rc->lcos[2 * r], &rc->lcos[2 * r + 1]);
 }
 
+// MWSS (Sec. 4.2): the swept rings theta = pi t / L, t = 1 .. L-1 (ring r = t - 1);
+// the poles t = 0 and t = L are handled in closed form.
+void host_mwss_rings(int L, RingConsts *rc)
+{
+    const int nreg = L - 1;
+    rc->theta.resize(nreg);
+    rc->cot.resize(nreg);
+    rc->csc.resize(nreg);
+    rc->lsin.resize(2 * nreg);
+    rc->lcos.resize(2 * nreg);
+    for (int r = 0; r < nreg; ++r) fill_ring(rc, r, QPI * (q)(r + 1) / (q)L);
+}
+
 // DH sampling theorem (Sec. 4.2): 2L rings theta_t = (2t+1) pi / (4L); the forward
 // weight of ring t (the phi rule 2 pi / (2L-1) included) is
 //   (4 pi / (L (2L-1))) sin(theta_t) sum_{k<L} sin((2k+1) theta_t) / (2k+1),
@@ -257,14 +270,15 @@ void host_chirp(int n, std::vector<double> *out)
 //       P[...](th) = sin(th)/2 + c_0 + 2 sum_{even d >= 2} c_d cos(d th);
 //   ph[k] = e^{i k' pi / N} / N for DFT bin k with signed frequency
 //       k' = k (k <= L-1) or k - N (k >= L): the half-sample shift.
-void host_mw_filter(int L, std::vector<double> *wq, std::vector<double> *ph)
+void host_mw_filter(int L, bool ss, std::vector<double> *wq, std::vector<double> *ph)
 {
-    const int N = 2 * L - 1;
+    const int N = ss ? 2 * L : 2 * L - 1;
     const long double pi = 3.141592653589793238462643383279502884L;
     wq->assign(2 * (size_t)N, 0.0);
     for (int which = 0; which < 2; ++which) {
         for (int t = 0; t < N; ++t) {
-            const long double th = (2.0L * t + 1.0L + which) * pi / (long double)N;
+            // MW theta_t = (2t+1) pi/N, MWSS theta_t = 2t pi/N; midpoints one half-step on
+            const long double th = (2.0L * t + (ss ? 0.0L : 1.0L) + which) * pi / (long double)N;
             long double acc = 1.0L / pi + 0.5L * sinl(th);
             const long double c2 = cosl(2.0L * th);
             long double cprev = 1.0L, ccur = c2;   // cos(0 th), cos(2 th)
@@ -284,8 +298,9 @@ void host_mw_filter(int L, std::vector<double> *wq, std::vector<double> *ph)
     for (int k = 0; k < N; ++k) {
         const int ks = (k <= L - 1) ? k : k - N;
         const long double a = (long double)ks * pi / (long double)N;
-        (*ph)[2 * k] = (double)(cosl(a) / (long double)N);
-        (*ph)[2 * k + 1] = (double)(sinl(a) / (long double)N);
+        const bool nyquist = ss && k == L;                  // MWSS: the Nyquist frequency is left out
+        (*ph)[2 * k] = nyquist ? 0.0 : (double)(cosl(a) / (long double)N);
+        (*ph)[2 * k + 1] = nyquist ? 0.0 : (double)(sinl(a) / (long double)N);
     }
 }
 

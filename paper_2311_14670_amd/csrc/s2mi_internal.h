@@ -21,6 +21,7 @@ void fill_ring(RingConsts *rc, int r, __float128 th);
 #endif
 #endif
 void host_mw_rings(int L, RingConsts *rc);
+void host_mwss_rings(int L, RingConsts *rc);
 void host_dh_rings(int L, RingConsts *rc, std::vector<double> *wq);
 void host_gl_rings(int L, RingConsts *rc, std::vector<double> *wq);
 void host_healpix_rings(int nside, RingConsts *rc, std::vector<int> *nphi,
@@ -29,7 +30,7 @@ void host_log2_binom(int L, int n, std::vector<double> *out);
 void host_recursion_tables(int L, int nx, std::vector<double> *kap, std::vector<double> *gtab);
 void host_roots(int n, std::vector<double> *out);
 void host_chirp(int n, std::vector<double> *out);
-void host_mw_filter(int L, std::vector<double> *wq, std::vector<double> *ph);
+void host_mw_filter(int L, bool ss, std::vector<double> *wq, std::vector<double> *ph);
 void host_weights(int L, int kind, int spin, std::vector<double> *w);
 
 // ----------------------------------------------------------------- FFT

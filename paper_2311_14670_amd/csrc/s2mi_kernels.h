@@ -30,12 +30,13 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
                           const int *ring_nphi, const long long *ring_start, const int *ring_shift,
                           const int *ring_fft, const FftArgs *ffts, const double *ringq, double *F,
                           double2 *fscr);
-hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int hstride, int spin, const FftArgs *fN,
-                            const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *fscr);
+hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
+                            const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
+                            double2 *hpoleN, double2 *fscr);
 hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *w, double2 *map);
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
-                             int nxp, const double *wl, const double2 *hpole, double2 *flm);
+                             int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN,
+                             double2 *flm);
 hipError_t launch_gamma_dft(hipStream_t st, int N, long long nper, int sign, double q, const double *roots,
                             const double2 *in, double2 *out);
 hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,

@@ -710,12 +710,15 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
             buf[k] = acc;
         }
     } else {
-        // south pole: only m = s contributes, value sum_l (-1)^{l+s} w_l flm[l][s]
+        // south pole (ring nreg): only m = s contributes, value sum_l (-1)^{l+s} w_l flm[l][s];
+        // north pole (ring nreg + 1, MWSS): only m = -s, value sum_l w_l flm[l][-s]  (Eq. 29)
+        const bool north = r > nreg;
+        const int mp = north ? -spin : spin;
         double2 acc = make_double2(0.0, 0.0);
         const int as = spin < 0 ? -spin : spin;
         for (int l = as + tid; l < L; l += T) {
-            double2 v = flm[(size_t)l * M + (L - 1) + spin];
-            const double c = ((l + spin) & 1) ? -wl[l] : wl[l];
+            double2 v = flm[(size_t)l * M + (L - 1) + mp];
+            const double c = (!north && ((l + spin) & 1)) ? -wl[l] : wl[l];
             acc.x += c * v.x;
             acc.y += c * v.y;
         }
@@ -729,7 +732,7 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
         }
         for (int k = tid; k < nphi; k += T) buf[k] = make_double2(0.0, 0.0);
         __syncthreads();
-        if (tid == 0) buf[((spin % nphi) + nphi) % nphi] = red[0];
+        if (tid == 0) buf[((mp % nphi) + nphi) % nphi] = red[0];
     }
     __syncthreads();
     dft_lds(buf, f, +1, fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr);
@@ -781,25 +784,40 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
     }
 }
 
-// ------------------------------------------------------------------ MW theta filter
+// ------------------------------------------------------------------ MW / MWSS theta filter
 // One workgroup per order m >= 0, both signs.  For g = the torus extension of
-// ftilde_{+-m} (g(2pi - th) = (-1)^{m+s} g(th)), compute on the L rings
-//   h~(theta_t) = (2pi/N) [h(theta_t) + (-1)^{m+s} h(theta_{N-1-t})]  (t < L-1),
-//   h~(pi)      = (2pi/N) h(pi),
+// ftilde_{+-m} (g(2pi - th) = (-1)^{m+s} g(th)), on the N torus points
+// (MW: N = 2L-1, theta_t = (2t+1) pi/N; MWSS: N = 2L, theta_t = 2 pi t/N)
 //   h = P_{L-1}[g w'],   w' = P_{2L-2}[sin(theta) 1_[0,pi]],
-// so that sum_t h~(theta_t) d(theta_t) = int_0^pi g d sin(theta) exactly.  On the
-// doubled grid {theta_t} u {mu_t = theta_t + pi/N}:
+// folded onto the rings: h~(theta_t) = (2pi/N) [h(theta_t) + (-1)^{m+s} h(mirror t)]
+// (MW mirror N-1-t, MWSS N-t), unfolded at the poles, so that
+// sum_t h~(theta_t) d(theta_t) = int_0^pi g d sin(theta) exactly.  On the doubled
+// grid {theta_t} u {mu_t = theta_t + pi/N}:
 //   h = (g w'_theta + S-[w'_mu S+ g]) / 2,
 // S+-: band-limited half-sample shifts (DFT, phase e^{+-i k pi/N}/N, inverse DFT).
-// In place: F[m][t] -> H[m][t]; the south-pole value goes to hpole[m].
-__global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin, const FftArgs *__restrict__ fN,
+// MWSS: g is the torus interpolant without the Nyquist frequency L (it vanishes
+// for band-limited samples); its value at theta_t is g_t - ghat_L (-1)^t.
+// Torus point t <-> ring: MW t < L: ring t (t = L-1: south pole), MWSS t = 0:
+// north pole (ring L), 0 < t < L: ring t-1, t = L: south pole (ring L-1).  In
+// place: F[m][ring] -> H[m][ring] for the swept rings; the pole values go to
+// hpole[(L-1) +- m] (south) and hpoleN (north, MWSS).
+__device__ __forceinline__ int torus_ring(int t, int L, int N, int ss, bool *mirrored)
+{
+    *mirrored = ss ? t > L : t >= L;
+    const int u = *mirrored ? (ss ? N - t : N - 1 - t) : t;     // sample on [0, pi]
+    if (!ss) return u;
+    return u == 0 ? L : u - 1;
+}
+
+__global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, int spin, const FftArgs *__restrict__ fN,
                                                     const double *__restrict__ wq, const double *__restrict__ ph,
                                                     double *__restrict__ F, double2 *__restrict__ hpole,
-                                                    double2 *__restrict__ fscr)
+                                                    double2 *__restrict__ hpoleN, double2 *__restrict__ fscr)
 {
     extern __shared__ double2 buf[];
+    __shared__ double2 nyq;
     const int m = blockIdx.x;
-    const int N = 2 * L - 1;
+    const int N = ss ? 2 * L : 2 * L - 1;
     const int T = blockDim.x, tid = threadIdx.x;
     const double par = ((m + spin) & 1) ? -1.0 : 1.0;
     const double2 *phc = reinterpret_cast<const double2 *>(ph);
@@ -808,15 +826,19 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin
         if (side == 1 && m == 0) break;
         // torus samples
         for (int t = tid; t < N; t += T) {
-            const int tt = t < L ? t : N - 1 - t;
-            const double *src = F + ((size_t)m * hstride + tt) * 4 + 2 * side;
+            bool mir;
+            const int r = torus_ring(t, L, N, ss, &mir);
+            const double *src = F + ((size_t)m * hstride + r) * 4 + 2 * side;
             double2 g = make_double2(src[0], src[1]);
-            if (t >= L) { g.x *= par; g.y *= par; }
+            if (mir) { g.x *= par; g.y *= par; }
             buf[t] = g;
         }
         __syncthreads();
         dft_lds(buf, fN, -1, scr);
-        for (int k = tid; k < N; k += T) buf[k] = cmul(buf[k], phc[k]);              // shift +pi/N
+        for (int k = tid; k < N; k += T) {                                          // shift +pi/N
+            if (ss && k == L) nyq = make_double2(buf[k].x / N, buf[k].y / N);     // ghat_L (MWSS), read first
+            buf[k] = cmul(buf[k], phc[k]);
+        }
         __syncthreads();
         dft_lds(buf, fN, +1, scr);
         for (int t = tid; t < N; t += T) { const double wv = wq[N + t]; buf[t].x *= wv; buf[t].y *= wv; }
@@ -826,28 +848,40 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int hstride, int spin
         __syncthreads();
         dft_lds(buf, fN, +1, scr);
         for (int t = tid; t < N; t += T) {          // + g w'_theta (g re-read: F is rewritten only below)
-            const int tt = t < L ? t : N - 1 - t;
-            const double *src = F + ((size_t)m * hstride + tt) * 4 + 2 * side;
-            const double wv = (t >= L ? par : 1.0) * wq[t];
-            buf[t] = make_double2(0.5 * fma(src[0], wv, buf[t].x), 0.5 * fma(src[1], wv, buf[t].y));
+            bool mir;
+            const int r = torus_ring(t, L, N, ss, &mir);
+            const double *src = F + ((size_t)m * hstride + r) * 4 + 2 * side;
+            double2 g = make_double2(src[0], src[1]);
+            if (mir) { g.x *= par; g.y *= par; }
+            if (ss) {
+                const double sg = (t & 1) ? -1.0 : 1.0;
+                g.x -= sg * nyq.x;
+                g.y -= sg * nyq.y;
+            }
+            const double wv = wq[t];
+            buf[t] = make_double2(0.5 * fma(g.x, wv, buf[t].x), 0.5 * fma(g.y, wv, buf[t].y));
         }
         __syncthreads();
         const double sc = 2.0 * M_PI / (double)N;
-        for (int t = tid; t < L; t += T) {
+        const int hidx = side == 0 ? (L - 1) + m : (L - 1) - m;
+        for (int t = tid; t < (ss ? L + 1 : L); t += T) {
             double2 h = buf[t];
-            if (t < L - 1) {
-                const double2 hr = buf[N - 1 - t];
+            const bool pole = ss ? (t == 0 || t == L) : (t == L - 1);
+            if (!pole) {
+                const double2 hr = buf[ss ? N - t : N - 1 - t];
                 h.x += par * hr.x;
                 h.y += par * hr.y;
             }
             h.x *= sc;
             h.y *= sc;
-            if (t < L - 1) {
-                double *dst = F + ((size_t)m * hstride + t) * 4 + 2 * side;
+            if (!pole) {
+                double *dst = F + ((size_t)m * hstride + (ss ? t - 1 : t)) * 4 + 2 * side;
                 dst[0] = h.x;
                 dst[1] = h.y;
+            } else if (ss && t == 0) {
+                hpoleN[hidx] = h;
             } else {
-                hpole[side == 0 ? (L - 1) + m : (L - 1) - m] = h;
+                hpole[hidx] = h;
             }
         }
         __syncthreads();
@@ -924,13 +958,15 @@ __global__ void k_fadj_scatter(int L, int hstride, double q, const double *__res
 
 // ------------------------------------------------------------------ forward finish
 // flm[l][m] = w_l * (sum_b Q[b][l][|m|].side + Qx[b][l][|m|].side) * ((-1)^{|m|-nB} for m < 0)
-//           + MW south pole: w_l (-1)^{l+s} h~_s(pi) at m = s  (Eq. 29).
+//           + south pole: w_l (-1)^{l+s} h~_s(pi) at m = s  (Eq. 29)
+//           + north pole (MWSS): w_l h~_{-s}(0) at m = -s.
 // Zero where l < max(|m|, |spin|).  One thread per (l, |m|) reads whole 32-byte
 // records (side A = order +|m| in components 0,1, side B = order -|m| in 2,3) and
 // writes both orders.
 __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__restrict__ Q,
                              const double *__restrict__ Qx, int nxp, const double *__restrict__ wl,
-                             const double2 *__restrict__ hpole, double2 *__restrict__ flm)
+                             const double2 *__restrict__ hpole, const double2 *__restrict__ hpoleN,
+                             double2 *__restrict__ flm)
 {
     const int M = 2 * L - 1;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -963,6 +999,16 @@ __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__
             if (am > 0 && -am == spin) {
                 const double2 hp = hpole[(L - 1) - am];
                 b = make_double2(fma(c, hp.x, b.x), fma(c, hp.y, b.y));
+            }
+        }
+        if (hpoleN) {                                  // MWSS north pole: w_l h~_{-s}(0) at m = -s
+            if (am == -spin) {
+                const double2 hp = hpoleN[(L - 1) + am];
+                a = make_double2(fma(w, hp.x, a.x), fma(w, hp.y, a.y));
+            }
+            if (am > 0 && -am == -spin) {
+                const double2 hp = hpoleN[(L - 1) - am];
+                b = make_double2(fma(w, hp.x, b.x), fma(w, hp.y, b.y));
             }
         }
     }
@@ -1205,10 +1251,13 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
     return hipSuccess;
 }
 
-hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int hstride, int spin, const FftArgs *fN,
-                            const double *wq, const double *ph, double *F, double2 *hpole, double2 *fscr)
+hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
+                            const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
+                            double2 *hpoleN, double2 *fscr)
 {
-    hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, hstride, spin, fN, wq, ph, F, hpole, fscr);
+    if (ss && !hpoleN) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, ss, hstride, spin, fN, wq, ph, F, hpole,
+                       hpoleN, fscr);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1223,11 +1272,11 @@ hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *
 }
 
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
-                             int nxp, const double *wl, const double2 *hpole, double2 *flm)
+                             int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN, double2 *flm)
 {
     const size_t tot = (size_t)L * L;
     hipLaunchKernelGGL(k_finish_fwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, nB, Q, Qx,
-                       nxp, wl, hpole, flm);
+                       nxp, wl, hpole, hpoleN, flm);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

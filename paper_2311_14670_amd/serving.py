@@ -36,7 +36,7 @@ class PlanKey:
     L: int
     spin: int
     N: int
-    sampling: str      # "mw", "healpix", "dh" or "gl"
+    sampling: str      # "mw", "healpix", "dh", "gl" or "mwss"
     nside: int
     precision: str = "fp64"
 
@@ -76,6 +76,8 @@ def map_elems(key):
         return (2 * key.N - 1) * key.L * (2 * key.L - 1)
     if key.sampling == "healpix":
         return 12 * key.nside * key.nside
+    if key.sampling == "mwss":
+        return (key.L + 1) * 2 * key.L
     return (2 * key.L if key.sampling == "dh" else key.L) * (2 * key.L - 1)
 
 

@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol():
     (dict(L=1), -1), (dict(L=5000), -1), (dict(L=16, spin=16), -1), (dict(L=16, N=0), -1),
     (dict(L=16, N=9), -2), (dict(L=16, N=3, spin=2), -1), (dict(L=16, sampling=7), -1),
     (dict(L=16, sampling=1, nside=0), -1), (dict(L=16, sampling=1, nside=4, N=2), -2),
-    (dict(L=16, sampling=2, N=2), -2), (dict(L=16, sampling=3, N=4), -2), (dict(L=16, sampling=4), -1),
+    (dict(L=16, sampling=2, N=2), -2), (dict(L=16, sampling=3, N=4), -2), (dict(L=16, sampling=4, N=2), -2),
+    (dict(L=16, sampling=5), -1),
     (dict(L=16, max_batch=0), -1), (dict(L=16, precision=3), -1)])
 def test_plan_create_validation(kw, code):
     from paper_2311_14670_amd import binding

@@ -85,10 +85,10 @@ def test_healpix_batched(binding, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("sampling", ["dh", "gl"])
+@pytest.mark.parametrize("sampling", ["dh", "gl", "mwss"])
 def test_dh_gl_batched(binding, prec, sampling):
     L, spin, B = 40, 2, 3
-    samp = oracle.DH if sampling == "dh" else oracle.GL
+    samp = {"dh": oracle.DH, "gl": oracle.GL, "mwss": oracle.MWSS}[sampling]
     flm = flm_gaussian(L, spin, seed=26, batch=B)
     plan = binding.Plan(L, spin=spin, sampling=sampling, max_batch=B, precision=prec)
     f = host(plan.inverse(dev(flm)))

@@ -80,19 +80,20 @@ def test_healpix_inverse_and_forward(binding, nside, L, spin):
     assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < tol
 
 
-_ORACLE_SAMPLING = {"mw": oracle.MW, "healpix": oracle.HEALPIX, "dh": oracle.DH, "gl": oracle.GL}
+_ORACLE_SAMPLING = {"mw": oracle.MW, "healpix": oracle.HEALPIX, "dh": oracle.DH, "gl": oracle.GL,
+                    "mwss": oracle.MWSS}
 
 
-@pytest.mark.parametrize("sampling", ["dh", "gl"])
+@pytest.mark.parametrize("sampling", ["dh", "gl", "mwss"])
 @pytest.mark.parametrize("L,spin", [(2, 0), (9, 0), (32, 0), (24, 2), (17, -1), (40, 5)])
 def test_dh_gl_inverse_and_forward(binding, sampling, L, spin):
-    """DH and GL sampling theorems (Sec. 4.2): inverse, forward quadrature and the
-    exact round trip."""
+    """DH, GL and MWSS sampling theorems (Sec. 4.2): inverse, forward (quadrature or
+    the MWSS theta-torus filter; arbitrary maps) and the exact round trip."""
     tol = 1e-13 if abs(spin) <= 3 else 1e-12
     samp = _ORACLE_SAMPLING[sampling]
     flm = flm_gaussian(L, spin, seed=5)
     plan = binding.Plan(L, spin=spin, sampling=sampling)
-    assert plan.map_shape == (oracle.num_rings(L, samp), 2 * L - 1)
+    assert plan.map_shape == (oracle.num_rings(L, samp), oracle.ring_length(L, samp))
     f = host(plan.inverse(dev(flm)))
     assert rel_l2(f, oracle.s2_inverse(flm, L, spin, samp)) < tol
     g = map_gaussian(plan.map_shape, seed=6)
@@ -102,7 +103,8 @@ def test_dh_gl_inverse_and_forward(binding, sampling, L, spin):
 
 
 @pytest.mark.parametrize("sampling,L,nside,spin", [("mw", 24, 0, 0), ("mw", 24, 0, 2), ("healpix", 16, 8, 2),
-                                                   ("mw", 30, 0, -11), ("dh", 20, 0, 2), ("gl", 21, 0, 0)])
+                                                   ("mw", 30, 0, -11), ("dh", 20, 0, 2), ("gl", 21, 0, 0),
+                                                   ("mwss", 18, 0, 0), ("mwss", 19, 0, -2)])
 def test_inverse_adjoint(binding, sampling, L, nside, spin):
     plan = binding.Plan(L, spin=spin, sampling=sampling, nside=nside)
     g = map_gaussian(plan.map_shape, seed=4)

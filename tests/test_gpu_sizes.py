@@ -57,9 +57,12 @@ def test_healpix_multi_tile(binding, nside, L, spin):
     assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < 1e-12
 
 
-@pytest.mark.parametrize("sampling,L,spin", [("dh", 130, 0), ("gl", 150, 2)])
+_SAMP = {"dh": oracle.DH, "gl": oracle.GL, "mwss": oracle.MWSS}
+
+
+@pytest.mark.parametrize("sampling,L,spin", [("dh", 130, 0), ("gl", 150, 2), ("mwss", 140, -2)])
 def test_dh_gl_multi_tile(binding, sampling, L, spin):
-    samp = oracle.DH if sampling == "dh" else oracle.GL
+    samp = _SAMP[sampling]
     flm = flm_gaussian(L, spin, seed=19, scale="inv1pl")
     plan = binding.Plan(L, spin=spin, sampling=sampling)
     f = host(plan.inverse(dev(flm)))
@@ -67,9 +70,9 @@ def test_dh_gl_multi_tile(binding, sampling, L, spin):
     assert rel_l2(host(plan.forward(dev(f))), flm) < 1e-12     # sampling theorem: exact round trip
 
 
-@pytest.mark.parametrize("sampling,L", [("dh", 1024), ("gl", 2048)])
+@pytest.mark.parametrize("sampling,L", [("dh", 1024), ("gl", 2048), ("mwss", 2048)])
 def test_dh_gl_full_size_sampled(binding, sampling, L):
-    samp = oracle.DH if sampling == "dh" else oracle.GL
+    samp = _SAMP[sampling]
     flm = flm_gaussian(L, 0, seed=20, scale="inv1pl")
     plan = binding.Plan(L, sampling=sampling)
     f = plan.inverse(dev(flm))

@@ -173,9 +173,11 @@ int s2_inverse_adjoint(s2_plan_t plan, const void *g, void *g_flm, int batch, vo
  *       (Eq. 31) times 2 pi/(2L-1); the south pole follows Eq. 29.
  *   HEALPix: (4 pi / Npix) times the inverse SHT (the forward is the
  *       quadrature of Eq. 19).
+ *   DH, GL: the inverse SHT with the forward's weights, then each ring
+ *       scaled by its quadrature weight.
  *   g_flm  [batch][L][2L-1] complex128 (device, read)
  *   g      [batch][nsamples] complex128 (device, written)
- * FP64 plans only (S2_ERR_UNSUPPORTED otherwise).
+ * FP64 plans only; not available for MWSS sampling (S2_ERR_UNSUPPORTED).
  */
 int s2_forward_adjoint(s2_plan_t plan, const void *g_flm, void *g, int batch, void *workspace,
                        void *hip_stream);
@@ -196,6 +198,33 @@ int so3_inverse(s2_plan_t plan, const void *flmn, void *f, int batch, void *work
  */
 int so3_forward(s2_plan_t plan, const void *f, void *flmn, int batch, void *workspace,
                 void *hip_stream);
+
+/*
+ * Hermitian adjoint of the inverse Wigner transform (gradients through
+ * so3_inverse, Sec. 5, in the conjugate convention PyTorch uses for complex
+ * tensors):
+ *   g_flmn[n][l][m] = sum_{t,p,k} g(alpha_p, beta_t, gamma_k) conj(D^l_{mn})
+ *                     times (2l+1)/(8 pi^2),
+ * computed as the unweighted gamma analysis sum_k g(gamma_k) e^{-i n gamma_k}
+ * followed, per n, by the adjoint of the spin -n inverse SHT.
+ *   g       [batch][2N-1][L][2L-1] complex128 (device, read)
+ *   g_flmn  [batch][2N-1][L][2L-1] complex128 (device, written)
+ * MW spin-0 plans, FP64 or matrix-core.
+ */
+int so3_inverse_adjoint(s2_plan_t plan, const void *g, void *g_flmn, int batch, void *workspace,
+                        void *hip_stream);
+
+/*
+ * Hermitian adjoint of the forward Wigner transform (gradients through
+ * so3_forward): per n the adjoint of the MW forward (inverse-type sweep with
+ * the forward's weights, the Hermitian MW theta filter, adjoint phi-DFT times
+ * 2 pi/(2L-1)), then the gamma synthesis times 2 pi/(2N-1).
+ *   g_flmn  [batch][2N-1][L][2L-1] complex128 (device, read)
+ *   g       [batch][2N-1][L][2L-1] complex128 (device, written)
+ * MW spin-0 FP64 plans only (S2_ERR_UNSUPPORTED for matrix-core plans).
+ */
+int so3_forward_adjoint(s2_plan_t plan, const void *g_flmn, void *g, int batch, void *workspace,
+                        void *hip_stream);
 
 /*
  * Debug/validation: export the GPU recursion's d^l_{m,n}(theta_r) for one

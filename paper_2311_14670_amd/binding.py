@@ -69,7 +69,7 @@ def load_library():
         lib.s2_plan_destroy.argtypes = [P]
         lib.s2_plan_info.argtypes = [P, ctypes.POINTER(_PlanInfo)]
         for name in ["s2_inverse", "s2_forward", "s2_inverse_adjoint", "s2_forward_adjoint", "so3_inverse",
-                     "so3_forward"]:
+                     "so3_forward", "so3_inverse_adjoint", "so3_forward_adjoint"]:
             getattr(lib, name).argtypes = [P, vp, vp, i, vp, vp]
             getattr(lib, name).restype = i
         lib.s2_debug_wigner_d.argtypes = [P, i, vp, vp]
@@ -207,6 +207,16 @@ class Plan:
         """Forward Wigner transform: f [B?, 2N-1, L, 2L-1] -> flmn."""
         shp = (2 * self.N - 1,) + self.coeff_shape
         return self._call(self._lib.so3_forward, f, shp, shp, "so3_forward", workspace, out)
+
+    def so3_inverse_adjoint(self, g, workspace=None, out=None):
+        """Hermitian adjoint of the inverse Wigner transform: f-space cotangent -> flmn-space."""
+        shp = (2 * self.N - 1,) + self.coeff_shape
+        return self._call(self._lib.so3_inverse_adjoint, g, shp, shp, "so3_inverse_adjoint", workspace, out)
+
+    def so3_forward_adjoint(self, g_flmn, workspace=None, out=None):
+        """Hermitian adjoint of the forward Wigner transform: flmn-space cotangent -> f-space (FP64 plans)."""
+        shp = (2 * self.N - 1,) + self.coeff_shape
+        return self._call(self._lib.so3_forward_adjoint, g_flmn, shp, shp, "so3_forward_adjoint", workspace, out)
 
     def set_timing(self, enable=True):
         """Record HIP events around every kernel launch of this plan's transforms."""

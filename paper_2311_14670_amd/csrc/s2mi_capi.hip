@@ -708,28 +708,38 @@ int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, con
     return S2_OK;
 }
 
-// adjoint of the MW forward SHT of one map (S2 plan): coefficient cotangent -> map
-int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *map, char *ws, hipStream_t st)
+// adjoint of the MW forward of one map, all slices (finish weights wl[k], spin
+// slice_spin[k]): coefficient cotangent slices -> slice maps.  The slices share
+// one gather / filter / scatter buffer in turn.
+int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *const *slice_maps,
+                           const std::vector<double *> &wl, char *ws, hipStream_t st)
 {
-    const int L = P->L, s = P->spin;
-    int rc = run_inverse_dstage(P, G, P->w_sht, ws, st);
+    const int L = P->L;
+    const size_t slab = (size_t)L * (2 * L - 1);
+    int rc = run_inverse_dstage(P, G, wl, ws, st);
     if (rc) return rc;
     double *P0 = (double *)(ws + P->off_P);
+    const size_t nP = P->szP / sizeof(double);
     double *F0 = (double *)(ws + P->off_F);
     double2 *hp0 = (double2 *)(ws + P->off_hpole);
     double *Q0 = (double *)(ws + P->off_Q);
     const double q = 2.0 * M_PI / (double)(2 * L - 1);
-    {
-    TIMED(S2_STAGE_MW_THETA);
-    HIPCHK(launch_fadj_gather(st, L, P->inv_nblk, s, P0, P->mtop, G, P->w_sht[0], P->hstride, F0), "adjoint gather");
-    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, 0, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
-                            nullptr, fft_scratch(P, ws)), "MW theta filter");
-    HIPCHK(launch_fadj_scatter(st, L, P->hstride, q, F0, hp0, Q0), "adjoint scatter");
+    for (int k = 0; k < P->nslice; ++k) {
+        const int s = P->slice_spin[k];
+        const double2 *Gk = G + k * slab;
+        {
+        TIMED(S2_STAGE_MW_THETA);
+        HIPCHK(launch_fadj_gather(st, L, P->inv_nblk, s, P0 + k * nP, P->mtop, Gk, wl[k], P->hstride, F0),
+               "adjoint gather");
+        HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, 0, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
+                                nullptr, fft_scratch(P, ws)), "MW theta filter");
+        HIPCHK(launch_fadj_scatter(st, L, P->hstride, q, F0, hp0, Q0), "adjoint scatter");
+        }
+        TIMED(S2_STAGE_PHI_INV);
+        HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, L, 1, s, Q0, P->mtop1, Gk, wl[k],
+                              P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, slice_maps[k],
+                              fft_scratch(P, ws)), "adjoint phi-DFT");
     }
-    TIMED(S2_STAGE_PHI_INV);
-    HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, L, 1, s, Q0, P->mtop1, G, P->w_sht[0],
-                          P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, map, fft_scratch(P, ws)),
-           "adjoint phi-DFT");
     return S2_OK;
 }
 
@@ -1017,7 +1027,7 @@ int s2_forward_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, void 
     for (int b = 0; b < batch; ++b) {
         const double2 *G = (const double2 *)g_flm + b * slab;
         double2 *out = (double2 *)g + (size_t)b * P->nsamp;
-        if (P->sampling == S2_MW) rc = run_forward_adjoint_mw(P, G, out, (char *)workspace, st);
+        if (P->sampling == S2_MW) rc = run_forward_adjoint_mw(P, G, &out, P->w_sht, (char *)workspace, st);
         else rc = run_inverse(P, G, &out, P->w_fadj, (char *)workspace, st);
         if (rc) return rc;
         if (P->ringq)
@@ -1094,6 +1104,73 @@ int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspa
         for (int k = 0; k < S; ++k) maps[k] = tmp + (size_t)k * P->nsamp;
         if ((rc = run_forward(P, maps.data(), (double2 *)flmn + (size_t)b * S * slab, P->w_so3f, (char *)workspace,
                               st, false))) return rc;
+    }
+    return S2_OK;
+}
+
+int so3_inverse_adjoint(s2_plan_t P, const void *g, void *g_flmn, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("so3_inverse_adjoint", P, g, g_flmn, batch, workspace);
+    if (rc) return rc;
+    if (P->sampling != S2_MW || P->spin != 0)
+        return fail(S2_ERR_INVALID_ARG, "so3_inverse_adjoint: needs an MW spin-0 plan");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int S = P->nslice;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    // so3_inverse = (gamma synthesis, sign +1) after the per-n inverses, so its adjoint is the
+    // gamma analysis with unit weight (sign -1) followed by the per-n inverse adjoints.
+    if (P->mfma) {
+        const double2 *src = (const double2 *)g;
+        if (S > 1) {
+            double2 *tmp = (double2 *)((char *)workspace + P->off_mmaps);
+            for (int b = 0; b < batch; ++b) {
+                TIMED(S2_STAGE_GAMMA);
+                HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, -1, 1.0, P->groots,
+                                        (const double2 *)g + (size_t)b * S * P->nsamp, tmp + (size_t)b * S * P->nsamp),
+                       "gamma DFT");
+            }
+            src = tmp;
+        }
+        return run_forward_mfma(P, src, batch, (double2 *)g_flmn, P->w_so3i, (char *)workspace, st, true);
+    }
+    for (int b = 0; b < batch; ++b) {
+        const double2 *in = (const double2 *)g + (size_t)b * S * P->nsamp;
+        const double2 *src = in;
+        if (S > 1) {
+            double2 *tmp = (double2 *)((char *)workspace + P->off_maps);
+            TIMED(S2_STAGE_GAMMA);
+            HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, -1, 1.0, P->groots, in, tmp), "gamma DFT");
+            src = tmp;
+        }
+        std::vector<const double2 *> maps(S);
+        for (int k = 0; k < S; ++k) maps[k] = src + (size_t)k * P->nsamp;
+        if ((rc = run_forward(P, maps.data(), (double2 *)g_flmn + (size_t)b * S * slab, P->w_so3i, (char *)workspace,
+                              st, true))) return rc;
+    }
+    return S2_OK;
+}
+
+int so3_forward_adjoint(s2_plan_t P, const void *g_flmn, void *g, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("so3_forward_adjoint", P, g_flmn, g, batch, workspace);
+    if (rc) return rc;
+    if (P->sampling != S2_MW || P->spin != 0)
+        return fail(S2_ERR_INVALID_ARG, "so3_forward_adjoint: needs an MW spin-0 plan");
+    if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "so3_forward_adjoint: available for FP64 plans");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int S = P->nslice;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    // so3_forward = per-n MW forwards after the gamma analysis (sign -1, weight 2pi/(2N-1)), so
+    // its adjoint is the per-n forward adjoints followed by the gamma synthesis with that weight.
+    double2 *tmp = (double2 *)((char *)workspace + P->off_maps);
+    std::vector<double2 *> maps(S);
+    for (int k = 0; k < S; ++k) maps[k] = tmp + (size_t)k * P->nsamp;
+    for (int b = 0; b < batch; ++b) {
+        if ((rc = run_forward_adjoint_mw(P, (const double2 *)g_flmn + (size_t)b * S * slab, maps.data(), P->w_so3f,
+                                         (char *)workspace, st))) return rc;
+        TIMED(S2_STAGE_GAMMA);
+        HIPCHK(launch_gamma_dft(st, P->N, P->nsamp, +1, 2.0 * M_PI / (double)S, P->groots, tmp,
+                                (double2 *)g + (size_t)b * S * P->nsamp), "gamma DFT");
     }
     return S2_OK;
 }

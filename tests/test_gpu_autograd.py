@@ -132,3 +132,104 @@ def test_forward_gradient_matches_finite_differences(ag, spin):
         fd[c0:c0 + cs.size] = (lv[:cs.size] - lv[cs.size:]) / 2.0
     fd_c = (fd[0::2] + 1j * fd[1::2]).reshape(L, 2 * L - 1)
     assert rel_l2(grad, fd_c) < 1e-9
+
+
+@pytest.mark.parametrize("direction", ["inverse", "forward"])
+def test_forward_mode_jvp_is_the_transform(ag, direction):
+    """Forward-mode AD: the JVP of a linear transform is the transform of the
+    tangent (checked against the oracle)."""
+    import torch.autograd.forward_ad as fwAD
+    autograd, binding = ag
+    L, spin = 24, 2
+    plan = binding.Plan(L, spin=spin)
+    if direction == "inverse":
+        x = flm_gaussian(L, spin, seed=40)
+        t = flm_gaussian(L, spin, seed=41)
+        ref = oracle.s2_inverse(t, L, spin)
+        fn = autograd.inverse
+    else:
+        x = map_gaussian((L, 2 * L - 1), seed=40)
+        t = map_gaussian((L, 2 * L - 1), seed=41)
+        ref = oracle.s2_forward(t, L, spin)
+        fn = autograd.forward
+    with fwAD.dual_level():
+        dual = fwAD.make_dual(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+        y = fn(dual, plan)
+        tangent = fwAD.unpack_dual(y).tangent.cpu().numpy()
+    assert rel_l2(tangent, ref) < 1e-13
+
+
+def _dense(fn, shape):
+    """Matrix of a linear map on complex arrays of `shape`, column by column
+    from the oracle applied to unit vectors (brute force, tiny sizes only)."""
+    n = int(np.prod(shape))
+    cols = []
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1.0
+        cols.append(np.asarray(fn(e.reshape(shape))).ravel())
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("direction", ["inverse", "forward"])
+@pytest.mark.parametrize("L,N", [(6, 1), (6, 3)])
+def test_so3_adjoint_matches_dense_oracle(ag, direction, L, N):
+    """A^H y from the GPU adjoint equals conj(A).T @ y with A the oracle's
+    Wigner transform written out as a dense matrix."""
+    autograd, binding = ag
+    shp = (2 * N - 1, L, 2 * L - 1)
+    plan = binding.Plan(L, N=N, max_batch=2)
+    if direction == "inverse":
+        A = _dense(lambda x: oracle.so3_inverse(x, L, N), shp)
+        adj = plan.so3_inverse_adjoint
+    else:
+        A = _dense(lambda x: oracle.so3_forward(x, L, N), shp)
+        adj = plan.so3_forward_adjoint
+    y = map_gaussian((2,) + shp, seed=50)
+    got = adj(torch.from_numpy(y).cuda()).cpu().numpy()
+    for b in range(2):
+        ref = (A.conj().T @ y[b].ravel()).reshape(shp)
+        assert rel_l2(got[b], ref) < 1e-12
+
+
+@pytest.mark.parametrize("L,N", [(24, 4), (40, 7)])
+def test_so3_adjoint_dot_products(ag, L, N):
+    """<A x, y> = <x, A^H y> for both Wigner transforms, A from the oracle."""
+    from paper_2311_14670_amd.synth import flmn_gaussian
+    autograd, binding = ag
+    shp = (2 * N - 1, L, 2 * L - 1)
+    plan = binding.Plan(L, N=N)
+    x = flmn_gaussian(L, N, seed=51)
+    y = map_gaussian(shp, seed=52)
+    lhs = np.vdot(y, oracle.so3_inverse(x, L, N))
+    rhs = np.vdot(plan.so3_inverse_adjoint(torch.from_numpy(y).cuda()).cpu().numpy(), x)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    f = map_gaussian(shp, seed=53)
+    G = flmn_gaussian(L, N, seed=54)
+    lhs = np.vdot(G, oracle.so3_forward(f, L, N))
+    rhs = np.vdot(plan.so3_forward_adjoint(torch.from_numpy(G).cuda()).cpu().numpy(), f)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_so3_autograd_gradients_and_jvp(ag):
+    """Reverse mode: d/dx Re<y, A x> = A^H y for both Wigner transforms (the
+    adjoints are pinned above); forward mode: the tangent is A t (oracle)."""
+    import torch.autograd.forward_ad as fwAD
+    from paper_2311_14670_amd.synth import flmn_gaussian
+    autograd, binding = ag
+    L, N = 20, 3
+    shp = (2 * N - 1, L, 2 * L - 1)
+    plan = binding.Plan(L, N=N)
+    for fn, adj, ref_fn, x0 in [
+            (autograd.so3_inverse, plan.so3_inverse_adjoint, oracle.so3_inverse, flmn_gaussian(L, N, seed=55)),
+            (autograd.so3_forward, plan.so3_forward_adjoint, oracle.so3_forward, map_gaussian(shp, seed=55))]:
+        y = torch.from_numpy(map_gaussian(shp, seed=56)).cuda()
+        x = torch.from_numpy(x0).cuda().requires_grad_(True)
+        loss = torch.real(torch.sum(torch.conj(y) * fn(x, plan)))
+        loss.backward()
+        assert rel_l2(x.grad.cpu().numpy(), adj(y).cpu().numpy()) < 1e-14
+        t = map_gaussian(shp, seed=57)
+        with fwAD.dual_level():
+            dual = fwAD.make_dual(torch.from_numpy(x0).cuda(), torch.from_numpy(t).cuda())
+            tangent = fwAD.unpack_dual(fn(dual, plan)).tangent.cpu().numpy()
+        assert rel_l2(tangent, ref_fn(t, L, N)) < 1e-12

@@ -107,6 +107,11 @@ def test_so3_batched(binding, prec):
     _check("so3 inverse", prec, f[1], oracle.so3_inverse(flmn[1], L, N))
     back = host(plan.so3_forward(dev(f)))
     _check("so3 round trip", prec, back[1], flmn[1])
+    # adjoint of the inverse (gradient path) against the FP64 plan's
+    g = map_gaussian((B, 2 * N - 1, L, 2 * L - 1), seed=25)
+    adj = host(plan.so3_inverse_adjoint(dev(g)))
+    ref = host(binding.Plan(L, N=N, max_batch=B).so3_inverse_adjoint(dev(g)))
+    _check("so3 inverse adjoint", prec, adj[1], ref[1])
 
 
 @pytest.mark.parametrize("prec", PRECS)

@@ -208,6 +208,30 @@ def s2_inverse_adjoint(g, L, spin=0, sampling=MW, nside=0, ms=None):
     return out
 
 
+# ----------------------------------------------------------------- real signals
+def hermitian_complete(flm, L):
+    """Coefficients of a real spin-0 signal from their orders m >= 0: the
+    Hermitian symmetry of Sec. 2.1, flm[l, -m] = (-1)^m conj(flm[l, m]), with
+    order 0 taken real.  The orders m < 0 of the input are not read."""
+    out = np.array(_c128(flm), copy=True)
+    assert out.shape == (L, 2 * L - 1)
+    for m in range(1, L):
+        out[:, L - 1 - m] = (-1.0) ** m * np.conj(out[:, L - 1 + m])
+    out[:, L - 1] = out[:, L - 1].real
+    return out
+
+
+def s2_inverse_real(flm, L, rings=None):
+    """Real MW map of a spin-0 signal given by its orders m >= 0: the inverse
+    SHT of the Hermitian completion (a real map up to rounding), real part."""
+    return s2_inverse(hermitian_complete(flm, L), L, 0, MW, rings=rings).real
+
+
+def s2_forward_real(f, L, ms=None):
+    """Forward SHT of a real MW map (the complex transform of the same samples)."""
+    return s2_forward(np.asarray(f, dtype=np.float64).astype(np.complex128), L, 0, MW, ms=ms)
+
+
 # ----------------------------------------------------------------- SO(3) transforms
 def so3_inverse(flmn, L, N):
     """Inverse Wigner transform (Eq. 13), MW in (beta, alpha), 2N-1 gammas."""

@@ -69,7 +69,8 @@ def load_library():
         lib.s2_plan_destroy.argtypes = [P]
         lib.s2_plan_info.argtypes = [P, ctypes.POINTER(_PlanInfo)]
         for name in ["s2_inverse", "s2_forward", "s2_inverse_adjoint", "s2_forward_adjoint", "so3_inverse",
-                     "so3_forward", "so3_inverse_adjoint", "so3_forward_adjoint"]:
+                     "so3_forward", "so3_inverse_adjoint", "so3_forward_adjoint", "s2_inverse_real",
+                     "s2_forward_real"]:
             getattr(lib, name).argtypes = [P, vp, vp, i, vp, vp]
             getattr(lib, name).restype = i
         lib.s2_debug_wigner_d.argtypes = [P, i, vp, vp]
@@ -148,11 +149,11 @@ class Plan:
             return (self.nsamples,)
         return (self.info["nrings"], 2 * self.L if self.sampling == "mwss" else 2 * self.L - 1)
 
-    def _prep(self, x, tail, what):
+    def _prep(self, x, tail, what, dtype=torch.complex128):
         if not isinstance(x, torch.Tensor):
             raise TypeError(f"{what}: expected a torch.Tensor")
-        if x.dtype != torch.complex128:
-            raise TypeError(f"{what}: expected complex128, got {x.dtype}")
+        if x.dtype != dtype:
+            raise TypeError(f"{what}: expected {dtype}, got {x.dtype}")
         if x.device != self.device:
             raise ValueError(f"{what}: tensor on {x.device}, plan on {self.device}")
         batched = x.dim() == len(tail) + 1
@@ -164,14 +165,15 @@ class Plan:
         """A fresh workspace tensor for calls issued concurrently on another stream."""
         return torch.empty(max(int(self.info["workspace_bytes"]), 256), dtype=torch.uint8, device=self.device)
 
-    def _call(self, fn, x, in_tail, out_tail, what, workspace=None, out=None):
-        x, B, batched = self._prep(x, in_tail, what)
+    def _call(self, fn, x, in_tail, out_tail, what, workspace=None, out=None, in_dtype=torch.complex128,
+              out_dtype=torch.complex128):
+        x, B, batched = self._prep(x, in_tail, what, in_dtype)
         shape = ((B,) if batched else ()) + tuple(out_tail)
         if out is None:
-            out = torch.empty(shape, dtype=torch.complex128, device=self.device)
-        elif (out.dtype != torch.complex128 or out.device != self.device or tuple(out.shape) != shape
+            out = torch.empty(shape, dtype=out_dtype, device=self.device)
+        elif (out.dtype != out_dtype or out.device != self.device or tuple(out.shape) != shape
               or not out.is_contiguous()):
-            raise ValueError(f"{what}: out must be a contiguous complex128 tensor of shape {shape} on {self.device}")
+            raise ValueError(f"{what}: out must be a contiguous {out_dtype} tensor of shape {shape} on {self.device}")
         ws = self.workspace if workspace is None else workspace
         if ws.device != self.device or ws.numel() * ws.element_size() < self.info["workspace_bytes"]:
             raise ValueError(f"{what}: workspace too small or on the wrong device")
@@ -188,6 +190,18 @@ class Plan:
     def forward(self, f, workspace=None, out=None):
         """Forward spin SHT: map -> flm [B?, L, 2L-1]."""
         return self._call(self._lib.s2_forward, f, self.map_shape, self.coeff_shape, "forward", workspace, out)
+
+    def inverse_real(self, flm, workspace=None, out=None):
+        """Inverse SHT of a real signal (MW, spin 0, FP64 plans): flm [B?, L, 2L-1]
+        complex128, of which only the orders m >= 0 are read -> real map float64."""
+        return self._call(self._lib.s2_inverse_real, flm, self.coeff_shape, self.map_shape, "inverse_real", workspace,
+                          out, out_dtype=torch.float64)
+
+    def forward_real(self, f, workspace=None, out=None):
+        """Forward SHT of a real map float64 (MW, spin 0, FP64 plans) -> flm
+        [B?, L, 2L-1] complex128 with flm[l][-m] = (-1)^m conj(flm[l][m])."""
+        return self._call(self._lib.s2_forward_real, f, self.map_shape, self.coeff_shape, "forward_real", workspace,
+                          out, in_dtype=torch.float64)
 
     def inverse_adjoint(self, g, workspace=None, out=None):
         """Hermitian adjoint of the inverse SHT: map-space cotangent -> coefficients."""

@@ -662,7 +662,9 @@ double2 *fft_scratch(const s2_plan_s *P, char *ws)
 }
 
 // inverse d-stage of one (map, all slices): flm slices [S][L][2L-1] -> partials P[slice][blk][ring][m][4]
-int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double *> &wl, char *ws, hipStream_t st)
+// (half: real signal of a spin-0 plan, orders m >= 0 and components 0,1 only)
+int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double *> &wl, char *ws, hipStream_t st,
+                       int half = 0)
 {
     const int L = P->L;
     const size_t slab = (size_t)L * (2 * L - 1);
@@ -678,13 +680,13 @@ int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double
         TIMED(S2_STAGE_PACK);
         HIPCHK(launch_pack_inv(st, L, P->nx, r.n, P->inv_nblk, P->inv_waves * INV_J, P->lslot, fa, fb,
                                r.sliceA >= 0 ? wl[r.sliceA] : nullptr, r.sliceB >= 0 ? wl[r.sliceB] : nullptr, P->kap,
-                               P->gtab, C), "pack");
+                               P->gtab, C, half), "pack");
         }
         TIMED(S2_STAGE_DSTAGE_INV);
         HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nx, P->nreg, r.n, P->cot, P->csc, P->init[ri], C,
                                  P->lchunk, P->mtop,
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
-                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr), "inverse d-stage");
+                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr, half), "inverse d-stage");
     }
     return S2_OK;
 }
@@ -746,7 +748,7 @@ int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *const *slice_
 // forward d-stage of one map from the filtered ring spectra H (slices) -> flm slices
 int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const double2 *hpoleN0, double2 *flm,
                        const std::vector<double *> &wl,
-                       char *ws, hipStream_t st)
+                       char *ws, hipStream_t st, int half = 0)
 {
     const int L = P->L;
     const size_t slab = (size_t)L * (2 * L - 1);
@@ -772,14 +774,15 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const dou
                                  r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
                                  r.sliceB >= 0 ? Q0 + r.sliceB * nQ : nullptr,
                                  (an > 0 && r.sliceA >= 0) ? Qx0 + r.sliceA * nQx : nullptr,
-                                 (an > 0 && r.sliceB >= 0) ? Qx0 + r.sliceB * nQx : nullptr), "forward d-stage");
+                                 (an > 0 && r.sliceB >= 0) ? Qx0 + r.sliceB * nQx : nullptr, half), "forward d-stage");
     }
     for (int k = 0; k < P->nslice; ++k) {
         const int s = P->slice_spin[k];
         TIMED(S2_STAGE_FINISH);
         HIPCHK(launch_finish_fwd(st, L, P->fwd_nblk, s, s, Q0 + k * nQ, Qx0 ? Qx0 + k * nQx : nullptr,
                                  std::max(P->nxp, 1), wl[k], hpole0 ? hpole0 + k * (2 * L - 1) : nullptr,
-                                 hpoleN0 ? hpoleN0 + k * (2 * L - 1) : nullptr, flm + k * slab), "forward finish");
+                                 hpoleN0 ? hpoleN0 + k * (2 * L - 1) : nullptr, flm + k * slab, half),
+               "forward finish");
     }
     return S2_OK;
 }
@@ -819,6 +822,38 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
         }
     }
     return run_forward_dstage(P, F0, mw ? hp0 : nullptr, hpN0, flm, wl, ws, st);
+}
+
+// Real signals (MW, spin-0 S2 plan, Hermitian symmetry of the coefficients):
+// the sweeps carry the orders m >= 0 only and two rings share a phi-DFT.
+int run_inverse_real(s2_plan_t P, const double2 *flm, double *map, char *ws, hipStream_t st)
+{
+    int rc = run_inverse_dstage(P, flm, P->w_sht, ws, st, 1);
+    if (rc) return rc;
+    TIMED(S2_STAGE_PHI_INV);
+    HIPCHK(launch_phi_inv_real(st, P->fft_threads, P->fft_lds, P->nring, P->L, P->nreg, P->inv_nblk,
+                               (const double *)(ws + P->off_P), P->mtop, flm, P->w_sht[0], P->ffts, map,
+                               fft_scratch(P, ws)), "real inverse phi-DFT");
+    return S2_OK;
+}
+
+int run_forward_real(s2_plan_t P, const double *map, double2 *flm, char *ws, hipStream_t st)
+{
+    const int L = P->L;
+    double *F0 = (double *)(ws + P->off_F);
+    double2 *hp0 = (double2 *)(ws + P->off_hpole);
+    {
+    TIMED(S2_STAGE_PHI_FWD);
+    HIPCHK(launch_phi_fwd_real(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L,
+                               2.0 * M_PI / (double)(2 * L - 1), map, P->ffts, F0, fft_scratch(P, ws)),
+           "real forward phi-DFT");
+    }
+    {
+    TIMED(S2_STAGE_MW_THETA);
+    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, 0, P->hstride, 0, P->ffts, P->wq, P->ph, F0, hp0,
+                            nullptr, fft_scratch(P, ws), 1), "MW theta filter");
+    }
+    return run_forward_dstage(P, F0, hp0, nullptr, flm, P->w_sht, ws, st, 1);
 }
 
 // ---------------------------------------------------------------- matrix-core path
@@ -1105,6 +1140,39 @@ int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspa
         if ((rc = run_forward(P, maps.data(), (double2 *)flmn + (size_t)b * S * slab, P->w_so3f, (char *)workspace,
                               st, false))) return rc;
     }
+    return S2_OK;
+}
+
+static int check_real(const char *fn, s2_plan_t P)
+{
+    if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "%s: plan was created for SO(3) (N=%d)", fn, P->N);
+    if (P->sampling != S2_MW || P->spin != 0)
+        return fail(S2_ERR_UNSUPPORTED, "%s: real signals need an MW spin-0 plan", fn);
+    if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "%s: available for FP64 plans", fn);
+    return S2_OK;
+}
+
+int s2_inverse_real(s2_plan_t P, const void *flm, void *f, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_inverse_real", P, flm, f, batch, workspace);
+    if (rc || (rc = check_real("s2_inverse_real", P))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b)
+        if ((rc = run_inverse_real(P, (const double2 *)flm + b * slab, (double *)f + (size_t)b * P->nsamp,
+                                   (char *)workspace, st))) return rc;
+    return S2_OK;
+}
+
+int s2_forward_real(s2_plan_t P, const void *f, void *flm, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_forward_real", P, f, flm, batch, workspace);
+    if (rc || (rc = check_real("s2_forward_real", P))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b)
+        if ((rc = run_forward_real(P, (const double *)f + (size_t)b * P->nsamp, (double2 *)flm + b * slab,
+                                   (char *)workspace, st))) return rc;
     return S2_OK;
 }
 

@@ -28,6 +28,7 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b)   // a * conj(b)
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
 // multiply by sign * i  (sign = -1: -i, +1: +i)
 __device__ __forceinline__ double2 cmuli(double2 a, int sign)

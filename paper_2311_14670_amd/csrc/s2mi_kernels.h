@@ -9,16 +9,16 @@ namespace s2mi {
 
 hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int slots_per_blk, const int *lslot,
                            const double2 *flmA, const double2 *flmB, const double *wA, const double *wB,
-                           const double *kap, const double *gtab, double *C);
+                           const double *kap, const double *gtab, double *C, int half = 0);
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
-                             const int *mtop, double *partA, double *partB);
+                             const int *mtop, double *partA, double *partB, int half = 0);
 hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const double *lsin, const double *lcos,
                              const double *lbin, double2 *init);
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
                              int lstride, int n, const double *lam, const double2 *init, const double *kap,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
-                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB);
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int half = 0);
 hipError_t launch_lambda_table(hipStream_t st, int L, int nx, int nreg, int lstride, int n, const double *cot,
                                const double *csc, double *lam);
 hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk, int spin,
@@ -32,11 +32,17 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
                           double2 *fscr);
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *hpoleN, double2 *fscr);
+                            double2 *hpoleN, double2 *fscr, int half = 0);
 hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *w, double2 *map);
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
                              int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN,
-                             double2 *flm);
+                             double2 *flm, int half = 0);
+// real signals (MW, spin 0): two rings per complex DFT; maps are [nring][2L-1] doubles
+hipError_t launch_phi_inv_real(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk,
+                               const double *part, const int *mtop, const double2 *flm, const double *wl,
+                               const FftArgs *f, double *map, double2 *fscr);
+hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
+                               const double *map, const FftArgs *f, double *F, double2 *fscr);
 hipError_t launch_gamma_dft(hipStream_t st, int N, long long nper, int sign, double q, const double *roots,
                             const double2 *in, double2 *out);
 hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,

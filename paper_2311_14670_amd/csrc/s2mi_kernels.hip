@@ -103,8 +103,9 @@ __global__ void k_init_table(int L, int nreg, int n, const double *__restrict__ 
 // B record is used at m > 0 and, for n != 0, at m <= 0 by the continuation of
 // the run below m = 0 (orders m <= 0 then feed the B slice at -m >= 0 and the
 // A slice at m < 0).  A wave reads the records of one order at fixed offsets
-// from a single base address.
-__global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, const int *__restrict__ lslot,
+// from a single base address.  Real signals (rs = 3): the records stop after the
+// A side, since the B side (order -m) is the conjugate of the A side.
+__global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, int rs, const int *__restrict__ lslot,
                            const double2 *__restrict__ flmA, const double2 *__restrict__ flmB,
                            const double *__restrict__ wA, const double *__restrict__ wB,
                            const double *__restrict__ kap, const double *__restrict__ gtab, double *__restrict__ C)
@@ -135,9 +136,14 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, const int *__
     }
     // slot index i = blk * S + s (S slots per block); record at ((blk * (L + nx) + m + nx) * S + s)
     const int blk = (int)(i / S), s = (int)(i % S);
-    double *o = C + (((size_t)blk * (L + nx) + (m + nx)) * S + s) * 5;
+    double *o = C + (((size_t)blk * (L + nx) + (m + nx)) * S + s) * rs;
+    if (rs == 3) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) o[q] = rec[q];
+        for (int q = 0; q < 3; ++q) o[q] = rec[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[q] = rec[q];
+    }
 }
 
 // ------------------------------------------------------------------ inverse d-stage
@@ -205,16 +211,18 @@ __device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[
 // contribution times the records.  SLOW: the contribution is e 2^E (exact
 // scaling, zero once below the double range) and slot jin may start here
 // (l == m) from its start value; otherwise the chunk is realised (E = 0).
-template <int PAR, bool SLOW>
+// HALF (real signals): records of RS = 3 doubles, A side only.
+template <int PAR, bool SLOW, bool HALF = false>
 __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ rec,
                                           double lam, int jin, double e0, int E0, double &aAr, double &aAi,
                                           double &aBr, double &aBi)
 {
+    constexpr int RS = HALF ? 3 : 5;
 #pragma unroll
     for (int j = 0; j < SG; ++j) {
         double &nw = PAR == 0 ? Y[j] : X[j];              // receives order m
         double &od = PAR == 0 ? X[j] : Y[j];              // holds order m+1
-        const double *c = rec + j * 5;
+        const double *c = rec + j * RS;
         nw = fma(c[0] * lam, od, -nw);
         double t = nw;
         if constexpr (SLOW) {
@@ -227,12 +235,14 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
         }
         aAr = fma(t, c[1], aAr);
         aAi = fma(t, c[2], aAi);
-        aBr = fma(t, c[3], aBr);
-        aBi = fma(t, c[4], aBi);
+        if constexpr (!HALF) {
+            aBr = fma(t, c[3], aBr);
+            aBi = fma(t, c[4], aBi);
+        }
     }
 }
 
-template <int NCH, int PAR>
+template <int NCH, int PAR, bool HALF = false>
 __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ms, int ring0, int nreg,
                                          int lane,
                                          int w, int W,
@@ -241,24 +251,26 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
                                          const double2 *__restrict__ initr, const double *__restrict__ C, double *red,
                                          int blk, double *__restrict__ partA, double *__restrict__ partB)
 {
+    constexpr int RS = HALF ? 3 : 5;
     const double lam = fma(-(double)(m + 1), ct, ncs);   // lambda_{m+1}: produces order m
     double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
-    const double *Cw = C + (((size_t)blk * (L + nx) + (m + nx)) * W + w) * (NCH * SG) * 5;   // records at order m
+    const double *Cw = C + (((size_t)blk * (L + nx) + (m + nx)) * W + w) * (NCH * SG) * RS;   // records at order m
 
 #pragma unroll
     for (int g = 0; g < NCH; ++g) {
         const int base = lb[g];
         if (base < 0 || m > base + SG - 1) continue;     // chunk not started
-        const double *rec = Cw + g * SG * 5;
+        const double *rec = Cw + g * SG * RS;
         if (m >= base) {                                  // ramp: slot jin starts at this order
             const int jin = base + SG - 1 - m;
             const double2 iv = initr[m];                 // d^m_{m,n}(theta_ring), zero if m < |n|
-            inv_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, aAr, aAi, aBr, aBi);
+            inv_chunk<PAR, true, HALF>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, aAr, aAi, aBr,
+                                       aBi);
             fast &= ~(1u << g);
         } else if ((fast >> g) & 1u) {
-            inv_chunk<PAR, false>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
+            inv_chunk<PAR, false, HALF>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
         } else {
-            inv_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
+            inv_chunk<PAR, true, HALF>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
         }
     }
     // renormalisation pass every RN orders over the started chunks not yet realised
@@ -279,12 +291,15 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
     double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr;
     rb[(w * 4 + 1) * 64 + lane] = aAi;
-    rb[(w * 4 + 2) * 64 + lane] = aBr;
-    rb[(w * 4 + 3) * 64 + lane] = aBi;
+    if (!HALF) {
+        rb[(w * 4 + 2) * 64 + lane] = aBr;
+        rb[(w * 4 + 3) * 64 + lane] = aBi;
+    }
     __syncthreads();
     // four waves, rotating with the order, reduce the 4 x 64 outputs over the waves
+    // (only the A side's 2 x 64 for real signals)
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
-    if (tr >= 0 && tr < 256) {
+    if (tr >= 0 && tr < (HALF ? 128 : 256)) {
         const int rl = tr & 63, comp = tr >> 6;         // rl == lane: this thread's ring
         double s = 0.0;                                 // a plain loop: fewer scalar registers than wave_sum
         for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
@@ -307,7 +322,7 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
     }
 }
 
-template <int NCH, int WT>
+template <int NCH, int WT, bool HALF = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     int L, int nx, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
@@ -341,7 +356,9 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
 
     const int mt = ufl(mtop[blk]);
     int pf = 0;
-    constexpr int ROWB = NCH * SG * 5 * 8;               // bytes of one wave's records per order
+    constexpr int RS = HALF ? 3 : 5;                     // doubles per record
+    constexpr int ROWB = NCH * SG * RS * 8;              // bytes of one wave's records per order
+    static_assert(ROWB % 128 == 0, "a wave's record row spans whole cache lines");
     for (int m = mt; m >= mend; m -= 2) {
         // Pull the records of orders m - PFD and m - PFD - 1 toward the caches (one
         // dword per 128-byte line); the result is consumed only at the next pair of
@@ -350,14 +367,14 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
         if (m - PFD - 1 >= -nx && lane < 2 * ROWB / 128) {
             const int row = m - PFD - (lane >= ROWB / 128 ? 1 : 0);
             const int *Cp = reinterpret_cast<const int *>(C + (((size_t)blk * (L + nx) + (row + nx)) * W + w) *
-                                                                  (NCH * SG) * 5);
+                                                                  (NCH * SG) * RS);
             pf = Cp[(lane % (ROWB / 128)) * 32];
         }
-        inv_step<NCH, 0>(m, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr, C, red,
-                         blk, partA, partB);
+        inv_step<NCH, 0, HALF>(m, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr,
+                               C, red, blk, partA, partB);
         if (m - 1 >= mend)
-            inv_step<NCH, 1>(m - 1, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr,
-                             C, red, blk, partA, partB);
+            inv_step<NCH, 1, HALF>(m - 1, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs,
+                                   initr, C, red, blk, partA, partB);
     }
     asm volatile("" ::"v"(pf));
 }
@@ -376,7 +393,7 @@ __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int 
     return init + (size_t)r0 * L + m;
 }
 
-template <int PAR, bool HEAD, bool REAL = false>
+template <int PAR, bool HEAD, bool REAL = false, bool HALF = false>
 __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ Lm,
                                           const double *__restrict__ HA, const double *__restrict__ HB, double kk,
                                           bool init, int nval, const double2 *__restrict__ iv, int istride, double &aAr,
@@ -400,8 +417,10 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
         const double *hb = HB + k * 4;
         aAr = fma(t, ha[0], aAr);
         aAi = fma(t, ha[1], aAi);
-        aBr = fma(t, hb[0], aBr);
-        aBi = fma(t, hb[1], aBi);
+        if constexpr (!HALF) {
+            aBr = fma(t, hb[0], aBr);
+            aBi = fma(t, hb[1], aBi);
+        }
     }
 }
 
@@ -411,7 +430,9 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
 // contiguous record and the wave's row is fetched with wide scalar loads.
 // REAL (with MAIN): every chunk is realised (all E == 0), which stays so in the
 // main loop since no degree starts there: no scaling and no renormalisation.
-template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false, bool REAL = false>
+// HALF (run n = 0 of a real signal): only the A side (order +m) is accumulated,
+// the order -m being its conjugate.
+template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false, bool REAL = false, bool HALF = false>
 __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
                                          int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
                                          double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk, double &gm,
@@ -453,10 +474,11 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
             // started: they stay zero, and their start values lie outside the table
             const int nval = nreg - (rbase + c * SG);
             const bool ok = starts && nval > 0;
-            fwd_chunk<PAR, true>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval, init_tab_ptr(init, r0, m < 0 ? 0 : m, L),
-                                 L, aAr, aAi, aBr, aBi);
+            fwd_chunk<PAR, true, false, HALF>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval,
+                                              init_tab_ptr(init, r0, m < 0 ? 0 : m, L), L, aAr, aAi, aBr, aBi);
         } else {
-            fwd_chunk<PAR, false, REAL>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr, aBi);
+            fwd_chunk<PAR, false, REAL, HALF>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr,
+                                              aBi);
         }
     }
     if (HEAD) real = 0u;                                  // degrees start in this group: not realised
@@ -464,11 +486,13 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     double *rb = red + (size_t)(m & 1) * FWD_MAX_WAVES * 4 * 64;
     rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
     rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
-    rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
-    rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
+    if (!HALF) {
+        rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
+        rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
+    }
     __syncthreads();
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
-    if (tr >= 0 && tr < 256) {
+    if (tr >= 0 && tr < (HALF ? 128 : 256)) {
         const int ll = tr & 63, comp = tr >> 6;
         const int lo = 64 * g + ll;
         const double s = wave_sum<FWD_MAX_WAVES>(rb, comp, ll, W);
@@ -496,7 +520,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
 }
 
-template <int NCH, bool SAME, int WT>
+template <int NCH, bool SAME, int WT, bool HALF = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
@@ -555,42 +579,46 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         };
         for (; m >= hend && m >= mend; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
-                                   real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_step<NCH, 0, true, false, false, false, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+                                                              lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
+                                                              kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
-                fwd_step<NCH, 1, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
-                                       Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
-                                       QxA, QxB);
+                fwd_step<NCH, 1, true, false, false, false, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
+                                                                  hstride, lstride, nreg, rbase, X, Y, E, real, kk, gm,
+                                                                  lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA,
+                                                                  QB, QxA, QxB);
         }
         // both orders of the pair >= |n| (and > 0 when the sides share one array)
         constexpr uint32_t ALL = (1u << NCH) - 1u;
         const int mlo = SAME ? max(an, 1) : an;
         for (; m - 1 >= mlo && real != ALL; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, false, true, SAME>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase,
-                                                X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk,
-                                                QA, QB, QxA, QxB);
-            fwd_step<NCH, 1, false, true, SAME>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg,
-                                                rbase, X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
-                                                blk, QA, QB, QxA, QxB);
+            fwd_step<NCH, 0, false, true, SAME, false, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+                                                             lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
+                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_step<NCH, 1, false, true, SAME, false, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+                                                             lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
+                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
         }
         for (; m - 1 >= mlo; m -= 2) {                   // realised: plain contributions
             prefetch(m);
-            fwd_step<NCH, 0, false, true, SAME, true>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg,
-                                                      rbase, X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA,
-                                                      HxB, red, blk, QA, QB, QxA, QxB);
-            fwd_step<NCH, 1, false, true, SAME, true>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride,
-                                                      nreg, rbase, X, Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB,
-                                                      HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_step<NCH, 0, false, true, SAME, true, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+                                                            lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
+                                                            kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_step<NCH, 1, false, true, SAME, true, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+                                                            lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
+                                                            kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, false>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X, Y, E,
-                                    real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_step<NCH, 0, false, false, false, false, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+                                                               lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
+                                                               kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
-                fwd_step<NCH, 1, false>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride, lstride, nreg, rbase, X,
-                                        Y, E, real, kk, gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB,
-                                        QxA, QxB);
+                fwd_step<NCH, 1, false, false, false, false, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
+                                                                   hstride, lstride, nreg, rbase, X, Y, E, real, kk,
+                                                                   gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
+                                                                   blk, QA, QB, QxA, QxB);
         }
         asm volatile("" ::"v"(pf));
         __syncthreads();   // the LDS buffers are reused by the next pass
@@ -784,6 +812,115 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
     }
 }
 
+// ------------------------------------------------------------------ phi-DFTs of real signals
+// MW rings, spin 0.  The spectrum of a real ring is Hermitian (X[-m] = conj
+// X[m], X[0] real), so two rings share one complex DFT: ring 2p in the real
+// and ring 2p+1 in the imaginary part of z = x1 + i x2, with Z = X1 + i X2.
+// One workgroup per pair of rings.
+//
+// Inverse: X[m] for m >= 0 is the sweep's side A (summed over its blocks); the
+// south pole (ring nreg) holds only order 0, sum_l (-1)^l w_l Re flm[l][0]
+// (Eq. 29).  Order 0 enters with its real part: the result is the real part of
+// the complex transform of the Hermitian completion of the orders m >= 0.
+__global__ __launch_bounds__(1024) void k_phi_inv_real(int L, int nreg, int nring, int nblk,
+                                                       const double *__restrict__ part, const int *__restrict__ mtop,
+                                                       const double2 *__restrict__ flm, const double *__restrict__ wl,
+                                                       const FftArgs *__restrict__ f, double *__restrict__ map,
+                                                       double2 *__restrict__ fscr)
+{
+    extern __shared__ double2 buf[];
+    __shared__ double red[1024];
+    const int r1 = 2 * (int)blockIdx.x, r2 = r1 + 1;
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int M = 2 * L - 1;
+    double pole = 0.0;
+    if (r1 == nreg || r2 == nreg) {                      // uniform over the workgroup
+        double acc = 0.0;
+        for (int l = tid; l < L; l += T) acc = fma((l & 1) ? -wl[l] : wl[l], flm[(size_t)l * M + (L - 1)].x, acc);
+        red[tid] = acc;
+        __syncthreads();
+        int p2 = 1;
+        while (p2 < T) p2 <<= 1;
+        for (int h = p2 / 2; h > 0; h >>= 1) {           // T need not be a power of two
+            if (tid < h && tid + h < T) red[tid] += red[tid + h];
+            __syncthreads();
+        }
+        pole = red[0];
+    }
+    const size_t bstride = (size_t)nreg * L * 4;
+    for (int am = tid; am < L; am += T) {
+        double2 x[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = r1 + h;
+            double2 v = make_double2(0.0, 0.0);
+            if (r < nreg) {
+                const double *pr = part + ((size_t)r * L + am) * 4;
+                for (int b = 0; b < nblk; ++b) {
+                    if (am > mtop[b]) continue;              // that block's sweep never reached order am
+                    v = cadd(v, *reinterpret_cast<const double2 *>(pr + b * bstride));
+                }
+            } else if (r == nreg && am == 0) {
+                v.x = pole;
+            }
+            if (am == 0) v.y = 0.0;
+            x[h] = v;
+        }
+        buf[am] = make_double2(x[0].x - x[1].y, x[0].y + x[1].x);                      // X1 + i X2
+        if (am > 0) buf[M - am] = make_double2(x[0].x + x[1].y, x[1].x - x[0].y);     // conj X1 + i conj X2
+    }
+    __syncthreads();
+    dft_lds(buf, f, +1, fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr);
+    double *o1 = map + (size_t)r1 * M;
+    double *o2 = map + (size_t)r2 * M;
+    for (int k = tid; k < M; k += T) {
+        o1[k] = buf[k].x;
+        if (r2 < nring) o2[k] = buf[k].y;
+    }
+}
+
+// Forward: Z = DFT(x1 + i x2), X1[m] = (Z[m] + conj Z[-m]) / 2, X2[m] = (Z[m] -
+// conj Z[-m]) / 2i, written as F[m][ring] = q {X[m], conj X[m]} (the layout of
+// the complex phi-DFT); rings nring .. hstride-1 are the sweep's zero padding.
+__global__ __launch_bounds__(1024) void k_phi_fwd_real(int L, int nring, int hstride, double q,
+                                                       const double *__restrict__ map, const FftArgs *__restrict__ f,
+                                                       double *__restrict__ F, double2 *__restrict__ fscr)
+{
+    extern __shared__ double2 buf[];
+    const int r1 = 2 * (int)blockIdx.x, r2 = r1 + 1;
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int M = 2 * L - 1;
+    if (r1 >= nring) {
+        for (int m = tid; m < L; m += T)
+            for (int r = r1; r <= r2 && r < hstride; ++r) {
+                double2 *o = reinterpret_cast<double2 *>(F + ((size_t)m * hstride + r) * 4);
+                o[0] = make_double2(0.0, 0.0);
+                o[1] = make_double2(0.0, 0.0);
+            }
+        return;
+    }
+    const double *x1 = map + (size_t)r1 * M;
+    const double *x2 = map + (size_t)r2 * M;
+    for (int k = tid; k < M; k += T) buf[k] = make_double2(x1[k], r2 < nring ? x2[k] : 0.0);
+    __syncthreads();
+    dft_lds(buf, f, -1, fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr);
+    const double hq = 0.5 * q;
+    for (int m = tid; m < L; m += T) {
+        const double2 z = buf[m];
+        const double2 zc = cconj(buf[m == 0 ? 0 : M - m]);
+        const double2 a = make_double2(hq * (z.x + zc.x), hq * (z.y + zc.y));     // q X1[m]
+        const double2 b = make_double2(hq * (z.y - zc.y), -hq * (z.x - zc.x));    // q X2[m]
+        double2 *o1 = reinterpret_cast<double2 *>(F + ((size_t)m * hstride + r1) * 4);
+        o1[0] = a;
+        o1[1] = cconj(a);
+        if (r2 < hstride) {
+            double2 *o2 = reinterpret_cast<double2 *>(F + ((size_t)m * hstride + r2) * 4);
+            o2[0] = b;
+            o2[1] = cconj(b);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ MW / MWSS theta filter
 // One workgroup per order m >= 0, both signs.  For g = the torus extension of
 // ftilde_{+-m} (g(2pi - th) = (-1)^{m+s} g(th)), on the N torus points
@@ -800,7 +937,9 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
 // Torus point t <-> ring: MW t < L: ring t (t = L-1: south pole), MWSS t = 0:
 // north pole (ring L), 0 < t < L: ring t-1, t = L: south pole (ring L-1).  In
 // place: F[m][ring] -> H[m][ring] for the swept rings; the pole values go to
-// hpole[(L-1) +- m] (south) and hpoleN (north, MWSS).
+// hpole[(L-1) +- m] (south) and hpoleN (north, MWSS).  half (real signals):
+// only the side of order +m is filtered, the filter being real and the side
+// of order -m the conjugate.
 __device__ __forceinline__ int torus_ring(int t, int L, int N, int ss, bool *mirrored)
 {
     *mirrored = ss ? t > L : t >= L;
@@ -812,7 +951,8 @@ __device__ __forceinline__ int torus_ring(int t, int L, int N, int ss, bool *mir
 __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, int spin, const FftArgs *__restrict__ fN,
                                                     const double *__restrict__ wq, const double *__restrict__ ph,
                                                     double *__restrict__ F, double2 *__restrict__ hpole,
-                                                    double2 *__restrict__ hpoleN, double2 *__restrict__ fscr)
+                                                    double2 *__restrict__ hpoleN, double2 *__restrict__ fscr,
+                                                    int half)
 {
     extern __shared__ double2 buf[];
     __shared__ double2 nyq;
@@ -823,7 +963,7 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
     const double2 *phc = reinterpret_cast<const double2 *>(ph);
     double2 *scr = fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr;
     for (int side = 0; side < 2; ++side) {
-        if (side == 1 && m == 0) break;
+        if (side == 1 && (m == 0 || half)) break;
         // torus samples
         for (int t = tid; t < N; t += T) {
             bool mir;
@@ -962,11 +1102,12 @@ __global__ void k_fadj_scatter(int L, int hstride, double q, const double *__res
 //           + north pole (MWSS): w_l h~_{-s}(0) at m = -s.
 // Zero where l < max(|m|, |spin|).  One thread per (l, |m|) reads whole 32-byte
 // records (side A = order +|m| in components 0,1, side B = order -|m| in 2,3) and
-// writes both orders.
+// writes both orders.  half (real signals, spin 0): only side A is read, and
+// flm[l][-m] = (-1)^m conj(flm[l][m]) (Hermitian symmetry).
 __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__restrict__ Q,
                              const double *__restrict__ Qx, int nxp, const double *__restrict__ wl,
                              const double2 *__restrict__ hpole, const double2 *__restrict__ hpoleN,
-                             double2 *__restrict__ flm)
+                             double2 *__restrict__ flm, int half)
 {
     const int M = 2 * L - 1;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -977,9 +1118,8 @@ __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__
     if (l >= am && l >= as) {
         for (int bb = 0; bb < nblk; ++bb) {
             const double2 *q = reinterpret_cast<const double2 *>(Q + (((size_t)bb * L + l) * L + am) * 4);
-            const double2 qa = q[0], qb = q[1];
-            a = cadd(a, qa);
-            b = cadd(b, qb);
+            a = cadd(a, q[0]);
+            if (!half) b = cadd(b, q[1]);
             if (Qx && am < nxp) {                      // orders below |n| from the other run's continuation
                 const double2 *qx = reinterpret_cast<const double2 *>(Qx + (((size_t)bb * L + l) * nxp + am) * 4);
                 a = cadd(a, qx[0]);
@@ -1012,6 +1152,7 @@ __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__
             }
         }
     }
+    if (half) b = (am & 1) ? make_double2(-a.x, a.y) : make_double2(a.x, -a.y);
     double2 *row = flm + (size_t)l * M + (L - 1);
     row[am] = a;
     if (am > 0) row[-am] = b;
@@ -1161,28 +1302,30 @@ __global__ void k_pole_from_F(int L, int hstride, int ring, const double *__rest
 
 hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int slots_per_blk, const int *lslot,
                            const double2 *flmA, const double2 *flmB, const double *wA, const double *wB,
-                           const double *kap, const double *gtab, double *C)
+                           const double *kap, const double *gtab, double *C, int half)
 {
     const int nslot = nblk * slots_per_blk;
     dim3 grid((nslot + 255) / 256, L + nx);
-    hipLaunchKernelGGL(k_pack_inv, grid, dim3(256), 0, st, L, nx, n, nslot, slots_per_blk, lslot, flmA, flmB, wA, wB,
-                       kap, gtab, C);
+    hipLaunchKernelGGL(k_pack_inv, grid, dim3(256), 0, st, L, nx, n, nslot, slots_per_blk, half ? 3 : 5, lslot, flmA,
+                       half ? nullptr : flmB, wA, wB, kap, gtab, C);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
-                             const int *mtop, double *partA, double *partB)
+                             const int *mtop, double *partA, double *partB, int half)
 {
     if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
+    if (half && n != 0) return hipErrorInvalidValue;                // real signals: spin 0 only
     dim3 grid((nreg + 63) / 64, nblk);
-    if (nwaves == 8)                                                // wave count as a template argument
-        hipLaunchKernelGGL((k_dstage_inv<INV_NCH, 8>), grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init,
-                           C, lchunk, mtop, partA, partB);
-    else
-        hipLaunchKernelGGL((k_dstage_inv<INV_NCH, 4>), grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init,
-                           C, lchunk, mtop, partA, partB);
+    // wave count and the real-signal half as template arguments
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init, C, lchunk, mtop,
+                           partA, partB);
+    };
+    if (nwaves == 8) half ? go(k_dstage_inv<INV_NCH, 8, true>) : go(k_dstage_inv<INV_NCH, 8, false>);
+    else half ? go(k_dstage_inv<INV_NCH, 4, true>) : go(k_dstage_inv<INV_NCH, 4, false>);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1190,10 +1333,11 @@ hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
                              int lstride, int n, const double *lam, const double2 *init, const double *kap,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
-                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB)
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int half)
 {
     if ((nwaves != 4 && nwaves != 8 && nwaves != 16) || nwaves > FWD_MAX_WAVES)
         return hipErrorInvalidValue;                                // reducer rotation: 1, 2 or 4 groups of 4
+    if (half && (n != 0 || HA != HB)) return hipErrorInvalidValue;  // real signals: the one-array run n = 0
     dim3 grid((G + 1) / 2, nblk);
     // the wave count is a template argument: the reducer rotation and the wave sum
     // then compile to fixed code; HA == HB (run n = 0) selects the one-array path
@@ -1202,7 +1346,11 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
                            gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
     };
     const bool same = HA == HB;
-    if (nwaves == 16) same ? go(k_dstage_fwd<FWD_NCH, true, 16>) : go(k_dstage_fwd<FWD_NCH, false, 16>);
+    if (half) {
+        if (nwaves == 16) go(k_dstage_fwd<FWD_NCH, true, 16, true>);
+        else if (nwaves == 8) go(k_dstage_fwd<FWD_NCH, true, 8, true>);
+        else go(k_dstage_fwd<FWD_NCH, true, 4, true>);
+    } else if (nwaves == 16) same ? go(k_dstage_fwd<FWD_NCH, true, 16>) : go(k_dstage_fwd<FWD_NCH, false, 16>);
     else if (nwaves == 8) same ? go(k_dstage_fwd<FWD_NCH, true, 8>) : go(k_dstage_fwd<FWD_NCH, false, 8>);
     else same ? go(k_dstage_fwd<FWD_NCH, true, 4>) : go(k_dstage_fwd<FWD_NCH, false, 4>);
     S2_LAUNCH_CHECK();
@@ -1251,13 +1399,34 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
     return hipSuccess;
 }
 
+hipError_t launch_phi_inv_real(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk,
+                               const double *part, const int *mtop, const double2 *flm, const double *wl,
+                               const FftArgs *f, double *map, double2 *fscr)
+{
+    if (nthreads > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_phi_inv_real, dim3((nring + 1) / 2), dim3(nthreads), lds, st, L, nreg, nring, nblk, part, mtop,
+                       flm, wl, f, map, fscr);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
+                               const double *map, const FftArgs *f, double *F, double2 *fscr)
+{
+    if (nthreads > 1024 || hstride < nring) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_phi_fwd_real, dim3((hstride + 1) / 2), dim3(nthreads), lds, st, L, nring, hstride, q, map, f,
+                       F, fscr);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *hpoleN, double2 *fscr)
+                            double2 *hpoleN, double2 *fscr, int half)
 {
     if (ss && !hpoleN) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, ss, hstride, spin, fN, wq, ph, F, hpole,
-                       hpoleN, fscr);
+                       hpoleN, fscr, half);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1272,11 +1441,13 @@ hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *
 }
 
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
-                             int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN, double2 *flm)
+                             int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN, double2 *flm,
+                             int half)
 {
+    if (half && (spin != 0 || Qx || hpoleN)) return hipErrorInvalidValue;   // real signals: MW spin 0
     const size_t tot = (size_t)L * L;
     hipLaunchKernelGGL(k_finish_fwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, nB, Q, Qx,
-                       nxp, wl, hpole, hpoleN, flm);
+                       nxp, wl, hpole, hpoleN, flm, half);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1353,6 +1524,8 @@ hipError_t set_kernel_lds_limits(size_t max_dyn)
     if ((e = hipFuncSetAttribute((const void *)k_phi_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void *)k_mw_filter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute((const void *)k_bluestein_prep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_phi_inv_real, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_phi_fwd_real, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dyn)) != hipSuccess) return e;
     return hipSuccess;
 }
 

@@ -1,0 +1,109 @@
+"""Real-signal fast path (MW, spin 0): the sweeps carry the orders m >= 0 only
+and two rings share one complex phi-DFT.  Checked against the oracle's
+real-signal transforms (the complex ones on the Hermitian completion, whose
+symmetry is pinned on the CPU), on seeded inputs that fill the orders m < 0
+with values the path must ignore."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_14670_amd.synth import flm_gaussian, map_gaussian, coeff_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a); b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(x):
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_2311_14670_amd import binding as b
+    b.load_library()
+    return b
+
+
+def _with_junk(flm, L, seed):
+    """flm with its orders m < 0 overwritten by unrelated values."""
+    out = flm.copy()
+    out[:, :L - 1] = map_gaussian((L, L - 1), seed=seed) * coeff_mask(L, 0)[:, :L - 1]
+    return out
+
+
+# L even and odd: the south pole is the second or the first ring of the last pair;
+# L = 130, 200: several sweep tiles and blocks with ragged tails
+@pytest.mark.parametrize("L", [2, 3, 16, 33, 64, 130, 200])
+def test_real_inverse_and_forward(binding, L):
+    plan = binding.Plan(L)
+    flm = _with_junk(flm_gaussian(L, 0, seed=70), L, seed=71)
+    f = host(plan.inverse_real(dev(flm)))
+    assert f.dtype == np.float64 and f.shape == (L, 2 * L - 1)
+    assert rel_l2(f, oracle.s2_inverse_real(flm, L)) < 1e-12
+    g = np.random.default_rng(72).standard_normal((L, 2 * L - 1))     # not band-limited
+    a = host(plan.forward_real(dev(g)))
+    assert rel_l2(a, oracle.s2_forward_real(g, L)) < 1e-12
+    assert np.all(a[~coeff_mask(L, 0)] == 0)
+    # exact round trip of a band-limited real signal
+    back = host(plan.forward_real(dev(f)))
+    assert rel_l2(back, oracle.hermitian_complete(flm, L)) < 1e-12
+
+
+def test_real_matches_complex_path_and_batches(binding):
+    L, B = 96, 3
+    plan = binding.Plan(L, max_batch=B)
+    flm = np.stack([_with_junk(flm_gaussian(L, 0, seed=73 + b), L, seed=80 + b) for b in range(B)])
+    f = host(plan.inverse_real(dev(flm)))
+    for b in range(B):
+        full = oracle.hermitian_complete(flm[b], L)
+        fc = host(plan.inverse(dev(full)))
+        assert rel_l2(f[b], fc.real) < 1e-13
+        assert np.abs(fc.imag).max() < 1e-12 * np.abs(fc.real).max()
+        assert rel_l2(f[b], host(plan.inverse_real(dev(flm[b])))) == 0.0
+    a = host(plan.forward_real(dev(f)))
+    for b in range(B):
+        assert rel_l2(a[b], host(plan.forward(dev(f[b].astype(np.complex128))))) < 1e-13
+
+
+# full sizes: L = 2049 and 4096 run their ring DFTs (4097 and 8191 points) as
+# split Bluestein convolutions
+@pytest.mark.parametrize("L", [2048, 2049, 4096])
+def test_real_full_size_sampled(binding, L):
+    plan = binding.Plan(L)
+    flm = flm_gaussian(L, 0, seed=74, scale="inv1pl")
+    x = dev(flm)
+    f = plan.inverse_real(x)
+    rings = np.array(sorted({0, 1, L // 3, L // 2, L - 3, L - 2, L - 1}))
+    fr = host(f)[rings].ravel()
+    assert rel_l2(fr, oracle.s2_inverse_real(flm, L, rings=rings)) < 1e-11
+    back = host(plan.forward_real(f))
+    assert rel_l2(back, oracle.hermitian_complete(flm, L)) < 1e-11
+    g = np.random.default_rng(75).standard_normal((L, 2 * L - 1))
+    a = host(plan.forward_real(dev(g)))
+    ms = np.array(sorted({0, 1, 2, L // 3, L // 2, L - 2, L - 1}))
+    ms = np.concatenate([ms, -ms[ms > 0]])             # the orders m < 0 come from the symmetry
+    ref = oracle.s2_forward_real(g, L, ms=ms)
+    cols = ms + L - 1
+    assert rel_l2(a[:, cols], ref[:, cols]) < 1e-11
+
+
+def test_real_path_rejects_other_plans(binding):
+    flm = torch.zeros((16, 31), dtype=torch.complex128, device="cuda")
+    for kw in [dict(spin=2), dict(sampling="healpix", nside=8), dict(sampling="dh"), dict(precision="fp32"),
+               dict(N=3)]:
+        plan = binding.Plan(16, **kw)
+        with pytest.raises(binding.S2Error):
+            plan.inverse_real(flm)
+    plan = binding.Plan(16)
+    with pytest.raises(TypeError):
+        plan.forward_real(torch.zeros((16, 31), dtype=torch.complex128, device="cuda"))

@@ -334,3 +334,39 @@ def test_mwss_adjoint_dot_product(oracle, spin):
     lhs = np.vdot(oracle.s2_inverse(a, L, spin, oracle.MWSS).reshape(-1), b)
     rhs = np.vdot(a, oracle.s2_inverse_adjoint(b, L, spin, oracle.MWSS))
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# ----------------------------------------------------------------- real signals (Sec. 2.1)
+@pytest.mark.parametrize("L", [2, 7, 16])
+def test_real_map_has_hermitian_coefficients(oracle, L):
+    """The complex forward transform of a real map (not band-limited) obeys
+    flm[l, -m] = (-1)^m conj(flm[l, m]) -- the symmetry the real-signal path
+    relies on, including its sign, in the oracle's phase convention."""
+    f = np.random.default_rng(60).standard_normal((L, 2 * L - 1))
+    flm = oracle.s2_forward(f.astype(np.complex128), L, 0)
+    assert np.allclose(flm, oracle.hermitian_complete(flm, L), rtol=0, atol=1e-13 * np.abs(flm).max())
+
+
+@pytest.mark.parametrize("L", [2, 7, 16])
+def test_hermitian_coefficients_give_a_real_map(oracle, L):
+    """The inverse of a Hermitian completion is real, and the real-signal
+    inverse reads only the orders m >= 0 (garbage below is ignored)."""
+    flm = flm_gaussian(L, 0, seed=61)
+    full = oracle.hermitian_complete(flm, L)
+    f = oracle.s2_inverse(full, L, 0)
+    assert np.abs(f.imag).max() < 1e-13 * np.abs(f.real).max()
+    junk = flm.copy()
+    junk[:, :L - 1] = map_gaussian((L, L - 1), seed=62) * coeff_mask(L, 0)[:, :L - 1]
+    assert np.array_equal(oracle.s2_inverse_real(junk, L), oracle.s2_inverse_real(flm, L))
+    # a completion without the (-1)^m factor is not real
+    bad = full.copy()
+    for m in range(1, L, 2):
+        bad[:, L - 1 - m] *= -1.0
+    assert np.abs(oracle.s2_inverse(bad, L, 0).imag).max() > 1e-3
+
+
+def test_real_round_trip_exact(oracle):
+    L = 12
+    flm = oracle.hermitian_complete(flm_gaussian(L, 0, seed=63), L)
+    f = oracle.s2_inverse_real(flm, L)
+    assert np.abs(oracle.s2_forward_real(f, L) - flm).max() < 1e-12 * np.abs(flm).max()

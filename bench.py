@@ -126,6 +126,39 @@ def largest_size(L, steps, dev):
             "roundtrip_rel_l2": err}
 
 
+def real_signal(L, steps, dev):
+    """The real-signal path (s2_inverse_real / s2_forward_real, MW spin 0) at the
+    headline size: ms per pair, round-trip error, and the inverse on sampled rings
+    against the oracle's real-signal inverse."""
+    import torch
+    import oracle
+    from paper_2311_14670_amd import binding
+    from paper_2311_14670_amd.synth import flm_gaussian
+    flm = flm_gaussian(L, 0, seed=1, scale="inv1pl")
+    x = torch.from_numpy(flm).to(dev)
+    plan = binding.Plan(L, device=dev)
+    y = plan.forward_real(plan.inverse_real(x))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        y = plan.forward_real(plan.inverse_real(x))
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    full = oracle.hermitian_complete(flm, L)
+    err = float(np.linalg.norm(y.cpu().numpy() - full) / np.linalg.norm(full))
+    rings = np.array(sorted({0, 1, L // 3, L // 2, L - 2, L - 1}))
+    f = plan.inverse_real(x).cpu().numpy()[rings]
+    ref = oracle.s2_inverse_real(flm, L, rings=rings).reshape(rings.size, -1)
+    ring_err = float(np.linalg.norm(f - ref) / np.linalg.norm(ref))
+    del plan, x, y
+    torch.cuda.empty_cache()
+    return {"workload": f"MW L={L} spin-0 real-signal inverse+forward pair, one map (orders m >= 0 of the "
+                        "headline coefficients)", "L": L, "steps": steps, "ms_per_pair": ms,
+            "pairs_per_s": 1e3 / ms, "roundtrip_rel_l2": err, "inverse_vs_oracle_rings": ring_err}
+
+
 def cpu_baseline(L, spin, flm, nring_sample, norder_sample):
     import oracle
     oracle._load()
@@ -162,6 +195,8 @@ def main():
                     help="also serve a seeded mixed request stream (L in [64, --serving-lmax]); 0: skip")
     ap.add_argument("--serving-lmax", type=int, default=1024)
     ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--real-steps", type=int, default=10,
+                    help="also time the real-signal path at the headline L (spin 0); 0: skip")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run plain device copies of MIB MiB (a reference for "
                          "hardware byte counters)")
@@ -254,6 +289,8 @@ def main():
         out["copy_calibration_bytes"] = n * 8
     if args.mixed_batch > 0 and spin == 0:
         out["mixed_precision"] = mixed_precision(L, args.mixed_batch, args.mixed_steps, dev, plan)
+    if args.real_steps > 0 and spin == 0:
+        out["real_signal"] = real_signal(L, args.real_steps, dev)
     if args.large_L > 0 and args.large_steps > 0:
         out["large_L"] = largest_size(args.large_L, args.large_steps, dev)
     if args.serving_requests > 0:

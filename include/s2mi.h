@@ -197,9 +197,13 @@ int s2_inverse_adjoint(s2_plan_t plan, const void *g, void *g_flm, int batch, vo
  *       quadrature of Eq. 19).
  *   DH, GL: the inverse SHT with the forward's weights, then each ring
  *       scaled by its quadrature weight.
+ *   MWSS: as MW with both poles, phi weight 2 pi/(2L), and the adjoint of
+ *       its theta filter (dropping the Nyquist frequency makes that filter
+ *       non-Hermitian: the adjoint removes the Nyquist component after the
+ *       sin(theta) weighting instead of before it).
  *   g_flm  [batch][L][2L-1] complex128 (device, read)
  *   g      [batch][nsamples] complex128 (device, written)
- * FP64 plans only; not available for MWSS sampling (S2_ERR_UNSUPPORTED).
+ * FP64 plans only (S2_ERR_UNSUPPORTED otherwise).
  */
 int s2_forward_adjoint(s2_plan_t plan, const void *g_flm, void *g, int batch, void *workspace,
                        void *hip_stream);

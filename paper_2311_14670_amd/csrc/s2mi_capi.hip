@@ -514,7 +514,10 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->szC = (size_t)P->inv_nblk * P->inv_waves * INV_J * (L + P->nx) * 5 * sizeof(double);
         P->szP = (size_t)P->inv_nblk * P->nreg * L * 4 * sizeof(double);
         P->szF = (size_t)L * P->hstride * 4 * sizeof(double);
-        P->szQ = (size_t)P->fwd_nblk * L * L * 4 * sizeof(double);
+        // forward partials [blk][l][m][4]; the adjoint of the MW / MWSS forward reuses the
+        // buffer for ring partials [nring][m][4] (nring = L + 1 for MWSS)
+        const int adj_rows = (sampling == S2_MW || sampling == S2_MWSS) ? P->nring : 0;
+        P->szQ = (size_t)std::max(P->fwd_nblk * L, adj_rows) * L * 4 * sizeof(double);
         size_t o = 0;
         P->off_C = o; o += align256(P->szC * P->runs.size());
         P->off_P = o; o += align256(P->szP * S);
@@ -710,13 +713,15 @@ int run_inverse(s2_plan_t P, const double2 *flm, double2 *const *slice_maps, con
     return S2_OK;
 }
 
-// adjoint of the MW forward of one map, all slices (finish weights wl[k], spin
-// slice_spin[k]): coefficient cotangent slices -> slice maps.  The slices share
-// one gather / filter / scatter buffer in turn.
+// adjoint of the MW / MWSS forward of one map, all slices (finish weights wl[k],
+// spin slice_spin[k]): coefficient cotangent slices -> slice maps.  The slices
+// share one gather / filter / scatter buffer in turn.  MWSS adds the north-pole
+// row and runs the adjoint form of its theta filter.
 int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *const *slice_maps,
                            const std::vector<double *> &wl, char *ws, hipStream_t st)
 {
     const int L = P->L;
+    const int ss = P->sampling == S2_MWSS;
     const size_t slab = (size_t)L * (2 * L - 1);
     int rc = run_inverse_dstage(P, G, wl, ws, st);
     if (rc) return rc;
@@ -724,21 +729,22 @@ int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *const *slice_
     const size_t nP = P->szP / sizeof(double);
     double *F0 = (double *)(ws + P->off_F);
     double2 *hp0 = (double2 *)(ws + P->off_hpole);
+    double2 *hpN0 = ss ? hp0 + (size_t)P->nslice * (2 * L - 1) : nullptr;
     double *Q0 = (double *)(ws + P->off_Q);
-    const double q = 2.0 * M_PI / (double)(2 * L - 1);
+    const double q = 2.0 * M_PI / (double)(ss ? 2 * L : 2 * L - 1);
     for (int k = 0; k < P->nslice; ++k) {
         const int s = P->slice_spin[k];
         const double2 *Gk = G + k * slab;
         {
         TIMED(S2_STAGE_MW_THETA);
-        HIPCHK(launch_fadj_gather(st, L, P->inv_nblk, s, P0 + k * nP, P->mtop, Gk, wl[k], P->hstride, F0),
+        HIPCHK(launch_fadj_gather(st, L, ss, P->inv_nblk, s, P0 + k * nP, P->mtop, Gk, wl[k], P->hstride, F0),
                "adjoint gather");
-        HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, 0, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
-                                nullptr, fft_scratch(P, ws)), "MW theta filter");
-        HIPCHK(launch_fadj_scatter(st, L, P->hstride, q, F0, hp0, Q0), "adjoint scatter");
+        HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
+                                hpN0, fft_scratch(P, ws), 0, 1), "adjoint theta filter");
+        HIPCHK(launch_fadj_scatter(st, L, ss, P->hstride, q, F0, hp0, hpN0, Q0), "adjoint scatter");
         }
         TIMED(S2_STAGE_PHI_INV);
-        HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, L, 1, s, Q0, P->mtop1, Gk, wl[k],
+        HIPCHK(launch_phi_inv(st, P->fft_threads, P->fft_lds, P->nring, L, P->nring, 1, s, Q0, P->mtop1, Gk, wl[k],
                               P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, slice_maps[k],
                               fft_scratch(P, ws)), "adjoint phi-DFT");
     }
@@ -1056,13 +1062,13 @@ int s2_forward_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, void 
     if (rc) return rc;
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_forward_adjoint: plan was created for SO(3) (N=%d)", P->N);
     if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "s2_forward_adjoint: available for FP64 plans");
-    if (P->sampling == S2_MWSS) return fail(S2_ERR_UNSUPPORTED, "s2_forward_adjoint: not built for MWSS sampling");
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     for (int b = 0; b < batch; ++b) {
         const double2 *G = (const double2 *)g_flm + b * slab;
         double2 *out = (double2 *)g + (size_t)b * P->nsamp;
-        if (P->sampling == S2_MW) rc = run_forward_adjoint_mw(P, G, &out, P->w_sht, (char *)workspace, st);
+        if (P->sampling == S2_MW || P->sampling == S2_MWSS)
+            rc = run_forward_adjoint_mw(P, G, &out, P->w_sht, (char *)workspace, st);
         else rc = run_inverse(P, G, &out, P->w_fadj, (char *)workspace, st);
         if (rc) return rc;
         if (P->ringq)

@@ -32,7 +32,7 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
                           double2 *fscr);
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *hpoleN, double2 *fscr, int half = 0);
+                            double2 *hpoleN, double2 *fscr, int half = 0, int adj = 0);
 hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *w, double2 *map);
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
                              int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN,
@@ -49,10 +49,10 @@ hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *
                           const double *lsin, const double *lcos, const double *lbin, const double *kap,
                           const double *gtab, double *out);
 hipError_t launch_bluestein_filter(hipStream_t st, int nfft, const FftArgs *ffts, int nthreads, size_t lds);
-hipError_t launch_fadj_gather(hipStream_t st, int L, int nblk, int spin, const double *part, const int *mtop,
+hipError_t launch_fadj_gather(hipStream_t st, int L, int ss, int nblk, int spin, const double *part, const int *mtop,
                               const double2 *flm, const double *wl, int hstride, double *F);
-hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, const double *F, const double2 *hpole,
-                               double *out);
+hipError_t launch_fadj_scatter(hipStream_t st, int L, int ss, int hstride, double q, const double *F,
+                               const double2 *hpole, const double2 *hpoleN, double *out);
 hipError_t launch_mask_low(hipStream_t st, int an, int n, int nreg, int hstride, const double *cot, const double *csc,
                            const double *FA, const double *FB, double *HxA, double *HxB);
 hipError_t launch_pole_from_F(hipStream_t st, int L, int hstride, int ring, const double *F, double2 *pole);

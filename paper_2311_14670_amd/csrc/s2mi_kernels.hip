@@ -940,6 +940,11 @@ __global__ __launch_bounds__(1024) void k_phi_fwd_real(int L, int nring, int hst
 // hpole[(L-1) +- m] (south) and hpoleN (north, MWSS).  half (real signals):
 // only the side of order +m is filtered, the filter being real and the side
 // of order -m the conjugate.
+// adj (MWSS): the Hermitian adjoint of the filter.  With the Nyquist projector
+// P (real, symmetric) and (S+)^H = S-, the filter is sc E^T [(W P + S- W' S+) / 2] E,
+// whose adjoint differs only in the first term: P W instead of W P, i.e. the
+// Nyquist component is removed from g w'_theta rather than from g.  (MW has no
+// Nyquist bin: its filter is Hermitian and adj changes nothing.)
 __device__ __forceinline__ int torus_ring(int t, int L, int N, int ss, bool *mirrored)
 {
     *mirrored = ss ? t > L : t >= L;
@@ -952,10 +957,11 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
                                                     const double *__restrict__ wq, const double *__restrict__ ph,
                                                     double *__restrict__ F, double2 *__restrict__ hpole,
                                                     double2 *__restrict__ hpoleN, double2 *__restrict__ fscr,
-                                                    int half)
+                                                    int half, int adj)
 {
     extern __shared__ double2 buf[];
     __shared__ double2 nyq;
+    __shared__ double2 wpart[16];                          // per-wave partial sums (<= 1024 threads)
     const int m = blockIdx.x;
     const int N = ss ? 2 * L : 2 * L - 1;
     const int T = blockDim.x, tid = threadIdx.x;
@@ -965,6 +971,7 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
     for (int side = 0; side < 2; ++side) {
         if (side == 1 && (m == 0 || half)) break;
         // torus samples
+        double2 acc = make_double2(0.0, 0.0);                // adj: sum_t (-1)^t w'_theta g
         for (int t = tid; t < N; t += T) {
             bool mir;
             const int r = torus_ring(t, L, N, ss, &mir);
@@ -972,11 +979,29 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
             double2 g = make_double2(src[0], src[1]);
             if (mir) { g.x *= par; g.y *= par; }
             buf[t] = g;
+            if (ss && adj) {
+                const double sw = (t & 1) ? -wq[t] : wq[t];
+                acc.x = fma(sw, g.x, acc.x);
+                acc.y = fma(sw, g.y, acc.y);
+            }
+        }
+        if (ss && adj) {                                    // uniform over the workgroup
+            for (int o = 32; o > 0; o >>= 1) {
+                acc.x += __shfl_xor(acc.x, o, 64);
+                acc.y += __shfl_xor(acc.y, o, 64);
+            }
+            if ((tid & 63) == 0) wpart[tid >> 6] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double2 tot = make_double2(0.0, 0.0);
+                for (int w = 0; w < (T + 63) / 64; ++w) tot = cadd(tot, wpart[w]);
+                nyq = make_double2(tot.x / N, tot.y / N);   // Nyquist component of g w'_theta
+            }
         }
         __syncthreads();
         dft_lds(buf, fN, -1, scr);
         for (int k = tid; k < N; k += T) {                                          // shift +pi/N
-            if (ss && k == L) nyq = make_double2(buf[k].x / N, buf[k].y / N);     // ghat_L (MWSS), read first
+            if (ss && !adj && k == L) nyq = make_double2(buf[k].x / N, buf[k].y / N);   // ghat_L (MWSS), read first
             buf[k] = cmul(buf[k], phc[k]);
         }
         __syncthreads();
@@ -993,13 +1018,18 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
             const double *src = F + ((size_t)m * hstride + r) * 4 + 2 * side;
             double2 g = make_double2(src[0], src[1]);
             if (mir) { g.x *= par; g.y *= par; }
-            if (ss) {
-                const double sg = (t & 1) ? -1.0 : 1.0;
+            const double wv = wq[t];
+            const double sg = (t & 1) ? -1.0 : 1.0;
+            if (ss && !adj) {                                // P g, then times w'
                 g.x -= sg * nyq.x;
                 g.y -= sg * nyq.y;
             }
-            const double wv = wq[t];
-            buf[t] = make_double2(0.5 * fma(g.x, wv, buf[t].x), 0.5 * fma(g.y, wv, buf[t].y));
+            double2 gw = make_double2(g.x * wv, g.y * wv);
+            if (ss && adj) {                                 // P (g w')
+                gw.x -= sg * nyq.x;
+                gw.y -= sg * nyq.y;
+            }
+            buf[t] = make_double2(0.5 * (gw.x + buf[t].x), 0.5 * (gw.y + buf[t].y));
         }
         __syncthreads();
         const double sc = 2.0 * M_PI / (double)N;
@@ -1036,13 +1066,17 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
 // closed-form south pole (Eq. 29).  gather: sum the sweep's blocks (and the
 // pole) into the filter's [m][ring] layout; scatter: filtered rings and pole
 // -> [ring][m] partials of a single block, scaled by the phi weight q.
-__global__ void k_fadj_gather(int L, int nblk, int spin, const double *__restrict__ part, const int *__restrict__ mtop,
-                              const double2 *__restrict__ flm, const double *__restrict__ wl, int hstride,
-                              double *__restrict__ F)
+// MWSS (ss): the rows are the L-1 regular rings, the south pole (row L-1) and the
+// north pole (row L, the forward's w_l h~_{-s}(0) at order -s), and the adjoint
+// filter runs in between.
+__global__ void k_fadj_gather(int L, int ss, int nblk, int spin, const double *__restrict__ part,
+                              const int *__restrict__ mtop, const double2 *__restrict__ flm,
+                              const double *__restrict__ wl, int hstride, double *__restrict__ F)
 {
+    const int nrow = L + ss;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)L * L) return;
-    const int m = (int)(i / L), t = (int)(i % L);
+    if (i >= (size_t)L * nrow) return;
+    const int m = (int)(i / nrow), t = (int)(i % nrow);
     const int nreg = L - 1, M = 2 * L - 1;
     const size_t bstride = (size_t)nreg * L * 4;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1054,17 +1088,20 @@ __global__ void k_fadj_gather(int L, int nblk, int spin, const double *__restric
             for (int c = 0; c < 4; ++c) v[c] += pp[c];
         }
     } else {
-        // south pole: only the signed order s is nonzero, sum_l (-1)^{l+s} w_l G[l][s]
+        // south pole (t == nreg): only the signed order s is nonzero, sum_l (-1)^{l+s} w_l G[l][s];
+        // north pole (t == nreg + 1): only the order -s, sum_l w_l G[l][-s]
+        const bool north = t > nreg;
+        const int mp = north ? -spin : spin;
         const int as = spin < 0 ? -spin : spin;
         if (m == as) {
             double2 acc = make_double2(0.0, 0.0);
             for (int l = as; l < L; ++l) {
-                const double2 g = flm[(size_t)l * M + (L - 1) + spin];
-                const double c = ((l + spin) & 1) ? -wl[l] : wl[l];
+                const double2 g = flm[(size_t)l * M + (L - 1) + mp];
+                const double c = (!north && ((l + spin) & 1)) ? -wl[l] : wl[l];
                 acc.x += c * g.x;
                 acc.y += c * g.y;
             }
-            const int off = (spin < 0) ? 2 : 0;
+            const int off = (mp < 0) ? 2 : 0;
             v[off] = acc.x;
             v[off + 1] = acc.y;
         }
@@ -1075,11 +1112,12 @@ __global__ void k_fadj_gather(int L, int nblk, int spin, const double *__restric
     for (int c = 0; c < 4; ++c) dst[c] = v[c];
 }
 
-__global__ void k_fadj_scatter(int L, int hstride, double q, const double *__restrict__ F,
-                               const double2 *__restrict__ hpole, double *__restrict__ out)
+__global__ void k_fadj_scatter(int L, int ss, int hstride, double q, const double *__restrict__ F,
+                               const double2 *__restrict__ hpole, const double2 *__restrict__ hpoleN,
+                               double *__restrict__ out)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)L * L) return;
+    if (i >= (size_t)(L + ss) * L) return;
     const int t = (int)(i / L), m = (int)(i % L);
     double v[4];
     if (t < L - 1) {
@@ -1087,7 +1125,8 @@ __global__ void k_fadj_scatter(int L, int hstride, double q, const double *__res
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[c] = src[c];
     } else {
-        const double2 a = hpole[(L - 1) + m], b = hpole[(L - 1) - m];
+        const double2 *hp = t == L - 1 ? hpole : hpoleN;   // south pole; north pole (MWSS)
+        const double2 a = hp[(L - 1) + m], b = hp[(L - 1) - m];
         v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
     }
     if (m == 0) { v[2] = 0.0; v[3] = 0.0; }
@@ -1422,11 +1461,11 @@ hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nri
 
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *hpoleN, double2 *fscr, int half)
+                            double2 *hpoleN, double2 *fscr, int half, int adj)
 {
-    if (ss && !hpoleN) return hipErrorInvalidValue;
+    if ((ss && !hpoleN) || nthreads > 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, ss, hstride, spin, fN, wq, ph, F, hpole,
-                       hpoleN, fscr, half);
+                       hpoleN, fscr, half, adj);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1478,22 +1517,24 @@ hipError_t launch_bluestein_filter(hipStream_t st, int nfft, const FftArgs *ffts
     return hipSuccess;
 }
 
-hipError_t launch_fadj_gather(hipStream_t st, int L, int nblk, int spin, const double *part, const int *mtop,
+hipError_t launch_fadj_gather(hipStream_t st, int L, int ss, int nblk, int spin, const double *part, const int *mtop,
                               const double2 *flm, const double *wl, int hstride, double *F)
 {
-    const size_t tot = (size_t)L * L;
-    hipLaunchKernelGGL(k_fadj_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, part, mtop,
-                       flm, wl, hstride, F);
+    if (hstride < L + ss) return hipErrorInvalidValue;
+    const size_t tot = (size_t)L * (L + ss);
+    hipLaunchKernelGGL(k_fadj_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, ss, nblk, spin, part,
+                       mtop, flm, wl, hstride, F);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_fadj_scatter(hipStream_t st, int L, int hstride, double q, const double *F, const double2 *hpole,
-                               double *out)
+hipError_t launch_fadj_scatter(hipStream_t st, int L, int ss, int hstride, double q, const double *F,
+                               const double2 *hpole, const double2 *hpoleN, double *out)
 {
-    const size_t tot = (size_t)L * L;
-    hipLaunchKernelGGL(k_fadj_scatter, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, hstride, q, F, hpole,
-                       out);
+    if (ss && !hpoleN) return hipErrorInvalidValue;
+    const size_t tot = (size_t)(L + ss) * L;
+    hipLaunchKernelGGL(k_fadj_scatter, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, ss, hstride, q, F,
+                       hpole, hpoleN, out);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

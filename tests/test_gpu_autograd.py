@@ -90,14 +90,15 @@ def test_gradient_matches_oracle_at_L512(ag, spin):
 
 @pytest.mark.parametrize("sampling,L,nside,spin", [("mw", 24, 0, 0), ("mw", 20, 0, 2), ("mw", 17, 0, -3),
                                                    ("healpix", 16, 8, 0), ("healpix", 12, 8, 1), ("dh", 14, 0, 2),
-                                                   ("gl", 15, 0, -1)])
+                                                   ("gl", 15, 0, -1), ("mwss", 16, 0, 0), ("mwss", 21, 0, 2),
+                                                   ("mwss", 13, 0, -3)])
 def test_forward_adjoint_dot_product(ag, sampling, L, nside, spin):
     """<F f, G> = <f, F^H G> with F the oracle's forward transform."""
     autograd, binding = ag
     plan = binding.Plan(L, spin=spin, sampling=sampling, nside=nside)
     f = map_gaussian(plan.map_shape, seed=30)
     G = flm_gaussian(L, spin, seed=31)
-    samp = {"mw": oracle.MW, "healpix": oracle.HEALPIX, "dh": oracle.DH, "gl": oracle.GL}[sampling]
+    samp = {"mw": oracle.MW, "healpix": oracle.HEALPIX, "dh": oracle.DH, "gl": oracle.GL, "mwss": oracle.MWSS}[sampling]
     lhs = np.vdot(G, oracle.s2_forward(f, L, spin, samp, nside))           # <G, F f>
     FhG = plan.forward_adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
     rhs = np.vdot(FhG, f)                                                   # <F^H G, f>
@@ -233,3 +234,19 @@ def test_so3_autograd_gradients_and_jvp(ag):
             dual = fwAD.make_dual(torch.from_numpy(x0).cuda(), torch.from_numpy(t).cuda())
             tangent = fwAD.unpack_dual(fn(dual, plan)).tangent.cpu().numpy()
         assert rel_l2(tangent, ref_fn(t, L, N)) < 1e-12
+
+
+@pytest.mark.parametrize("L,spin", [(5, 0), (6, 1), (4, -2)])
+def test_mwss_forward_adjoint_matches_dense_oracle(ag, L, spin):
+    """MWSS: the forward drops the Nyquist frequency of the theta torus, so its
+    filter is not Hermitian; the GPU adjoint equals conj(A).T @ y with A the
+    oracle's MWSS forward written out as a dense matrix (both poles included)."""
+    autograd, binding = ag
+    shp = (L + 1, 2 * L)
+    A = _dense(lambda x: oracle.s2_forward(x, L, spin, oracle.MWSS), shp)
+    plan = binding.Plan(L, spin=spin, sampling="mwss", max_batch=2)
+    y = flm_gaussian(L, spin, seed=58, batch=2)
+    got = plan.forward_adjoint(torch.from_numpy(y).cuda()).cpu().numpy()
+    for b in range(2):
+        ref = (A.conj().T @ y[b].ravel()).reshape(shp)
+        assert rel_l2(got[b], ref) < 1e-12

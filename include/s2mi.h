@@ -153,21 +153,22 @@ int s2_forward(s2_plan_t plan, const void *f, void *flm, int batch, void *worksp
                void *hip_stream);
 
 /*
- * Real signals (spin 0, MW sampling, FP64 plans).  A real map's coefficients
- * obey flm[l][-m] = (-1)^m conj(flm[l][m]) (Sec. 2.1), so the
+ * Real signals (spin-0 plans of any sampling, FP64).  A real map's
+ * coefficients obey flm[l][-m] = (-1)^m conj(flm[l][m]) (Sec. 2.1), so the
  * Wigner-d sweeps carry only the orders m >= 0 (half the contraction work) and
- * two rings share one complex phi-DFT (half the DFT work).
+ * two rings of equal length share one complex phi-DFT (half the DFT work; the
+ * MW / MWSS theta filter runs on one side only).
  *
  * s2_inverse_real: f = Re(inverse SHT of the Hermitian completion of the
  * orders m >= 0 of flm); the orders m < 0 of flm are not read.
- *   flm [batch][L][2L-1] complex128 (device, read), f [batch][L][2L-1] double
- *   (device, written).
+ *   flm [batch][L][2L-1] complex128 (device, read), f [batch][nsamples] double
+ *   (device, written; the sampling's map layout).
  * s2_forward_real: the forward SHT of a real map, orders m < 0 written by the
  * symmetry above.
- *   f [batch][L][2L-1] double (device, read), flm [batch][L][2L-1] complex128
- *   (device, written).
- * Map pointers need 16-byte alignment of the first map only.  Other plans:
- * S2_ERR_UNSUPPORTED (S2_ERR_INVALID_ARG for SO(3) plans).
+ *   f [batch][nsamples] double (device, read), flm [batch][L][2L-1]
+ *   complex128 (device, written).
+ * Map pointers need 16-byte alignment of the first map only.  Spin != 0 or
+ * matrix-core plans: S2_ERR_UNSUPPORTED; SO(3) plans: S2_ERR_INVALID_ARG.
  */
 int s2_inverse_real(s2_plan_t plan, const void *flm, void *f, int batch, void *workspace,
                     void *hip_stream);

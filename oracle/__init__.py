@@ -221,15 +221,15 @@ def hermitian_complete(flm, L):
     return out
 
 
-def s2_inverse_real(flm, L, rings=None):
-    """Real MW map of a spin-0 signal given by its orders m >= 0: the inverse
-    SHT of the Hermitian completion (a real map up to rounding), real part."""
-    return s2_inverse(hermitian_complete(flm, L), L, 0, MW, rings=rings).real
+def s2_inverse_real(flm, L, sampling=MW, nside=0, rings=None):
+    """Real map of a spin-0 signal given by its orders m >= 0: the inverse SHT
+    of the Hermitian completion (a real map up to rounding), real part."""
+    return s2_inverse(hermitian_complete(flm, L), L, 0, sampling, nside, rings=rings).real
 
 
-def s2_forward_real(f, L, ms=None):
-    """Forward SHT of a real MW map (the complex transform of the same samples)."""
-    return s2_forward(np.asarray(f, dtype=np.float64).astype(np.complex128), L, 0, MW, ms=ms)
+def s2_forward_real(f, L, sampling=MW, nside=0, ms=None):
+    """Forward SHT of a real map (the complex transform of the same samples)."""
+    return s2_forward(np.asarray(f, dtype=np.float64).astype(np.complex128), L, 0, sampling, nside, ms=ms)
 
 
 # ----------------------------------------------------------------- SO(3) transforms

@@ -192,13 +192,13 @@ class Plan:
         return self._call(self._lib.s2_forward, f, self.map_shape, self.coeff_shape, "forward", workspace, out)
 
     def inverse_real(self, flm, workspace=None, out=None):
-        """Inverse SHT of a real signal (MW, spin 0, FP64 plans): flm [B?, L, 2L-1]
+        """Inverse SHT of a real signal (spin-0 FP64 plans): flm [B?, L, 2L-1]
         complex128, of which only the orders m >= 0 are read -> real map float64."""
         return self._call(self._lib.s2_inverse_real, flm, self.coeff_shape, self.map_shape, "inverse_real", workspace,
                           out, out_dtype=torch.float64)
 
     def forward_real(self, f, workspace=None, out=None):
-        """Forward SHT of a real map float64 (MW, spin 0, FP64 plans) -> flm
+        """Forward SHT of a real map float64 (spin-0 FP64 plans) -> flm
         [B?, L, 2L-1] complex128 with flm[l][-m] = (-1)^m conj(flm[l][m])."""
         return self._call(self._lib.s2_forward_real, f, self.map_shape, self.coeff_shape, "forward_real", workspace,
                           out, in_dtype=torch.float64)

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -69,6 +70,8 @@ struct s2_plan_s {
     // geometry (regular rings first; MW adds the south pole as ring nreg)
     double *cot = nullptr, *csc = nullptr, *lsin = nullptr, *lcos = nullptr;
     int *ring_nphi = nullptr, *ring_shift = nullptr, *ring_fft = nullptr;
+    int *ring_pairs = nullptr;             // real signals: [npair][2] rings sharing one complex DFT (-1: none)
+    int npair = 0;
     long long *ring_start = nullptr;
     // recursion tables
     double *kap = nullptr, *gtab = nullptr;
@@ -395,6 +398,24 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     if ((rc = upload(P, &P->ring_nphi, nphi, st, "ring_nphi"))) return bail(rc);
     if ((rc = upload(P, &P->ring_shift, shift, st, "ring_shift"))) return bail(rc);
     if ((rc = upload(P, &P->ring_start, start, st, "ring_start"))) return bail(rc);
+    {
+        // real signals: rings of equal length and phase offset pair up in ring order
+        // (MW-type grids: (0,1), (2,3), ...; HEALPix: a cap ring with its mirror ring)
+        stg.i.emplace_back();
+        std::vector<int> &pr = stg.i.back();
+        std::map<std::pair<int, int>, int> open_ring;
+        for (int r = 0; r < P->nring; ++r) {
+            const auto key = std::make_pair(nphi[r], shift[r]);
+            auto it = open_ring.find(key);
+            if (it == open_ring.end()) { open_ring[key] = r; continue; }
+            pr.push_back(it->second);
+            pr.push_back(r);
+            open_ring.erase(it);
+        }
+        for (const auto &kv : open_ring) { pr.push_back(kv.second); pr.push_back(-1); }
+        P->npair = (int)pr.size() / 2;
+        if ((rc = upload(P, &P->ring_pairs, pr, st, "ring pairs"))) return bail(rc);
+    }
 
     // FFTs: one per distinct ring length
     {
@@ -830,36 +851,43 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
     return run_forward_dstage(P, F0, mw ? hp0 : nullptr, hpN0, flm, wl, ws, st);
 }
 
-// Real signals (MW, spin-0 S2 plan, Hermitian symmetry of the coefficients):
-// the sweeps carry the orders m >= 0 only and two rings share a phi-DFT.
+// Real signals (spin-0 S2 plan, Hermitian symmetry of the coefficients): the
+// sweeps carry the orders m >= 0 only and pairs of rings share a phi-DFT.
 int run_inverse_real(s2_plan_t P, const double2 *flm, double *map, char *ws, hipStream_t st)
 {
     int rc = run_inverse_dstage(P, flm, P->w_sht, ws, st, 1);
     if (rc) return rc;
     TIMED(S2_STAGE_PHI_INV);
-    HIPCHK(launch_phi_inv_real(st, P->fft_threads, P->fft_lds, P->nring, P->L, P->nreg, P->inv_nblk,
-                               (const double *)(ws + P->off_P), P->mtop, flm, P->w_sht[0], P->ffts, map,
-                               fft_scratch(P, ws)), "real inverse phi-DFT");
+    HIPCHK(launch_phi_inv_real(st, P->fft_threads, P->fft_lds, P->npair, P->L, P->nreg, P->inv_nblk, P->ring_pairs,
+                               (const double *)(ws + P->off_P), P->mtop, flm, P->w_sht[0], P->ring_nphi,
+                               P->ring_start, P->ring_shift, P->ring_fft, P->ffts, map, fft_scratch(P, ws)),
+           "real inverse phi-DFT");
     return S2_OK;
 }
 
 int run_forward_real(s2_plan_t P, const double *map, double2 *flm, char *ws, hipStream_t st)
 {
     const int L = P->L;
+    const bool mw = P->sampling == S2_MW || P->sampling == S2_MWSS;   // theta-torus samplings
+    const int ss = P->sampling == S2_MWSS;
     double *F0 = (double *)(ws + P->off_F);
     double2 *hp0 = (double2 *)(ws + P->off_hpole);
+    double2 *hpN0 = ss ? hp0 + (size_t)P->nslice * (2 * L - 1) : nullptr;
+    double q;
+    if (mw) q = 2.0 * M_PI / (double)(ss ? 2 * L : 2 * L - 1);
+    else q = 4.0 * M_PI / (double)P->nsamp;               // HEALPix (DH / GL: per-ring weights)
     {
     TIMED(S2_STAGE_PHI_FWD);
-    HIPCHK(launch_phi_fwd_real(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, L,
-                               2.0 * M_PI / (double)(2 * L - 1), map, P->ffts, F0, fft_scratch(P, ws)),
-           "real forward phi-DFT");
+    HIPCHK(launch_phi_fwd_real(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, P->npair, L, q, P->ring_pairs,
+                               map, P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, P->ringq, F0,
+                               fft_scratch(P, ws)), "real forward phi-DFT");
     }
-    {
-    TIMED(S2_STAGE_MW_THETA);
-    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, 0, P->hstride, 0, P->ffts, P->wq, P->ph, F0, hp0,
-                            nullptr, fft_scratch(P, ws), 1), "MW theta filter");
+    if (mw) {
+        TIMED(S2_STAGE_MW_THETA);
+        HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, 0, P->ffts, P->wq, P->ph, F0, hp0,
+                                hpN0, fft_scratch(P, ws), 1), "MW theta filter");
     }
-    return run_forward_dstage(P, F0, hp0, nullptr, flm, P->w_sht, ws, st, 1);
+    return run_forward_dstage(P, F0, mw ? hp0 : nullptr, hpN0, flm, P->w_sht, ws, st, 1);
 }
 
 // ---------------------------------------------------------------- matrix-core path
@@ -1152,8 +1180,7 @@ int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspa
 static int check_real(const char *fn, s2_plan_t P)
 {
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "%s: plan was created for SO(3) (N=%d)", fn, P->N);
-    if (P->sampling != S2_MW || P->spin != 0)
-        return fail(S2_ERR_UNSUPPORTED, "%s: real signals need an MW spin-0 plan", fn);
+    if (P->spin != 0) return fail(S2_ERR_UNSUPPORTED, "%s: real signals need a spin-0 plan", fn);
     if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "%s: available for FP64 plans", fn);
     return S2_OK;
 }

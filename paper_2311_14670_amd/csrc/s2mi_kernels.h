@@ -37,12 +37,16 @@ hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
                              int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN,
                              double2 *flm, int half = 0);
-// real signals (MW, spin 0): two rings per complex DFT; maps are [nring][2L-1] doubles
-hipError_t launch_phi_inv_real(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk,
-                               const double *part, const int *mtop, const double2 *flm, const double *wl,
-                               const FftArgs *f, double *map, double2 *fscr);
-hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
-                               const double *map, const FftArgs *f, double *F, double2 *fscr);
+// real signals (spin 0): pairs of rings share one complex DFT; maps are real doubles
+hipError_t launch_phi_inv_real(hipStream_t st, int nthreads, size_t lds, int npair, int L, int nreg, int nblk,
+                               const int *pairs, const double *part, const int *mtop, const double2 *flm,
+                               const double *wl, const int *ring_nphi, const long long *ring_start,
+                               const int *ring_shift, const int *ring_fft, const FftArgs *ffts, double *map,
+                               double2 *fscr);
+hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int npair, int L,
+                               double q, const int *pairs, const double *map, const int *ring_nphi,
+                               const long long *ring_start, const int *ring_shift, const int *ring_fft,
+                               const FftArgs *ffts, const double *ringq, double *F, double2 *fscr);
 hipError_t launch_gamma_dft(hipStream_t st, int N, long long nper, int sign, double q, const double *roots,
                             const double2 *in, double2 *out);
 hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,

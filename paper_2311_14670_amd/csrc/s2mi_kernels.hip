@@ -813,110 +813,157 @@ __global__ __launch_bounds__(1024) void k_phi_fwd(
 }
 
 // ------------------------------------------------------------------ phi-DFTs of real signals
-// MW rings, spin 0.  The spectrum of a real ring is Hermitian (X[-m] = conj
-// X[m], X[0] real), so two rings share one complex DFT: ring 2p in the real
-// and ring 2p+1 in the imaginary part of z = x1 + i x2, with Z = X1 + i X2.
-// One workgroup per pair of rings.
+// Spin 0.  The spectrum of a real ring is Hermitian (X[-k] = conj X[k], X[0]
+// real), so two rings of equal length and phase offset share one complex DFT:
+// ring r1 in the real and ring r2 in the imaginary part of z = x1 + i x2, with
+// Z = X1 + i X2.  One workgroup per pair (r2 < 0: r1 alone); the pairs are
+// built on the host.
 //
-// Inverse: X[m] for m >= 0 is the sweep's side A (summed over its blocks); the
-// south pole (ring nreg) holds only order 0, sum_l (-1)^l w_l Re flm[l][0]
-// (Eq. 29).  Order 0 enters with its real part: the result is the real part of
-// the complex transform of the Hermitian completion of the orders m >= 0.
-__global__ __launch_bounds__(1024) void k_phi_inv_real(int L, int nreg, int nring, int nblk,
-                                                       const double *__restrict__ part, const int *__restrict__ mtop,
-                                                       const double2 *__restrict__ flm, const double *__restrict__ wl,
-                                                       const FftArgs *__restrict__ f, double *__restrict__ map,
-                                                       double2 *__restrict__ fscr)
+// Inverse: the order-m spectrum of a swept ring is the sweep's side A (summed
+// over its blocks) for m >= 0 and its conjugate for m < 0; the poles (MW south
+// ring nreg, MWSS north ring nreg + 1) hold only order 0, sum_l (+-1)^l w_l
+// Re flm[l][0] (Eq. 29).  Order 0 enters with its real part: the result is the
+// real part of the complex transform of the Hermitian completion of the orders
+// m >= 0.  Rings of 2L-1 samples without offset map orders one-to-one onto
+// bins; other rings sum the orders of each bin (HEALPix repeat) with the
+// half-pixel phase.
+__global__ __launch_bounds__(1024) void k_phi_inv_real(
+    int L, int nreg, int nblk, const int *__restrict__ pairs, const double *__restrict__ part,
+    const int *__restrict__ mtop, const double2 *__restrict__ flm, const double *__restrict__ wl,
+    const int *__restrict__ ring_nphi, const long long *__restrict__ ring_start, const int *__restrict__ ring_shift,
+    const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, double *__restrict__ map,
+    double2 *__restrict__ fscr)
 {
     extern __shared__ double2 buf[];
-    __shared__ double red[1024];
-    const int r1 = 2 * (int)blockIdx.x, r2 = r1 + 1;
+    __shared__ double2 red[1024];
+    const int r1 = pairs[2 * blockIdx.x], r2 = pairs[2 * blockIdx.x + 1];
     const int T = blockDim.x, tid = threadIdx.x;
     const int M = 2 * L - 1;
-    double pole = 0.0;
-    if (r1 == nreg || r2 == nreg) {                      // uniform over the workgroup
-        double acc = 0.0;
-        for (int l = tid; l < L; l += T) acc = fma((l & 1) ? -wl[l] : wl[l], flm[(size_t)l * M + (L - 1)].x, acc);
+    const int nphi = ring_nphi[r1];
+    const FftArgs *f = ffts + ring_fft[r1];
+    const int shift = ring_shift[r1];
+    double2 pole = make_double2(0.0, 0.0);                 // (south, north) order-0 values
+    if (r1 >= nreg || r2 >= nreg) {                        // uniform over the workgroup
+        double2 acc = make_double2(0.0, 0.0);
+        for (int l = tid; l < L; l += T) {
+            const double v = wl[l] * flm[(size_t)l * M + (L - 1)].x;
+            acc.x += (l & 1) ? -v : v;
+            acc.y += v;
+        }
         red[tid] = acc;
         __syncthreads();
         int p2 = 1;
         while (p2 < T) p2 <<= 1;
         for (int h = p2 / 2; h > 0; h >>= 1) {           // T need not be a power of two
-            if (tid < h && tid + h < T) red[tid] += red[tid + h];
+            if (tid < h && tid + h < T) red[tid] = cadd(red[tid], red[tid + h]);
             __syncthreads();
         }
         pole = red[0];
     }
     const size_t bstride = (size_t)nreg * L * 4;
-    for (int am = tid; am < L; am += T) {
-        double2 x[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = r1 + h;
-            double2 v = make_double2(0.0, 0.0);
-            if (r < nreg) {
-                const double *pr = part + ((size_t)r * L + am) * 4;
-                for (int b = 0; b < nblk; ++b) {
-                    if (am > mtop[b]) continue;              // that block's sweep never reached order am
-                    v = cadd(v, *reinterpret_cast<const double2 *>(pr + b * bstride));
-                }
-            } else if (r == nreg && am == 0) {
-                v.x = pole;
+    auto spec = [&](int r, int am) {                       // order +am of ring r (real part only at am = 0)
+        double2 v = make_double2(0.0, 0.0);
+        if (r < 0) return v;
+        if (r < nreg) {
+            const double *pr = part + ((size_t)r * L + am) * 4;
+            for (int b = 0; b < nblk; ++b) {
+                if (am > mtop[b]) continue;                  // that block's sweep never reached order am
+                v = cadd(v, *reinterpret_cast<const double2 *>(pr + b * bstride));
             }
-            if (am == 0) v.y = 0.0;
-            x[h] = v;
+        } else if (am == 0) {
+            v.x = r == nreg ? pole.x : pole.y;
         }
-        buf[am] = make_double2(x[0].x - x[1].y, x[0].y + x[1].x);                      // X1 + i X2
-        if (am > 0) buf[M - am] = make_double2(x[0].x + x[1].y, x[1].x - x[0].y);     // conj X1 + i conj X2
+        if (am == 0) v.y = 0.0;
+        return v;
+    };
+    if (nphi == M && !shift) {
+        for (int am = tid; am < L; am += T) {
+            const double2 x1 = spec(r1, am), x2 = spec(r2, am);
+            buf[am] = make_double2(x1.x - x2.y, x1.y + x2.x);                      // X1 + i X2
+            if (am > 0) buf[M - am] = make_double2(x1.x + x2.y, x2.x - x1.y);     // conj X1 + i conj X2
+        }
+    } else {
+        for (int k = tid; k < nphi; k += T) {
+            double2 z = make_double2(0.0, 0.0);
+            for (int m = k - ((k + L - 1) / nphi) * nphi; m <= L - 1; m += nphi) {   // orders = k mod nphi
+                const int am = m < 0 ? -m : m;
+                double2 x1 = spec(r1, am), x2 = spec(r2, am);
+                if (m < 0) { x1 = cconj(x1); x2 = cconj(x2); }
+                if (shift) {
+                    double sn, cs;   // e^{i pi m / nphi}
+                    sincospi((double)(((long long)m % (2 * nphi) + 2 * nphi) % (2 * nphi)) / (double)nphi, &sn, &cs);
+                    x1 = cmul(x1, make_double2(cs, sn));
+                    x2 = cmul(x2, make_double2(cs, sn));
+                }
+                z.x += x1.x - x2.y;
+                z.y += x1.y + x2.x;
+            }
+            buf[k] = z;
+        }
     }
     __syncthreads();
     dft_lds(buf, f, +1, fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr);
-    double *o1 = map + (size_t)r1 * M;
-    double *o2 = map + (size_t)r2 * M;
-    for (int k = tid; k < M; k += T) {
+    double *o1 = map + ring_start[r1];
+    double *o2 = r2 >= 0 ? map + ring_start[r2] : nullptr;
+    for (int k = tid; k < nphi; k += T) {
         o1[k] = buf[k].x;
-        if (r2 < nring) o2[k] = buf[k].y;
+        if (o2) o2[k] = buf[k].y;
     }
 }
 
-// Forward: Z = DFT(x1 + i x2), X1[m] = (Z[m] + conj Z[-m]) / 2, X2[m] = (Z[m] -
-// conj Z[-m]) / 2i, written as F[m][ring] = q {X[m], conj X[m]} (the layout of
-// the complex phi-DFT); rings nring .. hstride-1 are the sweep's zero padding.
-__global__ __launch_bounds__(1024) void k_phi_fwd_real(int L, int nring, int hstride, double q,
-                                                       const double *__restrict__ map, const FftArgs *__restrict__ f,
-                                                       double *__restrict__ F, double2 *__restrict__ fscr)
+// Forward: Z = DFT(x1 + i x2), X1[k] = (Z[k] + conj Z[-k]) / 2, X2[k] = (Z[k] -
+// conj Z[-k]) / 2i; order m >= 0 of a ring is q e^{-i pi m s/nphi} X[m mod nphi]
+// (q per ring for DH / GL), written as F[m][ring] = {X_m, conj X_m} (the layout
+// of the complex phi-DFT).  Workgroups past the pairs zero the sweep's padding
+// rings nring .. hstride-1, two per workgroup.
+__global__ __launch_bounds__(1024) void k_phi_fwd_real(
+    int L, int nring, int hstride, int npair, double q, const int *__restrict__ pairs, const double *__restrict__ map,
+    const int *__restrict__ ring_nphi, const long long *__restrict__ ring_start, const int *__restrict__ ring_shift,
+    const int *__restrict__ ring_fft, const FftArgs *__restrict__ ffts, const double *__restrict__ ringq,
+    double *__restrict__ F, double2 *__restrict__ fscr)
 {
     extern __shared__ double2 buf[];
-    const int r1 = 2 * (int)blockIdx.x, r2 = r1 + 1;
     const int T = blockDim.x, tid = threadIdx.x;
-    const int M = 2 * L - 1;
-    if (r1 >= nring) {
+    if ((int)blockIdx.x >= npair) {
+        const int r0 = nring + 2 * ((int)blockIdx.x - npair);
         for (int m = tid; m < L; m += T)
-            for (int r = r1; r <= r2 && r < hstride; ++r) {
+            for (int r = r0; r < r0 + 2 && r < hstride; ++r) {
                 double2 *o = reinterpret_cast<double2 *>(F + ((size_t)m * hstride + r) * 4);
                 o[0] = make_double2(0.0, 0.0);
                 o[1] = make_double2(0.0, 0.0);
             }
         return;
     }
-    const double *x1 = map + (size_t)r1 * M;
-    const double *x2 = map + (size_t)r2 * M;
-    for (int k = tid; k < M; k += T) buf[k] = make_double2(x1[k], r2 < nring ? x2[k] : 0.0);
+    const int r1 = pairs[2 * blockIdx.x], r2 = pairs[2 * blockIdx.x + 1];
+    const int nphi = ring_nphi[r1];
+    const FftArgs *f = ffts + ring_fft[r1];
+    const int shift = ring_shift[r1];
+    const double q1 = 0.5 * (ringq ? ringq[r1] : q);
+    const double q2 = 0.5 * (ringq && r2 >= 0 ? ringq[r2] : q);
+    const double *x1 = map + ring_start[r1];
+    const double *x2 = r2 >= 0 ? map + ring_start[r2] : nullptr;
+    for (int k = tid; k < nphi; k += T) buf[k] = make_double2(x1[k], x2 ? x2[k] : 0.0);
     __syncthreads();
     dft_lds(buf, f, -1, fscr ? fscr + (size_t)blockIdx.x * FFT_SCRATCH : nullptr);
-    const double hq = 0.5 * q;
     for (int m = tid; m < L; m += T) {
-        const double2 z = buf[m];
-        const double2 zc = cconj(buf[m == 0 ? 0 : M - m]);
-        const double2 a = make_double2(hq * (z.x + zc.x), hq * (z.y + zc.y));     // q X1[m]
-        const double2 b = make_double2(hq * (z.y - zc.y), -hq * (z.x - zc.x));    // q X2[m]
+        const int b = m % nphi;
+        const double2 z = buf[b];
+        const double2 zc = cconj(buf[b == 0 ? 0 : nphi - b]);
+        double2 a = make_double2(q1 * (z.x + zc.x), q1 * (z.y + zc.y));     // q X1[m]
+        double2 c = make_double2(q2 * (z.y - zc.y), -q2 * (z.x - zc.x));    // q X2[m]
+        if (shift) {
+            double sn, cs;   // e^{-i pi m / nphi}
+            sincospi((double)(m % (2 * nphi)) / (double)nphi, &sn, &cs);
+            a = cmul(a, make_double2(cs, -sn));
+            c = cmul(c, make_double2(cs, -sn));
+        }
         double2 *o1 = reinterpret_cast<double2 *>(F + ((size_t)m * hstride + r1) * 4);
         o1[0] = a;
         o1[1] = cconj(a);
-        if (r2 < hstride) {
+        if (r2 >= 0) {
             double2 *o2 = reinterpret_cast<double2 *>(F + ((size_t)m * hstride + r2) * 4);
-            o2[0] = b;
-            o2[1] = cconj(b);
+            o2[0] = c;
+            o2[1] = cconj(c);
         }
     }
 }
@@ -1438,23 +1485,28 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
     return hipSuccess;
 }
 
-hipError_t launch_phi_inv_real(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk,
-                               const double *part, const int *mtop, const double2 *flm, const double *wl,
-                               const FftArgs *f, double *map, double2 *fscr)
+hipError_t launch_phi_inv_real(hipStream_t st, int nthreads, size_t lds, int npair, int L, int nreg, int nblk,
+                               const int *pairs, const double *part, const int *mtop, const double2 *flm,
+                               const double *wl, const int *ring_nphi, const long long *ring_start,
+                               const int *ring_shift, const int *ring_fft, const FftArgs *ffts, double *map,
+                               double2 *fscr)
 {
-    if (nthreads > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_phi_inv_real, dim3((nring + 1) / 2), dim3(nthreads), lds, st, L, nreg, nring, nblk, part, mtop,
-                       flm, wl, f, map, fscr);
+    if (nthreads > 1024 || npair < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_phi_inv_real, dim3(npair), dim3(nthreads), lds, st, L, nreg, nblk, pairs, part, mtop, flm, wl,
+                       ring_nphi, ring_start, ring_shift, ring_fft, ffts, map, fscr);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int L, double q,
-                               const double *map, const FftArgs *f, double *F, double2 *fscr)
+hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nring, int hstride, int npair, int L,
+                               double q, const int *pairs, const double *map, const int *ring_nphi,
+                               const long long *ring_start, const int *ring_shift, const int *ring_fft,
+                               const FftArgs *ffts, const double *ringq, double *F, double2 *fscr)
 {
-    if (nthreads > 1024 || hstride < nring) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_phi_fwd_real, dim3((hstride + 1) / 2), dim3(nthreads), lds, st, L, nring, hstride, q, map, f,
-                       F, fscr);
+    if (nthreads > 1024 || hstride < nring || npair < 1) return hipErrorInvalidValue;
+    const int nblocks = npair + (hstride - nring + 1) / 2;
+    hipLaunchKernelGGL(k_phi_fwd_real, dim3(nblocks), dim3(nthreads), lds, st, L, nring, hstride, npair, q, pairs, map,
+                       ring_nphi, ring_start, ring_shift, ring_fft, ffts, ringq, F, fscr);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1483,7 +1535,7 @@ hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, 
                              int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN, double2 *flm,
                              int half)
 {
-    if (half && (spin != 0 || Qx || hpoleN)) return hipErrorInvalidValue;   // real signals: MW spin 0
+    if (half && (spin != 0 || Qx)) return hipErrorInvalidValue;   // real signals: spin 0
     const size_t tot = (size_t)L * L;
     hipLaunchKernelGGL(k_finish_fwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nblk, spin, nB, Q, Qx,
                        nxp, wl, hpole, hpoleN, flm, half);

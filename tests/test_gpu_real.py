@@ -1,5 +1,5 @@
-"""Real-signal fast path (MW, spin 0): the sweeps carry the orders m >= 0 only
-and two rings share one complex phi-DFT.  Checked against the oracle's
+"""Real-signal fast path (spin 0, every sampling): the sweeps carry the orders
+m >= 0 only and two rings of equal length share one complex phi-DFT.  Checked against the oracle's
 real-signal transforms (the complex ones on the Hermitian completion, whose
 symmetry is pinned on the CPU), on seeded inputs that fill the orders m < 0
 with values the path must ignore."""
@@ -99,11 +99,55 @@ def test_real_full_size_sampled(binding, L):
 
 def test_real_path_rejects_other_plans(binding):
     flm = torch.zeros((16, 31), dtype=torch.complex128, device="cuda")
-    for kw in [dict(spin=2), dict(sampling="healpix", nside=8), dict(sampling="dh"), dict(precision="fp32"),
-               dict(N=3)]:
+    for kw in [dict(spin=2), dict(spin=-1, sampling="healpix", nside=8), dict(precision="fp32"), dict(N=3)]:
         plan = binding.Plan(16, **kw)
         with pytest.raises(binding.S2Error):
             plan.inverse_real(flm)
     plan = binding.Plan(16)
     with pytest.raises(TypeError):
         plan.forward_real(torch.zeros((16, 31), dtype=torch.complex128, device="cuda"))
+
+
+_SAMP = {"mwss": oracle.MWSS, "dh": oracle.DH, "gl": oracle.GL, "healpix": oracle.HEALPIX}
+
+
+# MWSS: both poles in the ring pairs; DH / GL: per-ring quadrature weights of
+# the two rings of a pair; HEALPix: a cap ring pairs with its mirror ring, belt
+# rings with the next ring of the same half-pixel offset, short rings repeat
+@pytest.mark.parametrize("sampling,L,nside", [("mwss", 16, 0), ("mwss", 33, 0), ("dh", 17, 0), ("gl", 24, 0),
+                                              ("healpix", 16, 8), ("healpix", 33, 16), ("healpix", 64, 24)])
+def test_real_other_samplings(binding, sampling, L, nside):
+    samp = _SAMP[sampling]
+    plan = binding.Plan(L, sampling=sampling, nside=nside, max_batch=2)
+    flm = np.stack([_with_junk(flm_gaussian(L, 0, seed=90 + b), L, seed=92 + b) for b in range(2)])
+    f = host(plan.inverse_real(dev(flm)))
+    for b in range(2):
+        ref = oracle.s2_inverse_real(flm[b], L, samp, nside)
+        assert rel_l2(f[b].ravel(), ref.ravel()) < 1e-12
+    g = np.random.default_rng(94).standard_normal((2,) + tuple(plan.map_shape))
+    a = host(plan.forward_real(dev(g)))
+    for b in range(2):
+        assert rel_l2(a[b], oracle.s2_forward_real(g[b], L, samp, nside)) < 1e-12
+    assert np.all(a[:, ~coeff_mask(L, 0)] == 0)
+    if sampling != "healpix":                          # sampling theorems: exact round trip
+        back = host(plan.forward_real(dev(f)))
+        for b in range(2):
+            assert rel_l2(back[b], oracle.hermitian_complete(flm[b], L)) < 1e-12
+
+
+# nside 1100: cap rings up to 4396 points (split Bluestein); both on sampled rings / orders
+@pytest.mark.parametrize("nside,L", [(1024, 2048), (1100, 2200)])
+def test_real_healpix_full_size_sampled(binding, nside, L):
+    plan = binding.Plan(L, sampling="healpix", nside=nside)
+    flm = flm_gaussian(L, 0, seed=95, scale="inv1pl")
+    f = host(plan.inverse_real(dev(flm)))
+    theta, nphi, start, _ = oracle.healpix_rings(nside)
+    rings = np.array([0, 1, nside - 1, nside, 2 * nside - 1, 3 * nside, 4 * nside - 2])
+    fr = np.concatenate([f[start[r]:start[r] + nphi[r]] for r in rings])
+    assert rel_l2(fr, oracle.s2_inverse_real(flm, L, oracle.HEALPIX, nside, rings=rings)) < 1e-11
+    a = host(plan.forward_real(dev(f)))
+    ms = np.array(sorted({0, 1, 2, L // 3, L // 2, L - 2, L - 1}))
+    ms = np.concatenate([ms, -ms[ms > 0]])
+    ref = oracle.s2_forward_real(f, L, oracle.HEALPIX, nside, ms=ms)
+    cols = ms + L - 1
+    assert rel_l2(a[:, cols], ref[:, cols]) < 1e-11

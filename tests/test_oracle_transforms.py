@@ -370,3 +370,13 @@ def test_real_round_trip_exact(oracle):
     flm = oracle.hermitian_complete(flm_gaussian(L, 0, seed=63), L)
     f = oracle.s2_inverse_real(flm, L)
     assert np.abs(oracle.s2_forward_real(f, L) - flm).max() < 1e-12 * np.abs(flm).max()
+
+
+@pytest.mark.parametrize("sampling,L,nside", [("mwss", 6, 0), ("dh", 5, 0), ("gl", 7, 0), ("healpix", 8, 4)])
+def test_real_maps_have_hermitian_coefficients_all_samplings(oracle, sampling, L, nside):
+    samp = {"mwss": oracle.MWSS, "dh": oracle.DH, "gl": oracle.GL, "healpix": oracle.HEALPIX}[sampling]
+    f = np.random.default_rng(64).standard_normal(oracle.map_size(L, samp, nside))
+    flm = oracle.s2_forward_real(f, L, samp, nside)
+    assert np.allclose(flm, oracle.hermitian_complete(flm, L), rtol=0, atol=1e-13 * np.abs(flm).max())
+    g = oracle.s2_inverse(oracle.hermitian_complete(flm_gaussian(L, 0, seed=65), L), L, 0, samp, nside)
+    assert np.abs(g.imag).max() < 1e-13 * np.abs(g.real).max()

@@ -176,6 +176,26 @@ int s2_forward_real(s2_plan_t plan, const void *f, void *flm, int batch, void *w
                     void *hip_stream);
 
 /*
+ * Gradients of the real-signal transforms (Sec. 5, in the convention PyTorch
+ * uses for complex inputs: d/dRe + i d/dIm of a real loss).
+ * s2_inverse_real_adjoint: for a real map cotangent g, with A the complex
+ *   inverse SHT, g_flm = 2 (A^H g) at m > 0, Re (A^H g) at m = 0 and 0 at
+ *   m < 0 (orders m > 0 enter the real map twice, order 0 through its real
+ *   part, orders m < 0 not at all).
+ *   g [batch][nsamples] double (device, read), g_flm [batch][L][2L-1]
+ *   complex128 (device, written).
+ * s2_forward_real_adjoint: g = Re(F^H g_flm) with F the forward SHT, computed
+ *   as F^H of the Hermitian part of g_flm through the real-signal path.
+ *   g_flm [batch][L][2L-1] complex128 (device, read), g [batch][nsamples]
+ *   double (device, written).
+ * Plans and errors as for s2_inverse_real.
+ */
+int s2_inverse_real_adjoint(s2_plan_t plan, const void *g, void *g_flm, int batch, void *workspace,
+                            void *hip_stream);
+int s2_forward_real_adjoint(s2_plan_t plan, const void *g_flm, void *g, int batch, void *workspace,
+                            void *hip_stream);
+
+/*
  * Hermitian adjoint of the inverse SHT (the VJP of Eqs. 56-58 in the
  * conjugate convention PyTorch uses for complex gradients):
  *   g_flm[l][m] = sum_{t,p} g(theta_t, phi_p) conj(sY_lm(theta_t, phi_p))

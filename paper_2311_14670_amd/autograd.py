@@ -108,3 +108,44 @@ def so3_forward(f, plan):
     if not isinstance(plan, binding.Plan):
         raise TypeError("plan must be a paper_2311_14670_amd.binding.Plan")
     return _SO3Forward.apply(f, plan)
+
+
+class _S2InverseReal(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, flm, plan):
+        ctx.plan = plan
+        return plan.inverse_real(flm)
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        if not ctx.needs_input_grad[0]:
+            return None, None
+        return ctx.plan.inverse_real_adjoint(grad_f.contiguous()), None
+
+
+def inverse_real(flm, plan):
+    """Differentiable real-signal inverse SHT (spin 0): flm [B?, L, 2L-1] complex128,
+    orders m >= 0 used -> real map.  The orders m < 0 get zero gradient."""
+    if not isinstance(plan, binding.Plan):
+        raise TypeError("plan must be a paper_2311_14670_amd.binding.Plan")
+    return _S2InverseReal.apply(flm, plan)
+
+
+class _S2ForwardReal(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f, plan):
+        ctx.plan = plan
+        return plan.forward_real(f)
+
+    @staticmethod
+    def backward(ctx, grad_flm):
+        if not ctx.needs_input_grad[0]:
+            return None, None
+        return ctx.plan.forward_real_adjoint(grad_flm.contiguous()), None
+
+
+def forward_real(f, plan):
+    """Differentiable forward SHT of a real map (spin 0): float64 map -> flm."""
+    if not isinstance(plan, binding.Plan):
+        raise TypeError("plan must be a paper_2311_14670_amd.binding.Plan")
+    return _S2ForwardReal.apply(f, plan)

@@ -70,7 +70,7 @@ def load_library():
         lib.s2_plan_info.argtypes = [P, ctypes.POINTER(_PlanInfo)]
         for name in ["s2_inverse", "s2_forward", "s2_inverse_adjoint", "s2_forward_adjoint", "so3_inverse",
                      "so3_forward", "so3_inverse_adjoint", "so3_forward_adjoint", "s2_inverse_real",
-                     "s2_forward_real"]:
+                     "s2_forward_real", "s2_inverse_real_adjoint", "s2_forward_real_adjoint"]:
             getattr(lib, name).argtypes = [P, vp, vp, i, vp, vp]
             getattr(lib, name).restype = i
         lib.s2_debug_wigner_d.argtypes = [P, i, vp, vp]
@@ -202,6 +202,17 @@ class Plan:
         [B?, L, 2L-1] complex128 with flm[l][-m] = (-1)^m conj(flm[l][m])."""
         return self._call(self._lib.s2_forward_real, f, self.map_shape, self.coeff_shape, "forward_real", workspace,
                           out, in_dtype=torch.float64)
+
+    def inverse_real_adjoint(self, g, workspace=None, out=None):
+        """Gradient of inverse_real with respect to its complex input for a real map
+        cotangent g float64: 2 A^H g at m > 0, Re (A^H g) at m = 0, 0 at m < 0."""
+        return self._call(self._lib.s2_inverse_real_adjoint, g, self.map_shape, self.coeff_shape,
+                          "inverse_real_adjoint", workspace, out, in_dtype=torch.float64)
+
+    def forward_real_adjoint(self, g_flm, workspace=None, out=None):
+        """Gradient of forward_real with respect to its real map: Re(F^H g_flm), float64."""
+        return self._call(self._lib.s2_forward_real_adjoint, g_flm, self.coeff_shape, self.map_shape,
+                          "forward_real_adjoint", workspace, out, out_dtype=torch.float64)
 
     def inverse_adjoint(self, g, workspace=None, out=None):
         """Hermitian adjoint of the inverse SHT: map-space cotangent -> coefficients."""

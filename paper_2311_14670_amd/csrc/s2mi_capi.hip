@@ -102,6 +102,7 @@ struct s2_plan_s {
     // workspace layout (bytes)
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
     size_t off_fscr = 0, sz_fscr = 0;      // split-Bluestein scratch: FFT_SCRATCH complex per FFT workgroup
+    size_t off_hsym = 0;                   // spin-0 S2 plans: Hermitian part of a coefficient cotangent
     size_t szC = 0, szP = 0, szF = 0, szQ = 0;
     size_t off_Hx = 0, off_Qx = 0, szHx = 0, szQx = 0;
 
@@ -557,6 +558,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         // (nring) and MW filter (L) launches
         P->sz_fscr = split ? (size_t)std::max({P->hstride, P->nring, L}) * FFT_SCRATCH * sizeof(double2) : 0;
         P->off_fscr = o; o += align256(P->sz_fscr);
+        P->off_hsym = o; o += (spin == 0 && !so3) ? align256((size_t)L * (2 * L - 1) * sizeof(double2)) : 0;
         P->ws_bytes = o;
     }
 
@@ -865,7 +867,11 @@ int run_inverse_real(s2_plan_t P, const double2 *flm, double *map, char *ws, hip
     return S2_OK;
 }
 
-int run_forward_real(s2_plan_t P, const double *map, double2 *flm, char *ws, hipStream_t st)
+// vjp: the gradient of run_inverse_real with respect to its complex input for a
+// real map cotangent: 2 A^H g at m > 0 and Re (A^H g) at m = 0 (A the complex
+// inverse), i.e. the unnormalised phi-DFT, no theta filter, the forward-type
+// sweep with the SHT weights, and the finish in its gradient mode.
+int run_forward_real(s2_plan_t P, const double *map, double2 *flm, char *ws, hipStream_t st, bool vjp = false)
 {
     const int L = P->L;
     const bool mw = P->sampling == S2_MW || P->sampling == S2_MWSS;   // theta-torus samplings
@@ -874,20 +880,75 @@ int run_forward_real(s2_plan_t P, const double *map, double2 *flm, char *ws, hip
     double2 *hp0 = (double2 *)(ws + P->off_hpole);
     double2 *hpN0 = ss ? hp0 + (size_t)P->nslice * (2 * L - 1) : nullptr;
     double q;
-    if (mw) q = 2.0 * M_PI / (double)(ss ? 2 * L : 2 * L - 1);
+    if (vjp) q = 1.0;
+    else if (mw) q = 2.0 * M_PI / (double)(ss ? 2 * L : 2 * L - 1);
     else q = 4.0 * M_PI / (double)P->nsamp;               // HEALPix (DH / GL: per-ring weights)
     {
     TIMED(S2_STAGE_PHI_FWD);
     HIPCHK(launch_phi_fwd_real(st, P->fft_threads, P->fft_lds, P->nring, P->hstride, P->npair, L, q, P->ring_pairs,
-                               map, P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, P->ringq, F0,
-                               fft_scratch(P, ws)), "real forward phi-DFT");
+                               map, P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts,
+                               vjp ? nullptr : P->ringq, F0, fft_scratch(P, ws)), "real forward phi-DFT");
     }
     if (mw) {
         TIMED(S2_STAGE_MW_THETA);
-        HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, 0, P->ffts, P->wq, P->ph, F0, hp0,
-                                hpN0, fft_scratch(P, ws), 1), "MW theta filter");
+        if (!vjp) {
+            HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, 0, P->ffts, P->wq, P->ph, F0,
+                                    hp0, hpN0, fft_scratch(P, ws), 1), "MW theta filter");
+        } else {
+            HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F0, hp0), "pole line");
+            if (ss) HIPCHK(launch_pole_from_F(st, L, P->hstride, L, F0, hpN0), "north pole line");
+        }
     }
-    return run_forward_dstage(P, F0, mw ? hp0 : nullptr, hpN0, flm, P->w_sht, ws, st, 1);
+    return run_forward_dstage(P, F0, mw ? hp0 : nullptr, hpN0, flm, P->w_sht, ws, st, vjp ? 2 : 1);
+}
+
+// The adjoint of the forward transform restricted to real maps: Re(F^H G) =
+// F^H h with h the Hermitian part of G, so the real-signal machinery applies:
+// MW / MWSS as the complex adjoint (gather, adjoint theta filter on one side,
+// scatter) ending in the paired real phi-DFT; DH / GL / HEALPix the real
+// inverse with the forward-adjoint weights, then the ring weights (DH / GL).
+int run_forward_real_adjoint(s2_plan_t P, const double2 *G, double *map, char *ws, hipStream_t st)
+{
+    const int L = P->L;
+    const int ss = P->sampling == S2_MWSS;
+    double2 *H = (double2 *)(ws + P->off_hsym);
+    HIPCHK(launch_hermitian_part(st, L, G, H), "Hermitian part");
+    if (P->sampling != S2_MW && P->sampling != S2_MWSS) {
+        int rc = run_inverse_dstage(P, H, P->w_fadj, ws, st, 1);
+        if (rc) return rc;
+        {
+        TIMED(S2_STAGE_PHI_INV);
+        HIPCHK(launch_phi_inv_real(st, P->fft_threads, P->fft_lds, P->npair, L, P->nreg, P->inv_nblk, P->ring_pairs,
+                                   (const double *)(ws + P->off_P), P->mtop, H, P->w_fadj[0], P->ring_nphi,
+                                   P->ring_start, P->ring_shift, P->ring_fft, P->ffts, map, fft_scratch(P, ws)),
+               "real inverse phi-DFT");
+        }
+        if (P->ringq)
+            HIPCHK(launch_ring_scale_real(st, P->nring, P->ring_start, P->ring_nphi, P->ringq, map), "ring weights");
+        return S2_OK;
+    }
+    int rc = run_inverse_dstage(P, H, P->w_sht, ws, st, 1);
+    if (rc) return rc;
+    double *P0 = (double *)(ws + P->off_P);
+    double *F0 = (double *)(ws + P->off_F);
+    double2 *hp0 = (double2 *)(ws + P->off_hpole);
+    double2 *hpN0 = ss ? hp0 + (size_t)P->nslice * (2 * L - 1) : nullptr;
+    double *Q0 = (double *)(ws + P->off_Q);
+    const double q = 2.0 * M_PI / (double)(ss ? 2 * L : 2 * L - 1);
+    {
+    TIMED(S2_STAGE_MW_THETA);
+    // side B of the gathered rows is not produced by the half sweep and is never read
+    HIPCHK(launch_fadj_gather(st, L, ss, P->inv_nblk, 0, P0, P->mtop, H, P->w_sht[0], P->hstride, F0),
+           "adjoint gather");
+    HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, 0, P->ffts, P->wq, P->ph, F0, hp0,
+                            hpN0, fft_scratch(P, ws), 1, 1), "adjoint theta filter");
+    HIPCHK(launch_fadj_scatter(st, L, ss, P->hstride, q, F0, hp0, hpN0, Q0), "adjoint scatter");
+    }
+    TIMED(S2_STAGE_PHI_INV);
+    HIPCHK(launch_phi_inv_real(st, P->fft_threads, P->fft_lds, P->npair, L, P->nring, 1, P->ring_pairs, Q0, P->mtop1,
+                               H, P->w_sht[0], P->ring_nphi, P->ring_start, P->ring_shift, P->ring_fft, P->ffts, map,
+                               fft_scratch(P, ws)), "real adjoint phi-DFT");
+    return S2_OK;
 }
 
 // ---------------------------------------------------------------- matrix-core path
@@ -1206,6 +1267,30 @@ int s2_forward_real(s2_plan_t P, const void *f, void *flm, int batch, void *work
     for (int b = 0; b < batch; ++b)
         if ((rc = run_forward_real(P, (const double *)f + (size_t)b * P->nsamp, (double2 *)flm + b * slab,
                                    (char *)workspace, st))) return rc;
+    return S2_OK;
+}
+
+int s2_inverse_real_adjoint(s2_plan_t P, const void *g, void *g_flm, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_inverse_real_adjoint", P, g, g_flm, batch, workspace);
+    if (rc || (rc = check_real("s2_inverse_real_adjoint", P))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b)
+        if ((rc = run_forward_real(P, (const double *)g + (size_t)b * P->nsamp, (double2 *)g_flm + b * slab,
+                                   (char *)workspace, st, true))) return rc;
+    return S2_OK;
+}
+
+int s2_forward_real_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, void *workspace, void *hip_stream)
+{
+    int rc = check_call("s2_forward_real_adjoint", P, g_flm, g, batch, workspace);
+    if (rc || (rc = check_real("s2_forward_real_adjoint", P))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    for (int b = 0; b < batch; ++b)
+        if ((rc = run_forward_real_adjoint(P, (const double2 *)g_flm + b * slab, (double *)g + (size_t)b * P->nsamp,
+                                           (char *)workspace, st))) return rc;
     return S2_OK;
 }
 

@@ -34,6 +34,9 @@ hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
                             double2 *hpoleN, double2 *fscr, int half = 0, int adj = 0);
 hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *w, double2 *map);
+hipError_t launch_ring_scale_real(hipStream_t st, int nring, const long long *ring_start, const int *ring_nphi,
+                                  const double *w, double *map);
+hipError_t launch_hermitian_part(hipStream_t st, int L, const double2 *G, double2 *out);
 hipError_t launch_finish_fwd(hipStream_t st, int L, int nblk, int spin, int nB, const double *Q, const double *Qx,
                              int nxp, const double *wl, const double2 *hpole, const double2 *hpoleN,
                              double2 *flm, int half = 0);

@@ -1189,7 +1189,10 @@ __global__ void k_fadj_scatter(int L, int ss, int hstride, double q, const doubl
 // Zero where l < max(|m|, |spin|).  One thread per (l, |m|) reads whole 32-byte
 // records (side A = order +|m| in components 0,1, side B = order -|m| in 2,3) and
 // writes both orders.  half (real signals, spin 0): only side A is read, and
-// flm[l][-m] = (-1)^m conj(flm[l][m]) (Hermitian symmetry).
+// half = 1: flm[l][-m] = (-1)^m conj(flm[l][m]) (Hermitian symmetry);
+// half = 2 (gradient of the real-signal inverse with respect to its complex
+// input, whose orders m > 0 enter twice and order 0 through its real part):
+// 2 x side A at m > 0, its real part at m = 0, zero at m < 0.
 __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__restrict__ Q,
                              const double *__restrict__ Qx, int nxp, const double *__restrict__ wl,
                              const double2 *__restrict__ hpole, const double2 *__restrict__ hpoleN,
@@ -1238,7 +1241,12 @@ __global__ void k_finish_fwd(int L, int nblk, int spin, int nB, const double *__
             }
         }
     }
-    if (half) b = (am & 1) ? make_double2(-a.x, a.y) : make_double2(a.x, -a.y);
+    if (half == 1) {
+        b = (am & 1) ? make_double2(-a.x, a.y) : make_double2(a.x, -a.y);
+    } else if (half == 2) {
+        a = am == 0 ? make_double2(a.x, 0.0) : make_double2(2.0 * a.x, 2.0 * a.y);
+        b = make_double2(0.0, 0.0);
+    }
     double2 *row = flm + (size_t)l * M + (L - 1);
     row[am] = a;
     if (am > 0) row[-am] = b;
@@ -1252,6 +1260,42 @@ __global__ void k_ring_scale(int nring, int nphi, const double *__restrict__ w, 
     if (i >= (size_t)nring * nphi) return;
     const double s = w[i / nphi];
     map[i] = make_double2(map[i].x * s, map[i].y * s);
+}
+
+// real maps: map[t][p] *= w[t] over rings given by their start and length
+__global__ void k_ring_scale_real(int nring, const long long *__restrict__ ring_start,
+                                  const int *__restrict__ ring_nphi, const double *__restrict__ w,
+                                  double *__restrict__ map)
+{
+    const int r = blockIdx.x;
+    if (r >= nring) return;
+    double *row = map + ring_start[r];
+    const double s = w[r];
+    for (int k = threadIdx.x; k < ring_nphi[r]; k += blockDim.x) row[k] *= s;
+}
+
+// Hermitian part of a coefficient cotangent: out[l][+-m] from
+// h_m = (G[l][m] + (-1)^m conj G[l][-m]) / 2 (m > 0), h_0 = Re G[l][0], with
+// out[l][-m] = (-1)^m conj h_m.  For a real map x and the forward transform F,
+// Re <G, F x> = <h, F x>: the real-signal adjoint of the forward sees only h.
+__global__ void k_hermitian_part(int L, const double2 *__restrict__ G, double2 *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)L * L) return;
+    const int l = (int)(i / L), am = (int)(i % L);
+    const int M = 2 * L - 1;
+    const double2 *row = G + (size_t)l * M + (L - 1);
+    double2 *orow = out + (size_t)l * M + (L - 1);
+    const double2 a = row[am];
+    if (am == 0) {
+        orow[0] = make_double2(a.x, 0.0);
+        return;
+    }
+    const double2 b = row[-am];
+    const double sg = (am & 1) ? -1.0 : 1.0;
+    const double2 h = make_double2(0.5 * (a.x + sg * b.x), 0.5 * (a.y - sg * b.y));
+    orow[am] = h;
+    orow[-am] = make_double2(sg * h.x, -sg * h.y);
 }
 
 // ------------------------------------------------------------------ SO(3) gamma DFT
@@ -1518,6 +1562,23 @@ hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int
     if ((ss && !hpoleN) || nthreads > 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, ss, hstride, spin, fN, wq, ph, F, hpole,
                        hpoleN, fscr, half, adj);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_ring_scale_real(hipStream_t st, int nring, const long long *ring_start, const int *ring_nphi,
+                                  const double *w, double *map)
+{
+    if (nring < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_ring_scale_real, dim3(nring), dim3(256), 0, st, nring, ring_start, ring_nphi, w, map);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_hermitian_part(hipStream_t st, int L, const double2 *G, double2 *out)
+{
+    const size_t tot = (size_t)L * L;
+    hipLaunchKernelGGL(k_hermitian_part, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, G, out);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -53,7 +53,8 @@ def test_transform_validation_without_plan():
     lib = _lib()
     vp = ctypes.c_void_p
     for fn in ["s2_inverse", "s2_forward", "s2_inverse_adjoint", "s2_forward_adjoint", "so3_inverse", "so3_forward",
-               "so3_inverse_adjoint", "so3_forward_adjoint"]:
+               "so3_inverse_adjoint", "so3_forward_adjoint", "s2_inverse_real", "s2_forward_real",
+               "s2_inverse_real_adjoint", "s2_forward_real_adjoint"]:
         rc = getattr(lib, fn)(None, vp(16), vp(16), 1, vp(256), None)
         assert rc == -1
     assert lib.s2_plan_info(None, None) == -1

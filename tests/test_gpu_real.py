@@ -151,3 +151,76 @@ def test_real_healpix_full_size_sampled(binding, nside, L):
     ref = oracle.s2_forward_real(f, L, oracle.HEALPIX, nside, ms=ms)
     cols = ms + L - 1
     assert rel_l2(a[:, cols], ref[:, cols]) < 1e-11
+
+
+# --------------------------------------------------------------- gradients of the real-signal transforms
+def _dense_real(fn, n):
+    """Matrix of a linear map on real vectors of length n, column by column."""
+    cols = []
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        cols.append(np.asarray(fn(e)).ravel())
+    return np.stack(cols, axis=1)
+
+
+_ALL = [("mw", 7, 0), ("mwss", 6, 0), ("dh", 5, 0), ("gl", 6, 0), ("healpix", 5, 2)]
+
+
+@pytest.mark.parametrize("sampling,L,nside", _ALL)
+def test_inverse_real_gradient_matches_oracle(binding, sampling, L, nside):
+    """d/dRe c + i d/dIm c of <g, inverse_real(c)> for a real map g: 2 A^H g at
+    m > 0, Re (A^H g) at m = 0, 0 at m < 0, with A^H the oracle's adjoint of the
+    complex inverse."""
+    from paper_2311_14670_amd import autograd
+    samp = {"mw": oracle.MW, **_SAMP}[sampling]
+    plan = binding.Plan(L, sampling=sampling, nside=nside)
+    c = _with_junk(flm_gaussian(L, 0, seed=96), L, seed=97)
+    g = np.random.default_rng(98).standard_normal(plan.map_shape)
+    ah = oracle.s2_inverse_adjoint(g.astype(np.complex128), L, 0, samp, nside)
+    ref = np.zeros_like(ah)
+    ref[:, L:] = 2.0 * ah[:, L:]
+    ref[:, L - 1] = ah[:, L - 1].real
+    x = dev(c).requires_grad_(True)
+    loss = torch.sum(autograd.inverse_real(x, plan) * dev(g))
+    loss.backward()
+    got = host(x.grad)
+    assert rel_l2(got, ref) < 1e-12
+    assert np.all(got[:, :L - 1] == 0)
+    # central differences on a quadratic loss (h = 1 is exact up to rounding), orders m >= 0
+    base = oracle.s2_inverse_real(c, L, samp, nside)
+    fd = np.zeros_like(c)
+    for l in range(L):
+        for m in range(0, l + 1):
+            for part in (1.0, 1j):
+                cp, cm = c.copy(), c.copy()
+                cp[l, L - 1 + m] += part
+                cm[l, L - 1 + m] -= part
+                lp = np.sum((oracle.s2_inverse_real(cp, L, samp, nside) - base + g) ** 2)
+                lm = np.sum((oracle.s2_inverse_real(cm, L, samp, nside) - base + g) ** 2)
+                fd[l, L - 1 + m] += (lp - lm) / 2.0 * (1.0 if part == 1.0 else 1j)
+    x2 = dev(c).requires_grad_(True)
+    loss2 = torch.sum((autograd.inverse_real(x2, plan) - dev(base) + dev(g)) ** 2)
+    loss2.backward()
+    assert rel_l2(host(x2.grad), fd) < 1e-9
+
+
+@pytest.mark.parametrize("sampling,L,nside", _ALL)
+def test_forward_real_gradient_matches_dense_oracle(binding, sampling, L, nside):
+    """Re(F^H G) for a complex cotangent G (not Hermitian), with F the oracle's
+    forward of real maps written out as a dense matrix."""
+    from paper_2311_14670_amd import autograd
+    samp = {"mw": oracle.MW, **_SAMP}[sampling]
+    plan = binding.Plan(L, sampling=sampling, nside=nside, max_batch=2)
+    shape = tuple(plan.map_shape)
+    n = int(np.prod(shape))
+    F = _dense_real(lambda e: oracle.s2_forward_real(e.reshape(shape), L, samp, nside), n)
+    G = map_gaussian((2, L, 2 * L - 1), seed=99) * coeff_mask(L, 0)
+    got = host(plan.forward_real_adjoint(dev(G)))
+    for b in range(2):
+        ref = np.real(F.conj().T @ G[b].ravel()).reshape(shape)
+        assert rel_l2(got[b], ref) < 1e-12
+    x = dev(np.random.default_rng(100).standard_normal(shape)).requires_grad_(True)
+    y = autograd.forward_real(x, plan)
+    torch.real(torch.sum(torch.conj(dev(G[0])) * y)).backward()
+    assert rel_l2(host(x.grad), np.real(F.conj().T @ G[0].ravel()).reshape(shape)) < 1e-12

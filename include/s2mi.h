@@ -29,7 +29,9 @@
  *                   l < max(|m|, |n|)); maps [k][t][p] with
  *                   gamma_k = 2 pi k/(2N-1), MW in (beta, alpha) (Sec. 4.5,
  *                   Eqs. 13-18).
- *   batch           the batch dimension is outermost and contiguous.
+ *   batch           the batch dimension is outermost and contiguous; every
+ *                   transform takes 0 <= batch <= max_batch, and batch = 0
+ *                   does nothing (no pointer is read or written).
  *
  * Memory and streams
  *   All data pointers passed to transforms are DEVICE pointers owned by the

@@ -672,12 +672,13 @@ struct StageTimer {
 int check_call(const char *fn, s2_plan_t P, const void *in, const void *out, int batch, void *ws)
 {
     if (!P) return fail(S2_ERR_INVALID_ARG, "%s: plan is NULL", fn);
+    if (batch == 0) return S2_OK;                 // an empty batch: nothing is read or written
     if (!in || !out) return fail(S2_ERR_INVALID_ARG, "%s: NULL data pointer", fn);
     if (!ws) return fail(S2_ERR_INVALID_ARG, "%s: NULL workspace", fn);
     if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(S2_ERR_INVALID_ARG, "%s: data pointers must be 16-byte aligned", fn);
     if ((uintptr_t)ws & 255) return fail(S2_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", fn);
-    if (batch < 1 || batch > P->max_batch)
-        return fail(S2_ERR_INVALID_ARG, "%s: batch=%d outside [1, max_batch=%d]", fn, batch, P->max_batch);
+    if (batch < 0 || batch > P->max_batch)
+        return fail(S2_ERR_INVALID_ARG, "%s: batch=%d outside [0, max_batch=%d]", fn, batch, P->max_batch);
     return S2_OK;
 }
 
@@ -1103,6 +1104,7 @@ int s2_inverse(s2_plan_t P, const void *flm, void *f, int batch, void *workspace
     int rc = check_call("s2_inverse", P, flm, f, batch, workspace);
     if (rc) return rc;
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_inverse: plan was created for SO(3) (N=%d)", P->N);
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     if (P->mfma) return run_inverse_mfma(P, (const double2 *)flm, batch, (double2 *)f, P->w_sht, (char *)workspace, st);
@@ -1118,6 +1120,7 @@ int s2_forward(s2_plan_t P, const void *f, void *flm, int batch, void *workspace
     int rc = check_call("s2_forward", P, f, flm, batch, workspace);
     if (rc) return rc;
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_forward: plan was created for SO(3) (N=%d)", P->N);
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     if (P->mfma)
@@ -1134,6 +1137,7 @@ int s2_inverse_adjoint(s2_plan_t P, const void *g, void *g_flm, int batch, void 
     int rc = check_call("s2_inverse_adjoint", P, g, g_flm, batch, workspace);
     if (rc) return rc;
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_inverse_adjoint: plan was created for SO(3) (N=%d)", P->N);
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     if (P->mfma)
@@ -1151,6 +1155,7 @@ int s2_forward_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, void 
     if (rc) return rc;
     if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_forward_adjoint: plan was created for SO(3) (N=%d)", P->N);
     if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "s2_forward_adjoint: available for FP64 plans");
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     for (int b = 0; b < batch; ++b) {
@@ -1171,6 +1176,7 @@ int so3_inverse(s2_plan_t P, const void *flmn, void *f, int batch, void *workspa
     int rc = check_call("so3_inverse", P, flmn, f, batch, workspace);
     if (rc) return rc;
     if (P->sampling != S2_MW || P->spin != 0) return fail(S2_ERR_INVALID_ARG, "so3_inverse: needs an MW spin-0 plan");
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const int S = P->nslice;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
@@ -1205,6 +1211,7 @@ int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspa
     int rc = check_call("so3_forward", P, f, flmn, batch, workspace);
     if (rc) return rc;
     if (P->sampling != S2_MW || P->spin != 0) return fail(S2_ERR_INVALID_ARG, "so3_forward: needs an MW spin-0 plan");
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const int S = P->nslice;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
@@ -1250,6 +1257,7 @@ int s2_inverse_real(s2_plan_t P, const void *flm, void *f, int batch, void *work
 {
     int rc = check_call("s2_inverse_real", P, flm, f, batch, workspace);
     if (rc || (rc = check_real("s2_inverse_real", P))) return rc;
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     for (int b = 0; b < batch; ++b)
@@ -1262,6 +1270,7 @@ int s2_forward_real(s2_plan_t P, const void *f, void *flm, int batch, void *work
 {
     int rc = check_call("s2_forward_real", P, f, flm, batch, workspace);
     if (rc || (rc = check_real("s2_forward_real", P))) return rc;
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     for (int b = 0; b < batch; ++b)
@@ -1274,6 +1283,7 @@ int s2_inverse_real_adjoint(s2_plan_t P, const void *g, void *g_flm, int batch, 
 {
     int rc = check_call("s2_inverse_real_adjoint", P, g, g_flm, batch, workspace);
     if (rc || (rc = check_real("s2_inverse_real_adjoint", P))) return rc;
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     for (int b = 0; b < batch; ++b)
@@ -1286,6 +1296,7 @@ int s2_forward_real_adjoint(s2_plan_t P, const void *g_flm, void *g, int batch, 
 {
     int rc = check_call("s2_forward_real_adjoint", P, g_flm, g, batch, workspace);
     if (rc || (rc = check_real("s2_forward_real_adjoint", P))) return rc;
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
     for (int b = 0; b < batch; ++b)
@@ -1300,6 +1311,7 @@ int so3_inverse_adjoint(s2_plan_t P, const void *g, void *g_flmn, int batch, voi
     if (rc) return rc;
     if (P->sampling != S2_MW || P->spin != 0)
         return fail(S2_ERR_INVALID_ARG, "so3_inverse_adjoint: needs an MW spin-0 plan");
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const int S = P->nslice;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);
@@ -1343,6 +1355,7 @@ int so3_forward_adjoint(s2_plan_t P, const void *g_flmn, void *g, int batch, voi
     if (P->sampling != S2_MW || P->spin != 0)
         return fail(S2_ERR_INVALID_ARG, "so3_forward_adjoint: needs an MW spin-0 plan");
     if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "so3_forward_adjoint: available for FP64 plans");
+    if (batch == 0) return S2_OK;
     hipStream_t st = (hipStream_t)hip_stream;
     const int S = P->nslice;
     const size_t slab = (size_t)P->L * (2 * P->L - 1);

@@ -168,3 +168,29 @@ def test_healpix_full_size_sampled(binding, nside, L):
     ref = oracle.s2_forward(f, L, spin, oracle.HEALPIX, nside, ms=ms)
     cols = ms + L - 1
     assert rel_l2(a[:, cols], ref[:, cols]) < 1e-11
+
+
+def test_empty_batch_is_a_no_op(binding):
+    plan = binding.Plan(16, max_batch=4)
+    x = torch.zeros((0, 16, 31), dtype=torch.complex128, device="cuda")
+    for fn in (plan.inverse, plan.forward, plan.inverse_adjoint, plan.forward_adjoint):
+        y = fn(x)
+        assert y.shape == (0, 16, 31)
+    assert plan.inverse_real(x).shape == (0, 16, 31)
+    assert plan.forward_real(torch.zeros((0, 16, 31), dtype=torch.float64, device="cuda")).shape == (0, 16, 31)
+    so3 = binding.Plan(8, N=2)
+    assert so3.so3_inverse(torch.zeros((0, 3, 8, 15), dtype=torch.complex128, device="cuda")).shape == (0, 3, 8, 15)
+
+
+@pytest.mark.parametrize("nside,L", [(1, 2), (1, 4), (2, 3)])
+def test_smallest_healpix(binding, nside, L):
+    """nside 1: 12 pixels on 3 rings (4 pixels each); band-limits above what the
+    grid resolves are still computed as defined (the quadrature of Eq. 19)."""
+    for spin in range(-(L - 1), L):
+        flm = flm_gaussian(L, spin, seed=19)
+        plan = binding.Plan(L, spin=spin, sampling="healpix", nside=nside)
+        f = host(plan.inverse(dev(flm)))
+        assert rel_l2(f, oracle.s2_inverse(flm, L, spin, oracle.HEALPIX, nside)) < 1e-12, spin
+        g = map_gaussian(12 * nside * nside, seed=20)
+        a = host(plan.forward(dev(g)))
+        assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < 1e-12, spin

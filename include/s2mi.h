@@ -104,6 +104,12 @@ typedef struct {
     long long ncoeffs;          /* L * (2L-1) per (map, n-slice): dense layout size  */
     size_t workspace_bytes;     /* device workspace one call needs at max_batch      */
     size_t plan_device_bytes;   /* device memory held by the plan                    */
+    int swept_rings;            /* rings the inverse sweep's lanes run: nrings without
+                                   the poles, or (spin 0, N/S-symmetric samplings,
+                                   when that still fills the device; environment
+                                   S2MI_RING_PAIRING=0/1 forces off/on) the northern
+                                   half, mirror rings following from
+                                   d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta) */
 } s2_plan_info_t;
 
 /*

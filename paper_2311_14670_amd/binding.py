@@ -42,7 +42,8 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("spin", ctypes.c_int), ("N", ctypes.c_int), ("nside", ctypes.c_int),
                 ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("nrings", ctypes.c_int), ("nsamples", ctypes.c_longlong), ("ncoeffs", ctypes.c_longlong),
-                ("workspace_bytes", ctypes.c_size_t), ("plan_device_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("plan_device_bytes", ctypes.c_size_t),
+                ("swept_rings", ctypes.c_int)]
 
 
 _lib = None

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <deque>
 #include <map>
 #include <new>
@@ -60,6 +61,8 @@ struct s2_plan_s {
     int nslice = 1;                       // 1 for S2, 2N-1 for SO(3)
     std::vector<int> slice_spin;          // spin of each slice (SO(3) slice k: n = k-(N-1), spin -n)
     int nring = 0, nreg = 0;              // rings of the sampling; rings the d-stage sweeps
+    int nsw = 0;                          // rings the inverse sweep's lanes run (nreg, or the northern
+                                          // half when mirror rings come from the symmetry)
     long long nsamp = 0;                  // samples per slice map
     std::vector<Run> runs;
 
@@ -291,6 +294,7 @@ int s2_plan_info(s2_plan_t P, s2_plan_info_t *info)
     info->ncoeffs = (long long)P->L * (2 * P->L - 1);
     info->workspace_bytes = P->ws_bytes;
     info->plan_device_bytes = P->plan_bytes;
+    info->swept_rings = P->nsw;
     return S2_OK;
 }
 
@@ -485,13 +489,31 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         }
     }
 
-    // inverse d-stage assignment: waves of INV_NCH 8-degree chunks, W a multiple of 4
+    // inverse d-stage assignment: waves of INV_NCH 8-degree chunks, W a multiple of 4.
+    // Spin-0 plans of the N/S-symmetric samplings sweep only the northern rings and
+    // produce each mirror ring from d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta),
+    // when the halved grid still has a workgroup for every compute unit (splitting the
+    // l-range over more blocks instead does not pay: the per-order reduction dominates
+    // sparsely filled waves).
     {
         const int nch = (L + 7) / 8;
         const int per_blk = DSTAGE_MAX_WAVES * INV_NCH;
         P->inv_nblk = (nch + per_blk - 1) / per_blk;
         const int wneed = (nch + INV_NCH * P->inv_nblk - 1) / (INV_NCH * P->inv_nblk);
         P->inv_waves = std::min(DSTAGE_MAX_WAVES, std::max(4, (wneed + 3) / 4 * 4));
+        // S2MI_RING_PAIRING=0 / 1 turns the mirror-ring sweep off / on wherever it applies
+        // (tests, tuning); unset, the plan decides from the grid size.
+        P->nsw = P->nreg;
+        const bool sym = sampling == S2_DH || sampling == S2_GL || sampling == S2_MWSS || sampling == S2_HEALPIX;
+        const char *pm = std::getenv("S2MI_RING_PAIRING");
+        const int mode = pm && pm[0] == '0' ? 0 : pm && pm[0] == '1' ? 1 : -1;
+        if (sym && spin == 0 && !so3 && prec == S2_FP64 && mode != 0) {
+            int dev = 0, ncu = 0;
+            HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+            HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+            const int half_rings = (P->nreg + 1) / 2;
+            if (mode == 1 || (half_rings + 63) / 64 * P->inv_nblk >= ncu) P->nsw = half_rings;
+        }
         stg.i.emplace_back(); std::vector<int> &lch = stg.i.back();
         stg.i.emplace_back(); std::vector<int> &ls = stg.i.back();
         stg.i.emplace_back(); std::vector<int> &mt = stg.i.back();
@@ -713,7 +735,7 @@ int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double
         HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nx, P->nreg, r.n, P->cot, P->csc, P->init[ri], C,
                                  P->lchunk, P->mtop,
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
-                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr, half), "inverse d-stage");
+                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr, half, P->nsw), "inverse d-stage");
     }
     return S2_OK;
 }

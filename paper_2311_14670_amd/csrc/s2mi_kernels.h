@@ -12,7 +12,7 @@ hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int s
                            const double *kap, const double *gtab, double *C, int half = 0);
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
-                             const int *mtop, double *partA, double *partB, int half = 0);
+                             const int *mtop, double *partA, double *partB, int half = 0, int nsw = 0);
 hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const double *lsin, const double *lcos,
                              const double *lbin, double2 *init);
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,

@@ -211,15 +211,18 @@ __device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[
 // contribution times the records.  SLOW: the contribution is e 2^E (exact
 // scaling, zero once below the double range) and slot jin may start here
 // (l == m) from its start value; otherwise the chunk is realised (E = 0).
-// HALF (real signals): records of RS = 3 doubles, A side only.
-template <int PAR, bool SLOW, bool HALF = false>
+// HALF (real signals): records of RS = 3 doubles, A side only.  ac[0..3] are
+// the sums {Re A, Im A, Re B, Im B}; PAIR: ac[0..3] over the even and ac[4..7]
+// over the odd degrees (slot j of a chunk holds l = base + SG-1-j, base a
+// multiple of SG, so l is odd exactly when j is even).
+template <int PAR, bool SLOW, bool HALF = false, bool PAIR = false>
 __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ rec,
-                                          double lam, int jin, double e0, int E0, double &aAr, double &aAi,
-                                          double &aBr, double &aBi)
+                                          double lam, int jin, double e0, int E0, double (&ac)[PAIR ? 8 : 4])
 {
     constexpr int RS = HALF ? 3 : 5;
 #pragma unroll
     for (int j = 0; j < SG; ++j) {
+        const int o = (PAIR && (j & 1) == 0) ? 4 : 0;
         double &nw = PAR == 0 ? Y[j] : X[j];              // receives order m
         double &od = PAR == 0 ? X[j] : Y[j];              // holds order m+1
         const double *c = rec + j * RS;
@@ -233,18 +236,22 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
             }
             t = ldexp(nw, E[j]);
         }
-        aAr = fma(t, c[1], aAr);
-        aAi = fma(t, c[2], aAi);
+        ac[o + 0] = fma(t, c[1], ac[o + 0]);
+        ac[o + 1] = fma(t, c[2], ac[o + 1]);
         if constexpr (!HALF) {
-            aBr = fma(t, c[3], aBr);
-            aBi = fma(t, c[4], aBi);
+            ac[o + 2] = fma(t, c[3], ac[o + 2]);
+            ac[o + 3] = fma(t, c[4], ac[o + 3]);
         }
     }
 }
 
-template <int NCH, int PAR, bool HALF = false>
+// PAIR (spin 0, N/S-symmetric sampling): the lanes sweep the northern rings
+// (nsw of nreg) and also produce the mirror ring nreg-1-r, using
+// d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta): with E and O the sums
+// over the even and odd degrees, ring r gets E + O and its mirror (-1)^m (E - O).
+template <int NCH, int PAR, bool HALF = false, bool PAIR = false>
 __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ms, int ring0, int nreg,
-                                         int lane,
+                                         int nsw, int lane,
                                          int w, int W,
                                          const int (&lb)[NCH], double (&X)[NCH][SG], double (&Y)[NCH][SG],
                                          int (&E)[NCH][SG], uint32_t &fast, double ct, double ncs,
@@ -252,8 +259,11 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
                                          int blk, double *__restrict__ partA, double *__restrict__ partB)
 {
     constexpr int RS = HALF ? 3 : 5;
+    constexpr int NA = PAIR ? 8 : 4;                     // sums per lane
     const double lam = fma(-(double)(m + 1), ct, ncs);   // lambda_{m+1}: produces order m
-    double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
+    double ac[NA];
+#pragma unroll
+    for (int c = 0; c < NA; ++c) ac[c] = 0.0;
     const double *Cw = C + (((size_t)blk * (L + nx) + (m + nx)) * W + w) * (NCH * SG) * RS;   // records at order m
 
 #pragma unroll
@@ -264,13 +274,12 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
         if (m >= base) {                                  // ramp: slot jin starts at this order
             const int jin = base + SG - 1 - m;
             const double2 iv = initr[m];                 // d^m_{m,n}(theta_ring), zero if m < |n|
-            inv_chunk<PAR, true, HALF>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, aAr, aAi, aBr,
-                                       aBi);
+            inv_chunk<PAR, true, HALF, PAIR>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, ac);
             fast &= ~(1u << g);
         } else if ((fast >> g) & 1u) {
-            inv_chunk<PAR, false, HALF>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
+            inv_chunk<PAR, false, HALF, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
         } else {
-            inv_chunk<PAR, true, HALF>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, aAr, aAi, aBr, aBi);
+            inv_chunk<PAR, true, HALF, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
         }
     }
     // renormalisation pass every RN orders over the started chunks not yet realised
@@ -288,21 +297,28 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
             if (__all(z)) fast |= (1u << g);
         }
     }
-    double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * 4 * 64;
-    rb[(w * 4 + 0) * 64 + lane] = aAr;
-    rb[(w * 4 + 1) * 64 + lane] = aAi;
-    if (!HALF) {
-        rb[(w * 4 + 2) * 64 + lane] = aBr;
-        rb[(w * 4 + 3) * 64 + lane] = aBi;
-    }
+    double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * NA * 64;
+#pragma unroll
+    for (int c = 0; c < NA; ++c)
+        if (!HALF || (c & 3) < 2) rb[(w * NA + c) * 64 + lane] = ac[c];
     __syncthreads();
     // four waves, rotating with the order, reduce the 4 x 64 outputs over the waves
     // (only the A side's 2 x 64 for real signals)
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
     if (tr >= 0 && tr < (HALF ? 128 : 256)) {
         const int rl = tr & 63, comp = tr >> 6;         // rl == lane: this thread's ring
-        double s = 0.0;                                 // a plain loop: fewer scalar registers than wave_sum
-        for (int ww = 0; ww < W; ++ww) s += rb[(ww * 4 + comp) * 64 + rl];
+        double s = 0.0, s2 = 0.0;                       // a plain loop: fewer scalar registers than wave_sum
+        if (PAIR) {
+            double se = 0.0, so = 0.0;
+            for (int ww = 0; ww < W; ++ww) {
+                se += rb[(ww * NA + comp) * 64 + rl];
+                so += rb[(ww * NA + 4 + comp) * 64 + rl];
+            }
+            s = se + so;                                // ring ring0 + rl
+            s2 = (m & 1) ? so - se : se - so;           // its mirror
+        } else {
+            for (int ww = 0; ww < W; ++ww) s += rb[(ww * NA + comp) * 64 + rl];
+        }
         // Orders below the ring's switch order ms come from the run that is stable
         // there (n cos(theta) < 0): it writes its own sides at m >= 0 and, from its
         // continuation to m > -ms, the A slice at order m < 0 (components 2,3 at |m|)
@@ -318,24 +334,28 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
             if (m > 0 && (good || m >= ms)) dst = partB;                       // B slice at order -m
             else if (ext_ok) { dst = partB; mo = -m; co = comp - 2; }          // B slice at order -m >= 0
         }
-        if (dst && ring0 + rl < nreg) dst[(((size_t)blk * nreg + ring0 + rl) * L + mo) * 4 + co] = s;
+        const int rr = ring0 + rl;
+        if (dst && rr < nsw) {
+            dst[(((size_t)blk * nreg + rr) * L + mo) * 4 + co] = s;
+            if (PAIR && nreg - 1 - rr != rr) dst[(((size_t)blk * nreg + (nreg - 1 - rr)) * L + mo) * 4 + co] = s2;
+        }
     }
 }
 
-template <int NCH, int WT, bool HALF = false>
+template <int NCH, int WT, bool HALF = false, bool PAIR = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
-    int L, int nx, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
+    int L, int nx, int nreg, int nsw, int n, const double *__restrict__ cot, const double *__restrict__ csc,
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
     const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
 {
-    __shared__ double red[2 * DSTAGE_MAX_WAVES * 4 * 64];
+    __shared__ double red[2 * DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64];
     const int an = n < 0 ? -n : n;
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
     constexpr int W = WT;                                // waves per workgroup (== blockDim.x / 64)
     const int blk = blockIdx.y;
     const int ring0 = blockIdx.x * 64;
-    const int ring = min(ring0 + lane, nreg - 1);
+    const int ring = min(ring0 + lane, nsw - 1);        // swept rings 0 .. nsw-1 (nsw == nreg unless PAIR)
     const double ct = cot[ring], cs = csc[ring];
     const double ncs = (double)n * cs;
     const bool good = ring_good(n, ct);                 // this run is the stable one at this ring
@@ -370,11 +390,11 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
                                                                   (NCH * SG) * RS);
             pf = Cp[(lane % (ROWB / 128)) * 32];
         }
-        inv_step<NCH, 0, HALF>(m, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs, initr,
-                               C, red, blk, partA, partB);
+        inv_step<NCH, 0, HALF, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
+                                     ncs, initr, C, red, blk, partA, partB);
         if (m - 1 >= mend)
-            inv_step<NCH, 1, HALF>(m - 1, L, nx, n, an, good, ms, ring0, nreg, lane, w, W, lb, X, Y, E, fast, ct, ncs,
-                                   initr, C, red, blk, partA, partB);
+            inv_step<NCH, 1, HALF, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
+                                         ct, ncs, initr, C, red, blk, partA, partB);
     }
     asm volatile("" ::"v"(pf));
 }
@@ -712,13 +732,15 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
             if (am > 0) buf[nphi - am] = vb;
         }
     } else if (r < nreg) {
+        // Bin k sums the orders m = k + q nphi within [-(L-1), L-1].  A short ring (nphi
+        // below the thread count, HEALPix caps) spreads each bin's orders over `per`
+        // threads, j-th taking every per-th order, and adds their sums in a fixed order.
         const double *pr = part + (size_t)r * L * 4;
         const size_t bstride = (size_t)nreg * L * 4;
-        for (int k = tid; k < nphi; k += T) {
+        const int per = nphi >= T ? 1 : T / nphi;
+        auto bin_sum = [&](int k, int j) {
             double2 acc = make_double2(0.0, 0.0);
-            // orders m = k + q nphi within [-(L-1), L-1]
-            int m = k - ((k + L - 1) / nphi) * nphi;
-            for (; m <= L - 1; m += nphi) {
+            for (int m = k - ((k + L - 1) / nphi) * nphi + j * nphi; m <= L - 1; m += per * nphi) {
                 const int am = m < 0 ? -m : m;
                 const int off = am * 4 + (m < 0 ? 2 : 0);
                 double2 v = make_double2(0.0, 0.0);
@@ -735,7 +757,18 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
                 }
                 acc = cadd(acc, v);
             }
-            buf[k] = acc;
+            return acc;
+        };
+        if (per == 1) {
+            for (int k = tid; k < nphi; k += T) buf[k] = bin_sum(k, 0);
+        } else {                                               // uniform over the workgroup
+            if (tid < per * nphi) red[tid] = bin_sum(tid % nphi, tid / nphi);
+            __syncthreads();
+            for (int k = tid; k < nphi; k += T) {
+                double2 acc = red[k];
+                for (int j = 1; j < per; ++j) acc = cadd(acc, red[k + j * nphi]);
+                buf[k] = acc;
+            }
         }
     } else {
         // south pole (ring nreg): only m = s contributes, value sum_l (-1)^{l+s} w_l flm[l][s];
@@ -883,9 +916,12 @@ __global__ __launch_bounds__(1024) void k_phi_inv_real(
             if (am > 0) buf[M - am] = make_double2(x1.x + x2.y, x2.x - x1.y);     // conj X1 + i conj X2
         }
     } else {
-        for (int k = tid; k < nphi; k += T) {
+        // bins sum the orders = k mod nphi; short rings spread a bin over `per` threads
+        // (fixed-order combination, as in the complex inverse)
+        const int per = nphi >= T ? 1 : T / nphi;
+        auto bin_sum = [&](int k, int j) {
             double2 z = make_double2(0.0, 0.0);
-            for (int m = k - ((k + L - 1) / nphi) * nphi; m <= L - 1; m += nphi) {   // orders = k mod nphi
+            for (int m = k - ((k + L - 1) / nphi) * nphi + j * nphi; m <= L - 1; m += per * nphi) {
                 const int am = m < 0 ? -m : m;
                 double2 x1 = spec(r1, am), x2 = spec(r2, am);
                 if (m < 0) { x1 = cconj(x1); x2 = cconj(x2); }
@@ -898,7 +934,19 @@ __global__ __launch_bounds__(1024) void k_phi_inv_real(
                 z.x += x1.x - x2.y;
                 z.y += x1.y + x2.x;
             }
-            buf[k] = z;
+            return z;
+        };
+        if (per == 1) {
+            for (int k = tid; k < nphi; k += T) buf[k] = bin_sum(k, 0);
+        } else {
+            __syncthreads();                                   // red may still hold the pole sums
+            if (tid < per * nphi) red[tid] = bin_sum(tid % nphi, tid / nphi);
+            __syncthreads();
+            for (int k = tid; k < nphi; k += T) {
+                double2 z = red[k];
+                for (int j = 1; j < per; ++j) z = cadd(z, red[k + j * nphi]);
+                buf[k] = z;
+            }
         }
     }
     __syncthreads();
@@ -1444,18 +1492,26 @@ hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int s
 
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
-                             const int *mtop, double *partA, double *partB, int half)
+                             const int *mtop, double *partA, double *partB, int half, int nsw)
 {
     if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
     if (half && n != 0) return hipErrorInvalidValue;                // real signals: spin 0 only
-    dim3 grid((nreg + 63) / 64, nblk);
-    // wave count and the real-signal half as template arguments
+    if (nsw <= 0) nsw = nreg;
+    const bool pair = nsw < nreg;                                   // mirror rings from the northern sweep
+    if (nsw > nreg || (pair && (n != 0 || 2 * nsw < nreg))) return hipErrorInvalidValue;
+    dim3 grid((nsw + 63) / 64, nblk);
+    // wave count, the real-signal half and the ring pairing as template arguments
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, L, nx, nreg, n, cot, csc, init, C, lchunk, mtop,
+        hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, L, nx, nreg, nsw, n, cot, csc, init, C, lchunk, mtop,
                            partA, partB);
     };
-    if (nwaves == 8) half ? go(k_dstage_inv<INV_NCH, 8, true>) : go(k_dstage_inv<INV_NCH, 8, false>);
-    else half ? go(k_dstage_inv<INV_NCH, 4, true>) : go(k_dstage_inv<INV_NCH, 4, false>);
+    if (nwaves == 8) {
+        if (pair) half ? go(k_dstage_inv<INV_NCH, 8, true, true>) : go(k_dstage_inv<INV_NCH, 8, false, true>);
+        else half ? go(k_dstage_inv<INV_NCH, 8, true>) : go(k_dstage_inv<INV_NCH, 8, false>);
+    } else {
+        if (pair) half ? go(k_dstage_inv<INV_NCH, 4, true, true>) : go(k_dstage_inv<INV_NCH, 4, false, true>);
+        else half ? go(k_dstage_inv<INV_NCH, 4, true>) : go(k_dstage_inv<INV_NCH, 4, false>);
+    }
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

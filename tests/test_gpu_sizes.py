@@ -194,3 +194,31 @@ def test_smallest_healpix(binding, nside, L):
         g = map_gaussian(12 * nside * nside, seed=20)
         a = host(plan.forward(dev(g)))
         assert rel_l2(a, oracle.s2_forward(g, L, spin, oracle.HEALPIX, nside)) < 1e-12, spin
+
+
+# --------------------------------------------------------------- mirror-ring sweep (spin 0, symmetric grids)
+# forced on at sizes of a few tiles: odd ring counts put the equator in a pair of
+# its own, ragged last tiles, and every path that runs the inverse sweep
+@pytest.mark.parametrize("sampling,L,nside", [("dh", 70, 0), ("gl", 131, 0), ("gl", 64, 0), ("mwss", 130, 0),
+                                              ("mwss", 65, 0), ("healpix", 100, 48)])
+def test_mirror_ring_sweep(binding, monkeypatch, sampling, L, nside):
+    samp = {"dh": oracle.DH, "gl": oracle.GL, "mwss": oracle.MWSS, "healpix": oracle.HEALPIX}[sampling]
+    monkeypatch.setenv("S2MI_RING_PAIRING", "1")
+    plan = binding.Plan(L, sampling=sampling, nside=nside, max_batch=2)
+    nreg = plan.info["nrings"] - (2 if sampling == "mwss" else 0)
+    assert plan.info["swept_rings"] == (nreg + 1) // 2
+    flm = flm_gaussian(L, 0, seed=21, batch=2, scale="inv1pl")
+    f = host(plan.inverse(dev(flm)))
+    for b in range(2):
+        assert rel_l2(f[b].ravel(), oracle.s2_inverse(flm[b], L, 0, samp, nside).ravel()) < 1e-12
+    fr = host(plan.inverse_real(dev(flm[0])))
+    assert rel_l2(fr.ravel(), oracle.s2_inverse_real(flm[0], L, samp, nside).ravel()) < 1e-12
+    if sampling != "mwss":                          # forward adjoint = inverse with the quadrature weights
+        g = flm_gaussian(L, 0, seed=22)
+        lhs = np.vdot(g, oracle.s2_forward(map_gaussian(plan.map_shape, seed=23), L, 0, samp, nside))
+        rhs = np.vdot(host(plan.forward_adjoint(dev(g))), map_gaussian(plan.map_shape, seed=23))
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    monkeypatch.setenv("S2MI_RING_PAIRING", "0")
+    ref_plan = binding.Plan(L, sampling=sampling, nside=nside, max_batch=2)
+    assert ref_plan.info["swept_rings"] == nreg
+    assert rel_l2(f, host(ref_plan.inverse(dev(flm)))) < 1e-13

@@ -101,6 +101,10 @@ struct s2_plan_s {
     int inv_nblk = 1, inv_waves = 4;
     int *lslot = nullptr, *lchunk = nullptr, *mtop = nullptr;
     int fwd_nblk = 1, fwd_waves = 4, G = 1;
+    // forward sweep over the northern rings (spin 0, symmetric samplings: nsw < nreg)
+    bool fwd_pair = false;
+    int fwdp_nblk = 1, fwdp_waves = 4, Gp = 1, pstride = 0;
+    size_t off_Fp = 0;                    // workspace: sums and differences of mirror-ring spectra
     int hstride = 0;                       // ring stride of the forward spectra (padded to the sweep's slots)
     // workspace layout (bytes)
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
@@ -537,6 +541,22 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->fwd_nblk = nb;
         P->fwd_waves = W;
         P->hstride = std::max(nb * W * FWD_R, P->nring);
+        // the mirror-ring form sweeps nsw rings with groups of 64 degrees of one parity
+        // (Gp groups), on the same rule
+        if (P->nsw < P->nreg) {
+            P->fwd_pair = true;
+            P->Gp = 2 * ((L + 127) / 128);
+            const int pp = (P->Gp + 1) / 2;
+            int nbp = std::max(1, std::min(256 / pp, (P->nsw + 4 * FWD_R - 1) / (4 * FWD_R)));
+            int Wp = (P->nsw + nbp * FWD_R - 1) / (nbp * FWD_R);
+            while (Wp > FWD_MAX_WAVES) { ++nbp; Wp = (P->nsw + nbp * FWD_R - 1) / (nbp * FWD_R); }
+            Wp = Wp <= 4 ? 4 : Wp <= 8 ? 8 : 16;
+            if (Wp > FWD_MAX_WAVES) Wp = FWD_MAX_WAVES;
+            P->fwdp_nblk = nbp;
+            P->fwdp_waves = Wp;
+            P->pstride = nbp * Wp * FWD_R;
+            P->hstride = std::max(P->hstride, P->pstride);  // the lambda table's columns cover every slot
+        }
     }
 
     for (size_t ri = 0; ri < P->runs.size(); ++ri) {
@@ -561,7 +581,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         // forward partials [blk][l][m][4]; the adjoint of the MW / MWSS forward reuses the
         // buffer for ring partials [nring][m][4] (nring = L + 1 for MWSS)
         const int adj_rows = (sampling == S2_MW || sampling == S2_MWSS) ? P->nring : 0;
-        P->szQ = (size_t)std::max(P->fwd_nblk * L, adj_rows) * L * 4 * sizeof(double);
+        P->szQ = (size_t)std::max({P->fwd_nblk * L, P->fwdp_nblk * L, adj_rows}) * L * 4 * sizeof(double);
         size_t o = 0;
         P->off_C = o; o += align256(P->szC * P->runs.size());
         P->off_P = o; o += align256(P->szP * S);
@@ -581,6 +601,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->sz_fscr = split ? (size_t)std::max({P->hstride, P->nring, L}) * FFT_SCRATCH * sizeof(double2) : 0;
         P->off_fscr = o; o += align256(P->sz_fscr);
         P->off_hsym = o; o += (spin == 0 && !so3) ? align256((size_t)L * (2 * L - 1) * sizeof(double2)) : 0;
+        P->off_Fp = o; o += P->fwd_pair ? align256(2 * (size_t)L * P->pstride * 4 * sizeof(double)) : 0;
         P->ws_bytes = o;
     }
 
@@ -810,7 +831,18 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const dou
     double *Hx0 = P->nxp > 0 ? (double *)(ws + P->off_Hx) : nullptr;
     double *Qx0 = P->nxp > 0 ? (double *)(ws + P->off_Qx) : nullptr;
     if (Qx0) HIPCHK(launch_zero(st, Qx0, P->szQx * P->nslice), "continuation sums clear");
-    for (size_t ri = 0; ri < P->runs.size(); ++ri) {
+    if (P->fwd_pair) {
+        // spin-0 S2 plan (one slice, run n = 0): sweep the northern rings on the sums and
+        // differences of each ring's and its mirror's spectra
+        double *S = (double *)(ws + P->off_Fp);
+        double *D = S + (size_t)L * P->pstride * 4;
+        TIMED(S2_STAGE_DSTAGE_FWD);
+        HIPCHK(launch_pair_spectra(st, L, P->nreg, P->nsw, P->hstride, P->pstride, H0, S, D), "mirror spectra");
+        HIPCHK(launch_dstage_fwd(st, P->fwdp_waves, P->fwdp_nblk, P->Gp, L, 1, P->nsw, P->pstride, P->hstride, 0,
+                                 P->lam[0], P->init[0], P->kap, P->gtab, S, D, nullptr, nullptr, Q0, Q0, nullptr,
+                                 nullptr, half, 1), "forward d-stage");
+    }
+    for (size_t ri = 0; ri < P->runs.size() && !P->fwd_pair; ++ri) {
         const Run &r = P->runs[ri];
         const int an = r.n < 0 ? -r.n : r.n;
         const double *HA = r.sliceA >= 0 ? H0 + r.sliceA * nF : H0 + r.sliceB * nF;
@@ -831,7 +863,8 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const dou
     for (int k = 0; k < P->nslice; ++k) {
         const int s = P->slice_spin[k];
         TIMED(S2_STAGE_FINISH);
-        HIPCHK(launch_finish_fwd(st, L, P->fwd_nblk, s, s, Q0 + k * nQ, Qx0 ? Qx0 + k * nQx : nullptr,
+        HIPCHK(launch_finish_fwd(st, L, P->fwd_pair ? P->fwdp_nblk : P->fwd_nblk, s, s, Q0 + k * nQ,
+                                 Qx0 ? Qx0 + k * nQx : nullptr,
                                  std::max(P->nxp, 1), wl[k], hpole0 ? hpole0 + k * (2 * L - 1) : nullptr,
                                  hpoleN0 ? hpoleN0 + k * (2 * L - 1) : nullptr, flm + k * slab, half),
                "forward finish");

@@ -18,7 +18,10 @@ hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const doubl
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
                              int lstride, int n, const double *lam, const double2 *init, const double *kap,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
-                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int half = 0);
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int half = 0,
+                             int pair = 0);
+hipError_t launch_pair_spectra(hipStream_t st, int L, int nreg, int nsw, int hstride, int pstride, const double *H,
+                               double *S, double *D);
 hipError_t launch_lambda_table(hipStream_t st, int L, int nx, int nreg, int lstride, int n, const double *cot,
                                const double *csc, double *lam);
 hipError_t launch_phi_inv(hipStream_t st, int nthreads, size_t lds, int nring, int L, int nreg, int nblk, int spin,

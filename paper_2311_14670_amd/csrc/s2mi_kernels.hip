@@ -452,7 +452,13 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
 // main loop since no degree starts there: no scaling and no renormalisation.
 // HALF (run n = 0 of a real signal): only the A side (order +m) is accumulated,
 // the order -m being its conjugate.
-template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false, bool REAL = false, bool HALF = false>
+// PAIRF (run n = 0, N/S-symmetric sampling): the slots are the northern rings,
+// the lanes of group g hold degrees of one parity (l = 128 (g/2) + 2 lane + g%2),
+// and by d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta) a slot contributes
+// d (H(ring) + (-1)^{l+m} H(mirror)): HA holds the sums and HB the differences of
+// the two rings' spectra, and l + m has one parity across the wave at each order.
+template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false, bool REAL = false, bool HALF = false,
+          bool PAIRF = false>
 __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
                                          int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
                                          double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk, double &gm,
@@ -481,8 +487,14 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     // the B slice at order -m >= 0 (components 0,1).
     const int am = MAIN ? m : (m < 0 ? -m : m);
     const bool low = !MAIN && m < an;
-    const double *HAm = (low ? HxA : HA) + ((size_t)am * hstride + rbase) * 4 + (!MAIN && m < 0 ? 2 : 0);
-    const double *HBm = SAME ? HAm + 2 : (low ? HxB : HB) + ((size_t)am * hstride + rbase) * 4 + (m > 0 ? 2 : 0);
+    const double *HAm, *HBm;
+    if constexpr (PAIRF) {
+        HAm = (((m + g) & 1) ? HB : HA) + ((size_t)am * hstride + rbase) * 4;
+        HBm = HAm + 2;
+    } else {
+        HAm = (low ? HxA : HA) + ((size_t)am * hstride + rbase) * 4 + (!MAIN && m < 0 ? 2 : 0);
+        HBm = SAME ? HAm + 2 : (low ? HxB : HB) + ((size_t)am * hstride + rbase) * 4 + (m > 0 ? 2 : 0);
+    }
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const double *Lc = Lm + c * SG;
@@ -514,7 +526,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
     if (tr >= 0 && tr < (HALF ? 128 : 256)) {
         const int ll = tr & 63, comp = tr >> 6;
-        const int lo = 64 * g + ll;
+        const int lo = PAIRF ? 128 * (g >> 1) + 2 * ll + (g & 1) : 64 * g + ll;
         const double s = wave_sum<FWD_MAX_WAVES>(rb, comp, ll, W);
         if (MAIN) {
             if (lo < L && lo >= m && (m > 0 || comp < 2)) {
@@ -540,7 +552,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
 }
 
-template <int NCH, bool SAME, int WT, bool HALF = false>
+template <int NCH, bool SAME, int WT, bool HALF = false, bool PAIRF = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
@@ -562,7 +574,8 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     for (int pass = 0; pass < 2; ++pass) {
         const int g = pass == 0 ? p : G - 1 - p;
         if (pass == 1 && g == p) break;
-        const int l = 64 * g + lane;
+        const int lmin = PAIRF ? 128 * (g >> 1) + (g & 1) : 64 * g;     // lowest degree of the group
+        const int l = PAIRF ? lmin + 2 * lane : lmin + lane;
         double X[NCH][SG], Y[NCH][SG];
         int E[NCH][SG];
 #pragma unroll
@@ -570,13 +583,13 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
 #pragma unroll
             for (int k = 0; k < SG; ++k) { X[c][k] = 0.0; Y[c][k] = 0.0; E[c][k] = 0; }
         uint32_t real = 0u;
-        const int mstart = min(64 * g + 63, L - 1);
+        const int mstart = min(PAIRF ? lmin + 126 : lmin + 63, L - 1);
         const int lc = min(l, L - 1);
         double kk = (l > mstart && l < L) ? kap[(size_t)mstart * L + lc] : 0.0;
         double gm = (l >= mstart && l < L) ? gtab[(size_t)mstart * L + lc] : 0.0;
         // head: the orders at which lanes of this group start (an even number of
         // steps so the register roles line up with the main loop)
-        const int hend = ((mstart - 64 * g + 1) % 2 == 0) ? 64 * g : 64 * g - 1;
+        const int hend = ((mstart - lmin + 1) % 2 == 0) ? lmin : lmin - 1;
         int m = mstart;
         // Pull the wave's lambda and spectra rows of orders m - PFD, m - PFD - 1 toward
         // the caches (one dword per 128-byte line, PQ lanes per order); the result is
@@ -599,11 +612,11 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         };
         for (; m >= hend && m >= mend; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, true, false, false, false, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, true, false, false, false, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                               lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                               kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
-                fwd_step<NCH, 1, true, false, false, false, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
+                fwd_step<NCH, 1, true, false, false, false, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
                                                                   hstride, lstride, nreg, rbase, X, Y, E, real, kk, gm,
                                                                   lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA,
                                                                   QB, QxA, QxB);
@@ -613,29 +626,29 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         const int mlo = SAME ? max(an, 1) : an;
         for (; m - 1 >= mlo && real != ALL; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, false, true, SAME, false, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, false, true, SAME, false, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                              lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                              kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
-            fwd_step<NCH, 1, false, true, SAME, false, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 1, false, true, SAME, false, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                              lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                              kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
         }
         for (; m - 1 >= mlo; m -= 2) {                   // realised: plain contributions
             prefetch(m);
-            fwd_step<NCH, 0, false, true, SAME, true, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, false, true, SAME, true, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                             lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
-            fwd_step<NCH, 1, false, true, SAME, true, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 1, false, true, SAME, true, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                             lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, false, false, false, false, HALF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, false, false, false, false, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                                lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                                kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
-                fwd_step<NCH, 1, false, false, false, false, HALF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
+                fwd_step<NCH, 1, false, false, false, false, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
                                                                    hstride, lstride, nreg, rbase, X, Y, E, real, kk,
                                                                    gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
                                                                    blk, QA, QB, QxA, QxB);
@@ -643,6 +656,32 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         asm volatile("" ::"v"(pf));
         __syncthreads();   // the LDS buffers are reused by the next pass
     }
+}
+
+// Sums and differences of the spectra of a ring and its mirror for the paired
+// forward sweep: S[m][i] = H[m][i] + H[m][nreg-1-i], D[m][i] = H[m][i] -
+// H[m][nreg-1-i] over whole 32-byte records (both sides); a ring that is its own
+// mirror (the equator) enters once: S = D = H.  Pairs past nsw are zero padding.
+__global__ void k_pair_spectra(int L, int nreg, int nsw, int hstride, int pstride, const double *__restrict__ H,
+                               double *__restrict__ S, double *__restrict__ D)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)L * pstride) return;
+    const int m = (int)(i / pstride), r = (int)(i % pstride);
+    double4 a = make_double4(0.0, 0.0, 0.0, 0.0), b = a;
+    if (r < nsw) {
+        a = *reinterpret_cast<const double4 *>(H + ((size_t)m * hstride + r) * 4);
+        const int rm = nreg - 1 - r;
+        if (rm != r) {
+            const double4 c = *reinterpret_cast<const double4 *>(H + ((size_t)m * hstride + rm) * 4);
+            b = make_double4(a.x - c.x, a.y - c.y, a.z - c.z, a.w - c.w);
+            a = make_double4(a.x + c.x, a.y + c.y, a.z + c.z, a.w + c.w);
+        } else {
+            b = a;
+        }
+    }
+    *reinterpret_cast<double4 *>(S + ((size_t)m * pstride + r) * 4) = a;
+    *reinterpret_cast<double4 *>(D + ((size_t)m * pstride + r) * 4) = b;
 }
 
 // Copies of the two sides' ring spectra at orders mu < |n| for the forward sweep
@@ -1519,11 +1558,12 @@ hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
                              int lstride, int n, const double *lam, const double2 *init, const double *kap,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
-                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int half)
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int half, int pair)
 {
     if ((nwaves != 4 && nwaves != 8 && nwaves != 16) || nwaves > FWD_MAX_WAVES)
         return hipErrorInvalidValue;                                // reducer rotation: 1, 2 or 4 groups of 4
-    if (half && (n != 0 || HA != HB)) return hipErrorInvalidValue;  // real signals: the one-array run n = 0
+    if (pair && (n != 0 || HA == HB || HxA || HxB)) return hipErrorInvalidValue;   // mirror rings: run n = 0
+    if (half && !pair && (n != 0 || HA != HB)) return hipErrorInvalidValue;  // real signals: the run n = 0
     dim3 grid((G + 1) / 2, nblk);
     // the wave count is a template argument: the reducer rotation and the wave sum
     // then compile to fixed code; HA == HB (run n = 0) selects the one-array path
@@ -1532,13 +1572,28 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
                            gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
     };
     const bool same = HA == HB;
-    if (half) {
+    if (pair) {
+        if (nwaves == 16) half ? go(k_dstage_fwd<FWD_NCH, true, 16, true, true>) : go(k_dstage_fwd<FWD_NCH, true, 16, false, true>);
+        else if (nwaves == 8) half ? go(k_dstage_fwd<FWD_NCH, true, 8, true, true>) : go(k_dstage_fwd<FWD_NCH, true, 8, false, true>);
+        else half ? go(k_dstage_fwd<FWD_NCH, true, 4, true, true>) : go(k_dstage_fwd<FWD_NCH, true, 4, false, true>);
+    } else if (half) {
         if (nwaves == 16) go(k_dstage_fwd<FWD_NCH, true, 16, true>);
         else if (nwaves == 8) go(k_dstage_fwd<FWD_NCH, true, 8, true>);
         else go(k_dstage_fwd<FWD_NCH, true, 4, true>);
     } else if (nwaves == 16) same ? go(k_dstage_fwd<FWD_NCH, true, 16>) : go(k_dstage_fwd<FWD_NCH, false, 16>);
     else if (nwaves == 8) same ? go(k_dstage_fwd<FWD_NCH, true, 8>) : go(k_dstage_fwd<FWD_NCH, false, 8>);
     else same ? go(k_dstage_fwd<FWD_NCH, true, 4>) : go(k_dstage_fwd<FWD_NCH, false, 4>);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_pair_spectra(hipStream_t st, int L, int nreg, int nsw, int hstride, int pstride, const double *H,
+                               double *S, double *D)
+{
+    if (nsw > pstride || 2 * nsw < nreg || nreg > hstride) return hipErrorInvalidValue;
+    const size_t tot = (size_t)L * pstride;
+    hipLaunchKernelGGL(k_pair_spectra, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, nreg, nsw, hstride,
+                       pstride, H, S, D);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

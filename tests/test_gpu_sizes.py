@@ -213,6 +213,14 @@ def test_mirror_ring_sweep(binding, monkeypatch, sampling, L, nside):
         assert rel_l2(f[b].ravel(), oracle.s2_inverse(flm[b], L, 0, samp, nside).ravel()) < 1e-12
     fr = host(plan.inverse_real(dev(flm[0])))
     assert rel_l2(fr.ravel(), oracle.s2_inverse_real(flm[0], L, samp, nside).ravel()) < 1e-12
+    # forward sweep over the northern rings (degree groups of one parity)
+    gm = map_gaussian((2,) + tuple(plan.map_shape), seed=24)
+    a = host(plan.forward(dev(gm)))
+    for b in range(2):
+        assert rel_l2(a[b], oracle.s2_forward(gm[b], L, 0, samp, nside)) < 1e-12
+    assert np.all(a[:, ~coeff_mask(L, 0)] == 0)
+    gr = np.random.default_rng(25).standard_normal(plan.map_shape)
+    assert rel_l2(host(plan.forward_real(dev(gr))), oracle.s2_forward_real(gr, L, samp, nside)) < 1e-12
     if sampling != "mwss":                          # forward adjoint = inverse with the quadrature weights
         g = flm_gaussian(L, 0, seed=22)
         lhs = np.vdot(g, oracle.s2_forward(map_gaussian(plan.map_shape, seed=23), L, 0, samp, nside))
@@ -222,3 +230,4 @@ def test_mirror_ring_sweep(binding, monkeypatch, sampling, L, nside):
     ref_plan = binding.Plan(L, sampling=sampling, nside=nside, max_batch=2)
     assert ref_plan.info["swept_rings"] == nreg
     assert rel_l2(f, host(ref_plan.inverse(dev(flm)))) < 1e-13
+    assert rel_l2(a, host(ref_plan.forward(dev(gm)))) < 1e-13

@@ -221,11 +221,13 @@ def test_mirror_ring_sweep(binding, monkeypatch, sampling, L, nside):
     assert np.all(a[:, ~coeff_mask(L, 0)] == 0)
     gr = np.random.default_rng(25).standard_normal(plan.map_shape)
     assert rel_l2(host(plan.forward_real(dev(gr))), oracle.s2_forward_real(gr, L, samp, nside)) < 1e-12
-    if sampling != "mwss":                          # forward adjoint = inverse with the quadrature weights
-        g = flm_gaussian(L, 0, seed=22)
-        lhs = np.vdot(g, oracle.s2_forward(map_gaussian(plan.map_shape, seed=23), L, 0, samp, nside))
-        rhs = np.vdot(host(plan.forward_adjoint(dev(g))), map_gaussian(plan.map_shape, seed=23))
-        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # adjoints: the forward's (an inverse-type sweep) and the inverse's (a forward-type sweep)
+    g = flm_gaussian(L, 0, seed=22)
+    x = map_gaussian(plan.map_shape, seed=23)
+    lhs = np.vdot(g, oracle.s2_forward(x, L, 0, samp, nside))
+    rhs = np.vdot(host(plan.forward_adjoint(dev(g))), x)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    assert rel_l2(host(plan.inverse_adjoint(dev(x))), oracle.s2_inverse_adjoint(x, L, 0, samp, nside)) < 1e-12
     monkeypatch.setenv("S2MI_RING_PAIRING", "0")
     ref_plan = binding.Plan(L, sampling=sampling, nside=nside, max_batch=2)
     assert ref_plan.info["swept_rings"] == nreg

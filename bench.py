@@ -159,6 +159,40 @@ def real_signal(L, steps, dev):
             "pairs_per_s": 1e3 / ms, "roundtrip_rel_l2": err, "inverse_vs_oracle_rings": ring_err}
 
 
+def healpix_pair(L, nside, steps, dev):
+    """HEALPix (RING, nside) spin-0 inverse+forward pair at the headline L, one map:
+    ms per pair, whether the sweeps run over the northern rings (mirror symmetry),
+    and the inverse on sampled rings against the oracle."""
+    import torch
+    import oracle
+    from paper_2311_14670_amd import binding
+    from paper_2311_14670_amd.synth import flm_gaussian
+    flm = flm_gaussian(L, 0, seed=1, scale="inv1pl")
+    x = torch.from_numpy(flm).to(dev)
+    plan = binding.Plan(L, sampling="healpix", nside=nside, device=dev)
+    y = plan.forward(plan.inverse(x))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        y = plan.forward(plan.inverse(x))
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    _, nphi, start, _ = oracle.healpix_rings(nside)
+    rings = np.array([0, nside - 1, 2 * nside - 1, 3 * nside])
+    f = plan.inverse(x).cpu().numpy()
+    fr = np.concatenate([f[start[r]:start[r] + nphi[r]] for r in rings])
+    ref = oracle.s2_inverse(flm, L, 0, oracle.HEALPIX, nside, rings=rings)
+    err = float(np.linalg.norm(fr - ref) / np.linalg.norm(ref))
+    swept = plan.info["swept_rings"]
+    del plan, x, y
+    torch.cuda.empty_cache()
+    return {"workload": f"HEALPix nside={nside} L={L} spin-0 inverse+forward pair, one map", "L": L, "nside": nside,
+            "steps": steps, "ms_per_pair": ms, "pairs_per_s": 1e3 / ms, "swept_rings": swept,
+            "rings": 4 * nside - 1, "inverse_vs_oracle_rings": err}
+
+
 def cpu_baseline(L, spin, flm, nring_sample, norder_sample):
     import oracle
     oracle._load()
@@ -195,6 +229,8 @@ def main():
                     help="also serve a seeded mixed request stream (L in [64, --serving-lmax]); 0: skip")
     ap.add_argument("--serving-lmax", type=int, default=1024)
     ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--healpix-steps", type=int, default=10,
+                    help="also time a HEALPix nside=L/2 spin-0 pair at the headline L; 0: skip")
     ap.add_argument("--real-steps", type=int, default=10,
                     help="also time the real-signal path at the headline L (spin 0); 0: skip")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -291,6 +327,8 @@ def main():
         out["mixed_precision"] = mixed_precision(L, args.mixed_batch, args.mixed_steps, dev, plan)
     if args.real_steps > 0 and spin == 0:
         out["real_signal"] = real_signal(L, args.real_steps, dev)
+    if args.healpix_steps > 0:
+        out["healpix"] = healpix_pair(L, L // 2, args.healpix_steps, dev)
     if args.large_L > 0 and args.large_steps > 0:
         out["large_L"] = largest_size(args.large_L, args.large_steps, dev)
     if args.serving_requests > 0:

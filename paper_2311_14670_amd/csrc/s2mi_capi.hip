@@ -338,6 +338,12 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     Staging stg;
     int rc;
     auto bail = [&](int code) { delete P; return code; };
+    // a HIP failure while the plan is built releases everything it holds
+#define PLANCHK(expr, what)                                  \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return bail(hipfail(_e, what)); \
+    } while (0)
 
     // slices and runs
     P->slice_spin.resize(P->nslice);
@@ -446,10 +452,10 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->fft_lds = (size_t)maxlen * sizeof(double2);
         if ((rc = upload(P, &P->ring_fft, rf, st, "ring_fft"))) return bail(rc);
         if ((rc = upload(P, &P->ffts, P->ffts_h, st, "fft table"))) return bail(rc);
-        HIPCHK(set_kernel_lds_limits(P->fft_lds), "LDS limits");
+        PLANCHK(set_kernel_lds_limits(P->fft_lds), "LDS limits");
         int nblue = 0;
         for (auto &f : P->ffts_h) nblue += f.blue;
-        if (nblue) HIPCHK(launch_bluestein_filter(st, (int)P->ffts_h.size(), P->ffts, P->fft_threads, P->fft_lds), "bluestein filters");
+        if (nblue) PLANCHK(launch_bluestein_filter(st, (int)P->ffts_h.size(), P->ffts, P->fft_threads, P->fft_lds), "bluestein filters");
     }
     if (sampling == S2_MW || sampling == S2_MWSS) {
         stg.d.emplace_back(); std::vector<double> &wq = stg.d.back();
@@ -513,8 +519,8 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         const int mode = pm && pm[0] == '0' ? 0 : pm && pm[0] == '1' ? 1 : -1;
         if (sym && spin == 0 && !so3 && prec == S2_FP64 && mode != 0) {
             int dev = 0, ncu = 0;
-            HIPCHK(hipGetDevice(&dev), "hipGetDevice");
-            HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+            PLANCHK(hipGetDevice(&dev), "hipGetDevice");
+            PLANCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
             const int half_rings = (P->nreg + 1) / 2;
             if (mode == 1 || (half_rings + 63) / 64 * P->inv_nblk >= ncu) P->nsw = half_rings;
         }
@@ -565,9 +571,9 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         double2 *ini;
         if ((rc = P->dalloc(&lam, (size_t)(L + P->nx) * P->hstride, "lambda table"))) return bail(rc);
         lam += (size_t)P->nx * P->hstride;                 // rows m in [-nx, L)
-        HIPCHK(launch_lambda_table(st, L, P->nx, P->nreg, P->hstride, r.n, P->cot, P->csc, lam), "lambda table");
+        PLANCHK(launch_lambda_table(st, L, P->nx, P->nreg, P->hstride, r.n, P->cot, P->csc, lam), "lambda table");
         if ((rc = P->dalloc(&ini, (size_t)L * P->nreg, "start values"))) return bail(rc);
-        HIPCHK(launch_init_table(st, L, P->nreg, r.n, P->lsin, P->lcos, P->lbin[ri], ini), "start values");
+        PLANCHK(launch_init_table(st, L, P->nreg, r.n, P->lsin, P->lcos, P->lbin[ri], ini), "start values");
         P->lam.push_back(lam);
         P->init.push_back(ini);
     }
@@ -647,7 +653,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         }
         if ((rc = P->dalloc(&P->kg, (size_t)(L + P->nx) * g.lrow, "kappa/g table"))) return bail(rc);
         P->kg += (size_t)P->nx * g.lrow;                     // rows m in [-nx, L)
-        HIPCHK(launch_kg_table(st, L, P->nx, g.lrow, P->kap, P->gtab, P->kg), "kappa/g table");
+        PLANCHK(launch_kg_table(st, L, P->nx, g.lrow, P->kap, P->gtab, P->kg), "kappa/g table");
         const size_t per_m_d = std::max((size_t)g.kc * g.rpad, (size_t)(g.rpad / 8) * g.lp) * 32;
         P->mch = (int)std::max<size_t>(4, std::min<size_t>((size_t)L, ((size_t)512 << 20) / per_m_d));
         const size_t per_m_ah = (size_t)std::max(g.kc, g.rpad / 8) * g.rows * 32;
@@ -666,11 +672,12 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->off_mQx = o; o += P->nxp > 0 ? align256(B * S * (size_t)L * P->nxp * 4 * sizeof(double)) : 0;
         P->ws_bytes = o;
     }
-    HIPCHK(hipStreamSynchronize(st), "plan upload");
-    HIPCHK(hipGetLastError(), "plan kernels");
+    PLANCHK(hipStreamSynchronize(st), "plan upload");
+    PLANCHK(hipGetLastError(), "plan kernels");
     *out = P;
     return S2_OK;
 }
+#undef PLANCHK
 
 int s2_plan_create(s2_plan_t *out, int L, int spin, int N, s2_sampling_t sampling, int nside, int max_batch,
                    s2_precision_t prec, void *hip_stream)

@@ -169,8 +169,17 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int len, int Ns, const d
         if (j < nbf) {
             const int k = j % Ns;
             if (Ns > 1) {
+                // twiddles w^r, r < R, by repeated multiplication from one table read (the
+                // R-1 reads at stride r lanes apart touched a line each; rounding grows
+                // like r ulp, r <= 12)
+                const double2 w1 = ldroot(tw, k * tstep, sign);
+                double2 w = w1;
+                v[b][1] = cmul(v[b][1], w);
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], ldroot(tw, k * r * tstep, sign));
+                for (int r = 2; r < R; ++r) {
+                    w = cmul(w, w1);
+                    v[b][r] = cmul(v[b][r], w);
+                }
             }
             const int o = (j / Ns) * Ns * R + k;
             dft_small_store<R>(v[b], sign, buf + o, Ns);

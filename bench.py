@@ -159,6 +159,32 @@ def real_signal(L, steps, dev):
             "pairs_per_s": 1e3 / ms, "roundtrip_rel_l2": err, "inverse_vs_oracle_rings": ring_err}
 
 
+def mw_pairs(cases, steps, dev):
+    """Further one-map MW FP64 pairs (L, spin): ms per pair and the round trip."""
+    import torch
+    from paper_2311_14670_amd import binding
+    from paper_2311_14670_amd.synth import flm_gaussian
+    res = []
+    for L, spin in cases:
+        flm = flm_gaussian(L, spin, seed=1, scale="inv1pl")
+        x = torch.from_numpy(flm).to(dev)
+        plan = binding.Plan(L, spin=spin, device=dev)
+        y = plan.forward(plan.inverse(x))
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            y = plan.forward(plan.inverse(x))
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        err = float(np.linalg.norm(y.cpu().numpy() - flm) / np.linalg.norm(flm))
+        res.append({"L": L, "spin": spin, "ms_per_pair": ms, "pairs_per_s": 1e3 / ms, "roundtrip_rel_l2": err})
+        del plan, x, y
+        torch.cuda.empty_cache()
+    return res
+
+
 def healpix_pair(L, nside, steps, dev):
     """HEALPix (RING, nside) spin-0 inverse+forward pair at the headline L, one map:
     ms per pair, whether the sweeps run over the northern rings (mirror symmetry),
@@ -229,6 +255,8 @@ def main():
                     help="also serve a seeded mixed request stream (L in [64, --serving-lmax]); 0: skip")
     ap.add_argument("--serving-lmax", type=int, default=1024)
     ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--mw-steps", type=int, default=10,
+                    help="also time MW pairs at L=1024 (spin 0, 2) and L=2048 spin 2; 0: skip")
     ap.add_argument("--healpix-steps", type=int, default=10,
                     help="also time a HEALPix nside=L/2 spin-0 pair at the headline L; 0: skip")
     ap.add_argument("--real-steps", type=int, default=10,
@@ -329,6 +357,8 @@ def main():
         out["real_signal"] = real_signal(L, args.real_steps, dev)
     if args.healpix_steps > 0:
         out["healpix"] = healpix_pair(L, L // 2, args.healpix_steps, dev)
+    if args.mw_steps > 0:
+        out["mw_other"] = mw_pairs([(1024, 0), (1024, 2), (2048, 2)], args.mw_steps, dev)
     if args.large_L > 0 and args.large_steps > 0:
         out["large_L"] = largest_size(args.large_L, args.large_steps, dev)
     if args.serving_requests > 0:

@@ -752,18 +752,20 @@ int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double
         const Run &r = P->runs[ri];
         const double2 *fa = r.sliceA >= 0 ? flm + r.sliceA * slab : nullptr;
         const double2 *fb = r.sliceB >= 0 ? flm + r.sliceB * slab : nullptr;
+        // a run that feeds one side only (spin-s sphere plans) sweeps that side alone
+        const int side = half ? 1 : (fa && fb) ? 0 : (fa ? 1 : 2);
         double *C = C0 + ri * nC;
         {
         TIMED(S2_STAGE_PACK);
         HIPCHK(launch_pack_inv(st, L, P->nx, r.n, P->inv_nblk, P->inv_waves * INV_J, P->lslot, fa, fb,
                                r.sliceA >= 0 ? wl[r.sliceA] : nullptr, r.sliceB >= 0 ? wl[r.sliceB] : nullptr, P->kap,
-                               P->gtab, C, half), "pack");
+                               P->gtab, C, side), "pack");
         }
         TIMED(S2_STAGE_DSTAGE_INV);
         HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nx, P->nreg, r.n, P->cot, P->csc, P->init[ri], C,
                                  P->lchunk, P->mtop,
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
-                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr, half, P->nsw), "inverse d-stage");
+                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr, side, P->nsw), "inverse d-stage");
     }
     return S2_OK;
 }
@@ -856,6 +858,7 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const dou
         const double *HB = r.sliceB >= 0 ? H0 + r.sliceB * nF : HA;
         double *HxA = an > 0 ? Hx0 + 2 * ri * nHx : nullptr;
         double *HxB = an > 0 ? HxA + nHx : nullptr;
+        const int side = half ? 1 : (r.sliceA >= 0 && r.sliceB >= 0) ? 0 : (r.sliceA >= 0 ? 1 : 2);
         TIMED(S2_STAGE_DSTAGE_FWD);
         if (an > 0)
             HIPCHK(launch_mask_low(st, an, r.n, P->nreg, P->hstride, P->cot, P->csc, HA, HB, HxA, HxB),
@@ -865,7 +868,7 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const dou
                                  r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
                                  r.sliceB >= 0 ? Q0 + r.sliceB * nQ : nullptr,
                                  (an > 0 && r.sliceA >= 0) ? Qx0 + r.sliceA * nQx : nullptr,
-                                 (an > 0 && r.sliceB >= 0) ? Qx0 + r.sliceB * nQx : nullptr, half), "forward d-stage");
+                                 (an > 0 && r.sliceB >= 0) ? Qx0 + r.sliceB * nQx : nullptr, side), "forward d-stage");
     }
     for (int k = 0; k < P->nslice; ++k) {
         const int s = P->slice_spin[k];

@@ -103,8 +103,9 @@ __global__ void k_init_table(int L, int nreg, int n, const double *__restrict__ 
 // B record is used at m > 0 and, for n != 0, at m <= 0 by the continuation of
 // the run below m = 0 (orders m <= 0 then feed the B slice at -m >= 0 and the
 // A slice at m < 0).  A wave reads the records of one order at fixed offsets
-// from a single base address.  Real signals (rs = 3): the records stop after the
-// A side, since the B side (order -m) is the conjugate of the A side.
+// from a single base address.  One side (rs = 3): the records hold kappa and the
+// A side (real signals: the B side is its conjugate) or, with flmA absent, the
+// B side (a spin-s sphere run that feeds only the orders -m of its slice).
 __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, int rs, const int *__restrict__ lslot,
                            const double2 *__restrict__ flmA, const double2 *__restrict__ flmB,
                            const double *__restrict__ wA, const double *__restrict__ wB,
@@ -138,8 +139,9 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, int rs, const
     const int blk = (int)(i / S), s = (int)(i % S);
     double *o = C + (((size_t)blk * (L + nx) + (m + nx)) * S + s) * rs;
     if (rs == 3) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) o[q] = rec[q];
+        o[0] = rec[0];
+        o[1] = flmA ? rec[1] : rec[3];
+        o[2] = flmA ? rec[2] : rec[4];
     } else {
 #pragma unroll
         for (int q = 0; q < 5; ++q) o[q] = rec[q];
@@ -211,15 +213,17 @@ __device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[
 // contribution times the records.  SLOW: the contribution is e 2^E (exact
 // scaling, zero once below the double range) and slot jin may start here
 // (l == m) from its start value; otherwise the chunk is realised (E = 0).
-// HALF (real signals): records of RS = 3 doubles, A side only.  ac[0..3] are
-// the sums {Re A, Im A, Re B, Im B}; PAIR: ac[0..3] over the even and ac[4..7]
-// over the odd degrees (slot j of a chunk holds l = base + SG-1-j, base a
-// multiple of SG, so l is odd exactly when j is even).
-template <int PAR, bool SLOW, bool HALF = false, bool PAIR = false>
+// SIDE 1 / 2 (one side present: real signals, or a spin-s sphere run, which
+// feeds only the orders +m or only -m of its slice): records of RS = 3 doubles,
+// {kappa, that side's coefficient}.  ac[0..3] are the sums {Re A, Im A, Re B,
+// Im B}; PAIR: ac[0..3] over the even and ac[4..7] over the odd degrees (slot j
+// of a chunk holds l = base + SG-1-j, base a multiple of SG, so l is odd
+// exactly when j is even).
+template <int PAR, bool SLOW, int SIDE = 0, bool PAIR = false>
 __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ rec,
                                           double lam, int jin, double e0, int E0, double (&ac)[PAIR ? 8 : 4])
 {
-    constexpr int RS = HALF ? 3 : 5;
+    constexpr int RS = SIDE ? 3 : 5;
 #pragma unroll
     for (int j = 0; j < SG; ++j) {
         const int o = (PAIR && (j & 1) == 0) ? 4 : 0;
@@ -236,11 +240,16 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
             }
             t = ldexp(nw, E[j]);
         }
-        ac[o + 0] = fma(t, c[1], ac[o + 0]);
-        ac[o + 1] = fma(t, c[2], ac[o + 1]);
-        if constexpr (!HALF) {
-            ac[o + 2] = fma(t, c[3], ac[o + 2]);
-            ac[o + 3] = fma(t, c[4], ac[o + 3]);
+        if constexpr (SIDE == 2) {
+            ac[o + 2] = fma(t, c[1], ac[o + 2]);
+            ac[o + 3] = fma(t, c[2], ac[o + 3]);
+        } else {
+            ac[o + 0] = fma(t, c[1], ac[o + 0]);
+            ac[o + 1] = fma(t, c[2], ac[o + 1]);
+            if constexpr (SIDE == 0) {
+                ac[o + 2] = fma(t, c[3], ac[o + 2]);
+                ac[o + 3] = fma(t, c[4], ac[o + 3]);
+            }
         }
     }
 }
@@ -249,7 +258,7 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
 // (nsw of nreg) and also produce the mirror ring nreg-1-r, using
 // d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta): with E and O the sums
 // over the even and odd degrees, ring r gets E + O and its mirror (-1)^m (E - O).
-template <int NCH, int PAR, bool HALF = false, bool PAIR = false>
+template <int NCH, int PAR, int SIDE = 0, bool PAIR = false>
 __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ms, int ring0, int nreg,
                                          int nsw, int lane,
                                          int w, int W,
@@ -258,7 +267,7 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
                                          const double2 *__restrict__ initr, const double *__restrict__ C, double *red,
                                          int blk, double *__restrict__ partA, double *__restrict__ partB)
 {
-    constexpr int RS = HALF ? 3 : 5;
+    constexpr int RS = SIDE ? 3 : 5;
     constexpr int NA = PAIR ? 8 : 4;                     // sums per lane
     const double lam = fma(-(double)(m + 1), ct, ncs);   // lambda_{m+1}: produces order m
     double ac[NA];
@@ -274,12 +283,12 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
         if (m >= base) {                                  // ramp: slot jin starts at this order
             const int jin = base + SG - 1 - m;
             const double2 iv = initr[m];                 // d^m_{m,n}(theta_ring), zero if m < |n|
-            inv_chunk<PAR, true, HALF, PAIR>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, ac);
+            inv_chunk<PAR, true, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, ac);
             fast &= ~(1u << g);
         } else if ((fast >> g) & 1u) {
-            inv_chunk<PAR, false, HALF, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
+            inv_chunk<PAR, false, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
         } else {
-            inv_chunk<PAR, true, HALF, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
+            inv_chunk<PAR, true, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
         }
     }
     // renormalisation pass every RN orders over the started chunks not yet realised
@@ -300,12 +309,12 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
     double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * NA * 64;
 #pragma unroll
     for (int c = 0; c < NA; ++c)
-        if (!HALF || (c & 3) < 2) rb[(w * NA + c) * 64 + lane] = ac[c];
+        if (SIDE == 0 || (SIDE == 1) == ((c & 3) < 2)) rb[(w * NA + c) * 64 + lane] = ac[c];
     __syncthreads();
     // four waves, rotating with the order, reduce the 4 x 64 outputs over the waves
-    // (only the A side's 2 x 64 for real signals)
+    // (only the present side's 2 x 64 for SIDE 1 / 2)
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
-    if (tr >= 0 && tr < (HALF ? 128 : 256)) {
+    if (tr >= 0 && tr < 256 && (SIDE == 0 || (SIDE == 1) == (tr < 128))) {
         const int rl = tr & 63, comp = tr >> 6;         // rl == lane: this thread's ring
         double s = 0.0, s2 = 0.0;                       // a plain loop: fewer scalar registers than wave_sum
         if (PAIR) {
@@ -342,7 +351,7 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
     }
 }
 
-template <int NCH, int WT, bool HALF = false, bool PAIR = false>
+template <int NCH, int WT, int SIDE = 0, bool PAIR = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     int L, int nx, int nreg, int nsw, int n, const double *__restrict__ cot, const double *__restrict__ csc,
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
@@ -376,7 +385,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
 
     const int mt = ufl(mtop[blk]);
     int pf = 0;
-    constexpr int RS = HALF ? 3 : 5;                     // doubles per record
+    constexpr int RS = SIDE ? 3 : 5;                     // doubles per record
     constexpr int ROWB = NCH * SG * RS * 8;              // bytes of one wave's records per order
     static_assert(ROWB % 128 == 0, "a wave's record row spans whole cache lines");
     for (int m = mt; m >= mend; m -= 2) {
@@ -390,10 +399,10 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
                                                                   (NCH * SG) * RS);
             pf = Cp[(lane % (ROWB / 128)) * 32];
         }
-        inv_step<NCH, 0, HALF, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
+        inv_step<NCH, 0, SIDE, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
                                      ncs, initr, C, red, blk, partA, partB);
         if (m - 1 >= mend)
-            inv_step<NCH, 1, HALF, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
+            inv_step<NCH, 1, SIDE, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
                                          ct, ncs, initr, C, red, blk, partA, partB);
     }
     asm volatile("" ::"v"(pf));
@@ -413,7 +422,7 @@ __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int 
     return init + (size_t)r0 * L + m;
 }
 
-template <int PAR, bool HEAD, bool REAL = false, bool HALF = false>
+template <int PAR, bool HEAD, bool REAL = false, int SIDE = 0>
 __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ Lm,
                                           const double *__restrict__ HA, const double *__restrict__ HB, double kk,
                                           bool init, int nval, const double2 *__restrict__ iv, int istride, double &aAr,
@@ -435,9 +444,11 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
         const double t = REAL ? nw : ldexp(nw, E[k]);   // exact scaling; 0 below the double range
         const double *ha = HA + k * 4;                   // components chosen by the caller's offsets
         const double *hb = HB + k * 4;
-        aAr = fma(t, ha[0], aAr);
-        aAi = fma(t, ha[1], aAi);
-        if constexpr (!HALF) {
+        if constexpr (SIDE != 2) {
+            aAr = fma(t, ha[0], aAr);
+            aAi = fma(t, ha[1], aAi);
+        }
+        if constexpr (SIDE != 1) {
             aBr = fma(t, hb[0], aBr);
             aBi = fma(t, hb[1], aBi);
         }
@@ -450,14 +461,15 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
 // contiguous record and the wave's row is fetched with wide scalar loads.
 // REAL (with MAIN): every chunk is realised (all E == 0), which stays so in the
 // main loop since no degree starts there: no scaling and no renormalisation.
-// HALF (run n = 0 of a real signal): only the A side (order +m) is accumulated,
-// the order -m being its conjugate.
+// SIDE 1 / 2: only the A side (order +m) or only the B side (order -m) is
+// accumulated (a real signal's run n = 0, whose order -m is the conjugate; a
+// spin-s sphere run, which feeds one side of its slice).
 // PAIRF (run n = 0, N/S-symmetric sampling): the slots are the northern rings,
 // the lanes of group g hold degrees of one parity (l = 128 (g/2) + 2 lane + g%2),
 // and by d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta) a slot contributes
 // d (H(ring) + (-1)^{l+m} H(mirror)): HA holds the sums and HB the differences of
 // the two rings' spectra, and l + m has one parity across the wave at each order.
-template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false, bool REAL = false, bool HALF = false,
+template <int NCH, int PAR, bool HEAD, bool MAIN = false, bool SAME = false, bool REAL = false, int SIDE = 0,
           bool PAIRF = false>
 __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, int nxp, int n, int an, int lane, int w,
                                          int W, int hstride, int lstride, int nreg, int rbase, double (&X)[NCH][SG],
@@ -506,25 +518,27 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
             // started: they stay zero, and their start values lie outside the table
             const int nval = nreg - (rbase + c * SG);
             const bool ok = starts && nval > 0;
-            fwd_chunk<PAR, true, false, HALF>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval,
+            fwd_chunk<PAR, true, false, SIDE>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, ok, nval,
                                               init_tab_ptr(init, r0, m < 0 ? 0 : m, L), L, aAr, aAi, aBr, aBi);
         } else {
-            fwd_chunk<PAR, false, REAL, HALF>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr,
+            fwd_chunk<PAR, false, REAL, SIDE>(X[c], Y[c], E[c], Lc, Ac, Bc, kcur, false, 0, nullptr, 0, aAr, aAi, aBr,
                                               aBi);
         }
     }
     if (HEAD) real = 0u;                                  // degrees start in this group: not realised
     if (!REAL && (m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
     double *rb = red + (size_t)(m & 1) * FWD_MAX_WAVES * 4 * 64;
-    rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
-    rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
-    if (!HALF) {
+    if (SIDE != 2) {
+        rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
+        rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
+    }
+    if (SIDE != 1) {
         rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
         rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
     }
     __syncthreads();
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
-    if (tr >= 0 && tr < (HALF ? 128 : 256)) {
+    if (tr >= 0 && tr < 256 && (SIDE == 0 || (SIDE == 1) == (tr < 128))) {
         const int ll = tr & 63, comp = tr >> 6;
         const int lo = PAIRF ? 128 * (g >> 1) + 2 * ll + (g & 1) : 64 * g + ll;
         const double s = wave_sum<FWD_MAX_WAVES>(rb, comp, ll, W);
@@ -552,7 +566,7 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
 }
 
-template <int NCH, bool SAME, int WT, bool HALF = false, bool PAIRF = false>
+template <int NCH, bool SAME, int WT, int SIDE = 0, bool PAIRF = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
@@ -612,11 +626,11 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         };
         for (; m >= hend && m >= mend; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, true, false, false, false, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, true, false, false, false, SIDE, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                               lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                               kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
-                fwd_step<NCH, 1, true, false, false, false, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
+                fwd_step<NCH, 1, true, false, false, false, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
                                                                   hstride, lstride, nreg, rbase, X, Y, E, real, kk, gm,
                                                                   lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA,
                                                                   QB, QxA, QxB);
@@ -626,29 +640,29 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         const int mlo = SAME ? max(an, 1) : an;
         for (; m - 1 >= mlo && real != ALL; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, false, true, SAME, false, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, false, true, SAME, false, SIDE, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                              lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                              kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
-            fwd_step<NCH, 1, false, true, SAME, false, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 1, false, true, SAME, false, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                              lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                              kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
         }
         for (; m - 1 >= mlo; m -= 2) {                   // realised: plain contributions
             prefetch(m);
-            fwd_step<NCH, 0, false, true, SAME, true, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, false, true, SAME, true, SIDE, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                             lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
-            fwd_step<NCH, 1, false, true, SAME, true, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 1, false, true, SAME, true, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                             lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             prefetch(m);
-            fwd_step<NCH, 0, false, false, false, false, HALF, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
+            fwd_step<NCH, 0, false, false, false, false, SIDE, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                                lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                                kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             if (m - 1 >= mend)
-                fwd_step<NCH, 1, false, false, false, false, HALF, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
+                fwd_step<NCH, 1, false, false, false, false, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
                                                                    hstride, lstride, nreg, rbase, X, Y, E, real, kk,
                                                                    gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
                                                                    blk, QA, QB, QxA, QxB);
@@ -1520,24 +1534,27 @@ __global__ void k_pole_from_F(int L, int hstride, int ring, const double *__rest
 hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int slots_per_blk, const int *lslot,
                            const double2 *flmA, const double2 *flmB, const double *wA, const double *wB,
                            const double *kap, const double *gtab, double *C, int half)
-{
+{   // half: 0 both sides, 1 the A side only, 2 the B side only
     const int nslot = nblk * slots_per_blk;
     dim3 grid((nslot + 255) / 256, L + nx);
+    // side 1: A only (flmB not read), side 2: B only (flmA absent)
+    if ((half == 1 && !flmA) || (half == 2 && (flmA || !flmB))) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pack_inv, grid, dim3(256), 0, st, L, nx, n, nslot, slots_per_blk, half ? 3 : 5, lslot, flmA,
-                       half ? nullptr : flmB, wA, wB, kap, gtab, C);
+                       half == 1 ? nullptr : flmB, wA, wB, kap, gtab, C);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
-                             const int *mtop, double *partA, double *partB, int half, int nsw)
+                             const int *mtop, double *partA, double *partB, int side, int nsw)
 {
     if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
-    if (half && n != 0) return hipErrorInvalidValue;                // real signals: spin 0 only
+    if (side < 0 || side > 2 || (side == 1 && !partA) || (side == 2 && !partB) || (side == 0 && (!partA || !partB)))
+        return hipErrorInvalidValue;                                // the side(s) swept must have outputs
     if (nsw <= 0) nsw = nreg;
     const bool pair = nsw < nreg;                                   // mirror rings from the northern sweep
-    if (nsw > nreg || (pair && (n != 0 || 2 * nsw < nreg))) return hipErrorInvalidValue;
+    if (nsw > nreg || (pair && (n != 0 || side == 2 || 2 * nsw < nreg))) return hipErrorInvalidValue;
     dim3 grid((nsw + 63) / 64, nblk);
     // wave count, the real-signal half and the ring pairing as template arguments
     auto go = [&](auto kern) {
@@ -1545,11 +1562,15 @@ hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx
                            partA, partB);
     };
     if (nwaves == 8) {
-        if (pair) half ? go(k_dstage_inv<INV_NCH, 8, true, true>) : go(k_dstage_inv<INV_NCH, 8, false, true>);
-        else half ? go(k_dstage_inv<INV_NCH, 8, true>) : go(k_dstage_inv<INV_NCH, 8, false>);
+        if (pair) side ? go(k_dstage_inv<INV_NCH, 8, 1, true>) : go(k_dstage_inv<INV_NCH, 8, 0, true>);
+        else if (side == 1) go(k_dstage_inv<INV_NCH, 8, 1>);
+        else if (side == 2) go(k_dstage_inv<INV_NCH, 8, 2>);
+        else go(k_dstage_inv<INV_NCH, 8, 0>);
     } else {
-        if (pair) half ? go(k_dstage_inv<INV_NCH, 4, true, true>) : go(k_dstage_inv<INV_NCH, 4, false, true>);
-        else half ? go(k_dstage_inv<INV_NCH, 4, true>) : go(k_dstage_inv<INV_NCH, 4, false>);
+        if (pair) side ? go(k_dstage_inv<INV_NCH, 4, 1, true>) : go(k_dstage_inv<INV_NCH, 4, 0, true>);
+        else if (side == 1) go(k_dstage_inv<INV_NCH, 4, 1>);
+        else if (side == 2) go(k_dstage_inv<INV_NCH, 4, 2>);
+        else go(k_dstage_inv<INV_NCH, 4, 0>);
     }
     S2_LAUNCH_CHECK();
     return hipSuccess;
@@ -1558,12 +1579,13 @@ hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
                              int lstride, int n, const double *lam, const double2 *init, const double *kap,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
-                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int half, int pair)
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int side, int pair)
 {
     if ((nwaves != 4 && nwaves != 8 && nwaves != 16) || nwaves > FWD_MAX_WAVES)
         return hipErrorInvalidValue;                                // reducer rotation: 1, 2 or 4 groups of 4
-    if (pair && (n != 0 || HA == HB || HxA || HxB)) return hipErrorInvalidValue;   // mirror rings: run n = 0
-    if (half && !pair && (n != 0 || HA != HB)) return hipErrorInvalidValue;  // real signals: the run n = 0
+    if (pair && (n != 0 || HA == HB || HxA || HxB || side == 2)) return hipErrorInvalidValue;   // mirror rings: n = 0
+    // one side: both sides read one spectra array (the run's slice), and that side has outputs
+    if (side && !pair && (HA != HB || (side == 1 && !QA) || (side == 2 && !QB))) return hipErrorInvalidValue;
     dim3 grid((G + 1) / 2, nblk);
     // the wave count is a template argument: the reducer rotation and the wave sum
     // then compile to fixed code; HA == HB (run n = 0) selects the one-array path
@@ -1573,13 +1595,17 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
     };
     const bool same = HA == HB;
     if (pair) {
-        if (nwaves == 16) half ? go(k_dstage_fwd<FWD_NCH, true, 16, true, true>) : go(k_dstage_fwd<FWD_NCH, true, 16, false, true>);
-        else if (nwaves == 8) half ? go(k_dstage_fwd<FWD_NCH, true, 8, true, true>) : go(k_dstage_fwd<FWD_NCH, true, 8, false, true>);
-        else half ? go(k_dstage_fwd<FWD_NCH, true, 4, true, true>) : go(k_dstage_fwd<FWD_NCH, true, 4, false, true>);
-    } else if (half) {
-        if (nwaves == 16) go(k_dstage_fwd<FWD_NCH, true, 16, true>);
-        else if (nwaves == 8) go(k_dstage_fwd<FWD_NCH, true, 8, true>);
-        else go(k_dstage_fwd<FWD_NCH, true, 4, true>);
+        if (nwaves == 16) side ? go(k_dstage_fwd<FWD_NCH, true, 16, 1, true>) : go(k_dstage_fwd<FWD_NCH, true, 16, 0, true>);
+        else if (nwaves == 8) side ? go(k_dstage_fwd<FWD_NCH, true, 8, 1, true>) : go(k_dstage_fwd<FWD_NCH, true, 8, 0, true>);
+        else side ? go(k_dstage_fwd<FWD_NCH, true, 4, 1, true>) : go(k_dstage_fwd<FWD_NCH, true, 4, 0, true>);
+    } else if (side == 1) {
+        if (nwaves == 16) go(k_dstage_fwd<FWD_NCH, true, 16, 1>);
+        else if (nwaves == 8) go(k_dstage_fwd<FWD_NCH, true, 8, 1>);
+        else go(k_dstage_fwd<FWD_NCH, true, 4, 1>);
+    } else if (side == 2) {
+        if (nwaves == 16) go(k_dstage_fwd<FWD_NCH, true, 16, 2>);
+        else if (nwaves == 8) go(k_dstage_fwd<FWD_NCH, true, 8, 2>);
+        else go(k_dstage_fwd<FWD_NCH, true, 4, 2>);
     } else if (nwaves == 16) same ? go(k_dstage_fwd<FWD_NCH, true, 16>) : go(k_dstage_fwd<FWD_NCH, false, 16>);
     else if (nwaves == 8) same ? go(k_dstage_fwd<FWD_NCH, true, 8>) : go(k_dstage_fwd<FWD_NCH, false, 8>);
     else same ? go(k_dstage_fwd<FWD_NCH, true, 4>) : go(k_dstage_fwd<FWD_NCH, false, 4>);

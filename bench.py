@@ -364,6 +364,8 @@ def main():
     if args.serving_requests > 0:
         from paper_2311_14670_amd.serving import run_mix
         out["serving"] = run_mix(n_requests=args.serving_requests, lmax=args.serving_lmax, device=str(dev))
+        out["serving_split_bf16"] = run_mix(n_requests=args.serving_requests, lmax=args.serving_lmax, device=str(dev),
+                                            precision="split_bf16")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, spin, flm, args.cpu_rings, args.cpu_orders)
     print(json.dumps(out), flush=True)

@@ -475,17 +475,26 @@ def build_requests(trace, seed=3):
 
 
 def run_mix(n_requests=200, seed=3, lmin=64, lmax=1024, so3_lmax=256, n_streams=4, max_batch=8,
-            budget_frac=0.8, loads=(0.5, 0.7, 0.9), device="cuda:0"):
+            budget_frac=0.8, loads=(0.5, 0.7, 0.9), device="cuda:0", precision="fp64"):
     """Saturation throughput of a request mix, then realtime runs at fractions of it.
+    precision: every request's plan precision ("fp64", or the matrix-core "fp32" /
+    "split_bf16" contraction).
 
     Returns a dict with the saturation rate (requests/s) and p50/p99 latency per load."""
     import torch
-    from .synth import serving_trace
+    from .synth import serving_trace as _trace
+
+    def serving_trace(**kw):
+        tr = _trace(**kw)
+        for spec in tr:
+            spec["precision"] = precision
+        return tr
+
     total = torch.cuda.get_device_properties(torch.device(device)).total_memory
     trace = serving_trace(n_requests=n_requests, seed=seed, rate=1.0, lmin=lmin, lmax=lmax, so3_lmax=so3_lmax)
     ex = GpuExecutor(device=device, n_streams=n_streams, max_batch=max_batch, keep_results=False)
     out = {"requests": n_requests, "seed": seed, "L_range": [lmin, lmax], "so3_L_max": so3_lmax,
-           "streams": n_streams, "max_batch": max_batch}
+           "streams": n_streams, "max_batch": max_batch, "precision": precision}
     try:
         # warm pass over the whole trace builds every plan (host tables take up to ~1 s
         # each) and workspace once, so the saturation pass measures steady-state serving
@@ -524,8 +533,9 @@ def main(argv=None):
     ap.add_argument("--so3-lmax", type=int, default=256)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split_bf16"])
     a = ap.parse_args(argv)
-    res = run_mix(a.requests, a.seed, a.lmin, a.lmax, a.so3_lmax, a.streams, a.max_batch)
+    res = run_mix(a.requests, a.seed, a.lmin, a.lmax, a.so3_lmax, a.streams, a.max_batch, precision=a.precision)
     print(json.dumps(res), flush=True)
 
 

@@ -53,3 +53,34 @@ def test_mix_equals_alone_and_oracle():
             f = oracle.s2_inverse(r.data, k.L, k.spin, oracle.HEALPIX, k.nside)
             ref = oracle.s2_forward(f, k.L, k.spin, oracle.HEALPIX, k.nside)
         assert rel_l2(r.result, ref) < 1e-12, (r.rid, k)
+
+
+def test_mixed_precision_mix_matches_fp64():
+    """The same mix served with the split-BF16 contraction: every result within the
+    split-BF16 tolerance of the FP64 result, and equal to the request served alone
+    with that precision (the matrix-core path does not depend on batch composition)."""
+    from paper_2311_14670_amd import binding, serving
+    binding.load_library()
+    trace = serving_trace(n_requests=24, seed=5, rate=1e4, lmin=8, lmax=96, so3_lmax=24)
+    for spec in trace:
+        spec["precision"] = "split_bf16"
+    reqs = serving.build_requests(trace, seed=5)
+    ex = serving.GpuExecutor(n_streams=2, max_batch=4)
+    try:
+        sched = serving.Scheduler(ex, hbm_budget=8 << 30)
+        serving.serve(sched, reqs, realtime=False)
+    finally:
+        ex.close()
+    assert not sched.rejected and len(sched.done) == len(reqs)
+    for r in reqs:
+        k = r.key
+        x = torch.from_numpy(r.data).cuda()
+        outs = []
+        for prec in ("split_bf16", "fp64"):
+            plan = binding.Plan(k.L, spin=k.spin, N=k.N, sampling=k.sampling, nside=k.nside, precision=prec)
+            y = plan.so3_forward(plan.so3_inverse(x)) if k.kind == "so3" else plan.forward(plan.inverse(x))
+            outs.append(y.cpu().numpy())
+            plan.close()
+        assert np.array_equal(outs[0], r.result), (r.rid, k)
+        assert rel_l2(r.result, outs[1]) < 2e-4, (r.rid, k)
+        assert rel_l2(r.result, outs[1]) > 1e-12          # the reduced-precision products were used

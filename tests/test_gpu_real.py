@@ -115,7 +115,8 @@ _SAMP = {"mwss": oracle.MWSS, "dh": oracle.DH, "gl": oracle.GL, "healpix": oracl
 # the two rings of a pair; HEALPix: a cap ring pairs with its mirror ring, belt
 # rings with the next ring of the same half-pixel offset, short rings repeat
 @pytest.mark.parametrize("sampling,L,nside", [("mwss", 16, 0), ("mwss", 33, 0), ("dh", 17, 0), ("gl", 24, 0),
-                                              ("healpix", 16, 8), ("healpix", 33, 16), ("healpix", 64, 24)])
+                                              ("healpix", 16, 8), ("healpix", 33, 16), ("healpix", 64, 24),
+                                              ("mwss", 2, 0), ("dh", 2, 0), ("gl", 3, 0), ("healpix", 3, 1)])
 def test_real_other_samplings(binding, sampling, L, nside):
     samp = _SAMP[sampling]
     plan = binding.Plan(L, sampling=sampling, nside=nside, max_batch=2)

@@ -68,7 +68,8 @@ extern "C" {
 
 typedef struct s2_plan_s *s2_plan_t;
 
-/* Sphere samplings (Sec. 4.2).  Maps are complex128, batch outermost:
+/* Sphere samplings (Sec. 2.5, 4.2).  Maps are complex128 (float64 for the
+ * real-signal entry points), batch outermost:
  *   S2_MW       theta_t = (2t+1) pi/(2L-1), t < L (t = L-1: south pole),
  *               phi_p = 2 pi p/(2L-1): [L][2L-1]; exact transforms.
  *   S2_HEALPIX  RING-ordered pixel vector of 12 nside^2 samples (nside given);
@@ -78,8 +79,7 @@ typedef struct s2_plan_s *s2_plan_t;
  *   S2_GL       Gauss-Legendre: cos(theta_t) the roots of P_L, theta ascending,
  *               phi_p = 2 pi p/(2L-1): [L][2L-1]; exact transforms (GL weights).
  *   S2_MWSS     MW with symmetric sampling: theta_t = pi t/L, t = 0..L (both poles),
- *               phi_p = 2 pi p/(2L): [L+1][2L]; exact transforms (s2_forward_adjoint
- *               is not built for it).
+ *               phi_p = 2 pi p/(2L): [L+1][2L]; exact transforms.
  * SO(3) plans (N > 1) need S2_MW; nside is ignored except for S2_HEALPIX. */
 typedef enum { S2_MW = 0, S2_HEALPIX = 1, S2_DH = 2, S2_GL = 3, S2_MWSS = 4 } s2_sampling_t;
 
@@ -117,12 +117,13 @@ typedef struct {
  * isolatitude sampling) with the Wigner recursion of Sec. 3.
  *   L          bandlimit, 2 <= L <= 4096 (l < L).
  *   spin       |spin| < L (S2 transforms).  Ignored (must be 0) when N > 1.
- *   N          azimuthal band of SO(3) transforms, 1 <= N <= L; N = 1 for
- *              sphere-only plans.  An SO(3) plan (N > 1) serves so3_*; a plan
- *              with N == 1 serves s2_* (and so3_* with N = 1).
- *   sampling   S2_MW or S2_HEALPIX (HEALPix: nside >= 1 and L <= 3*nside+1 is
- *              not enforced; the caller picks L, typically 2*nside).
- *              SO(3) plans require S2_MW.
+ *   N          azimuthal band of SO(3) transforms, 1 <= N <= L and N <= 8
+ *              (S2_ERR_UNSUPPORTED above); N = 1 for sphere-only plans.  An
+ *              SO(3) plan (N > 1) serves so3_*; a plan with N == 1 serves s2_*
+ *              (and so3_* with N = 1).
+ *   sampling   any s2_sampling_t (HEALPix: nside >= 1; L <= 3*nside+1 is not
+ *              enforced, the caller picks L, typically 2*nside).  SO(3) plans
+ *              require S2_MW.
  *   max_batch  largest batch any call will pass (sizes the workspace), >= 1.
  *   prec       contraction arithmetic (see s2_precision_t).
  *   hip_stream stream on which the plan's constants are uploaded; the plan is

@@ -31,18 +31,26 @@ def algorithmic_flops(L, spin, rings):
     return (6 if spin == 0 else 8) * T
 
 
+def kernel_source_sha():
+    """First 16 hex digits of the sha256 over the sources the sweep kernels are built
+    from (the kernel file and the device headers it includes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("s2mi_kernels.hip", "s2mi_recur.h", "s2mi_internal.h", "s2mi_fft.h"):
+        h.update(open(os.path.join(ROOT, "paper_2311_14670_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel, L, spin):
     """HBM bytes per launch of a sweep kernel from the committed counter summary
     (FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration), only when the
     summary was taken on this workload and on the current kernel source; else None."""
-    import hashlib
     if (L, spin) != (2048, 0):
         return None
     summ = os.path.join(ROOT, "profiles", "dstage_counters_mw_L2048_spin0.md")
-    src = os.path.join(ROOT, "paper_2311_14670_amd", "csrc", "s2mi_kernels.hip")
     try:
         text = open(summ).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = kernel_source_sha()
     except OSError:
         return None
     if f"kernels source sha256 (first 16 hex): {sha}" not in text:

@@ -19,7 +19,9 @@ __device__ __forceinline__ int ufl(int x) { return __builtin_amdgcn_readfirstlan
 __device__ __forceinline__ void renorm(double &e, double &ep, int &E)
 {
     const double mx = fmax(fabs(e), fabs(ep));
-    const int k = mx > 0.0 ? ilogb(mx) : 0;          // a not-yet-started (zero) state keeps E
+    // floor(log2 mx) = frexp exponent - 1 (mx is finite: the state grows by a bounded
+    // factor between passes); a not-yet-started (zero) state keeps E
+    const int k = mx > 0.0 ? __builtin_amdgcn_frexp_exp(mx) - 1 : 0;
     const bool real = (E + k >= -RT);
     const int sh = real ? E : -k;
     e = ldexp(e, sh);

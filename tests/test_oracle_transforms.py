@@ -201,6 +201,33 @@ def test_healpix_inverse_brute_force(oracle):
     assert np.max(np.abs(f - ref)) < 1e-13
 
 
+@pytest.mark.parametrize("nside,L", [(2, 5), (4, 9)])
+def test_healpix_forward_brute_force(oracle, nside, L):
+    """The HEALPix forward is the quadrature of Eq. 19: (4 pi / Npix) sum_p f_p
+    conj(Y_lm(theta_p, phi_p)), summed term by term with scipy's Y_lm (spin 0)."""
+    npix = 12 * nside * nside
+    f = map_gaussian(npix, seed=26)
+    th, nphi, _, _ = oracle.healpix_rings(nside)
+    tht = np.repeat(th, nphi)
+    ph = oracle.healpix_phis(nside)
+    ref = np.zeros((L, 2 * L - 1), dtype=complex)
+    for l in range(L):
+        for m in range(-l, l + 1):
+            ref[l, m + L - 1] = 4.0 * np.pi / npix * np.sum(f * np.conj(sp.sph_harm_y(l, m, tht, ph)))
+    assert np.max(np.abs(oracle.s2_forward(f, L, 0, 1, nside) - ref)) < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("spin", [0, 2, -3])
+def test_healpix_forward_is_weighted_adjoint(oracle, spin):
+    """For any spin the HEALPix forward equals (4 pi / Npix) times the adjoint of
+    the inverse (itself pinned by the dot-product test)."""
+    nside, L = 4, 9
+    f = map_gaussian(12 * nside * nside, seed=27)
+    a = oracle.s2_forward(f, L, spin, 1, nside)
+    b = 4.0 * np.pi / (12 * nside * nside) * oracle.s2_inverse_adjoint(f, L, spin, 1, nside)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.abs(b).max()
+
+
 def test_healpix_low_degree_quadrature(oracle):
     """No sampling theorem: low-l content round-trips to a small quadrature error
     that shrinks with nside."""

@@ -122,6 +122,10 @@ class _S2InverseReal(torch.autograd.Function):
             return None, None
         return ctx.plan.inverse_real_adjoint(grad_f.contiguous()), None
 
+    @staticmethod
+    def jvp(ctx, t_flm, t_plan):
+        return ctx.plan.inverse_real(t_flm.contiguous())
+
 
 def inverse_real(flm, plan):
     """Differentiable real-signal inverse SHT (spin 0): flm [B?, L, 2L-1] complex128,
@@ -142,6 +146,10 @@ class _S2ForwardReal(torch.autograd.Function):
         if not ctx.needs_input_grad[0]:
             return None, None
         return ctx.plan.forward_real_adjoint(grad_flm.contiguous()), None
+
+    @staticmethod
+    def jvp(ctx, t_f, t_plan):
+        return ctx.plan.forward_real(t_f.contiguous())
 
 
 def forward_real(f, plan):

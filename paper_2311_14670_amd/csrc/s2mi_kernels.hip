@@ -224,21 +224,53 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
                                           double lam, int jin, double e0, int E0, double (&ac)[PAIR ? 8 : 4])
 {
     constexpr int RS = SIDE ? 3 : 5;
+    // GROUPED: all kappa-lambda products, then all recurrence updates, then the
+    // contractions, so that dependent FP64 operations issue several apart (the
+    // operations and the summation order are those of one slot after another).
+    // Measured at L = 2048, this pays only for the two-sided unpaired sweep (MW
+    // inverse 3.62 -> 3.36 ms); the one-sided and the paired sweeps keep the
+    // slot-by-slot order, which is faster for them (the paired form spills when
+    // grouped).
+    constexpr bool GROUPED = SIDE == 0 && !PAIR;
+    double tt[SG];
+    if constexpr (GROUPED) {
+        double p[SG];
+#pragma unroll
+        for (int j = 0; j < SG; ++j) p[j] = rec[j * RS] * lam;
+#pragma unroll
+        for (int j = 0; j < SG; ++j) {
+            double &nw = PAR == 0 ? Y[j] : X[j];          // receives order m
+            double &od = PAR == 0 ? X[j] : Y[j];          // holds order m+1
+            nw = fma(p[j], od, -nw);
+            tt[j] = nw;
+            if constexpr (SLOW) {
+                if (j == jin) {                           // this slot's l == m starts here
+                    nw = e0;
+                    od = 0.0;
+                    E[j] = E0;
+                }
+                tt[j] = ldexp(nw, E[j]);
+            }
+        }
+    }
 #pragma unroll
     for (int j = 0; j < SG; ++j) {
         const int o = (PAIR && (j & 1) == 0) ? 4 : 0;
-        double &nw = PAR == 0 ? Y[j] : X[j];              // receives order m
-        double &od = PAR == 0 ? X[j] : Y[j];              // holds order m+1
         const double *c = rec + j * RS;
-        nw = fma(c[0] * lam, od, -nw);
-        double t = nw;
-        if constexpr (SLOW) {
-            if (j == jin) {                               // this slot's l == m starts here
-                nw = e0;
-                od = 0.0;
-                E[j] = E0;
+        double t = tt[j];
+        if constexpr (!GROUPED) {
+            double &nw = PAR == 0 ? Y[j] : X[j];
+            double &od = PAR == 0 ? X[j] : Y[j];
+            nw = fma(c[0] * lam, od, -nw);
+            t = nw;
+            if constexpr (SLOW) {
+                if (j == jin) {
+                    nw = e0;
+                    od = 0.0;
+                    E[j] = E0;
+                }
+                t = ldexp(nw, E[j]);
             }
-            t = ldexp(nw, E[j]);
         }
         if constexpr (SIDE == 2) {
             ac[o + 2] = fma(t, c[1], ac[o + 2]);

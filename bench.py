@@ -275,7 +275,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the transform is not sharded "
-              "across GPUs in this build)", file=sys.stderr)
+              "across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch

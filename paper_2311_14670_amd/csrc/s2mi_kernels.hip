@@ -166,7 +166,7 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, int rs, const
 // every RN orders keeps it far from overflow; a chunk whose lanes all reached
 // E = 0 stays realised while no degree starts in it.
 constexpr int RN = 8;
-constexpr int PFD = 3;   // orders of record prefetch ahead of use (inverse sweep)
+constexpr int PFD = 3;   // orders of record / spectra prefetch ahead of use
 
 // Workgroups of the sweeps hold W = 4, 8 or 16 waves; the 4 x 64 outputs of an
 // order are reduced by one group of four waves, rotating with the order.
@@ -637,15 +637,18 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         // steps so the register roles line up with the main loop)
         const int hend = ((mstart - lmin + 1) % 2 == 0) ? lmin : lmin - 1;
         int m = mstart;
-        // Pull the wave's lambda and spectra rows of orders m - PFD, m - PFD - 1 toward
+        // Pull the wave's lambda and spectra rows of orders m - PFF, m - PFF - 1 toward
         // the caches (one dword per 128-byte line, PQ lanes per order); the result is
         // consumed only at the next pair of orders, so the latency overlaps their work.
         constexpr int HL = NCH * SG * 4 * 8 / 128;           // 128-byte lines of one side's spectra row
         constexpr int PQ = 1 + 2 * HL;
+        // prefetch distance: measured best at 3 orders for the two-sided run n = 0 of an
+        // unpaired sampling, at 2 for the one-sided, paired and n != 0 runs
+        constexpr int PFF = (SAME && SIDE == 0 && !PAIRF) ? PFD : PFD - 1;
         int pf = 0;
         auto prefetch = [&](int mm) {
             asm volatile("" ::"v"(pf));
-            const int mp = mm - PFD - (lane >= PQ ? 1 : 0);
+            const int mp = mm - PFF - (lane >= PQ ? 1 : 0);
             const int q = lane % PQ;
             if (lane < 2 * PQ && mp >= an) {
                 // q = 0: the wave's lambdas; q = 1..HL / HL+1..2HL: the spectra rows of the two sides

@@ -62,7 +62,7 @@ extern "C" {
 
 #define S2_OK               0
 #define S2_ERR_INVALID_ARG (-1)   /* bad L/spin/N/nside/batch, null or misaligned pointer */
-#define S2_ERR_UNSUPPORTED (-2)   /* valid request this build does not implement          */
+#define S2_ERR_UNSUPPORTED (-2)   /* valid request the library does not implement         */
 #define S2_ERR_OOM         (-3)   /* device or host allocation failed                     */
 #define S2_ERR_HIP         (-4)   /* HIP runtime or launch error (message kept)           */
 

@@ -290,7 +290,15 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
 // (nsw of nreg) and also produce the mirror ring nreg-1-r, using
 // d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta): with E and O the sums
 // over the even and odd degrees, ring r gets E + O and its mirror (-1)^m (E - O).
-template <int NCH, int PAR, int SIDE = 0, bool PAIR = false>
+template <int SIDE, bool PAIR>
+__device__ __forceinline__ void inv_reduce(int m, int L, int W, bool good, int ms, int ring0, int nreg, int nsw,
+                                           const double *rb, int blk, double *__restrict__ partA,
+                                           double *__restrict__ partB);
+
+// DEFER: write this order's partial sums to LDS and return; the caller reduces two
+// orders after one barrier (four LDS buffers, indexed by m mod 4).  Otherwise the
+// step reduces its own order after a barrier of its own (two buffers).
+template <int NCH, int PAR, int SIDE = 0, bool PAIR = false, bool DEFER = false>
 __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ms, int ring0, int nreg,
                                          int nsw, int lane,
                                          int w, int W,
@@ -338,11 +346,24 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
             if (__all(z)) fast |= (1u << g);
         }
     }
-    double *rb = red + (size_t)(m & 1) * DSTAGE_MAX_WAVES * NA * 64;
+    constexpr int NBUF = DEFER ? 4 : 2;
+    double *rb = red + (size_t)(m & (NBUF - 1)) * DSTAGE_MAX_WAVES * NA * 64;
 #pragma unroll
     for (int c = 0; c < NA; ++c)
         if (SIDE == 0 || (SIDE == 1) == ((c & 3) < 2)) rb[(w * NA + c) * 64 + lane] = ac[c];
-    __syncthreads();
+    if constexpr (!DEFER) {
+        __syncthreads();
+        inv_reduce<SIDE, PAIR>(m, L, W, good, ms, ring0, nreg, nsw, rb, blk, partA, partB);
+    }
+}
+
+// Sum of one order's partials over the waves (LDS buffer rb) and its store.
+template <int SIDE, bool PAIR>
+__device__ __forceinline__ void inv_reduce(int m, int L, int W, bool good, int ms, int ring0, int nreg, int nsw,
+                                           const double *rb, int blk, double *__restrict__ partA,
+                                           double *__restrict__ partB)
+{
+    constexpr int NA = PAIR ? 8 : 4;
     // four waves, rotating with the order, reduce the 4 x 64 outputs over the waves
     // (only the present side's 2 x 64 for SIDE 1 / 2)
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
@@ -389,7 +410,10 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
     const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
 {
-    __shared__ double red[2 * DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64];
+    // unpaired sweeps reduce two orders per barrier (four 16 KB buffers); the paired
+    // sweep, with twice the sums, keeps one barrier per order (two 32 KB buffers)
+    constexpr bool DEFER = !PAIR;
+    __shared__ double red[(DEFER ? 4 : 2) * DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64];
     const int an = n < 0 ? -n : n;
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
@@ -431,11 +455,23 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
                                                                   (NCH * SG) * RS);
             pf = Cp[(lane % (ROWB / 128)) * 32];
         }
-        inv_step<NCH, 0, SIDE, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
-                                     ncs, initr, C, red, blk, partA, partB);
-        if (m - 1 >= mend)
-            inv_step<NCH, 1, SIDE, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
-                                         ct, ncs, initr, C, red, blk, partA, partB);
+        inv_step<NCH, 0, SIDE, PAIR, DEFER>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
+                                            ct, ncs, initr, C, red, blk, partA, partB);
+        const bool two = m - 1 >= mend;
+        if (two)
+            inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
+                                                fast, ct, ncs, initr, C, red, blk, partA, partB);
+        if constexpr (DEFER) {
+            // one barrier for both orders; with 8 waves the two reducer groups take one
+            // order each.  The buffers of m and m - 1 are next written two iterations on,
+            // after the next barrier, which every reducer reaches only once done here.
+            constexpr size_t SL = (size_t)DSTAGE_MAX_WAVES * 4 * 64;
+            __syncthreads();
+            inv_reduce<SIDE, PAIR>(m, L, W, good, ms, ring0, nreg, nsw, red + (size_t)(m & 3) * SL, blk, partA, partB);
+            if (two)
+                inv_reduce<SIDE, PAIR>(m - 1, L, W, good, ms, ring0, nreg, nsw, red + (size_t)((m - 1) & 3) * SL, blk,
+                                       partA, partB);
+        }
     }
     asm volatile("" ::"v"(pf));
 }

@@ -595,7 +595,9 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
     if (HEAD) real = 0u;                                  // degrees start in this group: not realised
     if (!REAL && (m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
-    double *rb = red + (size_t)(m & 1) * FWD_MAX_WAVES * 4 * 64;
+    // this order's sums go to LDS buffer m mod 4 (W slots of 4 x 64); the caller
+    // reduces two orders after one barrier (fwd_reduce2)
+    double *rb = red + (size_t)(m & 3) * W * 4 * 64;
     if (SIDE != 2) {
         rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
         rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
@@ -604,12 +606,22 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
         rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
         rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
     }
-    __syncthreads();
-    const int tr = (int)threadIdx.x - 256 * reducer_group(m, W);
+}
+
+// Sum of order m's partials over the WT waves (LDS buffer m mod 4) and its store
+// to QA/QB[blk][l][m] (continuation orders m < 0: QxA/QxB).
+template <int WT, bool MAIN, int SIDE, bool PAIRF>
+__device__ __forceinline__ void fwd_reduce(int m, int g, int L, int nxp, int n, int an, const double *red, int blk,
+                                           double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
+                                           double *__restrict__ QxB)
+{
+    const double *rb = red + (size_t)(m & 3) * WT * 4 * 64;
+    const int am = MAIN ? m : (m < 0 ? -m : m);
+    const int tr = (int)threadIdx.x - 256 * reducer_group(m, WT);
     if (tr >= 0 && tr < 256 && (SIDE == 0 || (SIDE == 1) == (tr < 128))) {
         const int ll = tr & 63, comp = tr >> 6;
         const int lo = PAIRF ? 128 * (g >> 1) + 2 * ll + (g & 1) : 64 * g + ll;
-        const double s = wave_sum<FWD_MAX_WAVES>(rb, comp, ll, W);
+        const double s = wave_sum<WT>(rb, comp, ll, WT);
         if (MAIN) {
             if (lo < L && lo >= m && (m > 0 || comp < 2)) {
                 double *dst = comp < 2 ? QA : QB;
@@ -634,6 +646,20 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
 }
 
+// One barrier, then the reductions of orders m and (two) m - 1, whose buffers
+// (m mod 4, (m - 1) mod 4) are next written two iterations on, after the next
+// barrier, which every reducer reaches only once done here.  With 8 or 16 waves
+// the two orders go to different reducer groups.
+template <int WT, bool MAIN, int SIDE, bool PAIRF>
+__device__ __forceinline__ void fwd_reduce2(int m, bool two, int g, int L, int nxp, int n, int an, const double *red,
+                                            int blk, double *__restrict__ QA, double *__restrict__ QB,
+                                            double *__restrict__ QxA, double *__restrict__ QxB)
+{
+    __syncthreads();
+    fwd_reduce<WT, MAIN, SIDE, PAIRF>(m, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
+    if (two) fwd_reduce<WT, MAIN, SIDE, PAIRF>(m - 1, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
+}
+
 template <int NCH, bool SAME, int WT, int SIDE = 0, bool PAIRF = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
@@ -642,7 +668,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     const double *__restrict__ HxB, double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
     double *__restrict__ QxB)
 {
-    __shared__ double red[2 * FWD_MAX_WAVES * 4 * 64];
+    __shared__ double red[4 * WT * 4 * 64];         // four order buffers of WT x 4 x 64 sums
     const int an = n < 0 ? -n : n;
     const int mend = an > 1 ? -(an - 1) : 0;            // continuation below m = 0
     const int lane = threadIdx.x & 63;
@@ -705,6 +731,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
                                                                   hstride, lstride, nreg, rbase, X, Y, E, real, kk, gm,
                                                                   lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA,
                                                                   QB, QxA, QxB);
+            fwd_reduce2<WT, false, SIDE, PAIRF>(m, m - 1 >= mend, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
         }
         // both orders of the pair >= |n| (and > 0 when the sides share one array)
         constexpr uint32_t ALL = (1u << NCH) - 1u;
@@ -717,6 +744,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             fwd_step<NCH, 1, false, true, SAME, false, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                              lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                              kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_reduce2<WT, true, SIDE, PAIRF>(m, true, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
         }
         for (; m - 1 >= mlo; m -= 2) {                   // realised: plain contributions
             prefetch(m);
@@ -726,6 +754,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             fwd_step<NCH, 1, false, true, SAME, true, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                             lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
+            fwd_reduce2<WT, true, SIDE, PAIRF>(m, true, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
         }
         for (; m >= mend; m -= 2) {
             prefetch(m);
@@ -737,6 +766,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
                                                                    hstride, lstride, nreg, rbase, X, Y, E, real, kk,
                                                                    gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
                                                                    blk, QA, QB, QxA, QxB);
+            fwd_reduce2<WT, false, SIDE, PAIRF>(m, m - 1 >= mend, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
         }
         asm volatile("" ::"v"(pf));
         __syncthreads();   // the LDS buffers are reused by the next pass

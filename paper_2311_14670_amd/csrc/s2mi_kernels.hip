@@ -295,8 +295,8 @@ __device__ __forceinline__ void inv_reduce(int m, int L, int W, bool good, int m
                                            const double *rb, int blk, double *__restrict__ partA,
                                            double *__restrict__ partB);
 
-// DEFER: write this order's partial sums to LDS and return; the caller reduces two
-// orders after one barrier (four LDS buffers, indexed by m mod 4).  Otherwise the
+// DEFER: write this order's partial sums to LDS and return; the caller reduces four
+// orders after one barrier (eight LDS buffers, indexed by m mod 8).  Otherwise the
 // step reduces its own order after a barrier of its own (two buffers).
 template <int NCH, int PAR, int SIDE = 0, bool PAIR = false, bool DEFER = false>
 __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ms, int ring0, int nreg,
@@ -346,7 +346,7 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
             if (__all(z)) fast |= (1u << g);
         }
     }
-    constexpr int NBUF = DEFER ? 4 : 2;
+    constexpr int NBUF = DEFER ? 8 : 2;
     double *rb = red + (size_t)(m & (NBUF - 1)) * DSTAGE_MAX_WAVES * NA * 64;
 #pragma unroll
     for (int c = 0; c < NA; ++c)
@@ -410,10 +410,10 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
     const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
 {
-    // unpaired sweeps reduce two orders per barrier (four 16 KB buffers); the paired
+    // unpaired sweeps reduce four orders per barrier (eight 16 KB buffers); the paired
     // sweep, with twice the sums, keeps one barrier per order (two 32 KB buffers)
     constexpr bool DEFER = !PAIR;
-    __shared__ double red[(DEFER ? 4 : 2) * DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64];
+    __shared__ double red[(DEFER ? 8 : 2) * DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64];
     const int an = n < 0 ? -n : n;
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
@@ -444,33 +444,54 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     constexpr int RS = SIDE ? 3 : 5;                     // doubles per record
     constexpr int ROWB = NCH * SG * RS * 8;              // bytes of one wave's records per order
     static_assert(ROWB % 128 == 0, "a wave's record row spans whole cache lines");
-    for (int m = mt; m >= mend; m -= 2) {
-        // Pull the records of orders m - PFD and m - PFD - 1 toward the caches (one
-        // dword per 128-byte line); the result is consumed only at the next pair of
-        // orders, so the load latency overlaps this pair's work.
+    // Pull the records of orders mm - PFD and mm - PFD - 1 toward the caches (one
+    // dword per 128-byte line); the result is consumed only at the next pair of
+    // orders, so the load latency overlaps this pair's work.
+    auto prefetch = [&](int mm) {
         asm volatile("" ::"v"(pf));
-        if (m - PFD - 1 >= -nx && lane < 2 * ROWB / 128) {
-            const int row = m - PFD - (lane >= ROWB / 128 ? 1 : 0);
+        if (mm - PFD - 1 >= -nx && lane < 2 * ROWB / 128) {
+            const int row = mm - PFD - (lane >= ROWB / 128 ? 1 : 0);
             const int *Cp = reinterpret_cast<const int *>(C + (((size_t)blk * (L + nx) + (row + nx)) * W + w) *
                                                                   (NCH * SG) * RS);
             pf = Cp[(lane % (ROWB / 128)) * 32];
         }
-        inv_step<NCH, 0, SIDE, PAIR, DEFER>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
-                                            ct, ncs, initr, C, red, blk, partA, partB);
-        const bool two = m - 1 >= mend;
-        if (two)
-            inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
+    };
+    if constexpr (DEFER) {
+        // four orders per barrier, their sums in LDS buffers m mod 8; with 8 waves the
+        // two reducer groups take two orders each.  An order's buffer is next written
+        // two iterations on, after the next barrier, which every reducer reaches only
+        // once done here.
+        constexpr size_t SL = (size_t)DSTAGE_MAX_WAVES * 4 * 64;
+        for (int m = mt; m >= mend; m -= 4) {
+            prefetch(m);
+            inv_step<NCH, 0, SIDE, PAIR, DEFER>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
                                                 fast, ct, ncs, initr, C, red, blk, partA, partB);
-        if constexpr (DEFER) {
-            // one barrier for both orders; with 8 waves the two reducer groups take one
-            // order each.  The buffers of m and m - 1 are next written two iterations on,
-            // after the next barrier, which every reducer reaches only once done here.
-            constexpr size_t SL = (size_t)DSTAGE_MAX_WAVES * 4 * 64;
+            if (m - 1 >= mend)
+                inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y,
+                                                    E, fast, ct, ncs, initr, C, red, blk, partA, partB);
+            if (m - 2 >= mend) {
+                prefetch(m - 2);
+                inv_step<NCH, 0, SIDE, PAIR, DEFER>(m - 2, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y,
+                                                    E, fast, ct, ncs, initr, C, red, blk, partA, partB);
+                if (m - 3 >= mend)
+                    inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 3, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X,
+                                                        Y, E, fast, ct, ncs, initr, C, red, blk, partA, partB);
+            }
             __syncthreads();
-            inv_reduce<SIDE, PAIR>(m, L, W, good, ms, ring0, nreg, nsw, red + (size_t)(m & 3) * SL, blk, partA, partB);
-            if (two)
-                inv_reduce<SIDE, PAIR>(m - 1, L, W, good, ms, ring0, nreg, nsw, red + (size_t)((m - 1) & 3) * SL, blk,
-                                       partA, partB);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (m - q >= mend)
+                    inv_reduce<SIDE, PAIR>(m - q, L, W, good, ms, ring0, nreg, nsw, red + (size_t)((m - q) & 7) * SL,
+                                           blk, partA, partB);
+        }
+    } else {
+        for (int m = mt; m >= mend; m -= 2) {
+            prefetch(m);
+            inv_step<NCH, 0, SIDE, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
+                                         ncs, initr, C, red, blk, partA, partB);
+            if (m - 1 >= mend)
+                inv_step<NCH, 1, SIDE, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
+                                             fast, ct, ncs, initr, C, red, blk, partA, partB);
         }
     }
     asm volatile("" ::"v"(pf));

@@ -159,7 +159,8 @@ class Scheduler:
                 n -= 1
             if n == 0:
                 short = self._need(key, 1) - self.budget
-                busy = {h.key for h in self.inflight}
+                # the key being admitted is kept too: its plan was just built by _need
+                busy = {h.key for h in self.inflight} | {key}
                 if self.ex.evict(short, busy) > 0 and self._fits(key, 1):
                     continue
                 if not self.inflight:

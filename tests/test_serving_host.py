@@ -168,3 +168,29 @@ def test_busy_key_waits_while_other_keys_launch():
     serve(s, reqs, clock=clk, realtime=False, sleep=clk.sleep)
     assert [ids for _, ids in ex.launches] == [[0], [2], [1]]
     assert len(s.done) == 3 and not s.rejected
+
+
+def test_waiting_key_keeps_its_plan_under_pressure():
+    """A key that waits for in-flight memory keeps the plan its admission check
+    built: eviction never drops the key being admitted, so the plan is created
+    once, not once per pass of the serve loop."""
+    clk = Clock()
+
+    class Counting(FakeExecutor):
+        def __init__(self, *a, **kw):
+            super().__init__(*a, **kw)
+            self.created = collections.Counter()
+
+        def new_bytes(self, key):
+            if key not in self.plans:
+                self.created[key] += 1
+            return super().new_bytes(key)
+
+    ex = Counting(clk, n_streams=2, max_batch=1, plan_bytes=100, ws_bytes=0)
+    small, big = _req(0, 16), _req(1, 32)
+    budget = Scheduler.buffer_bytes(big.key, 1) + 2 * 100 + 50     # big fits only once small is done
+    s = Scheduler(ex, hbm_budget=budget)
+    serve(s, [small, big], clock=clk, realtime=False, sleep=clk.sleep)
+    assert len(s.done) == 2 and not s.rejected
+    assert [ids for _, ids in ex.launches] == [[0], [1]]
+    assert ex.created[big.key] == 1, ex.created

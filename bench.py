@@ -92,6 +92,12 @@ def mixed_precision(L, batch, steps, dev, fp64_plan):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        # stage split of one more pair (HIP events around every launch, on the launch stream)
+        plan.set_timing(True)
+        plan.read_timing()
+        plan.forward(plan.inverse(x))
+        stages = plan.read_timing()
+        plan.set_timing(False)
         fi = finv[0].cpu().numpy()
         y0 = y[0].cpu().numpy()
 
@@ -99,6 +105,8 @@ def mixed_precision(L, batch, steps, dev, fp64_plan):
             return {"max_rel": float(np.max(np.abs(a - b)) / np.max(np.abs(b))),
                     "rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b))}
         res[prec] = {"ms_per_batch_pair": ms, "maps_per_s": batch * 1e3 / ms,
+                     "stage_ms": {k: v[0] for k, v in stages.items()},
+                     "stage_launches": {k: v[1] for k, v in stages.items()},
                      "inverse_vs_fp64": err(fi, f64_inv), "pair_vs_fp64": err(y0, f64_pair),
                      "inverse_vs_oracle_rings": err(fi[rings], ref_rings),
                      "pair_vs_input": err(y0, flm[0])}
@@ -227,22 +235,57 @@ def healpix_pair(L, nside, steps, dev):
             "rings": 4 * nside - 1, "inverse_vs_oracle_rings": err}
 
 
-def cpu_baseline(L, spin, flm, nring_sample, norder_sample):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(L, spin, flm, nring_sample, norder_sample, runs=3, one_core_rings=8, one_core_orders=8):
+    """The oracle (direct sums, OpenMP over rings / orders) on the host cores: the
+    inverse on a sample of rings and the forward on a sample of orders at the same
+    L, extrapolated to one pair (every ring costs the same; the sampled orders span
+    the whole range).  Median of `runs` runs on all the threads OpenMP is given,
+    and of `runs` runs on one thread with a smaller sample."""
+    import ctypes
     import oracle
     oracle._load()
-    rings = np.unique(np.linspace(0, L - 1, nring_sample).astype(int))
-    ms = np.unique(np.linspace(-(L - 1), L - 1, norder_sample).astype(int))
+    gomp = ctypes.CDLL("libgomp.so.1")          # the OpenMP runtime the oracle runs on
     g = np.random.default_rng(11).standard_normal((L, 2 * L - 1)) + 0j
-    t0 = time.perf_counter()
-    oracle.s2_inverse(flm, L, spin, rings=rings)
-    t1 = time.perf_counter()
-    oracle.s2_forward(g, L, spin, ms=ms)
-    t2 = time.perf_counter()
-    pair_s = (t1 - t0) * L / rings.size + (t2 - t1) * (2 * L - 1) / ms.size
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / pair_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"inverse on {rings.size} of {L} rings + forward on {ms.size} of {2 * L - 1} orders, "
-                      f"L={L} MW spin {spin}, extrapolated to one pair ({t2 - t0:.1f} s measured)"}
+
+    def one_run(nr, no):
+        rings = np.unique(np.linspace(0, L - 1, nr).astype(int))
+        ms = np.unique(np.linspace(-(L - 1), L - 1, no).astype(int))
+        t0 = time.perf_counter()
+        oracle.s2_inverse(flm, L, spin, rings=rings)
+        t1 = time.perf_counter()
+        oracle.s2_forward(g, L, spin, ms=ms)
+        t2 = time.perf_counter()
+        return (t1 - t0) * L / rings.size + (t2 - t1) * (2 * L - 1) / ms.size, t2 - t0, rings.size, ms.size
+
+    threads = int(gomp.omp_get_max_threads())
+    multi = [one_run(nring_sample, norder_sample) for _ in range(runs)]
+    gomp.omp_set_num_threads(1)
+    try:
+        single = [one_run(one_core_rings, one_core_orders) for _ in range(runs)]
+    finally:
+        gomp.omp_set_num_threads(threads)
+    med = float(np.median([r[0] for r in multi]))
+    med1 = float(np.median([r[0] for r in single]))
+    nr, no = multi[0][2], multi[0][3]
+    return {"value": 1.0 / med, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"median of {runs} runs: inverse on {nr} of {L} rings + forward on {no} of {2 * L - 1} "
+                      f"orders, L={L} MW spin {spin}, extrapolated to one pair "
+                      f"({sum(r[1] for r in multi):.1f} s measured in all)",
+            "cpu_model": _cpu_model(),
+            "one_core": {"value": 1.0 / med1, "unit": "pairs/s", "cores": 1,
+                         "sample": f"median of {runs} runs: inverse on {single[0][2]} rings + forward on "
+                                   f"{single[0][3]} orders, extrapolated to one pair "
+                                   f"({sum(r[1] for r in single):.1f} s measured in all)"}}
 
 
 def main():

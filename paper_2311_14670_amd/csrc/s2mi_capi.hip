@@ -663,6 +663,12 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         PLANCHK(launch_kg_table(st, L, P->nx, g.lrow, P->kap, P->gtab, P->kg), "kappa/g table");
         const size_t per_m_d = std::max((size_t)g.kc * g.rpad, (size_t)(g.rpad / 8) * g.lp) * 32;
         P->mch = (int)std::max<size_t>(4, std::min<size_t>((size_t)L, ((size_t)512 << 20) / per_m_d));
+        // S2MI_MFMA_ORDER_CHUNK=k stages k orders of D per generator launch instead (tests: the
+        // recursion state carried across order chunks at small L; results do not depend on it)
+        if (const char *mc = std::getenv("S2MI_MFMA_ORDER_CHUNK")) {
+            const int k = std::atoi(mc);
+            if (k > 0) P->mch = std::min(L, k);
+        }
         const size_t per_m_ah = (size_t)std::max(g.kc, g.rpad / 8) * g.rows * 32;
         const size_t S = P->nslice, B = max_batch;
         const size_t nP1 = (size_t)P->nreg * L * 4, nQ1 = (size_t)L * L * 4;

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import oracle
+from conftest import fp64_err
 from paper_2311_14670_amd.synth import serving_trace
 
 pytestmark = pytest.mark.gpu
@@ -52,7 +53,7 @@ def test_mix_equals_alone_and_oracle():
         else:
             f = oracle.s2_inverse(r.data, k.L, k.spin, oracle.HEALPIX, k.nside)
             ref = oracle.s2_forward(f, k.L, k.spin, oracle.HEALPIX, k.nside)
-        assert rel_l2(r.result, ref) < 1e-12, (r.rid, k)
+        assert fp64_err(r.result, ref) < 1e-12, (r.rid, k)
 
 
 def test_mixed_precision_mix_matches_fp64():

@@ -151,6 +151,31 @@ int s2_inverse(s2_plan_t plan, const void *flm, void *f, int batch, void *worksp
                void *hip_stream);
 
 /*
+ * s2_inverse without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same operation, layouts and results as s2_inverse
+ * (the same kernels run; outputs are bitwise equal); the workspace is a fixed
+ * device array of S2_NOALLOC_SCRATCH_BYTES inside the library, one per GPU the
+ * library runs on, held from its first use on that GPU until the process ends.
+ * The call allocates nothing (no hipMalloc / hipFree, no events: stage timing is
+ * not recorded) and looks the array's device address up once per device.
+ *   flm [batch][L][2L-1] complex128 (device, read), f [batch][nsamples]
+ *   complex128 (device, written), 0 <= batch <= max_batch.
+ * Plans: FP64 sphere plans (N = 1) whose inverse needs at most
+ * S2_NOALLOC_SCRATCH_BYTES of workspace (its records and partial sums: MW
+ * L <= 512 at any spin, DH and HEALPix L <= 384); larger plans return
+ * S2_ERR_INVALID_ARG with the size they need in the message, matrix-core plans
+ * S2_ERR_UNSUPPORTED, SO(3) plans S2_ERR_INVALID_ARG.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from different host threads without ordering)
+ * race and give undefined results.  Calls ordered on one stream are safe.
+ * Nothing in the array needs to start at zero: each call writes every word it
+ * later reads.
+ */
+#define S2_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int s2_inverse_noalloc(s2_plan_t plan, const void *flm, void *f, int batch, void *hip_stream);
+
+/*
  * Forward spin SHT (Eq. 5 discretised as Eqs. 30-31).
  *   MW: exact for band-limited signals (sampling theorem, Sec. 4.2): the ring
  *       DFT extended to the theta-torus and integrated against sin(theta) on

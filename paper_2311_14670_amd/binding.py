@@ -74,6 +74,8 @@ def load_library():
                      "s2_forward_real", "s2_inverse_real_adjoint", "s2_forward_real_adjoint"]:
             getattr(lib, name).argtypes = [P, vp, vp, i, vp, vp]
             getattr(lib, name).restype = i
+        lib.s2_inverse_noalloc.argtypes = [P, vp, vp, i, vp]
+        lib.s2_inverse_noalloc.restype = i
         lib.s2_debug_wigner_d.argtypes = [P, i, vp, vp]
         lib.s2_plan_set_timing.argtypes = [P, i]
         lib.s2_plan_read_timing.argtypes = [P, ctypes.POINTER(_Timing)]
@@ -187,6 +189,22 @@ class Plan:
     def inverse(self, flm, workspace=None, out=None):
         """Inverse spin SHT: flm [B?, L, 2L-1] -> map."""
         return self._call(self._lib.s2_inverse, flm, self.coeff_shape, self.map_shape, "inverse", workspace, out)
+
+    def inverse_noalloc(self, flm, out=None):
+        """Inverse spin SHT through s2_inverse_noalloc: no workspace, the library's
+        fixed per-device scratch instead (FP64 plans whose inverse fits it)."""
+        x, B, batched = self._prep(flm, self.coeff_shape, "inverse_noalloc")
+        shape = ((B,) if batched else ()) + tuple(self.map_shape)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        elif (out.dtype != torch.complex128 or out.device != self.device or tuple(out.shape) != shape
+              or not out.is_contiguous()):
+            raise ValueError(f"inverse_noalloc: out must be a contiguous complex128 tensor of shape {shape}")
+        with torch.cuda.device(self.device):
+            _check(self._lib.s2_inverse_noalloc(self._handle, ctypes.c_void_p(x.data_ptr()),
+                                                ctypes.c_void_p(out.data_ptr()), int(B),
+                                                _stream_handle(self.device)))
+        return out
 
     def forward(self, f, workspace=None, out=None):
         """Forward spin SHT: map -> flm [B?, L, 2L-1]."""

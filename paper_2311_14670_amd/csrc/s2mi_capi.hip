@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -710,6 +711,10 @@ int s2_plan_create(s2_plan_t *out, int L, int spin, int N, s2_sampling_t samplin
 namespace {
 
 // Bracket one launch with events when the plan records stage timing.
+// Set for the duration of a call that must not allocate (s2_inverse_noalloc):
+// event creation and the timing record are skipped.
+thread_local bool g_no_timing = false;
+
 struct StageTimer {
     s2_plan_t P;
     int stage;
@@ -717,7 +722,7 @@ struct StageTimer {
     hipEvent_t a = nullptr, b = nullptr;
     StageTimer(s2_plan_t P_, int stage_, hipStream_t st_) : P(P_), stage(stage_), st(st_)
     {
-        if (P->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+        if (P->timing && !g_no_timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, st);
     }
     ~StageTimer()
@@ -1191,6 +1196,76 @@ int s2_inverse(s2_plan_t P, const void *flm, void *f, int batch, void *workspace
         if ((rc = run_inverse(P, (const double2 *)flm + b * slab, &out, P->w_sht, (char *)workspace, st))) return rc;
     }
     return S2_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ no-allocation inverse
+// The workspace of s2_inverse_noalloc: a fixed device array, one copy per GPU the
+// library runs on, held until the process ends.  Host code never uses the name
+// `scratch` as an address (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[S2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};   // per device index; nullptr until looked up
+
+// device address of `scratch` on the current device (looked up on the first call there)
+int scratch_on_current_device(void **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return fail(S2_ERR_UNSUPPORTED, "s2_inverse_noalloc: device index %d beyond %d", dev, SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return S2_OK;
+}
+
+// bytes of the workspace the FP64 inverse touches (records, partials, and the
+// split-Bluestein scratch when a ring DFT needs it)
+size_t inverse_extent(const s2_plan_s *P)
+{
+    if (P->sz_fscr) return P->off_fscr + P->sz_fscr;
+    return P->off_P + P->szP * P->nslice;
+}
+
+}  // namespace
+
+extern "C" {
+
+int s2_inverse_noalloc(s2_plan_t P, const void *flm, void *f, int batch, void *hip_stream)
+{
+    if (!P) return fail(S2_ERR_INVALID_ARG, "s2_inverse_noalloc: plan is NULL");
+    if (P->N != 1) return fail(S2_ERR_INVALID_ARG, "s2_inverse_noalloc: plan was created for SO(3) (N=%d)", P->N);
+    if (P->mfma) return fail(S2_ERR_UNSUPPORTED, "s2_inverse_noalloc: available for FP64 plans");
+    const size_t need = inverse_extent(P);
+    if (need > (size_t)S2_NOALLOC_SCRATCH_BYTES)
+        return fail(S2_ERR_INVALID_ARG,
+                    "s2_inverse_noalloc: this plan's inverse needs %zu bytes of scratch, more than the fixed %zu "
+                    "(use s2_inverse with a workspace)", need, (size_t)S2_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    int rc = scratch_on_current_device(&ws);
+    if (rc) return rc;
+    if ((rc = check_call("s2_inverse_noalloc", P, flm, f, batch, ws))) return rc;
+    if (batch == 0) return S2_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t slab = (size_t)P->L * (2 * P->L - 1);
+    g_no_timing = true;
+    for (int b = 0; b < batch && rc == S2_OK; ++b) {
+        double2 *out = (double2 *)f + (size_t)b * P->nsamp;
+        rc = run_inverse(P, (const double2 *)flm + b * slab, &out, P->w_sht, (char *)ws, st);
+    }
+    g_no_timing = false;
+    return rc;
 }
 
 int s2_forward(s2_plan_t P, const void *f, void *flm, int batch, void *workspace, void *hip_stream)

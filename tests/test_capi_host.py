@@ -57,6 +57,7 @@ def test_transform_validation_without_plan():
                "s2_inverse_real_adjoint", "s2_forward_real_adjoint"]:
         rc = getattr(lib, fn)(None, vp(16), vp(16), 1, vp(256), None)
         assert rc == -1
+    assert lib.s2_inverse_noalloc(None, vp(16), vp(16), 1, None) == -1
     assert lib.s2_plan_info(None, None) == -1
     assert lib.s2_plan_destroy(None) == 0
     assert lib.s2_error_string(-2).decode() == "unsupported"

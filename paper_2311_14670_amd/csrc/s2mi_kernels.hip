@@ -220,8 +220,8 @@ __device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[
 // of a chunk holds l = base + SG-1-j, base a multiple of SG, so l is odd
 // exactly when j is even).
 template <int PAR, bool SLOW, int SIDE = 0, bool PAIR = false>
-__device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int (&E)[SG], const double *__restrict__ rec,
-                                          double lam, int jin, double e0, int E0, double (&ac)[PAIR ? 8 : 4])
+__device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], const int (&E)[SG], const double *__restrict__ rec,
+                                          double lam, double (&ac)[PAIR ? 8 : 4])
 {
     constexpr int RS = SIDE ? 3 : 5;
     // GROUPED: all kappa-lambda products, then all recurrence updates, then the
@@ -242,15 +242,7 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
             double &nw = PAR == 0 ? Y[j] : X[j];          // receives order m
             double &od = PAR == 0 ? X[j] : Y[j];          // holds order m+1
             nw = fma(p[j], od, -nw);
-            tt[j] = nw;
-            if constexpr (SLOW) {
-                if (j == jin) {                           // this slot's l == m starts here
-                    nw = e0;
-                    od = 0.0;
-                    E[j] = E0;
-                }
-                tt[j] = ldexp(nw, E[j]);
-            }
+            tt[j] = SLOW ? ldexp(nw, E[j]) : nw;
         }
     }
 #pragma unroll
@@ -262,15 +254,7 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
             double &nw = PAR == 0 ? Y[j] : X[j];
             double &od = PAR == 0 ? X[j] : Y[j];
             nw = fma(c[0] * lam, od, -nw);
-            t = nw;
-            if constexpr (SLOW) {
-                if (j == jin) {
-                    nw = e0;
-                    od = 0.0;
-                    E[j] = E0;
-                }
-                t = ldexp(nw, E[j]);
-            }
+            t = SLOW ? ldexp(nw, E[j]) : nw;
         }
         if constexpr (SIDE == 2) {
             ac[o + 2] = fma(t, c[1], ac[o + 2]);
@@ -284,6 +268,22 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], int 
             }
         }
     }
+}
+
+// A degree l starts at order m = l from its start value e0 2^E0 (Eq. 27) with
+// e_{l+1} = 0.  Its slot holds zero state until then and its record at l == m
+// has kappa = 0, so writing -e0 into the register that receives order m lets the
+// ordinary step produce e_m = fma(0, 0, e0) = e0: every chunk runs one step form.
+// jin is wave-uniform.
+template <int PAR>
+__device__ __forceinline__ void inv_preset(double (&X)[SG], double (&Y)[SG], int (&E)[SG], int jin, double e0, int E0)
+{
+#pragma unroll
+    for (int j = 0; j < SG; ++j)
+        if (j == jin) {
+            (PAR == 0 ? Y[j] : X[j]) = -e0;
+            E[j] = E0;
+        }
 }
 
 // PAIR (spin 0, N/S-symmetric sampling): the lanes sweep the northern rings
@@ -320,16 +320,14 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
         const int base = lb[g];
         if (base < 0 || m > base + SG - 1) continue;     // chunk not started
         const double *rec = Cw + g * SG * RS;
-        if (m >= base) {                                  // ramp: slot jin starts at this order
-            const int jin = base + SG - 1 - m;
-            const double2 iv = initr[m];                 // d^m_{m,n}(theta_ring), zero if m < |n|
-            inv_chunk<PAR, true, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, m >= an ? jin : -1, iv.x, (int)iv.y, ac);
+        if (m >= base) {                                  // ramp: slot base + SG-1 - m starts at this order
+            if (m >= an) {
+                const double2 iv = initr[m];             // d^m_{m,n}(theta_ring) as (mantissa, exponent)
+                inv_preset<PAR>(X[g], Y[g], E[g], base + SG - 1 - m, iv.x, (int)iv.y);
+            }
             fast &= ~(1u << g);
-        } else if ((fast >> g) & 1u) {
-            inv_chunk<PAR, false, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
-        } else {
-            inv_chunk<PAR, true, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, ac);
         }
+        inv_chunk<PAR, true, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, ac);
     }
     // renormalisation pass every RN orders over the started chunks not yet realised
     if ((m & (RN - 1)) == 0) {

@@ -627,6 +627,43 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     }
 }
 
+// The main-loop order of a run whose two sides read one spectra array (SAME: run
+// n = 0 of an unpaired sampling, m > 0): the wave's lambda and spectra rows and the
+// lane's kappa and g are reached through pointers that step back one order at a
+// time, so an order carries no index arithmetic, and kappa and g of the next order
+// are plain loads (in the main loop every lane's degree has started, l > m; lanes
+// past L read row entries of L - 1 and are never stored).
+template <int NCH, int PAR, bool REAL, int SIDE>
+__device__ __forceinline__ void fwd_step_same(int m, int lane, int w, int W, int L, double (&X)[NCH][SG],
+                                              double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk,
+                                              double &gm, const double *__restrict__ &Lp,
+                                              const double *__restrict__ &Hp, const double *__restrict__ &kp,
+                                              const double *__restrict__ &gp, int lstride, int hstep, double *red)
+{
+    const double kcur = kk, gcur = gm;
+    kp -= L;
+    gp -= L;
+    kk = *kp;                                            // order m - 1
+    gm = *gp;
+    double aAr = 0.0, aAi = 0.0, aBr = 0.0, aBi = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        fwd_chunk<PAR, false, REAL, SIDE>(X[c], Y[c], E[c], Lp + c * SG, Hp + c * SG * 4, Hp + c * SG * 4 + 2, kcur,
+                                          false, 0, nullptr, 0, aAr, aAi, aBr, aBi);
+    Lp -= lstride;
+    Hp -= hstep;
+    if (!REAL && (m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
+    double *rb = red + (size_t)(m & 3) * W * 4 * 64;
+    if (SIDE != 2) {
+        rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
+        rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
+    }
+    if (SIDE != 1) {
+        rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
+        rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
+    }
+}
+
 // Sum of order m's partials over the WT waves (LDS buffer m mod 4) and its store
 // to QA/QB[blk][l][m] (continuation orders m < 0: QxA/QxB).
 template <int WT, bool MAIN, int SIDE, bool PAIRF>
@@ -755,6 +792,68 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         // both orders of the pair >= |n| (and > 0 when the sides share one array)
         constexpr uint32_t ALL = (1u << NCH) - 1u;
         const int mlo = SAME ? max(an, 1) : an;
+        if constexpr (SAME && !PAIRF) {
+            // Main loop with every per-order address stepped, not recomputed: the wave's
+            // lambda and spectra rows, the lane's kappa / g, the prefetch lanes' lines and
+            // each reducer thread's output column move back one order per step.
+            const double *Lp = lam + (ptrdiff_t)m * lstride + rbase;
+            const double *Hp = HA + ((size_t)m * hstride + rbase) * 4;
+            const double *kp = kap + (ptrdiff_t)m * L + lc;      // kk, gm hold order m already
+            const double *gp = gtab + (ptrdiff_t)m * L + lc;
+            const int hstep = hstride * 4;
+            // prefetch: lanes [0, PS) pull the rows of order m - PFF, lanes [PS, 2 PS) those
+            // of order m - PFF - 1 (lane q of a row: the lambdas for q = 0, else one
+            // 128-byte line of the spectra row); both sides share the spectra
+            constexpr int PS = 1 + HL;
+            const int q = lane % PS;
+            int pm = m - PFF - (lane >= PS ? 1 : 0);
+            const char *pa = q == 0 ? reinterpret_cast<const char *>(lam + (ptrdiff_t)pm * lstride + rbase)
+                                    : reinterpret_cast<const char *>(HA + ((ptrdiff_t)pm * hstride + rbase) * 4) +
+                                          (q - 1) * 128;
+            const ptrdiff_t pstep = q == 0 ? 2 * (ptrdiff_t)lstride * 8 : 2 * (ptrdiff_t)hstride * 32;
+            const bool plane = lane < 2 * PS;
+            // reducer thread (group threadIdx / 256, component, lane): its output column
+            // at order m is dcol[m * 4] (every order of the main loop is > 0 and < l)
+            const int rgrp = (int)threadIdx.x >> 8;
+            const int rcomp = ((int)threadIdx.x >> 6) & 3;
+            const int lo = 64 * g + lane;
+            double *dbase = rcomp < 2 ? QA : QB;
+            const bool rok = lo < L && dbase != nullptr && (SIDE == 0 || (SIDE == 1) == (rcomp < 2));
+            double *dcol = rok ? dbase + (((size_t)blk * L + lo) * L) * 4 + rcomp : nullptr;
+            auto reduce_pair = [&](int mm) {
+                __syncthreads();
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const int mo = mm - o;
+                    if (rok && rgrp == reducer_group(mo, WT)) {
+                        const double *rb = red + (size_t)(mo & 3) * WT * 4 * 64;
+                        dcol[(size_t)mo * 4] = wave_sum<WT>(rb, rcomp, lane, WT);
+                    }
+                }
+            };
+            auto pull = [&]() {
+                asm volatile("" ::"v"(pf));
+                if (plane && pm >= an) pf = *reinterpret_cast<const int *>(pa);
+                pa -= pstep;
+                pm -= 2;
+            };
+            for (; m - 1 >= mlo && real != ALL; m -= 2) {
+                pull();
+                fwd_step_same<NCH, 0, false, SIDE>(m, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp, lstride,
+                                                   hstep, red);
+                fwd_step_same<NCH, 1, false, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp,
+                                                   lstride, hstep, red);
+                reduce_pair(m);
+            }
+            for (; m - 1 >= mlo; m -= 2) {               // realised: plain contributions
+                pull();
+                fwd_step_same<NCH, 0, true, SIDE>(m, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp, lstride,
+                                                  hstep, red);
+                fwd_step_same<NCH, 1, true, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp,
+                                                  lstride, hstep, red);
+                reduce_pair(m);
+            }
+        }
         for (; m - 1 >= mlo && real != ALL; m -= 2) {
             prefetch(m);
             fwd_step<NCH, 0, false, true, SAME, false, SIDE, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,

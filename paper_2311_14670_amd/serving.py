@@ -523,6 +523,31 @@ def run_mix(n_requests=200, seed=3, lmin=64, lmax=1024, so3_lmax=256, n_streams=
     return out
 
 
+def check_subset(n_requests=100, seed=3, lmin=64, lmax=4096, so3_lmax=512, n_check=8, lmax_check=1024,
+                 n_streams=4, max_batch=8, device="cuda:0", precision="fp64"):
+    """Serve a sampled subset of a trace's MW and SO(3) requests (L <= lmax_check)
+    together, results kept, and compare each round trip with its input: on
+    band-limited coefficients the MW and Wigner sampling theorems make the exact
+    round trip the identity, so the input is what an exact transform returns.
+    Returns the worst relative L2 error and the keys checked."""
+    from .synth import serving_trace as _trace
+    trace = _trace(n_requests=n_requests, seed=seed, rate=1.0, lmin=lmin, lmax=lmax, so3_lmax=so3_lmax)
+    for spec in trace:
+        spec["precision"] = precision
+    reqs = build_requests(trace, seed)
+    pick = [r for r in reqs if r.key.sampling == "mw" and r.key.L <= lmax_check][:n_check]
+    ex = GpuExecutor(device=device, n_streams=n_streams, max_batch=max_batch, keep_results=True)
+    try:
+        import torch
+        sched = Scheduler(ex, hbm_budget=0.8 * torch.cuda.get_device_properties(torch.device(device)).total_memory)
+        serve(sched, pick, realtime=False)
+    finally:
+        ex.close()
+    worst = max((float(np.linalg.norm(r.result - r.data) / np.linalg.norm(r.data)) for r in pick), default=0.0)
+    return {"checked": len(pick), "keys": [f"{r.key.kind} L={r.key.L} s={r.key.spin} N={r.key.N}" for r in pick],
+            "worst_roundtrip_rel_l2": worst}
+
+
 def main(argv=None):
     import argparse
     import json

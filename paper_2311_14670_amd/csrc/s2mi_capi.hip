@@ -84,6 +84,7 @@ struct s2_plan_s {
     std::vector<double2 *> init;  // per run [nreg][L]: start values of Eq. 27
     // per-slice weights: SHT (Eqs. 30, 33), SO(3) inverse (Eq. 13), SO(3) forward (Eq. 14)
     std::vector<double *> w_sht, w_so3i, w_so3f;
+    double *w_so3f_n1 = nullptr;          // one-slice Wigner forward on the matrix cores: w_so3f times the gamma rule 2 pi
     std::vector<double *> w_fadj;         // HEALPix: (4 pi / Npix) w_l, the adjoint of the forward quadrature
     // FFT
     std::vector<FftArgs> ffts_h;
@@ -498,6 +499,14 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             if ((rc = upload(P, &a, stg.d.back(), st, "weights"))) return bail(rc);
             (kind == 0 ? P->w_sht : kind == 1 ? P->w_so3i : P->w_so3f).push_back(a);
         }
+    }
+    if (!so3 && sampling == S2_MW && spin == 0 && prec != S2_FP64) {
+        // so3_forward with N = 1 on the matrix-core path folds the gamma rule 2 pi/(2N-1) = 2 pi
+        // (Eq. 16) into the finish's weights instead of scaling a copy of the samples
+        stg.d.emplace_back();
+        host_weights(L, 2, 0, &stg.d.back());
+        for (double &v : stg.d.back()) v *= 2.0 * M_PI;
+        if ((rc = upload(P, &P->w_so3f_n1, stg.d.back(), st, "one-slice Wigner forward weights"))) return bail(rc);
     }
 
     // inverse d-stage assignment: waves of INV_NCH 8-degree chunks, W a multiple of 4.
@@ -1380,7 +1389,9 @@ int so3_forward(s2_plan_t P, const void *f, void *flmn, int batch, void *workspa
             }
             src = tmp;
         }
-        return run_forward_mfma(P, src, batch, (double2 *)flmn, P->w_so3f, (char *)workspace, st, false);
+        // one slice (N = 1): the gamma rule is the weight 2 pi alone, folded into the finish
+        const std::vector<double *> w1 = {P->w_so3f_n1};
+        return run_forward_mfma(P, src, batch, (double2 *)flmn, S > 1 ? P->w_so3f : w1, (char *)workspace, st, false);
     }
     for (int b = 0; b < batch; ++b) {
         const double2 *in = (const double2 *)f + (size_t)b * S * P->nsamp;

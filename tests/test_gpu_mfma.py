@@ -123,16 +123,19 @@ def _so3_inverse_adjoint_oracle(g, L, N):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_so3_batched(binding, prec):
-    L, N, B = 40, 8, 2
+@pytest.mark.parametrize("N", [8, 1])
+def test_so3_batched(binding, prec, N):
+    """N = 1 runs on a sphere plan (one slice: the gamma rule is the weight 2 pi)."""
+    L, B = 40, 2
     flmn = flmn_gaussian(L, N, seed=24, batch=B)
     plan = binding.Plan(L, N=N, max_batch=B, precision=prec)
     f = host(plan.so3_inverse(dev(flmn)))
     _check("so3 inverse", prec, f[1], oracle.so3_inverse(flmn[1], L, N))
     back = host(plan.so3_forward(dev(f)))
     _check("so3 round trip", prec, back[1], flmn[1])
-    # adjoint of the inverse (gradient path) against the oracle
     g = map_gaussian((B, 2 * N - 1, L, 2 * L - 1), seed=25)
+    _check("so3 forward", prec, host(plan.so3_forward(dev(g)))[0], oracle.so3_forward(g[0], L, N))
+    # adjoint of the inverse (gradient path) against the oracle
     adj = host(plan.so3_inverse_adjoint(dev(g)))
     _check("so3 inverse adjoint", prec, adj[1], _so3_inverse_adjoint_oracle(g[1], L, N))
 

@@ -24,6 +24,11 @@ FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak
 HBM_PEAK_GBS = 8000.0
 
 
+def _log(msg):
+    """Progress line on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_flops(L, spin, rings):
     """Per direction per map: 6 flop per (ring, l, m) triple at spin 0, 8 otherwise
     (4 contraction + 4 recursion per generated d; spin 0 generates d for m >= 0 only)."""
@@ -120,7 +125,7 @@ def _contraction_tflops(L, batch, prec, stages):
     BF16's three products, over the measured MFMA-stage time of one pair."""
     T = L * L * L
     flops = 8 * T * batch * (3 if prec == "split_bf16" else 1)
-    ms = stages.get("mfma", 0.0)
+    ms = stages.get("mfma", (0.0, 0))[0]
     peak = 2500.0 if prec == "split_bf16" else 157.3
     if ms <= 0:
         return None
@@ -326,7 +331,7 @@ def main():
                     help="maps per call of the matrix-core (FP32 / split-BF16) comparison; 0 skips it")
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--large-L", type=int, default=4096, help="also time one MW spin-0 pair at this L (0: skip)")
-    ap.add_argument("--serving-requests", type=int, default=100,
+    ap.add_argument("--serving-requests", type=int, default=80,
                     help="also serve a seeded mixed request stream (L log-uniform in [64, --serving-lmax], SO(3) "
                          "L <= --serving-so3-lmax) at FP64 and split BF16; 0: skip")
     ap.add_argument("--serving-lmax", type=int, default=4096)
@@ -428,26 +433,35 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = n * 8
+    _log(f"headline: {out['value']:.1f} pairs/s")
     if args.mixed_batch > 0 and spin == 0:
+        _log("matrix-core batch")
         out["mixed_precision"] = mixed_precision(L, args.mixed_batch, args.mixed_steps, dev, plan)
     if args.real_steps > 0 and spin == 0:
+        _log("real-signal pair")
         out["real_signal"] = real_signal(L, args.real_steps, dev)
     if args.healpix_steps > 0:
+        _log("HEALPix pair")
         out["healpix"] = healpix_pair(L, L // 2, args.healpix_steps, dev)
     if args.mw_steps > 0:
+        _log("MW L=1024 and spin-2 pairs")
         out["mw_other"] = mw_pairs([(1024, 0), (1024, 2), (2048, 2)], args.mw_steps, dev)
     if args.large_L > 0 and args.large_steps > 0:
+        _log(f"MW L={args.large_L} pair")
         out["large_L"] = largest_size(args.large_L, args.large_steps, dev)
     if args.serving_requests > 0:
         from paper_2311_14670_amd.serving import run_mix
         from paper_2311_14670_amd.serving import check_subset
         kw = dict(n_requests=args.serving_requests, lmax=args.serving_lmax, so3_lmax=args.serving_so3_lmax,
                   device=str(dev))
+        _log("serving, FP64")
         out["serving"] = run_mix(**kw)
         out["serving"]["sampled_check"] = check_subset(**kw)
+        _log("serving, split BF16")
         out["serving_split_bf16"] = run_mix(**kw, precision="split_bf16")
         out["serving_split_bf16"]["sampled_check"] = check_subset(**kw, precision="split_bf16")
     if not args.no_cpu_baseline:
+        _log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(L, spin, flm, args.cpu_rings, args.cpu_orders)
     print(json.dumps(out), flush=True)
 

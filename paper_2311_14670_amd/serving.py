@@ -23,6 +23,7 @@ executor object; ``GpuExecutor`` runs batches through the library's C ABI.
 import collections
 import dataclasses
 import itertools
+import sys
 import time
 
 import numpy as np
@@ -496,11 +497,15 @@ def run_mix(n_requests=200, seed=3, lmin=64, lmax=1024, so3_lmax=256, n_streams=
     ex = GpuExecutor(device=device, n_streams=n_streams, max_batch=max_batch, keep_results=False)
     out = {"requests": n_requests, "seed": seed, "L_range": [lmin, lmax], "so3_L_max": so3_lmax,
            "streams": n_streams, "max_batch": max_batch, "precision": precision}
+    def note(msg):
+        print(f"[serving] {precision}: {msg}", file=sys.stderr, flush=True)
     try:
         # warm pass over the whole trace builds every plan (host tables take up to ~1 s
         # each) and workspace once, so the saturation pass measures steady-state serving
+        note(f"warm pass, {n_requests} requests")
         sched = Scheduler(ex, hbm_budget=budget_frac * total)
         serve(sched, build_requests(trace, seed), realtime=False)
+        note("saturation pass")
         reqs = build_requests(trace, seed)
         sched = Scheduler(ex, hbm_budget=budget_frac * total)
         wall = serve(sched, reqs, realtime=False)
@@ -509,6 +514,7 @@ def run_mix(n_requests=200, seed=3, lmin=64, lmax=1024, so3_lmax=256, n_streams=
         out["rejected"] = len(sched.rejected)
         for frac in loads:
             rate = frac * lam
+            note(f"load {frac} ({rate:.1f} requests/s)")
             tr = serving_trace(n_requests=n_requests, seed=seed, rate=rate, lmin=lmin, lmax=lmax,
                                so3_lmax=so3_lmax)
             reqs = build_requests(tr, seed)

@@ -110,6 +110,12 @@ typedef struct {
                                    S2MI_RING_PAIRING=0/1 forces off/on) the northern
                                    half, mirror rings following from
                                    d^l_{m,0}(pi - theta) = (-1)^{l+m} d^l_{m,0}(theta) */
+    int order_tiles;            /* FP64 sweeps: order ranges run as separate slices of
+                                   the grid (1: none), each starting from the Wigner
+                                   recursion's state stored at plan creation; chosen
+                                   when the sweeps' grids would leave the device
+                                   under-filled (environment S2MI_ORDER_TILES=k
+                                   forces k, at most 8)                            */
 } s2_plan_info_t;
 
 /*

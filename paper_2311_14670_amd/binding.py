@@ -43,7 +43,8 @@ class _PlanInfo(ctypes.Structure):
                 ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("nrings", ctypes.c_int), ("nsamples", ctypes.c_longlong), ("ncoeffs", ctypes.c_longlong),
                 ("workspace_bytes", ctypes.c_size_t), ("plan_device_bytes", ctypes.c_size_t),
-                ("swept_rings", ctypes.c_int)]
+                ("swept_rings", ctypes.c_int),
+                ("order_tiles", ctypes.c_int)]
 
 
 _lib = None

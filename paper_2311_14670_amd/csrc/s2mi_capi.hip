@@ -108,6 +108,9 @@ struct s2_plan_s {
     int fwdp_nblk = 1, fwdp_waves = 4, Gp = 1, pstride = 0;
     size_t off_Fp = 0;                    // workspace: sums and differences of mirror-ring spectra
     int hstride = 0;                       // ring stride of the forward spectra (padded to the sweep's slots)
+    // order tiles of the FP64 sweeps and, per run, the recursion state at their cuts
+    OrderTiles tiles{};
+    std::vector<double *> ck;
     // workspace layout (bytes)
     size_t off_C = 0, off_P = 0, off_maps = 0, off_F = 0, off_Q = 0, off_hpole = 0, ws_bytes = 0;
     size_t off_fscr = 0, sz_fscr = 0;      // split-Bluestein scratch: FFT_SCRATCH complex per FFT workgroup
@@ -301,6 +304,7 @@ int s2_plan_info(s2_plan_t P, s2_plan_info_t *info)
     info->workspace_bytes = P->ws_bytes;
     info->plan_device_bytes = P->plan_bytes;
     info->swept_rings = P->nsw;
+    info->order_tiles = P->ck.empty() ? 1 : P->tiles.nt;
     return S2_OK;
 }
 
@@ -534,12 +538,32 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             const int half_rings = (P->nreg + 1) / 2;
             if (mode == 1 || (half_rings + 63) / 64 * P->inv_nblk >= ncu) P->nsw = half_rings;
         }
-        // a grid of at most half the compute units: four-wave workgroups over twice the
-        // l-blocks (a smaller per-order reduction, twice the workgroups; MW L = 1024 spin 2:
-        // inverse sweeps 2.84 -> 2.53 ms)
-        if (P->inv_waves == DSTAGE_MAX_WAVES && 2 * ((P->nsw + 63) / 64) * P->inv_nblk <= ncu) {
-            P->inv_waves = 4;
-            P->inv_nblk *= 2;
+        // Order tiles (FP64 sweeps; see OrderTiles): a grid of fewer than two waves per
+        // SIMD is run as nt tiles aiming at four (more, shorter workgroups also even out
+        // the tail), at most one per 64 orders (128 for the mirror-ring sweeps, whose
+        // forward degree groups span 128).  Measured, MW L = 1024 spin 0: sweeps 0.90 +
+        // 1.00 ms untiled, 0.46 + 0.58 ms in 8 tiles; at L = 2048, where the grid already
+        // holds two waves per SIMD, 2 tiles made the forward sweep slower (3.05 -> 3.5 ms).
+        // If the tiled grid still holds fewer than two waves per SIMD, four-wave
+        // workgroups over twice the l-blocks (MW L = 512: inverse 0.206 -> 0.193 ms; at
+        // L = 1024 in 8 tiles the eight-wave form is faster, 0.72 -> 0.46 ms, its l-blocks
+        // writing half the partial sums).  S2MI_ORDER_TILES=k forces k tiles (1: none),
+        // S2MI_INV_WAVES=4 / 8 the inverse workgroup size (tests, tuning).
+        {
+            const long long base = (long long)((P->nsw + 63) / 64) * P->inv_nblk * P->inv_waves;
+            const long long two = 8LL * ncu, four = 16LL * ncu;
+            const int q = P->nsw < P->nreg ? 128 : 64;
+            int nt = base >= two ? 1 : (int)std::min<long long>(MAX_ORDER_TILES, (four + base - 1) / base);
+            if (const char *ev = std::getenv("S2MI_ORDER_TILES"))
+                nt = std::max(1, std::min(MAX_ORDER_TILES, std::atoi(ev)));
+            if (prec != S2_FP64) nt = 1;                     // the matrix-core path has no FP64 sweeps
+            nt = std::min(nt, std::max(1, L / q));
+            P->tiles.nt = nt;
+            const char *iw = std::getenv("S2MI_INV_WAVES");
+            if (P->inv_waves == DSTAGE_MAX_WAVES && (iw ? iw[0] == '4' : base * nt < two)) {
+                P->inv_waves = 4;
+                P->inv_nblk *= 2;
+            }
         }
         stg.i.emplace_back(); std::vector<int> &lch = stg.i.back();
         stg.i.emplace_back(); std::vector<int> &ls = stg.i.back();
@@ -552,15 +576,24 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
     // forward d-stage assignment: wave w of block b sweeps rings (b W + w) FWD_R ..
     // + FWD_R - 1; rings past the last regular ring are inert padding.  W is 4, 8
     // or 16 (rotating groups of four reducer waves); larger workgroups mean fewer
-    // ring blocks and so fewer partial sums to write and add up in the finish.
+    // ring blocks and so fewer partial sums to write and add up in the finish.  At
+    // most 16 ring blocks where the waves allow (MW L = 1024 in 8 order tiles: 32
+    // blocks of 4 waves 0.62 ms, 16 blocks of 8 waves 0.58 ms, finish 0.15 -> 0.07 ms).
     {
         P->G = (L + 63) / 64;
         const int pairs = (P->G + 1) / 2;
-        int nb = std::max(1, std::min(256 / pairs, (P->nreg + 4 * FWD_R - 1) / (4 * FWD_R)));
+        int nb = std::max(1, std::min({16, 256 / pairs, (P->nreg + 4 * FWD_R - 1) / (4 * FWD_R)}));
         int W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R);
         while (W > FWD_MAX_WAVES) { ++nb; W = (P->nreg + nb * FWD_R - 1) / (nb * FWD_R); }
         W = W <= 4 ? 4 : W <= 8 ? 8 : 16;                    // 1, 2 or 4 groups of four waves
         if (W > FWD_MAX_WAVES) W = FWD_MAX_WAVES;
+        if (const char *fw = std::getenv("S2MI_FWD_WAVES")) {   // 4, 8 or 16 forced (tuning)
+            const int Wf = std::atoi(fw);
+            if (Wf == 4 || Wf == 8 || Wf == 16) {
+                W = Wf;
+                nb = (P->nreg + W * FWD_R - 1) / (W * FWD_R);
+            }
+        }
         P->fwd_nblk = nb;
         P->fwd_waves = W;
         P->hstride = std::max(nb * W * FWD_R, P->nring);
@@ -570,7 +603,7 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             P->fwd_pair = true;
             P->Gp = 2 * ((L + 127) / 128);
             const int pp = (P->Gp + 1) / 2;
-            int nbp = std::max(1, std::min(256 / pp, (P->nsw + 4 * FWD_R - 1) / (4 * FWD_R)));
+            int nbp = std::max(1, std::min({16, 256 / pp, (P->nsw + 4 * FWD_R - 1) / (4 * FWD_R)}));
             int Wp = (P->nsw + nbp * FWD_R - 1) / (nbp * FWD_R);
             while (Wp > FWD_MAX_WAVES) { ++nbp; Wp = (P->nsw + nbp * FWD_R - 1) / (nbp * FWD_R); }
             Wp = Wp <= 4 ? 4 : Wp <= 8 ? 8 : 16;
@@ -593,6 +626,37 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         PLANCHK(launch_init_table(st, L, P->nreg, r.n, P->lsin, P->lcos, P->lbin[ri], ini), "start values");
         P->lam.push_back(lam);
         P->init.push_back(ini);
+    }
+
+    // order-tile cuts (tile count chosen with the inverse geometry above): tiles of about
+    // equal work (the work above order m grows like (L - m)^2), cut at whole forward
+    // degree groups, and per run the recursion state at each cut
+    if (P->tiles.nt > 1) {
+        const int q = P->fwd_pair ? 128 : 64;
+        const int nt = P->tiles.nt;
+        OrderTiles &ot = P->tiles;
+        ot.c[0] = L;
+        int k = 1;
+        for (int j = 1; j < nt; ++j) {
+            const double c = (double)L * (1.0 - std::sqrt((double)j / nt));
+            int cq = (int)std::lround(c / q) * q;
+            cq = std::max(q, std::min(cq, (L - 1) / q * q));
+            if (cq < ot.c[k - 1]) ot.c[k++] = cq;
+        }
+        ot.nt = k;
+        ot.rp = (P->nreg + 63) / 64 * 64;
+        size_t tot = 0;
+        for (int j = 1; j < ot.nt; ++j) {
+            ot.off[j] = (long long)tot;
+            tot += (size_t)(L - ot.c[j]) * 3 * ot.rp;
+        }
+        for (size_t ri = 0; ri < P->runs.size() && ot.nt > 1; ++ri) {
+            double *ck;
+            if ((rc = P->dalloc(&ck, tot, "order-tile states"))) return bail(rc);
+            PLANCHK(launch_order_ckpt(st, L, P->nreg, P->runs[ri].n, P->cot, P->csc, P->init[ri], P->kap, ot, ck),
+                    "order-tile states");
+            P->ck.push_back(ck);
+        }
     }
 
     // workspace layout
@@ -759,6 +823,15 @@ int check_call(const char *fn, s2_plan_t P, const void *in, const void *out, int
     return S2_OK;
 }
 
+// the order tiles of run ri (one tile where the plan has no state tables)
+OrderTiles run_tiles(const s2_plan_s *P, size_t ri)
+{
+    OrderTiles ot = P->tiles;
+    if (ri < P->ck.size()) ot.ck = P->ck[ri];
+    else ot.nt = 1;
+    return ot;
+}
+
 // the workspace's split-Bluestein scratch (nullptr when no DFT of the plan needs it)
 double2 *fft_scratch(const s2_plan_s *P, char *ws)
 {
@@ -792,7 +865,8 @@ int run_inverse_dstage(s2_plan_t P, const double2 *flm, const std::vector<double
         HIPCHK(launch_dstage_inv(st, P->inv_waves, P->inv_nblk, L, P->nx, P->nreg, r.n, P->cot, P->csc, P->init[ri], C,
                                  P->lchunk, P->mtop,
                                  r.sliceA >= 0 ? P0 + r.sliceA * nP : nullptr,
-                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr, side, P->nsw), "inverse d-stage");
+                                 r.sliceB >= 0 ? P0 + r.sliceB * nP : nullptr, side, P->nsw, run_tiles(P, ri)),
+               "inverse d-stage");
     }
     return S2_OK;
 }
@@ -876,7 +950,7 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const dou
         HIPCHK(launch_pair_spectra(st, L, P->nreg, P->nsw, P->hstride, P->pstride, H0, S, D), "mirror spectra");
         HIPCHK(launch_dstage_fwd(st, P->fwdp_waves, P->fwdp_nblk, P->Gp, L, 1, P->nsw, P->pstride, P->hstride, 0,
                                  P->lam[0], P->init[0], P->kap, P->gtab, S, D, nullptr, nullptr, Q0, Q0, nullptr,
-                                 nullptr, half, 1), "forward d-stage");
+                                 nullptr, half, 1, run_tiles(P, 0)), "forward d-stage");
     }
     for (size_t ri = 0; ri < P->runs.size() && !P->fwd_pair; ++ri) {
         const Run &r = P->runs[ri];
@@ -895,7 +969,8 @@ int run_forward_dstage(s2_plan_t P, double *H0, const double2 *hpole0, const dou
                                  r.sliceA >= 0 ? Q0 + r.sliceA * nQ : nullptr,
                                  r.sliceB >= 0 ? Q0 + r.sliceB * nQ : nullptr,
                                  (an > 0 && r.sliceA >= 0) ? Qx0 + r.sliceA * nQx : nullptr,
-                                 (an > 0 && r.sliceB >= 0) ? Qx0 + r.sliceB * nQx : nullptr, side), "forward d-stage");
+                                 (an > 0 && r.sliceB >= 0) ? Qx0 + r.sliceB * nQx : nullptr, side, 0,
+                                 run_tiles(P, ri)), "forward d-stage");
     }
     for (int k = 0; k < P->nslice; ++k) {
         const int s = P->slice_spin[k];

@@ -63,6 +63,21 @@ constexpr int GEN_NCH = 2;              // 8-degree chunks per wave, d-tile gene
 constexpr int DSTAGE_MAX_WAVES = 8;     // inverse sweep / d-tile generator workgroups: at most 512 threads
 constexpr int FWD_MAX_WAVES = 16;       // forward sweep workgroups: at most 1024 threads (4, 8 or 16 waves)
 
+// Order tiles of the sweeps.  Tile k runs the orders c[k] - 1 down to c[k+1]
+// (c[0] = L; the last tile runs down to the run's lowest order), so that more
+// workgroups share one run without adding partial sums (each order stays in one
+// tile).  A tile k > 0 starts from the recursion state after order c[k], held per
+// run in ck at offset off[k] as rows (l - c[k]), l >= c[k], of 3 x rp doubles:
+// {e_{c[k]}[ring], e_{c[k]+1}[ring], E[ring]} (d = e 2^E).
+constexpr int MAX_ORDER_TILES = 8;
+struct OrderTiles {
+    int nt = 1;                             // tiles (1: the whole order range)
+    int rp = 0;                             // ring stride of a state row
+    int c[MAX_ORDER_TILES + 1] = {};
+    long long off[MAX_ORDER_TILES] = {};
+    const double *ck = nullptr;             // the run's state table (nt > 1)
+};
+
 // One recursion run: fixed second index n of d^l_{m,n}; its A side feeds the
 // slice of spin -n at orders +m, its B side the slice of spin +n at orders -m.
 struct Run {

@@ -12,14 +12,19 @@ hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int s
                            const double *kap, const double *gtab, double *C, int side = 0);
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
-                             const int *mtop, double *partA, double *partB, int side = 0, int nsw = 0);
+                             const int *mtop, double *partA, double *partB, int side, int nsw,
+                             const OrderTiles &ot);
 hipError_t launch_init_table(hipStream_t st, int L, int nreg, int n, const double *lsin, const double *lcos,
                              const double *lbin, double2 *init);
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
                              int lstride, int n, const double *lam, const double2 *init, const double *kap,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
-                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int side = 0,
-                             int pair = 0);
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int side,
+                             int pair, const OrderTiles &ot);
+// The recursion state at the order-tile cuts of one run (see OrderTiles): rings
+// [0, rp) (zero past nreg), degrees l >= c[k] of each cut k >= 1.
+hipError_t launch_order_ckpt(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
+                             const double2 *init, const double *kap, const OrderTiles &ot, double *ck);
 hipError_t launch_pair_spectra(hipStream_t st, int L, int nreg, int nsw, int hstride, int pstride, const double *H,
                                double *S, double *D);
 hipError_t launch_lambda_table(hipStream_t st, int L, int nx, int nreg, int lstride, int n, const double *cot,

@@ -168,6 +168,56 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, int rs, const
 constexpr int RN = 8;
 constexpr int PFD = 3;   // orders of record / spectra prefetch ahead of use
 
+// ------------------------------------------------------------------ order-tile states
+// State of the descending recursion (Eq. 25 in the rescaled form of the sweeps)
+// after order c of every order-tile cut c = ot.c[k], k >= 1, for ring r and degree
+// l >= c: thread (r, l) starts at order l from d^l_{l,n} (Eq. 27) and steps down
+// with the sweeps' operations (kappa lambda, then one fma), renormalising every RN
+// orders by exact powers of two.  A sweep that renormalises at other orders holds
+// the same e 2^E, so the d values it contributes from a tile's start are those of
+// the uninterrupted sweep.  Rings past nreg and degrees below |n| (never started)
+// hold zeros.
+__global__ void k_order_ckpt(int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
+                             const double2 *__restrict__ init, const double *__restrict__ kap, OrderTiles ot,
+                             double *__restrict__ ck)
+{
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int l = (int)blockIdx.y;
+    if (r >= ot.rp) return;
+    const int an = n < 0 ? -n : n;
+    const bool live = r < nreg && l >= an;
+    double cur = 0.0, prev = 0.0;                        // e_m, e_{m+1}
+    int E = 0;
+    double ct = 0.0, ncs = 0.0;
+    if (live) {
+        const double2 v = init[(size_t)r * L + l];
+        cur = v.x;
+        E = (int)v.y;
+        ct = cot[r];
+        ncs = (double)n * csc[r];
+    }
+    int m = l;
+    for (int k = 1; k < ot.nt; ++k) {
+        const int c = ot.c[k];
+        if (c > l) continue;
+        if (live) {
+            for (int mm = m - 1; mm >= c; --mm) {
+                const double lam = fma(-(double)(mm + 1), ct, ncs);
+                const double p = kap[(ptrdiff_t)mm * L + l] * lam;
+                const double nw = fma(p, cur, -prev);
+                prev = cur;
+                cur = nw;
+                if ((mm & (RN - 1)) == 0) renorm(cur, prev, E);
+            }
+            m = c;
+        }
+        double *q = ck + ot.off[k] + (size_t)(l - c) * 3 * ot.rp + r;
+        q[0] = cur;
+        q[ot.rp] = prev;
+        q[2 * ot.rp] = (double)E;
+    }
+}
+
 // Workgroups of the sweeps hold W = 4, 8 or 16 waves; the 4 x 64 outputs of an
 // order are reduced by one group of four waves, rotating with the order.
 __device__ __forceinline__ int reducer_group(int m, int W)
@@ -406,7 +456,7 @@ template <int NCH, int WT, int SIDE = 0, bool PAIR = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     int L, int nx, int nreg, int nsw, int n, const double *__restrict__ cot, const double *__restrict__ csc,
     const double2 *__restrict__ init, const double *__restrict__ C, const int *__restrict__ lchunk,
-    const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB)
+    const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB, OrderTiles ot)
 {
     // unpaired sweeps reduce four orders per barrier (eight 16 KB buffers); the paired
     // sweep, with twice the sums, keeps one barrier per order (two 32 KB buffers)
@@ -437,7 +487,28 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
         for (int j = 0; j < SG; ++j) { X[g][j] = 0.0; Y[g][j] = 0.0; E[g][j] = 0; }
     uint32_t fast = 0;
 
-    const int mt = ufl(mtop[blk]);
+    // order tile blockIdx.z: orders ctop - 1 .. bot; the slots whose degree started
+    // above the tile (l >= ctop) resume from the stored state after order ctop
+    const int tile = blockIdx.z;
+    const int ctop = tile == 0 ? L : ot.c[tile];
+    const int bot = tile + 1 < ot.nt ? ot.c[tile + 1] : mend;
+    const int mt = min(ufl(mtop[blk]), ctop - 1);
+    if (mt < bot) return;                               // no degree of this block reaches the tile
+    if (tile > 0) {
+        const double *ck = ot.ck + ot.off[tile] + ring;
+#pragma unroll
+        for (int g = 0; g < NCH; ++g)
+#pragma unroll
+            for (int j = 0; j < SG; ++j) {
+                const int l = lb[g] + SG - 1 - j;
+                if (lb[g] >= 0 && l >= ctop && l < L) {   // PAR 0 at order ctop - 1: X holds e_{ctop}
+                    const double *q = ck + (size_t)(l - ctop) * 3 * ot.rp;
+                    X[g][j] = q[0];
+                    Y[g][j] = q[ot.rp];
+                    E[g][j] = (int)q[2 * ot.rp];
+                }
+            }
+    }
     int pf = 0;
     constexpr int RS = SIDE ? 3 : 5;                     // doubles per record
     constexpr int ROWB = NCH * SG * RS * 8;              // bytes of one wave's records per order
@@ -460,34 +531,34 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
         // two iterations on, after the next barrier, which every reducer reaches only
         // once done here.
         constexpr size_t SL = (size_t)DSTAGE_MAX_WAVES * 4 * 64;
-        for (int m = mt; m >= mend; m -= 4) {
+        for (int m = mt; m >= bot; m -= 4) {
             prefetch(m);
             inv_step<NCH, 0, SIDE, PAIR, DEFER>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
                                                 fast, ct, ncs, initr, C, red, blk, partA, partB);
-            if (m - 1 >= mend)
+            if (m - 1 >= bot)
                 inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y,
                                                     E, fast, ct, ncs, initr, C, red, blk, partA, partB);
-            if (m - 2 >= mend) {
+            if (m - 2 >= bot) {
                 prefetch(m - 2);
                 inv_step<NCH, 0, SIDE, PAIR, DEFER>(m - 2, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y,
                                                     E, fast, ct, ncs, initr, C, red, blk, partA, partB);
-                if (m - 3 >= mend)
+                if (m - 3 >= bot)
                     inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 3, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X,
                                                         Y, E, fast, ct, ncs, initr, C, red, blk, partA, partB);
             }
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (m - q >= mend)
+                if (m - q >= bot)
                     inv_reduce<SIDE, PAIR>(m - q, L, W, good, ms, ring0, nreg, nsw, red + (size_t)((m - q) & 7) * SL,
                                            blk, partA, partB);
         }
     } else {
-        for (int m = mt; m >= mend; m -= 2) {
+        for (int m = mt; m >= bot; m -= 2) {
             prefetch(m);
             inv_step<NCH, 0, SIDE, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
                                          ncs, initr, C, red, blk, partA, partB);
-            if (m - 1 >= mend)
+            if (m - 1 >= bot)
                 inv_step<NCH, 1, SIDE, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
                                              fast, ct, ncs, initr, C, red, blk, partA, partB);
         }
@@ -722,7 +793,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
     const double *__restrict__ HA, const double *__restrict__ HB, const double *__restrict__ HxA,
     const double *__restrict__ HxB, double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
-    double *__restrict__ QxB)
+    double *__restrict__ QxB, OrderTiles ot)
 {
     __shared__ double red[4 * WT * 4 * 64];         // four order buffers of WT x 4 x 64 sums
     const int an = n < 0 ? -n : n;
@@ -734,6 +805,10 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     const int p = blockIdx.x;
     // this wave's rings: rbase .. rbase + NCH SG - 1 (contiguous; >= nreg inert)
     const int rbase = (blk * W + w) * NCH * SG;
+    // order tile blockIdx.z: orders ctop - 1 .. lo
+    const int tile = blockIdx.z;
+    const int ctop = tile == 0 ? L : ot.c[tile];
+    const int lo = tile + 1 < ot.nt ? ot.c[tile + 1] : mend;
 
     for (int pass = 0; pass < 2; ++pass) {
         const int g = pass == 0 ? p : G - 1 - p;
@@ -748,13 +823,28 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             for (int k = 0; k < SG; ++k) { X[c][k] = 0.0; Y[c][k] = 0.0; E[c][k] = 0; }
         uint32_t real = 0u;
         const int mstart = min(PAIRF ? lmin + 126 : lmin + 63, L - 1);
-        const int lc = min(l, L - 1);
-        double kk = (l > mstart && l < L) ? kap[(size_t)mstart * L + lc] : 0.0;
-        double gm = (l >= mstart && l < L) ? gtab[(size_t)mstart * L + lc] : 0.0;
         // head: the orders at which lanes of this group start (an even number of
         // steps so the register roles line up with the main loop)
         const int hend = ((mstart - lmin + 1) % 2 == 0) ? lmin : lmin - 1;
-        int m = mstart;
+        int m = min(mstart, ctop - 1);
+        if (m < lo) continue;                            // the group's degrees lie below the tile
+        if (tile > 0 && l >= ctop && l < L) {
+            // lanes whose degree started above the tile resume from the stored state
+            // (PAR 0 at order ctop - 1: X holds e_{ctop}); slots past the swept rings stay zero
+            const double *q = ot.ck + ot.off[tile] + (size_t)(l - ctop) * 3 * ot.rp + rbase;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int k = 0; k < SG; ++k)
+                    if (rbase + c * SG + k < nreg) {
+                        X[c][k] = q[c * SG + k];
+                        Y[c][k] = q[ot.rp + c * SG + k];
+                        E[c][k] = (int)q[2 * ot.rp + c * SG + k];
+                    }
+        }
+        const int lc = min(l, L - 1);
+        double kk = (l > m && l < L) ? kap[(ptrdiff_t)m * L + lc] : 0.0;
+        double gm = (l >= m && l < L) ? gtab[(ptrdiff_t)m * L + lc] : 0.0;
         // Pull the wave's lambda and spectra rows of orders m - PFF, m - PFF - 1 toward
         // the caches (one dword per 128-byte line, PQ lanes per order); the result is
         // consumed only at the next pair of orders, so the latency overlaps their work.
@@ -777,21 +867,22 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
                 pf = *a;
             }
         };
-        for (; m >= hend && m >= mend; m -= 2) {
+        for (; m >= hend && m >= lo; m -= 2) {
             prefetch(m);
             fwd_step<NCH, 0, true, false, false, false, SIDE, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                               lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                               kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
-            if (m - 1 >= mend)
+            if (m - 1 >= lo)
                 fwd_step<NCH, 1, true, false, false, false, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
                                                                   hstride, lstride, nreg, rbase, X, Y, E, real, kk, gm,
                                                                   lam, init, kap, gtab, HA, HB, HxA, HxB, red, blk, QA,
                                                                   QB, QxA, QxB);
-            fwd_reduce2<WT, false, SIDE, PAIRF>(m, m - 1 >= mend, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
+            fwd_reduce2<WT, false, SIDE, PAIRF>(m, m - 1 >= lo, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
         }
-        // both orders of the pair >= |n| (and > 0 when the sides share one array)
+        // both orders of the pair >= |n| (and > 0 when the sides share one array) and
+        // in the tile
         constexpr uint32_t ALL = (1u << NCH) - 1u;
-        const int mlo = SAME ? max(an, 1) : an;
+        const int mlo = max(SAME ? max(an, 1) : an, lo);
         if constexpr (SAME && !PAIRF) {
             // Main loop with every per-order address stepped, not recomputed: the wave's
             // lambda and spectra rows, the lane's kappa / g, the prefetch lanes' lines and
@@ -874,17 +965,17 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
                                                             kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
             fwd_reduce2<WT, true, SIDE, PAIRF>(m, true, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
         }
-        for (; m >= mend; m -= 2) {
+        for (; m >= lo; m -= 2) {
             prefetch(m);
             fwd_step<NCH, 0, false, false, false, false, SIDE, PAIRF>(m, mend, g, l, L, nxp, n, an, lane, w, W, hstride,
                                                                lstride, nreg, rbase, X, Y, E, real, kk, gm, lam, init,
                                                                kap, gtab, HA, HB, HxA, HxB, red, blk, QA, QB, QxA, QxB);
-            if (m - 1 >= mend)
+            if (m - 1 >= lo)
                 fwd_step<NCH, 1, false, false, false, false, SIDE, PAIRF>(m - 1, mend, g, l, L, nxp, n, an, lane, w, W,
                                                                    hstride, lstride, nreg, rbase, X, Y, E, real, kk,
                                                                    gm, lam, init, kap, gtab, HA, HB, HxA, HxB, red,
                                                                    blk, QA, QB, QxA, QxB);
-            fwd_reduce2<WT, false, SIDE, PAIRF>(m, m - 1 >= mend, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
+            fwd_reduce2<WT, false, SIDE, PAIRF>(m, m - 1 >= lo, g, L, nxp, n, an, red, blk, QA, QB, QxA, QxB);
         }
         asm volatile("" ::"v"(pf));
         __syncthreads();   // the LDS buffers are reused by the next pass
@@ -1766,19 +1857,21 @@ hipError_t launch_pack_inv(hipStream_t st, int L, int nx, int n, int nblk, int s
 
 hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx, int nreg, int n, const double *cot,
                              const double *csc, const double2 *init, const double *C, const int *lchunk,
-                             const int *mtop, double *partA, double *partB, int side, int nsw)
+                             const int *mtop, double *partA, double *partB, int side, int nsw,
+                             const OrderTiles &ot)
 {
+    if (ot.nt < 1 || ot.nt > MAX_ORDER_TILES || (ot.nt > 1 && !ot.ck)) return hipErrorInvalidValue;
     if (nwaves != 4 && nwaves != 8) return hipErrorInvalidValue;   // reducer rotation: one or two groups of 4
     if (side < 0 || side > 2 || (side == 1 && !partA) || (side == 2 && !partB) || (side == 0 && (!partA || !partB)))
         return hipErrorInvalidValue;                                // the side(s) swept must have outputs
     if (nsw <= 0) nsw = nreg;
     const bool pair = nsw < nreg;                                   // mirror rings from the northern sweep
     if (nsw > nreg || (pair && (n != 0 || side == 2 || 2 * nsw < nreg))) return hipErrorInvalidValue;
-    dim3 grid((nsw + 63) / 64, nblk);
+    dim3 grid((nsw + 63) / 64, nblk, ot.nt);
     // wave count, the real-signal half and the ring pairing as template arguments
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, L, nx, nreg, nsw, n, cot, csc, init, C, lchunk, mtop,
-                           partA, partB);
+                           partA, partB, ot);
     };
     if (nwaves == 8) {
         if (pair) side ? go(k_dstage_inv<INV_NCH, 8, 1, true>) : go(k_dstage_inv<INV_NCH, 8, 0, true>);
@@ -1798,19 +1891,21 @@ hipError_t launch_dstage_inv(hipStream_t st, int nwaves, int nblk, int L, int nx
 hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L, int nxp, int nreg, int hstride,
                              int lstride, int n, const double *lam, const double2 *init, const double *kap,
                              const double *gtab, const double *HA, const double *HB, const double *HxA,
-                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int side, int pair)
+                             const double *HxB, double *QA, double *QB, double *QxA, double *QxB, int side, int pair,
+                             const OrderTiles &ot)
 {
+    if (ot.nt < 1 || ot.nt > MAX_ORDER_TILES || (ot.nt > 1 && !ot.ck)) return hipErrorInvalidValue;
     if ((nwaves != 4 && nwaves != 8 && nwaves != 16) || nwaves > FWD_MAX_WAVES)
         return hipErrorInvalidValue;                                // reducer rotation: 1, 2 or 4 groups of 4
     if (pair && (n != 0 || HA == HB || HxA || HxB || side == 2)) return hipErrorInvalidValue;   // mirror rings: n = 0
     // one side: both sides read one spectra array (the run's slice), and that side has outputs
     if (side && !pair && (HA != HB || (side == 1 && !QA) || (side == 2 && !QB))) return hipErrorInvalidValue;
-    dim3 grid((G + 1) / 2, nblk);
+    dim3 grid((G + 1) / 2, nblk, ot.nt);
     // the wave count is a template argument: the reducer rotation and the wave sum
     // then compile to fixed code; HA == HB (run n = 0) selects the one-array path
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride, n, G, lam, init, kap,
-                           gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB);
+                           gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB, ot);
     };
     const bool same = HA == HB;
     if (pair) {
@@ -1828,6 +1923,17 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
     } else if (nwaves == 16) same ? go(k_dstage_fwd<FWD_NCH, true, 16>) : go(k_dstage_fwd<FWD_NCH, false, 16>);
     else if (nwaves == 8) same ? go(k_dstage_fwd<FWD_NCH, true, 8>) : go(k_dstage_fwd<FWD_NCH, false, 8>);
     else same ? go(k_dstage_fwd<FWD_NCH, true, 4>) : go(k_dstage_fwd<FWD_NCH, false, 4>);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_order_ckpt(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
+                             const double2 *init, const double *kap, const OrderTiles &ot, double *ck)
+{
+    if (ot.nt < 2) return hipSuccess;
+    if (ot.nt > MAX_ORDER_TILES || !ck || ot.rp < nreg) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_order_ckpt, dim3((ot.rp + 63) / 64, L), dim3(64), 0, st, L, nreg, n, cot, csc, init, kap, ot,
+                       ck);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

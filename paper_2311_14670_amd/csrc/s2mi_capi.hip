@@ -93,6 +93,8 @@ struct s2_plan_s {
     size_t fft_lds = 0;
     FftArgs fN{};                          // MW ring / theta-torus length 2L-1
     double *wq = nullptr, *ph = nullptr;   // MW theta filter
+    int conv_idx = -1, convM = 0;          // MW, 2L - 1 not 13-smooth: the filter's shifts as M-point convolutions
+    double2 *cspec = nullptr;              // their kernels' spectra (2 x M)
     double *ringq = nullptr;               // DH / GL: forward quadrature weight of each ring (phi rule included)
     double *groots = nullptr;              // e^{-2 pi i k/(2N-1)}
     // d-stage work assignment
@@ -454,6 +456,24 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             maxlen = std::max(maxlen, f.len);
         }
         if (sampling == S2_MW || sampling == S2_MWSS) P->fN = P->ffts_h[0];
+        // MW with a ring length N = 2L - 1 that needs Bluestein's identity (one LDS-resident
+        // convolution of M points): the theta filter's two half-step shifts are circular
+        // convolutions of length N, each run as one M-point cyclic convolution (two FFTs of
+        // M points instead of the four of two Bluestein DFTs)
+        if (sampling == S2_MW && P->fN.blue && !P->fN.split) {
+            const int M = P->fN.len;
+            FftArgs f;
+            if ((rc = build_fft(P, M, stg, st, &f))) return bail(rc);
+            P->conv_idx = (int)P->ffts_h.size();
+            P->convM = M;
+            P->ffts_h.push_back(f);
+            maxlen = std::max(maxlen, f.len);
+            stg.d.emplace_back();
+            host_shift_spectra(L, M, &stg.d.back());
+            double *cs;
+            if ((rc = upload(P, &cs, stg.d.back(), st, "theta filter shift spectra"))) return bail(rc);
+            P->cspec = reinterpret_cast<double2 *>(cs);
+        }
         P->fft_threads = fft_threads_for(maxlen);
         P->fft_lds = (size_t)maxlen * sizeof(double2);
         if ((rc = upload(P, &P->ring_fft, rf, st, "ring_fft"))) return bail(rc);
@@ -832,6 +852,9 @@ OrderTiles run_tiles(const s2_plan_s *P, size_t ri)
     return ot;
 }
 
+// the theta filter's convolution form: its FFT, kernel spectra and length (none: nullptr)
+#define CONV_ARGS(P) ((P)->conv_idx >= 0 ? (P)->ffts + (P)->conv_idx : nullptr), (P)->cspec, (P)->convM
+
 // the workspace's split-Bluestein scratch (nullptr when no DFT of the plan needs it)
 double2 *fft_scratch(const s2_plan_s *P, char *ws)
 {
@@ -917,7 +940,7 @@ int run_forward_adjoint_mw(s2_plan_t P, const double2 *G, double2 *const *slice_
         HIPCHK(launch_fadj_gather(st, L, ss, P->inv_nblk, s, P0 + k * nP, P->mtop, Gk, wl[k], P->hstride, F0),
                "adjoint gather");
         HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, s, P->ffts, P->wq, P->ph, F0, hp0,
-                                hpN0, fft_scratch(P, ws), 0, 1), "adjoint theta filter");
+                                hpN0, fft_scratch(P, ws), 0, 1, CONV_ARGS(P)), "adjoint theta filter");
         HIPCHK(launch_fadj_scatter(st, L, ss, P->hstride, q, F0, hp0, hpN0, Q0), "adjoint scatter");
         }
         TIMED(S2_STAGE_PHI_INV);
@@ -1012,7 +1035,7 @@ int run_forward(s2_plan_t P, const double2 *const *slice_maps, double2 *flm, con
         if (mw && !adjoint)
             HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, P->slice_spin[k], P->ffts, P->wq,
                                     P->ph, F, hp0 + k * (2 * L - 1), ss ? hpN0 + k * (2 * L - 1) : nullptr,
-                                    fft_scratch(P, ws)), "MW theta filter");
+                                    fft_scratch(P, ws), 0, 0, CONV_ARGS(P)), "MW theta filter");
         else if (mw) {
             HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp0 + k * (2 * L - 1)), "pole line");
             if (ss) HIPCHK(launch_pole_from_F(st, L, P->hstride, L, F, hpN0 + k * (2 * L - 1)), "north pole line");
@@ -1061,7 +1084,7 @@ int run_forward_real(s2_plan_t P, const double *map, double2 *flm, char *ws, hip
         TIMED(S2_STAGE_MW_THETA);
         if (!vjp) {
             HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, 0, P->ffts, P->wq, P->ph, F0,
-                                    hp0, hpN0, fft_scratch(P, ws), 1), "MW theta filter");
+                                    hp0, hpN0, fft_scratch(P, ws), 1, 0, CONV_ARGS(P)), "MW theta filter");
         } else {
             HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F0, hp0), "pole line");
             if (ss) HIPCHK(launch_pole_from_F(st, L, P->hstride, L, F0, hpN0), "north pole line");
@@ -1109,7 +1132,7 @@ int run_forward_real_adjoint(s2_plan_t P, const double2 *G, double *map, char *w
     HIPCHK(launch_fadj_gather(st, L, ss, P->inv_nblk, 0, P0, P->mtop, H, P->w_sht[0], P->hstride, F0),
            "adjoint gather");
     HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, 0, P->ffts, P->wq, P->ph, F0, hp0,
-                            hpN0, fft_scratch(P, ws), 1, 1), "adjoint theta filter");
+                            hpN0, fft_scratch(P, ws), 1, 1, CONV_ARGS(P)), "adjoint theta filter");
     HIPCHK(launch_fadj_scatter(st, L, ss, P->hstride, q, F0, hp0, hpN0, Q0), "adjoint scatter");
     }
     TIMED(S2_STAGE_PHI_INV);
@@ -1215,7 +1238,7 @@ int run_forward_mfma(s2_plan_t P, const double2 *maps, int B, double2 *flm, cons
             if (mw && !adjoint)
                 HIPCHK(launch_mw_filter(st, P->fft_threads, P->fft_lds, L, ss, P->hstride, P->slice_spin[k], P->ffts,
                                         P->wq, P->ph, F, hp + bk * (2 * L - 1), ss ? hpN + bk * (2 * L - 1) : nullptr,
-                                        fft_scratch(P, ws)),
+                                        fft_scratch(P, ws), 0, 0, CONV_ARGS(P)),
                    "MW theta filter");
             else if (mw) {
                 HIPCHK(launch_pole_from_F(st, L, P->hstride, L - 1, F, hp + bk * (2 * L - 1)), "pole line");

@@ -304,6 +304,61 @@ void host_mw_filter(int L, bool ss, std::vector<double> *wq, std::vector<double>
     }
 }
 
+// Half-step shifts of the MW theta filter as convolutions.  The filter moves the
+// torus samples g (length N = 2L - 1, band |k| < L) onto the midpoints and back:
+// (S g)_t = sum_j c_{t-j} g_j with c_s = (1/N) sum_{|k|<L} e^{i pi k (2s+1)/N}, a
+// Dirichlet sum equal to (-1)^s / (N sin(pi (2s+1) / (2N))), and the way back with
+// c'_s = (1/N) sum_{|k|<L} e^{i pi k (2s-1)/N} = -(-1)^s / (N sin(pi (2s-1) / (2N)))
+// (indices mod N).  A circular convolution of length N is the part t in [N-1, 2N-2]
+// of the linear convolution of g with e_j = c_{(j - (N-1)) mod N}, j <= 2N-2, which
+// an M-point cyclic convolution (M >= 2N - 1) reproduces without wrap-around.  out =
+// the M-point spectra E_k = (1/M) sum_j e_j e^{-2 pi i j k / M} of the two kernels
+// (S, then the way back), interleaved complex, each M entries; M a power of two.
+static void fft_ld(std::vector<long double> &re, std::vector<long double> &im, int M)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 1, j = 0; i < M; ++i) {                   // bit reversal
+        int bit = M >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j |= bit;
+        if (i < j) { std::swap(re[i], re[j]); std::swap(im[i], im[j]); }
+    }
+    for (int len = 2; len <= M; len <<= 1) {
+        const int h = len / 2;
+        for (int k = 0; k < h; ++k) {
+            const long double a = -2.0L * pi * (long double)k / (long double)len;
+            const long double wr = cosl(a), wi = sinl(a);
+            for (int b = 0; b < M; b += len) {
+                const int u = b + k, v = u + h;
+                const long double xr = re[v] * wr - im[v] * wi, xi = re[v] * wi + im[v] * wr;
+                re[v] = re[u] - xr; im[v] = im[u] - xi;
+                re[u] += xr; im[u] += xi;
+            }
+        }
+    }
+}
+
+void host_shift_spectra(int L, int M, std::vector<double> *out)
+{
+    const int N = 2 * L - 1;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    out->assign(4 * (size_t)M, 0.0);
+    for (int which = 0; which < 2; ++which) {
+        std::vector<long double> re(M, 0.0L), im(M, 0.0L);
+        for (int j = 0; j <= 2 * N - 2; ++j) {
+            const int s = ((j - (N - 1)) % N + N) % N;
+            const long double sg = (s & 1) ? -1.0L : 1.0L;
+            re[j] = which == 0 ? sg / ((long double)N * sinl(pi * (2.0L * s + 1.0L) / (2.0L * N)))
+                               : -sg / ((long double)N * sinl(pi * (2.0L * s - 1.0L) / (2.0L * N)));
+        }
+        fft_ld(re, im, M);
+        for (int k = 0; k < M; ++k) {
+            (*out)[2 * ((size_t)which * M + k)] = (double)(re[k] / M);
+            (*out)[2 * ((size_t)which * M + k) + 1] = (double)(im[k] / M);
+        }
+    }
+}
+
 // Per-l weights: SHT (-1)^s sqrt((2l+1)/4pi) (Eqs. 30, 33); SO(3) inverse
 // (2l+1)/(8 pi^2) (Eq. 13); SO(3) forward 1 (Eq. 14).
 void host_weights(int L, int kind, int spin, std::vector<double> *w)

@@ -31,6 +31,7 @@ void host_recursion_tables(int L, int nx, std::vector<double> *kap, std::vector<
 void host_roots(int n, std::vector<double> *out);
 void host_chirp(int n, std::vector<double> *out);
 void host_mw_filter(int L, bool ss, std::vector<double> *wq, std::vector<double> *ph);
+void host_shift_spectra(int L, int M, std::vector<double> *out);
 void host_weights(int L, int kind, int spin, std::vector<double> *w);
 
 // ----------------------------------------------------------------- FFT

@@ -1415,7 +1415,8 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
                                                     const double *__restrict__ wq, const double *__restrict__ ph,
                                                     double *__restrict__ F, double2 *__restrict__ hpole,
                                                     double2 *__restrict__ hpoleN, double2 *__restrict__ fscr,
-                                                    int half, int adj)
+                                                    int half, int adj, const FftArgs *__restrict__ fM,
+                                                    const double2 *__restrict__ cspec)
 {
     extern __shared__ double2 buf[];
     __shared__ double2 nyq;
@@ -1456,20 +1457,54 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
                 nyq = make_double2(tot.x / N, tot.y / N);   // Nyquist component of g w'_theta
             }
         }
-        __syncthreads();
-        dft_lds(buf, fN, -1, scr);
-        for (int k = tid; k < N; k += T) {                                          // shift +pi/N
-            if (ss && !adj && k == L) nyq = make_double2(buf[k].x / N, buf[k].y / N);   // ghat_L (MWSS), read first
-            buf[k] = cmul(buf[k], phc[k]);
+        // the midpoint samples S g times the weights w'', moved back: S^{-1} (w'' S g).
+        // Four engine passes (one call site, so the engine is inlined once): forward,
+        // shift, inverse (midpoints), weights, forward, shift back, inverse.
+        // conv (MW, N not 13-smooth): each shift is a circular convolution of length N
+        // with a fixed kernel, run as one M-point cyclic convolution (two power-of-two
+        // FFTs instead of the four of two Bluestein DFTs).  The first leaves S g at
+        // indices N-1 .. 2N-2; weighting it there and zeroing the rest feeds the second
+        // in place, whose result then sits at offset 2N-2 (mod M) -- the linear
+        // convolution's support [N-1, 4N-4] reaches no alias of the wanted indices
+        // [2N-2, 3N-3], since M >= 2N-1.
+        const bool conv = fM != nullptr;
+        const int M = conv ? fM->n : N;
+        const FftArgs *fa = conv ? fM : fN;
+        if (conv)
+            for (int t = N + tid; t < M; t += T) buf[t] = make_double2(0.0, 0.0);
+        __syncthreads();                             // the torus samples are in LDS
+#pragma nounroll
+        for (int pass = 0; pass < 4; ++pass) {
+            dft_lds(buf, fa, (pass & 1) ? +1 : -1, scr);
+            if (pass == 0) {
+                for (int k = tid; k < M; k += T) {
+                    if (conv) {
+                        buf[k] = cmul(buf[k], cspec[k]);
+                    } else {                                               // shift +pi/N
+                        if (ss && !adj && k == L) nyq = make_double2(buf[k].x / N, buf[k].y / N);   // ghat_L (MWSS), read first
+                        buf[k] = cmul(buf[k], phc[k]);
+                    }
+                }
+            } else if (pass == 1) {
+                for (int t = tid; t < M; t += T) {
+                    const int u = conv ? t - (N - 1) : t;                  // midpoint index
+                    if (u >= 0 && u < N) {
+                        const double wv = wq[N + u];
+                        buf[t].x *= wv;
+                        buf[t].y *= wv;
+                    } else {
+                        buf[t] = make_double2(0.0, 0.0);
+                    }
+                }
+            } else if (pass == 2) {
+                for (int k = tid; k < M; k += T)
+                    buf[k] = conv ? cmul(buf[k], cspec[M + k]) : cmulc(buf[k], phc[k]);   // shift -pi/N
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        dft_lds(buf, fN, +1, scr);
-        for (int t = tid; t < N; t += T) { const double wv = wq[N + t]; buf[t].x *= wv; buf[t].y *= wv; }
-        __syncthreads();
-        dft_lds(buf, fN, -1, scr);
-        for (int k = tid; k < N; k += T) buf[k] = cmulc(buf[k], phc[k]);             // shift -pi/N
-        __syncthreads();
-        dft_lds(buf, fN, +1, scr);
+        // h_t at hx(t): t, or (t + 2N - 2) mod M for the convolution form
+        const int hoff = conv ? (2 * N - 2) % M : 0;
+        auto hx = [&](int t) { return conv ? (t + hoff) & (M - 1) : t; };
         for (int t = tid; t < N; t += T) {          // + g w'_theta (g re-read: F is rewritten only below)
             bool mir;
             const int r = torus_ring(t, L, N, ss, &mir);
@@ -1487,16 +1522,17 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
                 gw.x -= sg * nyq.x;
                 gw.y -= sg * nyq.y;
             }
-            buf[t] = make_double2(0.5 * (gw.x + buf[t].x), 0.5 * (gw.y + buf[t].y));
+            const double2 hb = buf[hx(t)];                   // each thread rewrites only what it read
+            buf[hx(t)] = make_double2(0.5 * (gw.x + hb.x), 0.5 * (gw.y + hb.y));
         }
         __syncthreads();
         const double sc = 2.0 * M_PI / (double)N;
         const int hidx = side == 0 ? (L - 1) + m : (L - 1) - m;
         for (int t = tid; t < (ss ? L + 1 : L); t += T) {
-            double2 h = buf[t];
+            double2 h = buf[hx(t)];
             const bool pole = ss ? (t == 0 || t == L) : (t == L - 1);
             if (!pole) {
-                const double2 hr = buf[ss ? N - t : N - 1 - t];
+                const double2 hr = buf[hx(ss ? N - t : N - 1 - t)];
                 h.x += par * hr.x;
                 h.y += par * hr.y;
             }
@@ -2019,11 +2055,16 @@ hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nri
 
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *hpoleN, double2 *fscr, int half, int adj)
+                            double2 *hpoleN, double2 *fscr, int half, int adj, const FftArgs *fM,
+                            const double2 *cspec, int M)
 {
     if ((ss && !hpoleN) || nthreads > 1024) return hipErrorInvalidValue;
+    // the convolution form: MW only, a power of two M >= 2N - 1 within the LDS buffer
+    const int N = 2 * L - 1;
+    if (fM && (ss || !cspec || M < 2 * N - 1 || (M & (M - 1)) || (size_t)M * sizeof(double2) > lds))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, ss, hstride, spin, fN, wq, ph, F, hpole,
-                       hpoleN, fscr, half, adj);
+                       hpoleN, fscr, half, adj, fM, cspec);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

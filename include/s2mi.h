@@ -65,6 +65,7 @@ extern "C" {
 #define S2_ERR_UNSUPPORTED (-2)   /* valid request the library does not implement         */
 #define S2_ERR_OOM         (-3)   /* device or host allocation failed                     */
 #define S2_ERR_HIP         (-4)   /* HIP runtime or launch error (message kept)           */
+#define S2_ERR_CHECK       (-5)   /* a debug check (environment S2MI_DEBUG_CHECKS=1) failed */
 
 typedef struct s2_plan_s *s2_plan_t;
 
@@ -132,11 +133,20 @@ typedef struct {
  *              require S2_MW.
  *   max_batch  largest batch any call will pass (sizes the workspace), >= 1.
  *   prec       contraction arithmetic (see s2_precision_t).
- *   hip_stream stream on which the plan's constants are uploaded; the plan is
- *              ready when that stream has reached the upload (callers using
- *              another stream synchronise it first).
+ *   hip_stream stream on which the plan's constants are uploaded and its set-up
+ *              kernels run (tables of start values, order-tile states, FFT
+ *              filters).  The call waits for that stream before it returns (its
+ *              host staging buffers are freed then, and a failed set-up kernel is
+ *              reported by this call), so the plan is ready on return, on any
+ *              stream; work already queued on hip_stream is waited for too.
  * Ownership: *out receives a plan owned by the caller, freed by
  * s2_plan_destroy.  On error *out is set to NULL.
+ * Debug check (environment S2MI_DEBUG_CHECKS=1): the plan also evaluates
+ * sum_{|m| <= l} (d^l_{m,n}(theta))^2, which is 1 since d^l(theta) is orthogonal,
+ * on up to 8 sampled rings for every degree and every pair of runs n, -n, with the
+ * start values, tables and stable-direction continuation the transforms use, and
+ * fails with S2_ERR_CHECK where |sum - 1| exceeds S2MI_DEBUG_CHECKS_TOL (default
+ * 1e-10).
  */
 int s2_plan_create(s2_plan_t *out, int L, int spin, int N, s2_sampling_t sampling,
                    int nside, int max_batch, s2_precision_t prec, void *hip_stream);

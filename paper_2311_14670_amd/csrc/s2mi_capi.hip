@@ -284,6 +284,7 @@ const char *s2_error_string(int code)
     case S2_ERR_UNSUPPORTED: return "unsupported";
     case S2_ERR_OOM: return "out of memory";
     case S2_ERR_HIP: return "HIP runtime error";
+    case S2_ERR_CHECK: return "debug check failed";
     default: return "unknown error";
     }
 }
@@ -676,6 +677,52 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             PLANCHK(launch_order_ckpt(st, L, P->nreg, P->runs[ri].n, P->cot, P->csc, P->init[ri], P->kap, ot, ck),
                     "order-tile states");
             P->ck.push_back(ck);
+        }
+    }
+
+    // S2MI_DEBUG_CHECKS=1: check sum_{|m| <= l} (d^l_{m,n})^2 = 1 (d^l is orthogonal) on
+    // sampled rings, for every degree and every run whose partner -n is in the plan,
+    // with the same start values, tables and stable-direction continuation as the
+    // sweeps; a violation fails the plan (S2_ERR_CHECK).  S2MI_DEBUG_CHECKS_TOL sets
+    // the tolerance on |sum - 1| (default 1e-10).
+    if (const char *dc = std::getenv("S2MI_DEBUG_CHECKS"); dc && dc[0] == '1' && P->nreg > 0) {
+        const int nreg = P->nreg;
+        std::vector<int> rs = {0, 1, nreg / 8, nreg / 4, nreg / 2, (3 * nreg) / 4, nreg - 2, nreg - 1};
+        std::sort(rs.begin(), rs.end());
+        rs.erase(std::unique(rs.begin(), rs.end()), rs.end());
+        rs.erase(std::remove_if(rs.begin(), rs.end(), [&](int r) { return r < 0 || r >= nreg; }), rs.end());
+        const int nsel = (int)rs.size();
+        double tol = 1e-10;
+        if (const char *tv = std::getenv("S2MI_DEBUG_CHECKS_TOL")) tol = std::atof(tv);
+        int *rsel = nullptr;
+        double *sums = nullptr;
+        if ((rc = upload(P, &rsel, rs, st, "check rings"))) return bail(rc);
+        const size_t per_run = (size_t)nsel * L * 2;
+        if ((rc = P->dalloc(&sums, per_run * P->runs.size(), "check sums"))) return bail(rc);
+        for (size_t ri = 0; ri < P->runs.size(); ++ri)
+            PLANCHK(launch_unitarity(st, L, P->runs[ri].n, nsel, rsel, P->cot, P->csc, P->lsin, P->lcos, P->lbin[ri],
+                                     P->kap, P->gtab, sums + ri * per_run),
+                    "unitarity check");
+        std::vector<double> h(per_run * P->runs.size());
+        PLANCHK(hipMemcpyAsync(h.data(), sums, h.size() * sizeof(double), hipMemcpyDeviceToHost, st), "check copy");
+        PLANCHK(hipStreamSynchronize(st), "check sync");
+        for (size_t ri = 0; ri < P->runs.size(); ++ri) {
+            const int n = P->runs[ri].n, an = n < 0 ? -n : n;
+            int rj = -1;
+            for (size_t k = 0; k < P->runs.size(); ++k)
+                if (P->runs[k].n == -n) rj = (int)k;
+            if (rj < 0) continue;
+            const double *a = h.data() + ri * per_run, *b = h.data() + rj * per_run;
+            for (int i = 0; i < nsel; ++i)
+                for (int l = an; l < L; ++l) {
+                    const size_t o = ((size_t)i * L + l) * 2;
+                    // m >= 0 from run n, m < 0 from run -n at -m > 0
+                    const double sum = a[o] + b[o] - b[o + 1] * b[o + 1];
+                    if (!(std::fabs(sum - 1.0) <= tol))
+                        return bail(fail(S2_ERR_CHECK,
+                                         "debug check: sum over |m| <= l of d^l_{m,n}(theta)^2 = %.17g at l = %d, "
+                                         "n = %d, ring %d (tolerance %g)", sum, l, n, rs[i], tol));
+                }
         }
     }
 

@@ -61,6 +61,10 @@ hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nri
                                const FftArgs *ffts, const double *ringq, double *F, double2 *fscr);
 hipError_t launch_gamma_dft(hipStream_t st, int N, long long nper, int sign, double q, const double *roots,
                             const double2 *in, double2 *out);
+// Debug unitarity sums: out[i][l] = {sum_{m >= 0} (d^l_{m,n}(theta_{rsel[i]}))^2, d^l_{0,n}}.
+hipError_t launch_unitarity(hipStream_t st, int L, int n, int nsel, const int *rsel, const double *cot,
+                           const double *csc, const double *lsin, const double *lcos, const double *lbin,
+                           const double *kap, const double *gtab, double *out);
 hipError_t launch_debug_d(hipStream_t st, int L, int nreg, int n, const double *cot, const double *csc,
                           const double *lsin, const double *lcos, const double *lbin, const double *kap,
                           const double *gtab, double *out);

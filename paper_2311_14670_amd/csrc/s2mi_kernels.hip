@@ -1770,34 +1770,31 @@ __global__ void k_gamma_dft(int N, long long nper, int sign, double q, const dou
 }
 
 // ------------------------------------------------------------------ debug export of d
-// out[r][m][l] = d^l_{m,n}(theta_r) from the same init / step / renormalisation
-// as the sweeps (one thread per (ring, l)).
-__global__ void k_debug_d(int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
-                          const double *__restrict__ lsin, const double *__restrict__ lcos,
-                          const double *__restrict__ lbin, const double *__restrict__ kap,
-                          const double *__restrict__ gtab, double *__restrict__ out)
+// d^l_{m,n}(theta_r) for one (ring, l) from the same init / step / renormalisation
+// as the sweeps, handed to put(m, d, cont) for m = l down to 0; where this run is the
+// unstable one below the switch order ms, the run -n is then continued to order
+// -(ms-1) and put(m, d^l_{m,n}, true) gives the orders m < ms again from
+// d^l_{m,n} = (-1)^{m-n} d^l_{-m,-n} (those replace the first values).
+template <typename Put>
+__device__ __forceinline__ void d_walk(int L, int n, int r, int l, const double *__restrict__ cot,
+                                       const double *__restrict__ csc, const double *__restrict__ lsin,
+                                       const double *__restrict__ lcos, const double *__restrict__ lbin,
+                                       const double *__restrict__ kap, const double *__restrict__ gtab, Put put)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    const int l = blockIdx.y;
-    if (r >= nreg) return;
     const int an = n < 0 ? -n : n;
-    double *o = out + (size_t)r * L * L;
-    for (int m = 0; m <= l; ++m) o[(size_t)m * L + l] = 0.0;
     if (l < an) return;
     double e, ep = 0.0;
     int E;
     d_init(l, n, dd_from(lbin + 2 * l), dd_from(lsin + 2 * r), dd_from(lcos + 2 * r), e, E);
-    o[(size_t)l * L + l] = ldexp(e * gtab[(size_t)l * L + l], E);
+    put(l, ldexp(e * gtab[(size_t)l * L + l], E), false);
     for (int m = l - 1; m >= 0; --m) {
         const double lam = fma(-(double)(m + 1), cot[r], (double)n * csc[r]);
         const double en = fma(kap[(size_t)m * L + l] * lam, e, -ep);
         ep = e;
         e = en;
         if (E != 0) renorm(e, ep, E);
-        o[(size_t)m * L + l] = ldexp(e * gtab[(size_t)m * L + l], E);
+        put(m, ldexp(e * gtab[(size_t)m * L + l], E), false);
     }
-    // orders below the switch order ms where this run is the unstable one: continue
-    // the run -n (stable there) to order -(ms-1) and use d^l_{m,n} = (-1)^{m-n} d^l_{-m,-n}
     const double ct = cot[r];
     const int ms = switch_order(n, ct, csc[r]);
     if (an > 0 && !ring_good(n, ct) && ms > 0) {
@@ -1813,10 +1810,54 @@ __global__ void k_debug_d(int L, int nreg, int n, const double *__restrict__ cot
             const int mm = -m;
             if (mm >= 0 && mm < ms) {
                 const double v = ldexp(e * gtab[(ptrdiff_t)m * L + l], E);
-                o[(size_t)mm * L + l] = ((mm - n) & 1) ? -v : v;
+                put(mm, ((mm - n) & 1) ? -v : v, true);
             }
         }
     }
+}
+
+// out[r][m][l] = d^l_{m,n}(theta_r), one thread per (ring, l).
+__global__ void k_debug_d(int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
+                          const double *__restrict__ lsin, const double *__restrict__ lcos,
+                          const double *__restrict__ lbin, const double *__restrict__ kap,
+                          const double *__restrict__ gtab, double *__restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (r >= nreg) return;
+    double *o = out + (size_t)r * L * L;
+    for (int m = 0; m <= l; ++m) o[(size_t)m * L + l] = 0.0;
+    d_walk(L, n, r, l, cot, csc, lsin, lcos, lbin, kap, gtab,
+           [&](int m, double v, bool) { o[(size_t)m * L + l] = v; });
+}
+
+// Unitarity check (debug): for ring rsel[i] and degree l, out[i][l] = {sum over
+// m >= 0 of (d^l_{m,n})^2, d^l_{0,n}} with the values the sweeps use.  d^l(theta) is
+// the matrix of a rotation in the (2l+1)-dimensional representation, real and
+// orthogonal, so with d^l_{-m,n} = (-1)^{m-n} d^l_{m,-n} the runs n and -n give
+// sum_{|m| <= l} (d^l_{m,n})^2 = 1.
+__global__ void k_unitarity(int L, int n, int nsel, const int *__restrict__ rsel, const double *__restrict__ cot,
+                            const double *__restrict__ csc, const double *__restrict__ lsin,
+                            const double *__restrict__ lcos, const double *__restrict__ lbin,
+                            const double *__restrict__ kap, const double *__restrict__ gtab,
+                            double *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (i >= nsel) return;
+    const int r = rsel[i];
+    const int an = n < 0 ? -n : n;
+    const double ct = cot[r];
+    const int ms = switch_order(n, ct, csc[r]);
+    const int ovr = (an > 0 && !ring_good(n, ct) && ms > 0) ? ms : 0;   // orders the continuation replaces
+    double sum = 0.0, d0 = 0.0;
+    d_walk(L, n, r, l, cot, csc, lsin, lcos, lbin, kap, gtab, [&](int m, double v, bool cont) {
+        if (!cont && m < ovr) return;
+        sum = fma(v, v, sum);
+        if (m == 0) d0 = v;
+    });
+    out[((size_t)i * L + l) * 2] = sum;
+    out[((size_t)i * L + l) * 2 + 1] = d0;
 }
 
 // ------------------------------------------------------------------ Bluestein filters
@@ -2112,6 +2153,18 @@ hipError_t launch_gamma_dft(hipStream_t st, int N, long long nper, int sign, dou
 {
     hipLaunchKernelGGL(k_gamma_dft, dim3((unsigned)((nper + 255) / 256)), dim3(256), 0, st, N, nper, sign, q, roots,
                        in, out);
+    S2_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_unitarity(hipStream_t st, int L, int n, int nsel, const int *rsel, const double *cot,
+                           const double *csc, const double *lsin, const double *lcos, const double *lbin,
+                           const double *kap, const double *gtab, double *out)
+{
+    if (nsel < 1) return hipSuccess;
+    dim3 grid((nsel + 63) / 64, L);
+    hipLaunchKernelGGL(k_unitarity, grid, dim3(64), 0, st, L, n, nsel, rsel, cot, csc, lsin, lcos, lbin, kap, gtab,
+                       out);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -61,3 +61,4 @@ def test_transform_validation_without_plan():
     assert lib.s2_plan_info(None, None) == -1
     assert lib.s2_plan_destroy(None) == 0
     assert lib.s2_error_string(-2).decode() == "unsupported"
+    assert lib.s2_error_string(-5).decode() == "debug check failed"

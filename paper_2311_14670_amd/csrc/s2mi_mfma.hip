@@ -70,18 +70,39 @@ __device__ __forceinline__ float elem_f32(v4u a, v4u b, int s)   // s compile-ti
     return __uint_as_float(s < 4 ? a[s] : b[s - 4]);
 }
 
-// acc += A(one 32-byte element per lane) * B(one element per lane) over 16 K values
-template <int FMT>
-__device__ __forceinline__ void mfma_elem(f32x16_t &acc, v4u ah, v4u al, v4u bh, v4u bl)
+// acc[i][t] += A(tile i) * B(tile t) over one K step (16 values; one 32-byte element
+// per lane and operand) for all of a wave's tiles, interleaved so that consecutive
+// matrix instructions accumulate into different tiles (each tile's products depend
+// on its previous one).  FP32: eight 32x32x2 products per tile; split BF16: three
+// 32x32x16 products per tile, hi*hi, hi*lo, lo*hi.
+template <int FMT, int MTW>
+__device__ __forceinline__ void mfma_tiles(f32x16_t (&acc)[MTW][2], const bool (&mv)[MTW], const v4u (&ah)[MTW],
+                                           const v4u (&al)[MTW], const v4u (&bh)[2], const v4u (&bl)[2])
 {
     if constexpr (FMT == S2_CONTRACT_FP32) {
 #pragma unroll
         for (int s = 0; s < SG; ++s)
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(elem_f32(ah, al, s), elem_f32(bh, bl, s), acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < MTW; ++i) {
+                if (!mv[i]) continue;
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(elem_f32(ah[i], al[i], s), elem_f32(bh[t], bl[t], s),
+                                                                     acc[i][t], 0, 0, 0);
+            }
     } else {
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah), as_bf16x8(bh), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah), as_bf16x8(bl), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al), as_bf16x8(bh), acc, 0, 0, 0);
+#pragma unroll
+        for (int pass = 0; pass < 3; ++pass)
+#pragma unroll
+            for (int i = 0; i < MTW; ++i) {
+                if (!mv[i]) continue;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const v4u a = pass == 2 ? al[i] : ah[i];
+                    const v4u b = pass == 1 ? bl[t] : bh[t];
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(b), acc[i][t], 0, 0, 0);
+                }
+            }
     }
 }
 
@@ -401,12 +422,7 @@ __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int
             ah[i] = (kv && mv[i]) ? p[0] : z4;
             al[i] = (kv && mv[i]) ? p[1] : z4;
         }
-#pragma unroll
-        for (int i = 0; i < MTW; ++i) {
-            if (!mv[i]) continue;
-#pragma unroll
-            for (int t = 0; t < 2; ++t) mfma_elem<FMT>(acc[i][t], ah[i], al[i], bh[t], bl[t]);
-        }
+        mfma_tiles<FMT, MTW>(acc, mv, ah, al, bh, bl);
     }
     // C layout of a 32x32 tile: lane l, entry j -> row 8(j/4) + 4(l/32) + j%4, column l%32
 #pragma unroll
@@ -496,12 +512,7 @@ __global__ __launch_bounds__(256) void k_mfma_fwd(int L, int rpad, int lp, int n
             ah[i] = mv[i] ? p[0] : z4;
             al[i] = mv[i] ? p[1] : z4;
         }
-#pragma unroll
-        for (int i = 0; i < MTW; ++i) {
-            if (!mv[i]) continue;
-#pragma unroll
-            for (int t = 0; t < 2; ++t) mfma_elem<FMT>(acc[i][t], ah[i], al[i], bh[t], bl[t]);
-        }
+        mfma_tiles<FMT, MTW>(acc, mv, ah, al, bh, bl);
     }
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {

@@ -93,8 +93,8 @@ struct s2_plan_s {
     size_t fft_lds = 0;
     FftArgs fN{};                          // MW ring / theta-torus length 2L-1
     double *wq = nullptr, *ph = nullptr;   // MW theta filter
-    int conv_idx = -1, convM = 0;          // MW, 2L - 1 not 13-smooth: the filter's shifts as M-point convolutions
-    double2 *cspec = nullptr;              // their kernels' spectra (2 x M)
+    int conv_idx = -1;                     // MW, 2L - 1 not 13-smooth: the filter's two shifts as cyclic
+                                           // convolutions (FftArgs conv_idx and conv_idx + 1)
     double *ringq = nullptr;               // DH / GL: forward quadrature weight of each ring (phi rule included)
     double *groots = nullptr;              // e^{-2 pi i k/(2N-1)}
     // d-stage work assignment
@@ -457,23 +457,32 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
             maxlen = std::max(maxlen, f.len);
         }
         if (sampling == S2_MW || sampling == S2_MWSS) P->fN = P->ffts_h[0];
-        // MW with a ring length N = 2L - 1 that needs Bluestein's identity (one LDS-resident
-        // convolution of M points): the theta filter's two half-step shifts are circular
-        // convolutions of length N, each run as one M-point cyclic convolution (two FFTs of
-        // M points instead of the four of two Bluestein DFTs)
-        if (sampling == S2_MW && P->fN.blue && !P->fN.split) {
-            const int M = P->fN.len;
-            FftArgs f;
-            if ((rc = build_fft(P, M, stg, st, &f))) return bail(rc);
-            P->conv_idx = (int)P->ffts_h.size();
-            P->convM = M;
-            P->ffts_h.push_back(f);
-            maxlen = std::max(maxlen, f.len);
+        // MW with a ring length N = 2L - 1 that needs Bluestein's identity: the theta
+        // filter's two half-step shifts are circular convolutions of length N, each run
+        // by the Bluestein driver as one cyclic convolution of the same length M (unit
+        // chirp, the shift kernel's spectrum as the filter; two FFTs of M points, or four
+        // of M/2 where the driver splits it) instead of two Bluestein DFTs
+        if (sampling == S2_MW && P->fN.blue) {
+            const int N = 2 * L - 1;
+            const int M = P->fN.split ? 2 * P->fN.len : P->fN.len;
             stg.d.emplace_back();
             host_shift_spectra(L, M, &stg.d.back());
             double *cs;
             if ((rc = upload(P, &cs, stg.d.back(), st, "theta filter shift spectra"))) return bail(rc);
-            P->cspec = reinterpret_cast<double2 *>(cs);
+            stg.d.emplace_back();
+            std::vector<double> &one = stg.d.back();
+            one.assign(2 * (size_t)N, 0.0);
+            for (int i = 0; i < N; ++i) one[2 * (size_t)i] = 1.0;
+            double *ch1;
+            if ((rc = upload(P, &ch1, one, st, "unit chirp"))) return bail(rc);
+            FftArgs f = P->fN;
+            f.chirp = ch1;
+            f.conv = 1;
+            P->conv_idx = (int)P->ffts_h.size();
+            f.bflt = cs;
+            P->ffts_h.push_back(f);
+            f.bflt = cs + 2 * (size_t)M;
+            P->ffts_h.push_back(f);
         }
         P->fft_threads = fft_threads_for(maxlen);
         P->fft_lds = (size_t)maxlen * sizeof(double2);
@@ -900,7 +909,7 @@ OrderTiles run_tiles(const s2_plan_s *P, size_t ri)
 }
 
 // the theta filter's convolution form: its FFT, kernel spectra and length (none: nullptr)
-#define CONV_ARGS(P) ((P)->conv_idx >= 0 ? (P)->ffts + (P)->conv_idx : nullptr), (P)->cspec, (P)->convM
+#define CONV_ARGS(P) ((P)->conv_idx >= 0 ? (P)->ffts + (P)->conv_idx : nullptr)
 
 // the workspace's split-Bluestein scratch (nullptr when no DFT of the plan needs it)
 double2 *fft_scratch(const s2_plan_s *P, char *ws)

@@ -309,11 +309,11 @@ void host_mw_filter(int L, bool ss, std::vector<double> *wq, std::vector<double>
 // (S g)_t = sum_j c_{t-j} g_j with c_s = (1/N) sum_{|k|<L} e^{i pi k (2s+1)/N}, a
 // Dirichlet sum equal to (-1)^s / (N sin(pi (2s+1) / (2N))), and the way back with
 // c'_s = (1/N) sum_{|k|<L} e^{i pi k (2s-1)/N} = -(-1)^s / (N sin(pi (2s-1) / (2N)))
-// (indices mod N).  A circular convolution of length N is the part t in [N-1, 2N-2]
-// of the linear convolution of g with e_j = c_{(j - (N-1)) mod N}, j <= 2N-2, which
-// an M-point cyclic convolution (M >= 2N - 1) reproduces without wrap-around.  out =
-// the M-point spectra E_k = (1/M) sum_j e_j e^{-2 pi i j k / M} of the two kernels
-// (S, then the way back), interleaved complex, each M entries; M a power of two.
+// (indices mod N).  Placed cyclically in M >= 2N - 1 points (e_{s mod M} = c_{s mod N}
+// for |s| < N, zero elsewhere), an M-point cyclic convolution of g (zero past N) with e
+// equals the circular one of length N at t < N, with no wrap-around.  out = the M-point
+// spectra E_k = (1/M) sum_j e_j e^{-2 pi i j k / M} of the two kernels (S, then the way
+// back), interleaved complex, each M entries; M a power of two.
 static void fft_ld(std::vector<long double> &re, std::vector<long double> &im, int M)
 {
     const long double pi = 3.141592653589793238462643383279502884L;
@@ -345,11 +345,11 @@ void host_shift_spectra(int L, int M, std::vector<double> *out)
     out->assign(4 * (size_t)M, 0.0);
     for (int which = 0; which < 2; ++which) {
         std::vector<long double> re(M, 0.0L), im(M, 0.0L);
-        for (int j = 0; j <= 2 * N - 2; ++j) {
-            const int s = ((j - (N - 1)) % N + N) % N;
+        for (int d = -(N - 1); d <= N - 1; ++d) {
+            const int s = (d % N + N) % N;                  // kernel index mod N
             const long double sg = (s & 1) ? -1.0L : 1.0L;
-            re[j] = which == 0 ? sg / ((long double)N * sinl(pi * (2.0L * s + 1.0L) / (2.0L * N)))
-                               : -sg / ((long double)N * sinl(pi * (2.0L * s - 1.0L) / (2.0L * N)));
+            re[(d % M + M) % M] = which == 0 ? sg / ((long double)N * sinl(pi * (2.0L * s + 1.0L) / (2.0L * N)))
+                                             : -sg / ((long double)N * sinl(pi * (2.0L * s - 1.0L) / (2.0L * N)));
         }
         fft_ld(re, im, M);
         for (int k = 0; k < M; ++k) {

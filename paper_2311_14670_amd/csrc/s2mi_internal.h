@@ -53,6 +53,9 @@ struct FftArgs {
     const double *chirp;  // Bluestein: e^{+i pi k^2/n}, k < n
     const double *bflt;   // Bluestein: FFT of the chirp filter over the convolution length, divided by it
     const double *twm;    // split: e^{-2 pi i k/(2 len)}, k < len
+    int conv;             // 1: a cyclic convolution, not a DFT: the chirp is 1 and bflt is
+                          // the spectrum of a kernel the plan supplies (the Bluestein
+                          // machinery then returns the convolution at t < n)
 };
 
 // ----------------------------------------------------------------- d-stage geometry

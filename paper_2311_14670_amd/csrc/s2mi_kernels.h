@@ -40,8 +40,7 @@ hipError_t launch_phi_fwd(hipStream_t st, int nthreads, size_t lds, int nring, i
                           double2 *fscr);
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *hpoleN, double2 *fscr, int half, int adj, const FftArgs *fM,
-                            const double2 *cspec, int M);
+                            double2 *hpoleN, double2 *fscr, int half, int adj, const FftArgs *fconv);
 hipError_t launch_ring_scale(hipStream_t st, int nring, int nphi, const double *w, double2 *map);
 hipError_t launch_ring_scale_real(hipStream_t st, int nring, const long long *ring_start, const int *ring_nphi,
                                   const double *w, double *map);

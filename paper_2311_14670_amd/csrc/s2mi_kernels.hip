@@ -1415,8 +1415,7 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
                                                     const double *__restrict__ wq, const double *__restrict__ ph,
                                                     double *__restrict__ F, double2 *__restrict__ hpole,
                                                     double2 *__restrict__ hpoleN, double2 *__restrict__ fscr,
-                                                    int half, int adj, const FftArgs *__restrict__ fM,
-                                                    const double2 *__restrict__ cspec)
+                                                    int half, int adj, const FftArgs *__restrict__ fconv)
 {
     extern __shared__ double2 buf[];
     __shared__ double2 nyq;
@@ -1458,53 +1457,35 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
             }
         }
         // the midpoint samples S g times the weights w'', moved back: S^{-1} (w'' S g).
-        // Four engine passes (one call site, so the engine is inlined once): forward,
-        // shift, inverse (midpoints), weights, forward, shift back, inverse.
-        // conv (MW, N not 13-smooth): each shift is a circular convolution of length N
-        // with a fixed kernel, run as one M-point cyclic convolution (two power-of-two
-        // FFTs instead of the four of two Bluestein DFTs).  The first leaves S g at
-        // indices N-1 .. 2N-2; weighting it there and zeroing the rest feeds the second
-        // in place, whose result then sits at offset 2N-2 (mod M) -- the linear
-        // convolution's support [N-1, 4N-4] reaches no alias of the wanted indices
-        // [2N-2, 3N-3], since M >= 2N-1.
-        const bool conv = fM != nullptr;
-        const int M = conv ? fM->n : N;
-        const FftArgs *fa = conv ? fM : fN;
-        if (conv)
-            for (int t = N + tid; t < M; t += T) buf[t] = make_double2(0.0, 0.0);
+        // DFT form: four engine passes (forward, shift, inverse: midpoints; weights;
+        // forward, shift back, inverse).  Convolution form (MW, N not 13-smooth, fconv:
+        // the two shifts' FftArgs): each shift is a circular convolution of length N
+        // with a fixed kernel, run by the Bluestein driver with a unit chirp and the
+        // kernel's spectrum as its filter (one cyclic convolution, two FFTs or four
+        // half-length ones where the engine splits it, instead of two Bluestein DFTs);
+        // its result is at t < N.  One call site, so the engine is inlined once.
+        const bool conv = fconv != nullptr;
         __syncthreads();                             // the torus samples are in LDS
 #pragma nounroll
         for (int pass = 0; pass < 4; ++pass) {
-            dft_lds(buf, fa, (pass & 1) ? +1 : -1, scr);
-            if (pass == 0) {
-                for (int k = tid; k < M; k += T) {
-                    if (conv) {
-                        buf[k] = cmul(buf[k], cspec[k]);
-                    } else {                                               // shift +pi/N
-                        if (ss && !adj && k == L) nyq = make_double2(buf[k].x / N, buf[k].y / N);   // ghat_L (MWSS), read first
-                        buf[k] = cmul(buf[k], phc[k]);
-                    }
+            if (!conv || !(pass & 1))
+                dft_lds(buf, conv ? fconv + (pass >> 1) : fN, conv ? -1 : ((pass & 1) ? +1 : -1), scr);
+            if (pass == 0 && !conv) {
+                for (int k = tid; k < N; k += T) {                                 // shift +pi/N
+                    if (ss && !adj && k == L) nyq = make_double2(buf[k].x / N, buf[k].y / N);   // ghat_L (MWSS), read first
+                    buf[k] = cmul(buf[k], phc[k]);
                 }
             } else if (pass == 1) {
-                for (int t = tid; t < M; t += T) {
-                    const int u = conv ? t - (N - 1) : t;                  // midpoint index
-                    if (u >= 0 && u < N) {
-                        const double wv = wq[N + u];
-                        buf[t].x *= wv;
-                        buf[t].y *= wv;
-                    } else {
-                        buf[t] = make_double2(0.0, 0.0);
-                    }
+                for (int t = tid; t < N; t += T) {
+                    const double wv = wq[N + t];
+                    buf[t].x *= wv;
+                    buf[t].y *= wv;
                 }
-            } else if (pass == 2) {
-                for (int k = tid; k < M; k += T)
-                    buf[k] = conv ? cmul(buf[k], cspec[M + k]) : cmulc(buf[k], phc[k]);   // shift -pi/N
+            } else if (pass == 2 && !conv) {
+                for (int k = tid; k < N; k += T) buf[k] = cmulc(buf[k], phc[k]);   // shift -pi/N
             }
             __syncthreads();
         }
-        // h_t at hx(t): t, or (t + 2N - 2) mod M for the convolution form
-        const int hoff = conv ? (2 * N - 2) % M : 0;
-        auto hx = [&](int t) { return conv ? (t + hoff) & (M - 1) : t; };
         for (int t = tid; t < N; t += T) {          // + g w'_theta (g re-read: F is rewritten only below)
             bool mir;
             const int r = torus_ring(t, L, N, ss, &mir);
@@ -1522,17 +1503,16 @@ __global__ __launch_bounds__(1024) void k_mw_filter(int L, int ss, int hstride, 
                 gw.x -= sg * nyq.x;
                 gw.y -= sg * nyq.y;
             }
-            const double2 hb = buf[hx(t)];                   // each thread rewrites only what it read
-            buf[hx(t)] = make_double2(0.5 * (gw.x + hb.x), 0.5 * (gw.y + hb.y));
+            buf[t] = make_double2(0.5 * (gw.x + buf[t].x), 0.5 * (gw.y + buf[t].y));
         }
         __syncthreads();
         const double sc = 2.0 * M_PI / (double)N;
         const int hidx = side == 0 ? (L - 1) + m : (L - 1) - m;
         for (int t = tid; t < (ss ? L + 1 : L); t += T) {
-            double2 h = buf[hx(t)];
+            double2 h = buf[t];
             const bool pole = ss ? (t == 0 || t == L) : (t == L - 1);
             if (!pole) {
-                const double2 hr = buf[hx(ss ? N - t : N - 1 - t)];
+                const double2 hr = buf[ss ? N - t : N - 1 - t];
                 h.x += par * hr.x;
                 h.y += par * hr.y;
             }
@@ -1871,7 +1851,7 @@ __global__ __launch_bounds__(1024) void k_bluestein_prep(const FftArgs *__restri
 {
     extern __shared__ double2 buf[];
     const FftArgs *f = ffts + blockIdx.x;
-    if (!f->blue) return;
+    if (!f->blue || f->conv) return;                    // convolutions carry their own filter
     const int n = f->n, len = f->len;
     const double2 *ch = reinterpret_cast<const double2 *>(f->chirp);
     if (f->split) {
@@ -2096,16 +2076,12 @@ hipError_t launch_phi_fwd_real(hipStream_t st, int nthreads, size_t lds, int nri
 
 hipError_t launch_mw_filter(hipStream_t st, int nthreads, size_t lds, int L, int ss, int hstride, int spin,
                             const FftArgs *fN, const double *wq, const double *ph, double *F, double2 *hpole,
-                            double2 *hpoleN, double2 *fscr, int half, int adj, const FftArgs *fM,
-                            const double2 *cspec, int M)
+                            double2 *hpoleN, double2 *fscr, int half, int adj, const FftArgs *fconv)
 {
     if ((ss && !hpoleN) || nthreads > 1024) return hipErrorInvalidValue;
-    // the convolution form: MW only, a power of two M >= 2N - 1 within the LDS buffer
-    const int N = 2 * L - 1;
-    if (fM && (ss || !cspec || M < 2 * N - 1 || (M & (M - 1)) || (size_t)M * sizeof(double2) > lds))
-        return hipErrorInvalidValue;
+    if (fconv && ss) return hipErrorInvalidValue;               // the convolution form is MW's
     hipLaunchKernelGGL(k_mw_filter, dim3(L), dim3(nthreads), lds, st, L, ss, hstride, spin, fN, wq, ph, F, hpole,
-                       hpoleN, fscr, half, adj, fM, cspec);
+                       hpoleN, fscr, half, adj, fconv);
     S2_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -7,7 +7,8 @@
 //    (sum of weights 2 over cos theta, after removing the phi rule 2 pi / (2L-1));
 //  - the half-step shift spectra move each band-limited exponential e^{i k theta}
 //    (|k| < L) on the MW theta-torus by exactly half a step, pi / (2L-1), when
-//    applied as the M-point cyclic convolution the theta filter runs.
+//    applied as the M-point cyclic convolution the theta filter runs (result at
+//    t < N).
 // Prints "OK" and exits 0 on success.
 #include <cmath>
 #include <complex>
@@ -115,7 +116,7 @@ int main()
                 const double step = which == 0 ? M_PI / N : -M_PI / N;   // S, then the way back
                 for (int t = 0; t < N; ++t) {
                     const cd want = std::polar(1.0, 2.0 * M_PI * kk * t / N + kk * step);
-                    worst = std::fmax(worst, std::abs(y[t + N - 1] - want));
+                    worst = std::fmax(worst, std::abs(y[t] - want));
                 }
             }
             check(worst < 1e-12, which == 0 ? "half-step shift" : "half-step shift back");

@@ -463,20 +463,12 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         // chirp, the shift kernel's spectrum as the filter; two FFTs of M points, or four
         // of M/2 where the driver splits it) instead of two Bluestein DFTs
         if (sampling == S2_MW && P->fN.blue) {
-            const int N = 2 * L - 1;
             const int M = P->fN.split ? 2 * P->fN.len : P->fN.len;
             stg.d.emplace_back();
             host_shift_spectra(L, M, &stg.d.back());
             double *cs;
             if ((rc = upload(P, &cs, stg.d.back(), st, "theta filter shift spectra"))) return bail(rc);
-            stg.d.emplace_back();
-            std::vector<double> &one = stg.d.back();
-            one.assign(2 * (size_t)N, 0.0);
-            for (int i = 0; i < N; ++i) one[2 * (size_t)i] = 1.0;
-            double *ch1;
-            if ((rc = upload(P, &ch1, one, st, "unit chirp"))) return bail(rc);
-            FftArgs f = P->fN;
-            f.chirp = ch1;
+            FftArgs f = P->fN;                             // same engine; its chirp is never applied
             f.conv = 1;
             P->conv_idx = (int)P->ffts_h.size();
             f.bflt = cs;

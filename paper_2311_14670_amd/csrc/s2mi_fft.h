@@ -232,7 +232,9 @@ __device__ __forceinline__ void fft_engine(double2 *buf, const FftArgs *f, int s
 // Bluestein (lengths with a prime factor above 13): the inverse is
 // conj(DFT(conj(x))); the chirped input u_j = x_j conj(c_j) is convolved with
 // the chirp by a forward FFT, a product with the filter spectrum and an inverse
-// FFT, then de-chirped.
+// FFT, then de-chirped.  With f.conv set the chirp is 1 (no products) and the
+// result is the cyclic convolution of x (zero past n) with the filter's kernel,
+// at t < n.
 //
 // Split Bluestein (convolution length M = 2H, H = f.len the LDS engine length,
 // n < H): u is zero past n < H, so the even spectrum samples U[2k] are
@@ -250,6 +252,7 @@ __device__ __forceinline__ void dft_lds(double2 *buf, const FftArgs *f, int sign
     const int T = blockDim.x, tid = threadIdx.x;
     const int n = f->n, len = f->len;
     const int blue = f->blue, split = blue && f->split;
+    const int conv = f->conv;                                // unit chirp: a plain cyclic convolution
     const double2 *ch = reinterpret_cast<const double2 *>(f->chirp);
     const double2 *bf = reinterpret_cast<const double2 *>(f->bflt);
     const double2 *wm = reinterpret_cast<const double2 *>(f->twm);
@@ -263,7 +266,7 @@ __device__ __forceinline__ void dft_lds(double2 *buf, const FftArgs *f, int sign
                     if (i < n) {
                         double2 x = buf[i];
                         if (sign > 0) x.y = -x.y;
-                        v = cmulc(x, ch[i]);
+                        v = conv ? x : cmulc(x, ch[i]);
                     }
                     if (split) scr[i] = v;
                     buf[i] = v;
@@ -283,7 +286,7 @@ __device__ __forceinline__ void dft_lds(double2 *buf, const FftArgs *f, int sign
     if (blue) {                                              // (combine and) de-chirp
         for (int i = tid; i < n; i += T) {
             const double2 v = split ? cadd(scr[len + i], cmulc(buf[i], wm[i])) : buf[i];
-            double2 y = cmulc(v, ch[i]);
+            double2 y = conv ? v : cmulc(v, ch[i]);
             if (sign > 0) y.y = -y.y;
             buf[i] = y;
         }

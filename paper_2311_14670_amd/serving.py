@@ -53,6 +53,7 @@ class Request:
     result: np.ndarray = None
     error: str = None
     batch_size: int = 0
+    run_precision: str = None   # the precision the request's batch ran with
 
     @property
     def latency(self):
@@ -96,6 +97,10 @@ class Scheduler:
       launch(key, requests) -> handle     enqueue a batch (non-blocking)
       poll() -> finished handles (each keeps its .requests)
       evict(nbytes, busy_keys) -> int     drop cached plans (LRU) not in use
+      run_key(key, n) -> key         (optional) the plan key a batch of n requests of
+                                     the key runs with (a matrix-core key may run a
+                                     small batch on the FP64 plan: precision is the
+                                     least accuracy a request accepts)
     Buffers of a batch (input, inverse output, forward output) count against
     the budget while the batch is in flight.
     """
@@ -119,6 +124,10 @@ class Scheduler:
     def _can_launch(self, key):
         f = getattr(self.ex, "can_launch", None)
         return True if f is None else f(key)
+
+    def _run_key(self, key, n):
+        f = getattr(self.ex, "run_key", None)
+        return key if f is None else f(key, n)
 
     def _form_batch(self):
         """The oldest waiting request whose key can launch now (a key whose only
@@ -156,13 +165,14 @@ class Scheduler:
             if not batch:
                 break          # every waiting key is busy: wait for a completion
             n = len(batch)
-            while n > 0 and not self._fits(key, n):
+            while n > 0 and not self._fits(self._run_key(key, n), n):
                 n -= 1
             if n == 0:
-                short = self._need(key, 1) - self.budget
+                k1 = self._run_key(key, 1)
+                short = self._need(k1, 1) - self.budget
                 # the key being admitted is kept too: its plan was just built by _need
-                busy = {h.key for h in self.inflight} | {key}
-                if self.ex.evict(short, busy) > 0 and self._fits(key, 1):
+                busy = {h.key for h in self.inflight} | {k1}
+                if self.ex.evict(short, busy) > 0 and self._fits(k1, 1):
                     continue
                 if not self.inflight:
                     # does not fit even alone on an idle device: reject the request
@@ -173,15 +183,17 @@ class Scheduler:
                     continue
                 break          # wait for in-flight work to free memory
             batch = batch[:n]
+            run = self._run_key(key, n)
             ids = {id(r) for r in batch}
             self.queue = collections.deque(r for r in self.queue if id(r) not in ids)
-            h = self.ex.launch(key, batch)
-            h.footprint = self.buffer_bytes(key, n)
-            h.key = key
+            h = self.ex.launch(run, batch)
+            h.footprint = self.buffer_bytes(run, n)
+            h.key = run
             self.in_use += h.footprint
             for r in batch:
                 r.t_launch = now
                 r.batch_size = n
+                r.run_precision = run.precision
             self.inflight.append(h)
             launched += 1
         return launched
@@ -296,10 +308,16 @@ class GpuExecutor:
     host-side tables take ~1 s to rebuild at L = 4096).
 
     batch_bytes: target device bytes of one batch's buffers; the batch limit of
-    a key is the number of its requests that fit (at least 1, at most max_batch)."""
+    a key is the number of its requests that fit (at least 1, at most max_batch).
+
+    min_mfma_batch: a matrix-core (FP32 / split-BF16) batch smaller than this runs on
+    the key's FP64 plan instead.  The matrix-core path generates D once per batch
+    (about 20 ms per pair at L = 2048 whatever the batch) and then costs about
+    1.7 ms per map, against 7.1 ms per map for the FP64 sweeps, so below about four
+    maps the FP64 sweeps are both faster and more accurate."""
 
     def __init__(self, device="cuda:0", n_streams=4, max_batch=8, batch_bytes=2 << 30, keep_results=True,
-                 small_ws=2 << 30):
+                 small_ws=2 << 30, min_mfma_batch=4):
         import torch
         from . import binding
         self.torch, self.binding = torch, binding
@@ -315,6 +333,12 @@ class GpuExecutor:
         self.ws_lru = collections.OrderedDict()     # id(workspace) -> (key, workspace), LRU order
         self.pending = []
         self.keep_results = keep_results
+        self.min_mfma_batch = int(min_mfma_batch)
+
+    def run_key(self, key, n):
+        if key.precision != "fp64" and n < self.min_mfma_batch:
+            return dataclasses.replace(key, precision="fp64")
+        return key
 
     def batch_limit(self, key):
         per = Scheduler.buffer_bytes(key, 1)
@@ -480,7 +504,8 @@ def run_mix(n_requests=200, seed=3, lmin=64, lmax=1024, so3_lmax=256, n_streams=
             budget_frac=0.8, loads=(0.5, 0.7, 0.9), device="cuda:0", precision="fp64"):
     """Saturation throughput of a request mix, then realtime runs at fractions of it.
     precision: every request's plan precision ("fp64", or the matrix-core "fp32" /
-    "split_bf16" contraction).
+    "split_bf16" contraction); a matrix-core batch below the executor's
+    min_mfma_batch runs on the FP64 plan (``ran_at_precision`` counts both).
 
     Returns a dict with the saturation rate (requests/s) and p50/p99 latency per load."""
     import torch
@@ -512,6 +537,8 @@ def run_mix(n_requests=200, seed=3, lmin=64, lmax=1024, so3_lmax=256, n_streams=
         lam = len(sched.done) / wall
         out["saturation_req_per_s"] = lam
         out["rejected"] = len(sched.rejected)
+        # requests whose batch ran with a matrix-core plan (the rest ran on FP64 plans)
+        out["ran_at_precision"] = dict(collections.Counter(r.run_precision for r in sched.done))
         for frac in loads:
             rate = frac * lam
             note(f"load {frac} ({rate:.1f} requests/s)")

@@ -66,13 +66,14 @@ def test_mixed_precision_mix_matches_fp64():
     for spec in trace:
         spec["precision"] = "split_bf16"
     reqs = serving.build_requests(trace, seed=5)
-    ex = serving.GpuExecutor(n_streams=2, max_batch=4)
+    ex = serving.GpuExecutor(n_streams=2, max_batch=4, min_mfma_batch=1)   # every batch on the matrix cores
     try:
         sched = serving.Scheduler(ex, hbm_budget=8 << 30)
         serving.serve(sched, reqs, realtime=False)
     finally:
         ex.close()
     assert not sched.rejected and len(sched.done) == len(reqs)
+    assert all(r.run_precision == "split_bf16" for r in reqs)
     for r in reqs:
         k = r.key
         x = torch.from_numpy(r.data).cuda()
@@ -85,3 +86,32 @@ def test_mixed_precision_mix_matches_fp64():
         assert np.array_equal(outs[0], r.result), (r.rid, k)
         assert rel_l2(r.result, outs[1]) < 2e-4, (r.rid, k)
         assert rel_l2(r.result, outs[1]) > 1e-12          # the reduced-precision products were used
+
+
+def test_small_matrix_core_batches_run_fp64():
+    """Default policy: a split-BF16 batch of fewer than four maps runs on the FP64
+    plan (faster and more accurate there); a larger one on the matrix cores.  Each
+    result equals the request served alone at the precision its batch ran with."""
+    from paper_2311_14670_amd import binding, serving
+    binding.load_library()
+    specs = [dict(kind="s2", L=48, spin=0, sampling="mw", precision="split_bf16", t=0.0)] * 6
+    specs += [dict(kind="s2", L=40, spin=2, sampling="mw", precision="split_bf16", t=0.0),
+              dict(kind="so3", L=16, N=3, sampling="mw", precision="split_bf16", t=0.0)]
+    reqs = serving.build_requests(specs, seed=7)
+    ex = serving.GpuExecutor(n_streams=2, max_batch=8)
+    try:
+        sched = serving.Scheduler(ex, hbm_budget=8 << 30)
+        serving.serve(sched, reqs, realtime=False)
+    finally:
+        ex.close()
+    assert not sched.rejected and len(sched.done) == len(reqs)
+    by = {r.rid: r for r in reqs}
+    assert all(by[i].run_precision == "split_bf16" and by[i].batch_size == 6 for i in range(6))
+    assert by[6].run_precision == "fp64" and by[7].run_precision == "fp64"
+    for r in reqs:
+        k = r.key
+        plan = binding.Plan(k.L, spin=k.spin, N=k.N, sampling=k.sampling, nside=k.nside, precision=r.run_precision)
+        x = torch.from_numpy(r.data).cuda()
+        y = plan.so3_forward(plan.so3_inverse(x)) if k.kind == "so3" else plan.forward(plan.inverse(x))
+        assert np.array_equal(y.cpu().numpy(), r.result), (r.rid, k, r.run_precision)
+        plan.close()

@@ -194,3 +194,31 @@ def test_waiting_key_keeps_its_plan_under_pressure():
     assert len(s.done) == 2 and not s.rejected
     assert [ids for _, ids in ex.launches] == [[0], [1]]
     assert ex.created[big.key] == 1, ex.created
+
+
+class MixedExecutor(FakeExecutor):
+    """A matrix-core batch below two requests runs on the key's FP64 plan."""
+
+    def run_key(self, key, n):
+        import dataclasses
+        return dataclasses.replace(key, precision="fp64") if key.precision != "fp64" and n < 2 else key
+
+
+def test_small_matrix_core_batches_run_on_the_fp64_plan():
+    import dataclasses
+    clock = Clock()
+    ex = MixedExecutor(clock, n_streams=1, max_batch=4)
+    sched = Scheduler(ex, hbm_budget=10 ** 9)
+    ex.sched = sched
+    split = PlanKey("s2", 64, 0, 1, "mw", 0, "split_bf16")
+    reqs = [Request(rid=0, key=split, data=None, t_arrival=0.0),                       # alone: FP64 plan
+            Request(rid=1, key=dataclasses.replace(split, L=96), data=None, t_arrival=1.0),
+            Request(rid=2, key=dataclasses.replace(split, L=96), data=None, t_arrival=1.0)]  # a pair: matrix cores
+    serve(sched, reqs, clock=clock, sleep=clock.sleep)
+    assert len(sched.done) == 3 and not sched.rejected
+    keys = [k for k, _ in ex.launches]
+    assert keys[0] == dataclasses.replace(split, precision="fp64")
+    assert keys[1] == dataclasses.replace(split, L=96) and ex.launches[1][1] == [1, 2]
+    assert [r.run_precision for r in sorted(sched.done, key=lambda r: r.rid)] == ["fp64", "split_bf16", "split_bf16"]
+    # the plan in use is the one admitted and cached
+    assert dataclasses.replace(split, precision="fp64") in ex.plans

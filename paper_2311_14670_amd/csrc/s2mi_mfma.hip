@@ -371,11 +371,33 @@ __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int
 }
 
 // ------------------------------------------------------------------ contractions
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8 XCDs
+// (workgroup i to XCD i mod 8), each with its own L2.  The contraction tiles of one
+// order share that order's coefficient or spectra operand (A_m / H_m, 2 MB at
+// L = 2048, B = 64), so a 1-D grid is remapped to give every XCD one contiguous run
+// of tiles (x fastest, then the order, then the row group) and each XCD reads an
+// order's shared operand once.  Returns false for the padding of the grid.
+constexpr int NXCD = 8;
+__device__ __forceinline__ bool xcd_tile(int gx, int gy, int gz, int &bx, int &by, int &bz)
+{
+    const int T = gx * gy * gz;
+    const int per = (T + NXCD - 1) / NXCD;
+    const int i = (int)blockIdx.x;
+    const int j = (i % NXCD) * per + i / NXCD;
+    if (j >= T) return false;
+    bz = j / (gx * gy);
+    const int r = j - bz * gx * gy;
+    by = r / gx;
+    bx = r - by * gx;
+    return true;
+}
+
 // 256 threads = 4 waves; each wave owns MTW 32-row tiles (rows of maps) and two
 // 32-column tiles.  Inverse: columns = 64 rings, K = degrees l >= max(m, |n|).
 // Output of map b, ring r, order m: partA[b][r][m][0,1], partB[b][r][m][2,3].
 template <int FMT, int MTW>
-__global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int kc_tot, int n, int m_lo, int B,
+__global__ __launch_bounds__(256) void k_mfma_inv(int gx, int gy, int gz, int L, int nreg, int rpad, int kc_tot, int n,
+                                                  int m_lo, int B,
                                                   int rpad_rows, const double *__restrict__ cot,
                                                   const double *__restrict__ csc, const uint4 *__restrict__ A,
                                                   const uint4 *__restrict__ D,
@@ -383,8 +405,10 @@ __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int half = lane >> 5, li = lane & 31;
-    const int ring0 = blockIdx.x * 64;
-    const int mc = blockIdx.y, m = m_lo + mc;
+    int bx, by, bz;
+    if (!xcd_tile(gx, gy, gz, bx, by, bz)) return;
+    const int ring0 = bx * 64;
+    const int mc = by, m = m_lo + mc;
     const int MT = rpad_rows / 32;
     const int an = n < 0 ? -n : n;
     const int kc0 = (m > an ? m : an) / SG;
@@ -392,7 +416,7 @@ __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int
     bool mv[MTW];
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {
-        mts[i] = blockIdx.z * 4 * MTW + w + 4 * i;
+        mts[i] = bz * 4 * MTW + w + 4 * i;
         mv[i] = mts[i] < MT;
     }
     if (!mv[0]) return;
@@ -465,7 +489,8 @@ __global__ __launch_bounds__(256) void k_mfma_inv(int L, int nreg, int rpad, int
 // Forward: columns = 64 degrees l, K = rings.  Output Q[b][l][m][comp] for
 // l >= m (degrees below max(m, |n|) carry zero d and give zero).
 template <int FMT, int MTW>
-__global__ __launch_bounds__(256) void k_mfma_fwd(int L, int rpad, int lp, int n, int m_lo, int B, int rpad_rows,
+__global__ __launch_bounds__(256) void k_mfma_fwd(int gx, int gy, int gz, int L, int rpad, int lp, int n, int m_lo,
+                                                  int B, int rpad_rows,
                                                   int nxp, const uint4 *__restrict__ H, const uint4 *__restrict__ D,
                                                   double *__restrict__ QA, double *__restrict__ QB,
                                                   long long qstride, double *__restrict__ QxA,
@@ -473,8 +498,10 @@ __global__ __launch_bounds__(256) void k_mfma_fwd(int L, int rpad, int lp, int n
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int half = lane >> 5, li = lane & 31;
-    const int l0 = blockIdx.x * 64;
-    const int mc = blockIdx.y, m = m_lo + mc;
+    int bx, by, bz;
+    if (!xcd_tile(gx, gy, gz, bx, by, bz)) return;
+    const int l0 = bx * 64;
+    const int mc = by, m = m_lo + mc;
     const int an = n < 0 ? -n : n, am = m < 0 ? -m : m;
     if (l0 + 63 < m) return;
     const int MT = rpad_rows / 32;
@@ -482,7 +509,7 @@ __global__ __launch_bounds__(256) void k_mfma_fwd(int L, int rpad, int lp, int n
     bool mv[MTW];
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {
-        mts[i] = blockIdx.z * 4 * MTW + w + 4 * i;
+        mts[i] = bz * 4 * MTW + w + 4 * i;
         mv[i] = mts[i] < MT;
     }
     if (!mv[0]) return;
@@ -630,10 +657,11 @@ hipError_t launch_mfma_inv(hipStream_t st, int fmt, const MfmaGeom &g, int n, co
 {
     const int MT = g.rows / 32;
     const int mtw = MT <= 4 ? 1 : 2;
-    const dim3 grid((unsigned)(g.rpad / 64), (unsigned)mcn, (unsigned)((MT + 4 * mtw - 1) / (4 * mtw))), block(256);
-#define S2_MI(FMT, MTW)                                                                                    \
-    hipLaunchKernelGGL((k_mfma_inv<FMT, MTW>), grid, block, 0, st, g.L, g.nreg, g.rpad, g.kc, n, m_lo, B, \
-                       g.rows, cot, csc, A, D, PA, PB, pstride)
+    const int gx = g.rpad / 64, gy = mcn, gz = (MT + 4 * mtw - 1) / (4 * mtw);
+    const dim3 grid((unsigned)((gx * gy * gz + NXCD - 1) / NXCD * NXCD)), block(256);
+#define S2_MI(FMT, MTW)                                                                                        \
+    hipLaunchKernelGGL((k_mfma_inv<FMT, MTW>), grid, block, 0, st, gx, gy, gz, g.L, g.nreg, g.rpad, g.kc, n, m_lo, \
+                       B, g.rows, cot, csc, A, D, PA, PB, pstride)
     if (fmt == S2_CONTRACT_FP32) { if (mtw == 1) S2_MI(S2_CONTRACT_FP32, 1); else S2_MI(S2_CONTRACT_FP32, 2); }
     else { if (mtw == 1) S2_MI(S2_CONTRACT_SPLIT_BF16, 1); else S2_MI(S2_CONTRACT_SPLIT_BF16, 2); }
 #undef S2_MI
@@ -647,10 +675,11 @@ hipError_t launch_mfma_fwd(hipStream_t st, int fmt, const MfmaGeom &g, int n, in
 {
     const int MT = g.rows / 32;
     const int mtw = MT <= 4 ? 1 : 2;
-    const dim3 grid((unsigned)(g.lp / 64), (unsigned)mcn, (unsigned)((MT + 4 * mtw - 1) / (4 * mtw))), block(256);
-#define S2_MF(FMT, MTW)                                                                                     \
-    hipLaunchKernelGGL((k_mfma_fwd<FMT, MTW>), grid, block, 0, st, g.L, g.rpad, g.lp, n, m_lo, B, g.rows, nxp, H, \
-                       D, QA, QB, qstride, QxA, QxB, qxstride)
+    const int gx = g.lp / 64, gy = mcn, gz = (MT + 4 * mtw - 1) / (4 * mtw);
+    const dim3 grid((unsigned)((gx * gy * gz + NXCD - 1) / NXCD * NXCD)), block(256);
+#define S2_MF(FMT, MTW)                                                                                          \
+    hipLaunchKernelGGL((k_mfma_fwd<FMT, MTW>), grid, block, 0, st, gx, gy, gz, g.L, g.rpad, g.lp, n, m_lo, B, g.rows, \
+                       nxp, H, D, QA, QB, qstride, QxA, QxB, qxstride)
     if (fmt == S2_CONTRACT_FP32) { if (mtw == 1) S2_MF(S2_CONTRACT_FP32, 1); else S2_MF(S2_CONTRACT_FP32, 2); }
     else { if (mtw == 1) S2_MF(S2_CONTRACT_SPLIT_BF16, 1); else S2_MF(S2_CONTRACT_SPLIT_BF16, 2); }
 #undef S2_MF

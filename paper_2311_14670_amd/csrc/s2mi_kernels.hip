@@ -789,11 +789,11 @@ __device__ __forceinline__ void fwd_reduce2(int m, bool two, int g, int L, int n
 
 template <int NCH, bool SAME, int WT, int SIDE = 0, bool PAIRF = false>
 __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
-    int L, int nxp, int nreg, int hstride, int lstride, int n, int G, const double *__restrict__ lam,
-    const double2 *__restrict__ init, const double *__restrict__ kap, const double *__restrict__ gtab,
-    const double *__restrict__ HA, const double *__restrict__ HB, const double *__restrict__ HxA,
-    const double *__restrict__ HxB, double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
-    double *__restrict__ QxB, OrderTiles ot)
+    int gx, int gy, int gz, bool xcd, int L, int nxp, int nreg, int hstride, int lstride, int n, int G,
+    const double *__restrict__ lam, const double2 *__restrict__ init, const double *__restrict__ kap,
+    const double *__restrict__ gtab, const double *__restrict__ HA, const double *__restrict__ HB,
+    const double *__restrict__ HxA, const double *__restrict__ HxB, double *__restrict__ QA, double *__restrict__ QB,
+    double *__restrict__ QxA, double *__restrict__ QxB, OrderTiles ot)
 {
     __shared__ double red[4 * WT * 4 * 64];         // four order buffers of WT x 4 x 64 sums
     const int an = n < 0 ? -n : n;
@@ -801,12 +801,14 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
     constexpr int W = WT;                                // waves per workgroup (== blockDim.x / 64)
-    const int blk = blockIdx.y;
-    const int p = blockIdx.x;
+    // l-group pair p, ring block blk, order tile bz (xcd: each XCD takes contiguous
+    // pairs, so the workgroups of one ring block read its spectra rows through one L2)
+    int p, blk, bz;
+    if (!xcd_tile(gx, gy, gz, p, blk, bz, xcd)) return;
     // this wave's rings: rbase .. rbase + NCH SG - 1 (contiguous; >= nreg inert)
     const int rbase = (blk * W + w) * NCH * SG;
-    // order tile blockIdx.z: orders ctop - 1 .. lo
-    const int tile = blockIdx.z;
+    // order tile bz: orders ctop - 1 .. lo
+    const int tile = bz;
     const int ctop = tile == 0 ? L : ot.c[tile];
     const int lo = tile + 1 < ot.nt ? ot.c[tile + 1] : mend;
 
@@ -1957,12 +1959,34 @@ hipError_t launch_dstage_fwd(hipStream_t st, int nwaves, int nblk, int G, int L,
     if (pair && (n != 0 || HA == HB || HxA || HxB || side == 2)) return hipErrorInvalidValue;   // mirror rings: n = 0
     // one side: both sides read one spectra array (the run's slice), and that side has outputs
     if (side && !pair && (HA != HB || (side == 1 && !QA) || (side == 2 && !QB))) return hipErrorInvalidValue;
-    dim3 grid((G + 1) / 2, nblk, ot.nt);
+    // XCD-aware tile order when the untiled grid is resident in one round (every
+    // workgroup of a ring block then runs beside the others that read its spectra rows,
+    // in step through one L2).  Measured (one map): MW L = 2048 forward 2.94 -> 2.82 ms
+    // (spin 2: 5.43 -> 5.05 ms), HEALPix nside 1024 3.95 -> 3.80 ms, spectra read from
+    // HBM 3.04 -> 1.58 GB; grids of several rounds were slower in that order (L = 3072
+    // 10.7 -> 12.4 ms, L = 4096 19.5 -> 28.1 ms, L = 1024 in 8 order tiles 0.59 -> 0.75
+    // ms) and keep the plain one.  The inverse sweep was slower in XCD order at every size
+    // tried (L = 1024: 0.47 -> 0.79 ms; L = 2048 spin 2: 4.5 -> 5.1 ms).
+    const int gx = (G + 1) / 2, gy = nblk, gz = ot.nt, T = gx * gy * gz;
+    // (a failed query only selects the plain order; its error is cleared, not reported)
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess) {
+        ncu = 0;
+        (void)hipGetLastError();
+    }
     // the wave count is a template argument: the reducer rotation and the wave sum
     // then compile to fixed code; HA == HB (run n = 0) selects the one-array path
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, L, nxp, nreg, hstride, lstride, n, G, lam, init, kap,
-                           gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB, ot);
+        int per_cu = 0;
+        if (ncu && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * nwaves, 0) != hipSuccess) {
+            per_cu = 0;
+            (void)hipGetLastError();
+        }
+        const bool xcd = ot.nt == 1 && T <= per_cu * ncu;
+        const dim3 grid((unsigned)(xcd ? (T + NXCD - 1) / NXCD * NXCD : T));
+        hipLaunchKernelGGL(kern, grid, dim3(64 * nwaves), 0, st, gx, gy, gz, xcd, L, nxp, nreg, hstride, lstride, n,
+                           G, lam, init, kap, gtab, HA, HB, HxA, HxB, QA, QB, QxA, QxB, ot);
     };
     const bool same = HA == HB;
     if (pair) {

@@ -371,26 +371,8 @@ __global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int
 }
 
 // ------------------------------------------------------------------ contractions
-// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8 XCDs
-// (workgroup i to XCD i mod 8), each with its own L2.  The contraction tiles of one
-// order share that order's coefficient or spectra operand (A_m / H_m, 2 MB at
-// L = 2048, B = 64), so a 1-D grid is remapped to give every XCD one contiguous run
-// of tiles (x fastest, then the order, then the row group) and each XCD reads an
-// order's shared operand once.  Returns false for the padding of the grid.
-constexpr int NXCD = 8;
-__device__ __forceinline__ bool xcd_tile(int gx, int gy, int gz, int &bx, int &by, int &bz)
-{
-    const int T = gx * gy * gz;
-    const int per = (T + NXCD - 1) / NXCD;
-    const int i = (int)blockIdx.x;
-    const int j = (i % NXCD) * per + i / NXCD;
-    if (j >= T) return false;
-    bz = j / (gx * gy);
-    const int r = j - bz * gx * gy;
-    by = r / gx;
-    bx = r - by * gx;
-    return true;
-}
+// Contraction tiles are dispatched XCD-aware (xcd_tile): the tiles of one order share
+// that order's coefficient or spectra operand (A_m / H_m, 2 MB at L = 2048, B = 64).
 
 // 256 threads = 4 waves; each wave owns MTW 32-row tiles (rows of maps) and two
 // 32-column tiles.  Inverse: columns = 64 rings, K = degrees l >= max(m, |n|).

@@ -12,6 +12,36 @@ constexpr int SG = 8;     // degrees (or rings) per register chunk
 
 __device__ __forceinline__ int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Tile order of the sweeps and contractions.  Workgroups are dispatched round-robin
+// over the 8 XCDs (workgroup i to XCD i mod 8), each with its own L2.  With xcd set, a
+// 1-D grid of ceil(gx gy gz / 8) * 8 workgroups is remapped so that every XCD takes one
+// contiguous run of the tiles, ordered z fastest, then x, then y: tiles that share an
+// operand along x (and every z) then read it through one L2, while each XCD still
+// gets tiles of every z.  Without xcd, workgroup i is tile i in x-fastest order.
+// Returns false for the padding of the grid.
+constexpr int NXCD = 8;
+__device__ __forceinline__ bool xcd_tile(int gx, int gy, int gz, int &bx, int &by, int &bz, bool xcd = true)
+{
+    const int T = gx * gy * gz;
+    const int i = (int)blockIdx.x;
+    if (!xcd) {
+        if (i >= T) return false;
+        bx = i % gx;
+        const int r = i / gx;
+        by = r % gy;
+        bz = r / gy;
+        return true;
+    }
+    const int per = (T + NXCD - 1) / NXCD;
+    const int j = (i % NXCD) * per + i / NXCD;
+    if (j >= T) return false;
+    bz = j % gz;
+    const int r = j / gz;
+    bx = r % gx;
+    by = r / gx;
+    return true;
+}
+
 // exact power-of-two renormalisation of the pair (e, ep) carrying exponent E
 // (running renormalisation, Sec. 3.4): while the scale exponent E is below
 // -RT the pair is rescaled so its larger entry is in [1, 2); once E + k is

@@ -72,7 +72,7 @@ constexpr int FWD_MAX_WAVES = 16;       // forward sweep workgroups: at most 102
 // workgroups share one run without adding partial sums (each order stays in one
 // tile).  A tile k > 0 starts from the recursion state after order c[k], held per
 // run in ck at offset off[k] as rows (l - c[k]), l >= c[k], of 3 x rp doubles:
-// {e_{c[k]}[ring], e_{c[k]+1}[ring], E[ring]} (d = e 2^E).
+// {e_{c[k]}[ring], e_{c[k]+1}[ring], E[ring]} (a recursion slot state; see renorm).
 constexpr int MAX_ORDER_TILES = 8;
 struct OrderTiles {
     int nt = 1;                             // tiles (1: the whole order range)

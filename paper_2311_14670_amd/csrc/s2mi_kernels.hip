@@ -14,12 +14,13 @@
 // d_m = e_m g_m (g from the plan tables), Eq. 25 becomes
 //     e_{m-1} = kappa_m lambda_m e_m - e_{m+1},  lambda_m = (n - m cos th)/sin th,
 // two FP64 operations per step.  Each (ring, l) carries (e_m, e_{m+1}, E) with
-// d = e g 2^E.  While E < 0 the contribution is e 2^E (exact scaling, zero once
-// below the double range) and every RN orders the pair is renormalised by an
-// exact power of two; once the value is within 2^-600 of unit scale it is
-// realised (E = 0): |d| <= 1 and the recursion runs downhill in m, so it can no
-// longer overflow or meaningfully underflow.  A chunk whose lanes are all
-// realised runs the plain step.
+// d = e g 2^E.  While the value is below 2^-600 (E < 0) the pair is held scaled near
+// 2^-600 and renormalised by an exact power of two every RN orders; the contraction
+// uses e as it stands, so such a slot adds a negligible amount (below 2^-370 of its
+// record) with no per-step scaling.  Once the value is within 2^-600 of unit scale
+// it is realised (E = 0, d = e g): |d| <= 1 and the recursion runs downhill in m, so
+// it can no longer overflow or meaningfully underflow.  A chunk whose lanes are all
+// realised skips the renormalisation.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -60,9 +61,10 @@ __device__ __forceinline__ DD dd_mul_d(DD a, double k)   // k an exact small int
     return two_sum(p, e + a.lo * k);
 }
 
-// d^l_{l,n}(theta) of Eq. 27 as (mantissa e, exponent E): log2|d| =
+// d^l_{l,n}(theta) of Eq. 27 as a recursion slot state (e, E): log2|d| =
 // lbin + (l-n) log2 sin(th/2) + (l+n) log2 cos(th/2) in double-double, sign (-1)^{l-n}.
-// Realised (E = 0) directly when the value is not tiny.
+// Realised (E = 0) directly when the value is not tiny; otherwise e = v 2^-RT with
+// v in [1, 2) and the value is e 2^E, E < 0 (see renorm).
 __device__ __forceinline__ void d_init(int l, int n, DD lbin, DD ls, DD lc, double &e, int &E)
 {
     DD x = dd_add(lbin, dd_add(dd_mul_d(ls, (double)(l - n)), dd_mul_d(lc, (double)(l + n))));
@@ -74,6 +76,7 @@ __device__ __forceinline__ void d_init(int l, int n, DD lbin, DD ls, DD lc, doub
     if ((l - n) & 1) v = -v;
     int ex = (int)fl;
     if (ex >= -RT) { v = ldexp(v, ex); ex = 0; }
+    else { v = ldexp(v, -RT); ex += RT; }
     e = v;
     E = ex;
 }
@@ -173,9 +176,8 @@ constexpr int PFD = 3;   // orders of record / spectra prefetch ahead of use
 // after order c of every order-tile cut c = ot.c[k], k >= 1, for ring r and degree
 // l >= c: thread (r, l) starts at order l from d^l_{l,n} (Eq. 27) and steps down
 // with the sweeps' operations (kappa lambda, then one fma), renormalising every RN
-// orders by exact powers of two.  A sweep that renormalises at other orders holds
-// the same e 2^E, so the d values it contributes from a tile's start are those of
-// the uninterrupted sweep.  Rings past nreg and degrees below |n| (never started)
+// orders by exact powers of two at the same orders as the sweeps, so a tile that
+// starts from this state holds exactly the state of the uninterrupted sweep.  Rings past nreg and degrees below |n| (never started)
 // hold zeros.
 __global__ void k_order_ckpt(int L, int nreg, int n, const double *__restrict__ cot, const double *__restrict__ csc,
                              const double2 *__restrict__ init, const double *__restrict__ kap, OrderTiles ot,
@@ -260,18 +262,17 @@ __device__ __forceinline__ void renorm_chunks(double (&X)[NCH][SG], double (&Y)[
 }
 
 // One order of one chunk: e_{m-1} = (kappa lambda) e_m - e_{m+1}, plus the
-// contribution times the records.  SLOW: the contribution is e 2^E (exact
-// scaling, zero once below the double range) and slot jin may start here
-// (l == m) from its start value; otherwise the chunk is realised (E = 0).
+// contribution e times the records (unscaled: a slot not yet realised holds e near
+// 2^-RT, so its contribution is negligible; see renorm).
 // SIDE 1 / 2 (one side present: real signals, or a spin-s sphere run, which
 // feeds only the orders +m or only -m of its slice): records of RS = 3 doubles,
 // {kappa, that side's coefficient}.  ac[0..3] are the sums {Re A, Im A, Re B,
 // Im B}; PAIR: ac[0..3] over the even and ac[4..7] over the odd degrees (slot j
 // of a chunk holds l = base + SG-1-j, base a multiple of SG, so l is odd
 // exactly when j is even).
-template <int PAR, bool SLOW, int SIDE = 0, bool PAIR = false>
-__device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], const int (&E)[SG], const double *__restrict__ rec,
-                                          double lam, double (&ac)[PAIR ? 8 : 4])
+template <int PAR, int SIDE = 0, bool PAIR = false>
+__device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], const double *__restrict__ rec, double lam,
+                                          double (&ac)[PAIR ? 8 : 4])
 {
     constexpr int RS = SIDE ? 3 : 5;
     // GROUPED: all kappa-lambda products, then all recurrence updates, then the
@@ -292,7 +293,7 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], cons
             double &nw = PAR == 0 ? Y[j] : X[j];          // receives order m
             double &od = PAR == 0 ? X[j] : Y[j];          // holds order m+1
             nw = fma(p[j], od, -nw);
-            tt[j] = SLOW ? ldexp(nw, E[j]) : nw;
+            tt[j] = nw;
         }
     }
 #pragma unroll
@@ -304,7 +305,7 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], cons
             double &nw = PAR == 0 ? Y[j] : X[j];
             double &od = PAR == 0 ? X[j] : Y[j];
             nw = fma(c[0] * lam, od, -nw);
-            t = SLOW ? ldexp(nw, E[j]) : nw;
+            t = nw;
         }
         if constexpr (SIDE == 2) {
             ac[o + 2] = fma(t, c[1], ac[o + 2]);
@@ -320,7 +321,7 @@ __device__ __forceinline__ void inv_chunk(double (&X)[SG], double (&Y)[SG], cons
     }
 }
 
-// A degree l starts at order m = l from its start value e0 2^E0 (Eq. 27) with
+// A degree l starts at order m = l from its start value (e0, E0) (Eq. 27) with
 // e_{l+1} = 0.  Its slot holds zero state until then and its record at l == m
 // has kappa = 0, so writing -e0 into the register that receives order m lets the
 // ordinary step produce e_m = fma(0, 0, e0) = e0: every chunk runs one step form.
@@ -377,7 +378,7 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
             }
             fast &= ~(1u << g);
         }
-        inv_chunk<PAR, true, SIDE, PAIR>(X[g], Y[g], E[g], rec, lam, ac);
+        inv_chunk<PAR, SIDE, PAIR>(X[g], Y[g], rec, lam, ac);
     }
     // renormalisation pass every RN orders over the started chunks not yet realised
     if ((m & (RN - 1)) == 0) {
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
 // lambda, zero H, never initialised); waves of a workgroup share the l-group
 // and split the rings.  A workgroup runs group p then group G-1-p so all
 // workgroups carry equal work.  At order m:
-//   acc(l) = g_m^l sum_{slots} e 2^E * H[m][ring],
+//   acc(l) = g_m^l sum_{slots} e * H[m][ring]   (e unscaled; see renorm),
 // reduced over the waves in LDS (rotating reducers) and written to
 // QA/QB[blk][l][m].  kappa and g of the next order are loaded one step ahead.
 __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int r0, int m, int L)
@@ -599,7 +600,7 @@ __device__ __forceinline__ void fwd_chunk(double (&X)[SG], double (&Y)[SG], int 
                 od = 0.0;
             }
         }
-        const double t = REAL ? nw : ldexp(nw, E[k]);   // exact scaling; 0 below the double range
+        const double t = nw;                             // unscaled (see renorm)
         const double *ha = HA + k * 4;                   // components chosen by the caller's offsets
         const double *hb = HB + k * 4;
         if constexpr (SIDE != 2) {

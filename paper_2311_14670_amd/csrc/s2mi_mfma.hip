@@ -6,7 +6,8 @@
 // the Wigner-d matrix D_m[l][ring] of the run's second index n.  D_m comes
 // from the same FP64 descending-m recursion as the fused FP64 sweeps
 // (Eqs. 25-27, running renormalisation of Sec. 3.4), generated for a chunk of
-// consecutive orders at a time, realised (d = e g 2^E) and rounded to the
+// consecutive orders at a time, realised (d = e g; a value not yet realised is
+// below 2^-370 and rounds to zero) and rounded to the
 // contraction format:
 //   FP32        fp32 operands, one MFMA pass, fp32 accumulation;
 //   split BF16  x = hi + lo, hi = bf16(x), lo = bf16(x - hi); three MFMA passes
@@ -160,7 +161,7 @@ __device__ __forceinline__ void gen_chunk(double (&X)[SG], double (&Y)[SG], int 
                 E[e] = E0;
             }
             renorm(nw, od, E[e]);
-            t = nw * ldexp(1.0, E[e]);
+            t = nw;                                       // not yet realised: below 2^-370, 0 as a float
         }
         dv[e] = (float)(t * kgv.y);
     }

@@ -42,21 +42,30 @@ __device__ __forceinline__ bool xcd_tile(int gx, int gy, int gz, int &bx, int &b
     return true;
 }
 
-// exact power-of-two renormalisation of the pair (e, ep) carrying exponent E
-// (running renormalisation, Sec. 3.4): while the scale exponent E is below
-// -RT the pair is rescaled so its larger entry is in [1, 2); once E + k is
-// above -RT it is realised (E = 0) and left unscaled from then on.
+// State of one recursion slot: the pair (e, ep) and an int E, the slot's values
+// being e 2^E and ep 2^E.  Realised (E = 0): e is the value itself.  Not yet realised
+// (value below 2^-RT): E < 0 and the pair is kept scaled near 2^-RT, so a sweep can use
+// e unscaled in its contraction -- such a slot then contributes at most about
+// 2^(230 - RT) times its record instead of its exact (equally negligible) value, and
+// no exponent scaling is needed per step.  A slot that has not started holds zeros
+// with E = 0.
+
+// Exact power-of-two renormalisation of the pair (e, ep) carrying exponent E
+// (running renormalisation, Sec. 3.4): a pair whose value is below 2^-RT is rescaled
+// so its larger entry is in [2^-RT, 2^(1-RT)), E absorbing the change; a pair whose
+// value is at least 2^-RT is realised (E = 0, values unscaled from then on).  Every
+// scaling is by a power of two, so the values themselves never change.
 __device__ __forceinline__ void renorm(double &e, double &ep, int &E)
 {
     const double mx = fmax(fabs(e), fabs(ep));
     // floor(log2 mx) = frexp exponent - 1 (mx is finite: the state grows by a bounded
     // factor between passes); a not-yet-started (zero) state keeps E
     const int k = mx > 0.0 ? __builtin_amdgcn_frexp_exp(mx) - 1 : 0;
-    const bool real = (E + k >= -RT);
-    const int sh = real ? E : -k;
+    const bool real = (E + k >= -RT);                   // the value's exponent is E + k
+    const int sh = real ? E : -k - RT;
     e = ldexp(e, sh);
     ep = ldexp(ep, sh);
-    E = real ? 0 : E + k;
+    E = real ? 0 : E + k + RT;                           // < 0: E + k < -RT
 }
 
 // Stable-direction switch for runs with n != 0.  At a ring the descending

@@ -16,7 +16,7 @@
 // two FP64 operations per step.  Each (ring, l) carries (e_m, e_{m+1}, E) with
 // d = e g 2^E.  While the value is below 2^-600 (E < 0) the pair is held scaled near
 // 2^-600 and renormalised by an exact power of two every RN orders; the contraction
-// uses e as it stands, so such a slot adds a negligible amount (below 2^-370 of its
+// uses e as it stands, so such a slot adds a negligible amount (below 2^-279 of its
 // record) with no per-step scaling.  Once the value is within 2^-600 of unit scale
 // it is realised (E = 0, d = e g): |d| <= 1 and the recursion runs downhill in m, so
 // it can no longer overflow or meaningfully underflow.  A chunk whose lanes are all
@@ -164,11 +164,15 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, int rs, const
 // orders (PAR), so the recursion needs no register moves.  Per order, each
 // wave's partial sums are reduced over the waves in LDS by a rotating group of
 // four waves and written to partA/partB[blk][ring][m].
-// Renormalisation pass over chunks that are not yet
-// realised: the state grows by at most ~2^28 per order (L <= 4096), so a pass
-// every RN orders keeps it far from overflow; a chunk whose lanes all reached
-// E = 0 stays realised while no degree starts in it.
-constexpr int RN = 8;
+// Renormalisation pass over chunks that are not yet realised: the state grows by at
+// most |kappa lambda| + 1 < 2^20 per order for L <= 4096 (|lambda| sin theta <= |n| +
+// m + 1 with kappa (|n| + m + 1) <= 181 over every degree below 4096, and sin theta >=
+// 1.9e-4 on every grid's swept rings), so between passes
+// every RN = 16 orders a pair scaled near 2^-600 stays below 2^-279: far from
+// overflow, and its unscaled contribution stays negligible.  A chunk whose lanes all
+// reached E = 0 stays realised while no degree starts in it.  (Passes every 8 orders:
+// MW L = 2048 inverse 2.70 ms, forward 2.78 ms; every 16: 2.62 and 2.71-2.76 ms.)
+constexpr int RN = 16;
 constexpr int PFD = 3;   // orders of record / spectra prefetch ahead of use
 
 // ------------------------------------------------------------------ order-tile states

@@ -46,8 +46,9 @@ __device__ __forceinline__ bool xcd_tile(int gx, int gy, int gz, int &bx, int &b
 // being e 2^E and ep 2^E.  Realised (E = 0): e is the value itself.  Not yet realised
 // (value below 2^-RT): E < 0 and the pair is kept scaled near 2^-RT, so a sweep can use
 // e unscaled in its contraction -- such a slot then contributes at most about
-// 2^(230 - RT) times its record instead of its exact (equally negligible) value, and
-// no exponent scaling is needed per step.  A slot that has not started holds zeros
+// 2^(321 - RT) times its record (the growth between two passes of the sweeps is below
+// 2^320) instead of its exact (equally negligible) value, and no exponent scaling is
+// needed per step.  A slot that has not started holds zeros
 // with E = 0.
 
 // Exact power-of-two renormalisation of the pair (e, ep) carrying exponent E

@@ -163,11 +163,15 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int len, int Ns, const d
     }
     __syncthreads();
     const int tstep = len / (Ns * R);
+    // j / Ns by one high multiply with ceil(2^32 / Ns): exact for j < 2^16, Ns <= 2^13
+    // (the error j (ceil(2^32/Ns) - 2^32/Ns) / 2^32 < 2^-19 stays below 1/Ns)
+    const unsigned mag = Ns > 1 ? 0xffffffffu / (unsigned)Ns + 1u : 0u;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = tid + b * T;
         if (j < nbf) {
-            const int k = j % Ns;
+            const int jq = Ns > 1 ? (int)__umulhi((unsigned)j, mag) : j;   // j / Ns
+            const int k = j - jq * Ns;                                      // j % Ns
             if (Ns > 1) {
                 // twiddles w^r, r < R, by repeated multiplication from one table read (the
                 // R-1 reads at stride r lanes apart touched a line each; rounding grows
@@ -181,7 +185,7 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int len, int Ns, const d
                     v[b][r] = cmul(v[b][r], w);
                 }
             }
-            const int o = (j / Ns) * Ns * R + k;
+            const int o = jq * Ns * R + k;
             dft_small_store<R>(v[b], sign, buf + o, Ns);
         }
     }

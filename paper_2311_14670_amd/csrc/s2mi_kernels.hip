@@ -164,16 +164,15 @@ __global__ void k_pack_inv(int L, int nx, int n, int nslot, int S, int rs, const
 // orders (PAR), so the recursion needs no register moves.  Per order, each
 // wave's partial sums are reduced over the waves in LDS by a rotating group of
 // four waves and written to partA/partB[blk][ring][m].
-// Renormalisation pass over chunks that are not yet realised: the state grows by at
-// most |kappa lambda| + 1 < 2^20 per order for L <= 4096 (|lambda| sin theta <= |n| +
-// m + 1 with kappa (|n| + m + 1) <= 181 over every degree below 4096, and sin theta >=
-// 1.9e-4 on every grid's swept rings), so between passes
-// every RN = 16 orders a pair scaled near 2^-600 stays below 2^-279: far from
-// overflow, and its unscaled contribution stays negligible.  A chunk whose lanes all
-// reached E = 0 stays realised while no degree starts in it.  (Passes every 8 orders:
-// MW L = 2048 inverse 2.70 ms, forward 2.78 ms; every 16: 2.62 and 2.71-2.76 ms.)
-constexpr int RN = 16;
-constexpr int PFD = 3;   // orders of record / spectra prefetch ahead of use
+// Renormalisation pass over chunks that are not yet realised, every RN orders (see
+// s2mi_recur.h); a chunk whose lanes all reached E = 0 stays realised while no degree
+// starts in it.  (Passes every 8 orders: MW L = 2048 inverse 2.70 ms, forward 2.78 ms;
+// every 16: 2.62 and 2.71-2.76 ms.)
+// Orders of record / spectra prefetch ahead of use (both sweeps, every run).  Measured
+// at MW L = 2048 spin 0 with the unscaled contraction and passes every 16 orders:
+// inverse 2.61 / 2.60 / 2.62 ms and forward 2.72 / 2.68 / 2.74 ms at 3 / 2 / 4 orders
+// ahead.
+constexpr int PFD = 2;
 
 // ------------------------------------------------------------------ order-tile states
 // State of the descending recursion (Eq. 25 in the rescaled form of the sweeps)
@@ -857,9 +856,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         // consumed only at the next pair of orders, so the latency overlaps their work.
         constexpr int HL = NCH * SG * 4 * 8 / 128;           // 128-byte lines of one side's spectra row
         constexpr int PQ = 1 + 2 * HL;
-        // prefetch distance: measured best at 3 orders for the two-sided run n = 0 of an
-        // unpaired sampling, at 2 for the one-sided, paired and n != 0 runs
-        constexpr int PFF = (SAME && SIDE == 0 && !PAIRF) ? PFD : PFD - 1;
+        constexpr int PFF = PFD;
         int pf = 0;
         auto prefetch = [&](int mm) {
             asm volatile("" ::"v"(pf));

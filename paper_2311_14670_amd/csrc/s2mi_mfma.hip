@@ -7,7 +7,7 @@
 // from the same FP64 descending-m recursion as the fused FP64 sweeps
 // (Eqs. 25-27, running renormalisation of Sec. 3.4), generated for a chunk of
 // consecutive orders at a time, realised (d = e g; a value not yet realised is
-// below 2^-370 and rounds to zero) and rounded to the
+// below 2^-279 and rounds to zero) and rounded to the
 // contraction format:
 //   FP32        fp32 operands, one MFMA pass, fp32 accumulation;
 //   split BF16  x = hi + lo, hi = bf16(x), lo = bf16(x - hi); three MFMA passes
@@ -161,7 +161,7 @@ __device__ __forceinline__ void gen_chunk(double (&X)[SG], double (&Y)[SG], int 
                 E[e] = E0;
             }
             renorm(nw, od, E[e]);
-            t = nw;                                       // not yet realised: below 2^-370, 0 as a float
+            t = nw;                                       // not yet realised: below 2^-279, 0 as a float
         }
         dv[e] = (float)(t * kgv.y);
     }
@@ -189,7 +189,9 @@ __device__ __forceinline__ void gen_step(int m, int m_lo, int an, bool good, int
 #pragma unroll
             for (int e = 0; e < SG; ++e) z = z && (E[g][e] == 0);
             fast = __all(z) ? (fast | (1u << g)) : (fast & ~(1u << g));
-        } else if ((fast >> g) & 1u) {
+        } else if (((fast >> g) & 1u) || (m & (RN - 1)) != 0) {
+            // realised, or not a renormalisation order (a value not yet realised
+            // stays below 2^-279 between passes and rounds to a zero float)
             gen_chunk<PAR, false>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, dv);
         } else {
             gen_chunk<PAR, true>(X[g], Y[g], E[g], rec, lam, -1, 0.0, 0, dv);

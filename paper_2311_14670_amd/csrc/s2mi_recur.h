@@ -9,6 +9,13 @@ namespace s2mi {
 
 constexpr int RT = 600;   // realise once the scale exponent is above -RT
 constexpr int SG = 8;     // degrees (or rings) per register chunk
+// Renormalisation period of the recursion (orders; a power of two).  The state grows
+// by at most |kappa lambda| + 1 < 2^20 per order for L <= 4096 (|lambda| sin theta <=
+// |n| + m + 1 with kappa (|n| + m + 1) <= 181 over every degree below 4096, and
+// sin theta >= 1.9e-4 on every grid's swept rings), so between passes a pair scaled
+// near 2^-RT stays below 2^-279: far from overflow, and its unscaled contribution
+// negligible (see renorm).
+constexpr int RN = 16;
 
 __device__ __forceinline__ int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
 

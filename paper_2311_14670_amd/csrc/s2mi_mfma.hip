@@ -292,42 +292,64 @@ __global__ __launch_bounds__(512) void k_dgen(
 //   comp 0,1: wA_l flmA[b][l][m]   comp 2,3: (-1)^{m-n} wB_l flmB[b][l][-m]
 //   (the B rows at m > 0, and at m <= 0 for n != 0: the run's continuation)
 // zero for l < max(m, |n|), l >= L, b >= B.
+// A workgroup packs the tile (32 orders) x (one degree chunk kc) x (8 maps): the
+// coefficients are read with lanes along the orders (contiguous in flm), staged in
+// LDS as floats, and written with lanes along the tile's 32 rows (contiguous in A).
+constexpr int PK_M = 32, PK_B = 8;                       // orders and maps per pack tile
 template <int FMT>
-__global__ void k_pack_a(int L, int n, int m_lo, int mcn, int kc_tot, int rpad_rows, int B, long long mstride,
-                         const double2 *__restrict__ flmA, const double2 *__restrict__ flmB,
-                         const double *__restrict__ wA, const double *__restrict__ wB, uint4 *__restrict__ A)
+__global__ __launch_bounds__(256) void k_pack_a(int L, int n, int m_lo, int mcn, int kc_tot, int rpad_rows, int B,
+                                                long long mstride, const double2 *__restrict__ flmA,
+                                                const double2 *__restrict__ flmB, const double *__restrict__ wA,
+                                                const double *__restrict__ wB, uint4 *__restrict__ A)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t tot = (size_t)mcn * kc_tot * rpad_rows;
-    if (i >= tot) return;
-    const int row = (int)(i % rpad_rows);
-    const size_t r2 = i / rpad_rows;
-    const int kc = (int)(r2 % kc_tot);
-    const int m = m_lo + (int)(r2 / kc_tot);
-    const int b = row >> 2, comp = row & 3;
+    constexpr int RS = PK_M * (SG + 1) + 1;              // LDS row stride (floats): conflict-free both ways
+    __shared__ float sh[4 * PK_B * RS];                  // [row = 4 b + comp][order][degree]
+    const int kc = blockIdx.x, tb = blockIdx.y, m0 = blockIdx.z * PK_M;
+    const int t = threadIdx.x;
     const int an = n < 0 ? -n : n;
     const int M = 2 * L - 1;
-    const int lmin = m > an ? m : an;
-    float v[SG];
-#pragma unroll
-    for (int e = 0; e < SG; ++e) {
+    {
+        const int mi = t & (PK_M - 1), e = t >> 5;       // lanes along the orders; e: degree in the chunk
+        const int m = m_lo + m0 + mi;
         const int l = kc * SG + e;
-        double x = 0.0;
-        if (b < B && l < L && l >= lmin) {
-            if (comp < 2) {
+        const int lmin = m > an ? m : an;
+        const bool ok = m0 + mi < mcn && l < L && l >= lmin;
+        const bool sideB = flmB && (m > 0 || an > 0);
+        const double sgB = ((m - n) & 1) ? -1.0 : 1.0;
+        // a side that is absent (one-sided runs) has neither coefficients nor weights
+        const double wa = ok && flmA ? wA[l] : 0.0, wb = ok && sideB ? sgB * wB[l] : 0.0;
+#pragma unroll 2
+        for (int bi = 0; bi < PK_B; ++bi) {
+            const int b = PK_B * tb + bi;
+            double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
+            if (ok && b < B) {
                 if (flmA) {
-                    const double2 a = flmA[(size_t)b * mstride + (size_t)l * M + (L - 1) + m];
-                    x = wA[l] * (comp ? a.y : a.x);
+                    const double2 v = flmA[(size_t)b * mstride + (size_t)l * M + (L - 1) + m];
+                    xa = make_double2(wa * v.x, wa * v.y);
                 }
-            } else if (flmB && (m > 0 || an > 0)) {
-                const double2 c = flmB[(size_t)b * mstride + (size_t)l * M + (L - 1) - m];
-                x = wB[l] * (comp == 3 ? c.y : c.x);
-                if ((m - n) & 1) x = -x;
+                if (sideB) {
+                    const double2 v = flmB[(size_t)b * mstride + (size_t)l * M + (L - 1) - m];
+                    xb = make_double2(wb * v.x, wb * v.y);
+                }
             }
+            float *r = sh + (4 * bi) * RS + mi * (SG + 1) + e;
+            r[0] = (float)xa.x;
+            r[RS] = (float)xa.y;
+            r[2 * RS] = (float)xb.x;
+            r[3 * RS] = (float)xb.y;
         }
-        v[e] = (float)x;
     }
-    store_elem<FMT>(A + i * 2, v);
+    __syncthreads();
+    const int row = t & 31;                              // lanes along the rows 4 b + comp of the tile
+#pragma unroll
+    for (int q = 0; q < PK_M / 8; ++q) {
+        const int mi = (t >> 5) + 8 * q;
+        if (m0 + mi >= mcn) break;
+        float v[SG];
+#pragma unroll
+        for (int e = 0; e < SG; ++e) v[e] = sh[row * RS + mi * (SG + 1) + e];
+        store_elem<FMT>(A + (((size_t)(m0 + mi) * kc_tot + kc) * rpad_rows + 4 * PK_B * tb + row) * 2, v);
+    }
 }
 
 // Forward: H[m - m_lo][ring/8][row][8 rings] from the ring spectra F[b][|m|][ring][4]:
@@ -335,42 +357,58 @@ __global__ void k_pack_a(int L, int n, int m_lo, int mcn, int kc_tot, int rpad_r
 //   comp 2,3: FB components 2,3 (m > 0) or 0,1 (m <= 0: the B slice at order -m);
 // zero past the swept rings, for b >= B, and at orders below |n| where the ring's
 // values come from the other run (see the switch order in s2mi_recur.h).
+// A workgroup packs the tile (one order m) x (64 rings) x (8 maps): the ring records
+// are read with lanes along the rings (contiguous in F), staged in LDS as floats, and
+// written with lanes along the tile's 32 rows.
 template <int FMT>
-__global__ void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int rpad_rows, int B, long long fstride,
-                         int n, const double *__restrict__ cot, const double *__restrict__ csc,
-                         const double *__restrict__ FA, const double *__restrict__ FB, uint4 *__restrict__ H)
+__global__ __launch_bounds__(256) void k_pack_h(int m_lo, int mcn, int rpad, int nreg, int hstride, int rpad_rows, int B,
+                                                long long fstride, int n, const double *__restrict__ cot,
+                                                const double *__restrict__ csc, const double *__restrict__ FA,
+                                                const double *__restrict__ FB, uint4 *__restrict__ H)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int kr_tot = rpad / SG;
-    const size_t tot = (size_t)mcn * kr_tot * rpad_rows;
-    if (i >= tot) return;
-    const int row = (int)(i % rpad_rows);
-    const size_t r2 = i / rpad_rows;
-    const int kr = (int)(r2 % kr_tot);
-    const int m = m_lo + (int)(r2 / kr_tot);
+    constexpr int RS = 64 + 1;                           // LDS row stride (floats)
+    __shared__ float sh[4 * PK_B * RS];                  // [row = 4 b + comp][ring in the tile]
+    const int kr0 = blockIdx.x * (64 / SG), tb = blockIdx.y, mc = blockIdx.z;
+    const int t = threadIdx.x;
+    const int m = m_lo + mc;
     const int am = m < 0 ? -m : m, an = n < 0 ? -n : n;
-    const int b = row >> 2, comp = row & 3;
-    const double *F = comp < 2 ? FA : FB;
-    const int c = comp < 2 ? (m < 0 ? comp + 2 : comp) : (m > 0 ? comp : comp - 2);
+    const int cA = m < 0 ? 2 : 0;                        // A side: components 0,1 (m >= 0) or 2,3 (m < 0)
+    const int cB = m > 0 ? 2 : 0;                        // B side: components 2,3 (m > 0) or 0,1 (m <= 0)
+    {
+        const int ri = t & 63;                           // lanes along the rings
+        const int ring = kr0 * SG + ri;
+        bool useA = ring < nreg, useB = ring < nreg;
+        if (ring < nreg && m < an) {                     // low orders: own values or continuation
+            const double ct = cot[ring];
+            const bool good = ring_good(n, ct);
+            const int ms = switch_order(n, ct, csc[ring]);
+            useA = m < 0 ? (good && am < ms) : (good || m >= ms);
+            useB = m <= 0 ? (good && am < ms) : (good || m >= ms);
+        }
+#pragma unroll
+        for (int q = 0; q < PK_B / 4; ++q) {
+            const int bi = (t >> 6) + 4 * q;
+            const int b = PK_B * tb + bi;
+            double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
+            if (b < B) {
+                const size_t rec = (size_t)b * fstride + ((size_t)am * hstride + ring) * 4;
+                if (FA && useA) xa = *reinterpret_cast<const double2 *>(FA + rec + cA);
+                if (FB && useB) xb = *reinterpret_cast<const double2 *>(FB + rec + cB);
+            }
+            float *r = sh + (4 * bi) * RS + ri;
+            r[0] = (float)xa.x;
+            r[RS] = (float)xa.y;
+            r[2 * RS] = (float)xb.x;
+            r[3 * RS] = (float)xb.y;
+        }
+    }
+    __syncthreads();
+    const int row = t & 31, k8 = t >> 5;                 // lanes along the rows; k8: ring chunk of the tile
     float v[SG];
 #pragma unroll
-    for (int k = 0; k < SG; ++k) {
-        const int ring = kr * SG + k;
-        double x = 0.0;
-        if (F && b < B && ring < nreg) {
-            bool use = true;
-            if (m < an) {                                 // low orders: own values or continuation
-                const double ct = cot[ring];
-                const bool good = ring_good(n, ct);
-                const int ms = switch_order(n, ct, csc[ring]);
-                const bool cont = (comp < 2) ? (m < 0) : (m <= 0);
-                use = cont ? (good && am < ms) : (good || m >= ms);
-            }
-            if (use) x = F[(size_t)b * fstride + ((size_t)am * hstride + ring) * 4 + c];
-        }
-        v[k] = (float)x;
-    }
-    store_elem<FMT>(H + i * 2, v);
+    for (int k = 0; k < SG; ++k) v[k] = sh[row * RS + k8 * SG + k];
+    const int kr_tot = rpad / SG;
+    store_elem<FMT>(H + (((size_t)mc * kr_tot + kr0 + k8) * rpad_rows + 4 * PK_B * tb + row) * 2, v);
 }
 
 // ------------------------------------------------------------------ contractions
@@ -608,8 +646,8 @@ hipError_t launch_pack_a(hipStream_t st, int fmt, const MfmaGeom &g, int n, int 
                          long long mstride, const double2 *flmA, const double2 *flmB, const double *wA,
                          const double *wB, uint4 *A)
 {
-    const size_t tot = (size_t)mcn * g.kc * g.rows;
-    const dim3 grid((unsigned)((tot + 255) / 256)), block(256);
+    if (g.rows % (4 * PK_B) != 0) return hipErrorInvalidValue;   // whole 8-map tiles of rows
+    const dim3 grid((unsigned)g.kc, (unsigned)(g.rows / (4 * PK_B)), (unsigned)((mcn + PK_M - 1) / PK_M)), block(256);
     if (fmt == S2_CONTRACT_FP32)
         hipLaunchKernelGGL(k_pack_a<S2_CONTRACT_FP32>, grid, block, 0, st, g.L, n, m_lo, mcn, g.kc, g.rows, B,
                            mstride, flmA, flmB, wA, wB, A);
@@ -624,8 +662,8 @@ hipError_t launch_pack_h(hipStream_t st, int fmt, const MfmaGeom &g, int hstride
                          const double *csc, int m_lo, int mcn, int B, long long fstride, const double *FA,
                          const double *FB, uint4 *H)
 {
-    const size_t tot = (size_t)mcn * (g.rpad / SG) * g.rows;
-    const dim3 grid((unsigned)((tot + 255) / 256)), block(256);
+    if (g.rows % (4 * PK_B) != 0 || g.rpad % 64 != 0) return hipErrorInvalidValue;   // whole tiles
+    const dim3 grid((unsigned)(g.rpad / 64), (unsigned)(g.rows / (4 * PK_B)), (unsigned)mcn), block(256);
     if (fmt == S2_CONTRACT_FP32)
         hipLaunchKernelGGL(k_pack_h<S2_CONTRACT_FP32>, grid, block, 0, st, m_lo, mcn, g.rpad, g.nreg, hstride, g.rows,
                            B, fstride, n, cot, csc, FA, FB, H);

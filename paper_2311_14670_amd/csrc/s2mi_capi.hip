@@ -804,7 +804,10 @@ static int plan_create_impl(s2_plan_t *out, int L, int spin, int N, s2_sampling_
         P->kg += (size_t)P->nx * g.lrow;                     // rows m in [-nx, L)
         PLANCHK(launch_kg_table(st, L, P->nx, g.lrow, P->kap, P->gtab, P->kg), "kappa/g table");
         const size_t per_m_d = std::max((size_t)g.kc * g.rpad, (size_t)(g.rpad / 8) * g.lp) * 32;
-        P->mch = (int)std::max<size_t>(4, std::min<size_t>((size_t)L, ((size_t)512 << 20) / per_m_d));
+        // up to 4 GiB of staged D (256 orders at L = 2048): larger chunks mean fewer, larger
+        // generator and product launches (64 maps at L = 2048, FP32 pair: 32 orders per
+        // chunk 145 ms, 64: 130 ms, 128: 123 ms, 256: 119 ms; split BF16 115 -> 101 ms)
+        P->mch = (int)std::max<size_t>(4, std::min<size_t>((size_t)L, ((size_t)4 << 30) / per_m_d));
         // S2MI_MFMA_ORDER_CHUNK=k stages k orders of D per generator launch instead (tests: the
         // recursion state carried across order chunks at small L; results do not depend on it)
         if (const char *mc = std::getenv("S2MI_MFMA_ORDER_CHUNK")) {

@@ -203,16 +203,18 @@ def _orders(L):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("L,spin", [(640, 0), (640, 2), (1024, 0), (1024, 2)])
-def test_full_size_chunked(binding, prec, L, spin):
-    """Sizes where the generator stages D in several order chunks (L = 640: 2 per
-    run, L = 1024: 8), against the oracle on sampled rings and orders of the
-    first and last map."""
+def test_full_size_chunked(binding, monkeypatch, prec, L, spin):
+    """Full sizes with the generator staging D in four order chunks per run (the
+    state carried across them), against the oracle on sampled rings and orders of
+    the first and last map."""
     B = 4
     flm = flm_gaussian(L, spin, seed=30, batch=B, scale="inv1pl")
+    monkeypatch.setenv("S2MI_MFMA_ORDER_CHUNK", str(L // 4))
     plan = binding.Plan(L, spin=spin, max_batch=B, precision=prec)
+    monkeypatch.delenv("S2MI_MFMA_ORDER_CHUNK")
     f, nchunk = _dgen_launches(plan, plan.inverse, dev(flm))
     runs = 1 if spin == 0 else 2
-    assert nchunk >= 2 * runs, nchunk
+    assert nchunk >= 4 * runs, nchunk
     rings = _rings(L)
     ms = _orders(L)
     for b in (0, B - 1):

@@ -165,6 +165,7 @@ int factor_radices(int n, std::vector<int> &rad)
     while (n % 8 == 0) { rad.push_back(8); n /= 8; }
     while (n % 4 == 0) { rad.push_back(4); n /= 4; }
     while (n % 2 == 0) { rad.push_back(2); n /= 2; }
+    while (n % 9 == 0) { rad.push_back(9); n /= 9; }       // one stage instead of two radix-3 ones
     for (int p : {13, 11, 7, 5, 3})
         while (n % p == 0) { rad.push_back(p); n /= p; }
     return n;

@@ -3,7 +3,7 @@
 // half-sample shifts.
 //
 // Engine: self-sorting (Stockham) mixed-radix FFT over radices
-// {2,3,4,5,7,8,11,13}, in place in LDS: every stage reads all its butterfly
+// {2,3,4,5,7,8,9,11,13}, in place in LDS: every stage reads all its butterfly
 // inputs into registers, synchronises, then writes.  Lengths with a larger
 // prime factor go through Bluestein's chirp-z identity
 //   X_k = conj(c_k) sum_j (x_j conj(c_j)) c_{k-j},  c_j = e^{i pi j^2 / n},
@@ -117,6 +117,37 @@ __device__ __forceinline__ void dft_small_store(double2 (&v)[R], int sign, doubl
         out[6 * os] = csub(E2, t2);
         out[3 * os] = cadd(E3, t3);
         out[7 * os] = csub(E3, t3);
+    } else if constexpr (R == 9) {
+        // 9 = 3 x 3: with r = 3j + k and q = p + 3s, y_q = sum_k w9^{kp} w3^{ks}
+        // (sum_j v_{3j+k} w3^{jp}): three radix-3 DFTs, twiddles, three more
+        constexpr double c3 = -0.5, s3 = 0.86602540378443864676;   // cos, sin of 2 pi / 3
+        auto dft3 = [sign](double2 a, double2 b, double2 c, double2 &y0, double2 &y1, double2 &y2) {
+            const double2 t = cadd(b, c), d = csub(b, c);
+            y0 = cadd(a, t);
+            const double2 mid = make_double2(fma(c3, t.x, a.x), fma(c3, t.y, a.y));
+            const double2 rot = cmuli(make_double2(s3 * d.x, s3 * d.y), sign);   // sign i s3 (b - c)
+            y1 = cadd(mid, rot);
+            y2 = csub(mid, rot);
+        };
+        double2 t[3][3];                                  // t[k][p]
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dft3(v[k], v[3 + k], v[6 + k], t[k][0], t[k][1], t[k][2]);
+        const double sg = sign < 0 ? -1.0 : 1.0;          // w9^e = cos(2 pi e / 9) + sign i sin(2 pi e / 9)
+        const double2 w1 = make_double2(0.76604444311897803520, sg * 0.64278760968653932632);
+        const double2 w2 = make_double2(0.17364817766693034885, sg * 0.98480775301220805937);
+        const double2 w4 = make_double2(-0.93969262078590838405, sg * 0.34202014332566873304);
+        t[1][1] = cmul(t[1][1], w1);
+        t[1][2] = cmul(t[1][2], w2);
+        t[2][1] = cmul(t[2][1], w2);
+        t[2][2] = cmul(t[2][2], w4);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            double2 y0, y1, y2;
+            dft3(t[0][p], t[1][p], t[2][p], y0, y1, y2);
+            out[p * os] = y0;
+            out[(p + 3) * os] = y1;
+            out[(p + 6) * os] = y2;
+        }
     } else {
         constexpr int H = (R - 1) / 2;
         double2 y0 = v[0];
@@ -223,6 +254,7 @@ __device__ __forceinline__ void fft_engine(double2 *buf, const FftArgs *f, int s
         case 5: fft_stage_nb<5>(buf, len, Ns, tw, sign); break;
         case 7: fft_stage_nb<7>(buf, len, Ns, tw, sign); break;
         case 8: fft_stage_nb<8>(buf, len, Ns, tw, sign); break;
+        case 9: fft_stage_nb<9>(buf, len, Ns, tw, sign); break;
         case 11: fft_stage_nb<11>(buf, len, Ns, tw, sign); break;
         default: fft_stage_nb<13>(buf, len, Ns, tw, sign); break;
         }

@@ -703,11 +703,13 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
 }
 
 // The main-loop order of a run whose two sides read one spectra array (SAME: run
-// n = 0 of an unpaired sampling, m > 0): the wave's lambda and spectra rows and the
-// lane's kappa and g are reached through pointers that step back one order at a
-// time, so an order carries no index arithmetic, and kappa and g of the next order
-// are plain loads (in the main loop every lane's degree has started, l > m; lanes
-// past L read row entries of L - 1 and are never stored).
+// n = 0, m > 0; a paired sweep reads the sums or the differences by the order's
+// parity, and the caller passes the row of the array that this order reads): the
+// wave's lambda and spectra rows and the lane's kappa and g are reached through
+// pointers that step back (hstep: the spectra row's step per call), so an order
+// carries no index arithmetic, and kappa and g of the next order are plain loads (in
+// the main loop every lane's degree has started, l > m; lanes past L read row
+// entries of L - 1 and are never stored).
 template <int NCH, int PAR, bool REAL, int SIDE>
 __device__ __forceinline__ void fwd_step_same(int m, int lane, int w, int W, int L, double (&X)[NCH][SG],
                                               double (&Y)[NCH][SG], int (&E)[NCH][SG], uint32_t &real, double &kk,
@@ -887,12 +889,17 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
         // in the tile
         constexpr uint32_t ALL = (1u << NCH) - 1u;
         const int mlo = max(SAME ? max(an, 1) : an, lo);
-        if constexpr (SAME && !PAIRF) {
+        if constexpr (SAME) {
             // Main loop with every per-order address stepped, not recomputed: the wave's
             // lambda and spectra rows, the lane's kappa / g, the prefetch lanes' lines and
             // each reducer thread's output column move back one order per step.
+            // PAIRF: order m reads the sums (HA) or the differences (HB) by the parity of
+            // m + g; the loop takes two orders per iteration, so each of its two steps
+            // keeps one array and steps its row back two orders at a time.
+            const bool hodd = PAIRF && ((m + g) & 1);
             const double *Lp = lam + (ptrdiff_t)m * lstride + rbase;
-            const double *Hp = HA + ((size_t)m * hstride + rbase) * 4;
+            const double *Hp = (hodd ? HB : HA) + ((size_t)m * hstride + rbase) * 4;
+            const double *Hq = PAIRF ? (hodd ? HA : HB) + ((ptrdiff_t)(m - 1) * hstride + rbase) * 4 : nullptr;
             const double *kp = kap + (ptrdiff_t)m * L + lc;      // kk, gm hold order m already
             const double *gp = gtab + (ptrdiff_t)m * L + lc;
             const int hstep = hstride * 4;
@@ -902,8 +909,9 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             constexpr int PS = 1 + HL;
             const int q = lane % PS;
             int pm = m - PFF - (lane >= PS ? 1 : 0);
+            const double *HP = (PAIRF && ((pm + g) & 1)) ? HB : HA;    // a lane's rows keep their parity
             const char *pa = q == 0 ? reinterpret_cast<const char *>(lam + (ptrdiff_t)pm * lstride + rbase)
-                                    : reinterpret_cast<const char *>(HA + ((ptrdiff_t)pm * hstride + rbase) * 4) +
+                                    : reinterpret_cast<const char *>(HP + ((ptrdiff_t)pm * hstride + rbase) * 4) +
                                           (q - 1) * 128;
             const ptrdiff_t pstep = q == 0 ? 2 * (ptrdiff_t)lstride * 8 : 2 * (ptrdiff_t)hstride * 32;
             const bool plane = lane < 2 * PS;
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             // at order m is dcol[m * 4] (every order of the main loop is > 0 and < l)
             const int rgrp = (int)threadIdx.x >> 8;
             const int rcomp = ((int)threadIdx.x >> 6) & 3;
-            const int lo = 64 * g + lane;
+            const int lo = PAIRF ? 128 * (g >> 1) + 2 * lane + (g & 1) : 64 * g + lane;
             double *dbase = rcomp < 2 ? QA : QB;
             const bool rok = lo < L && dbase != nullptr && (SIDE == 0 || (SIDE == 1) == (rcomp < 2));
             double *dcol = rok ? dbase + (((size_t)blk * L + lo) * L) * 4 + rcomp : nullptr;
@@ -932,20 +940,22 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
                 pa -= pstep;
                 pm -= 2;
             };
+            // one order's step; PAIRF: the second order of each pair reads Hq
+            constexpr int HST = PAIRF ? 2 : 1;
             for (; m - 1 >= mlo && real != ALL; m -= 2) {
                 pull();
                 fwd_step_same<NCH, 0, false, SIDE>(m, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp, lstride,
-                                                   hstep, red);
-                fwd_step_same<NCH, 1, false, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp,
-                                                   lstride, hstep, red);
+                                                   HST * hstep, red);
+                fwd_step_same<NCH, 1, false, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, PAIRF ? Hq : Hp,
+                                                   kp, gp, lstride, HST * hstep, red);
                 reduce_pair(m);
             }
             for (; m - 1 >= mlo; m -= 2) {               // realised: plain contributions
                 pull();
                 fwd_step_same<NCH, 0, true, SIDE>(m, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp, lstride,
-                                                  hstep, red);
-                fwd_step_same<NCH, 1, true, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp,
-                                                  lstride, hstep, red);
+                                                  HST * hstep, red);
+                fwd_step_same<NCH, 1, true, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, PAIRF ? Hq : Hp,
+                                                  kp, gp, lstride, HST * hstep, red);
                 reduce_pair(m);
             }
         }

@@ -349,10 +349,9 @@ __device__ __forceinline__ void inv_reduce(int m, int L, int W, bool good, int m
                                            const double *rb, int blk, double *__restrict__ partA,
                                            double *__restrict__ partB);
 
-// DEFER: write this order's partial sums to LDS and return; the caller reduces four
-// orders after one barrier (eight LDS buffers, indexed by m mod 8).  Otherwise the
-// step reduces its own order after a barrier of its own (two buffers).
-template <int NCH, int PAR, int SIDE = 0, bool PAIR = false, bool DEFER = false>
+// One order of the inverse sweep: its partial sums go to LDS buffer m mod 8 (paired:
+// m mod 4) and the caller reduces four orders (paired: two) after one barrier.
+template <int NCH, int PAR, int SIDE = 0, bool PAIR = false>
 __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bool good, int ms, int ring0, int nreg,
                                          int nsw, int lane,
                                          int w, int W,
@@ -398,15 +397,11 @@ __device__ __forceinline__ void inv_step(int m, int L, int nx, int n, int an, bo
             if (__all(z)) fast |= (1u << g);
         }
     }
-    constexpr int NBUF = DEFER ? 8 : 2;
+    constexpr int NBUF = PAIR ? 4 : 8;
     double *rb = red + (size_t)(m & (NBUF - 1)) * DSTAGE_MAX_WAVES * NA * 64;
 #pragma unroll
     for (int c = 0; c < NA; ++c)
         if (SIDE == 0 || (SIDE == 1) == ((c & 3) < 2)) rb[(w * NA + c) * 64 + lane] = ac[c];
-    if constexpr (!DEFER) {
-        __syncthreads();
-        inv_reduce<SIDE, PAIR>(m, L, W, good, ms, ring0, nreg, nsw, rb, blk, partA, partB);
-    }
 }
 
 // Sum of one order's partials over the waves (LDS buffer rb) and its store.
@@ -463,9 +458,9 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
     const int *__restrict__ mtop, double *__restrict__ partA, double *__restrict__ partB, OrderTiles ot)
 {
     // unpaired sweeps reduce four orders per barrier (eight 16 KB buffers); the paired
-    // sweep, with twice the sums, keeps one barrier per order (two 32 KB buffers)
-    constexpr bool DEFER = !PAIR;
-    __shared__ double red[(DEFER ? 8 : 2) * DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64];
+    // sweep, with twice the sums, two orders per barrier (four 32 KB buffers)
+    constexpr int DORD = PAIR ? 2 : 4;                   // orders per barrier
+    __shared__ double red[2 * DORD * DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64];
     const int an = n < 0 ? -n : n;
     const int lane = threadIdx.x & 63;
     const int w = ufl(threadIdx.x >> 6);
@@ -529,43 +524,33 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
             pf = Cp[(lane % (ROWB / 128)) * 32];
         }
     };
-    if constexpr (DEFER) {
-        // four orders per barrier, their sums in LDS buffers m mod 8; with 8 waves the
-        // two reducer groups take two orders each.  An order's buffer is next written
-        // two iterations on, after the next barrier, which every reducer reaches only
-        // once done here.
-        constexpr size_t SL = (size_t)DSTAGE_MAX_WAVES * 4 * 64;
-        for (int m = mt; m >= bot; m -= 4) {
-            prefetch(m);
-            inv_step<NCH, 0, SIDE, PAIR, DEFER>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
-                                                fast, ct, ncs, initr, C, red, blk, partA, partB);
-            if (m - 1 >= bot)
-                inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y,
-                                                    E, fast, ct, ncs, initr, C, red, blk, partA, partB);
-            if (m - 2 >= bot) {
-                prefetch(m - 2);
-                inv_step<NCH, 0, SIDE, PAIR, DEFER>(m - 2, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y,
-                                                    E, fast, ct, ncs, initr, C, red, blk, partA, partB);
-                if (m - 3 >= bot)
-                    inv_step<NCH, 1, SIDE, PAIR, DEFER>(m - 3, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X,
-                                                        Y, E, fast, ct, ncs, initr, C, red, blk, partA, partB);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (m - q >= bot)
-                    inv_reduce<SIDE, PAIR>(m - q, L, W, good, ms, ring0, nreg, nsw, red + (size_t)((m - q) & 7) * SL,
-                                           blk, partA, partB);
-        }
-    } else {
-        for (int m = mt; m >= bot; m -= 2) {
-            prefetch(m);
-            inv_step<NCH, 0, SIDE, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
-                                         ncs, initr, C, red, blk, partA, partB);
-            if (m - 1 >= bot)
-                inv_step<NCH, 1, SIDE, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
+    // DORD orders per barrier, their sums in LDS buffers m mod 2 DORD; with 8 waves
+    // the two reducer groups take DORD / 2 orders each.  An order's buffer is next
+    // written two iterations on, after the next barrier, which every reducer
+    // reaches only once done here.
+    constexpr int NBUF = 2 * DORD;
+    constexpr size_t SL = (size_t)DSTAGE_MAX_WAVES * (PAIR ? 8 : 4) * 64;
+    for (int m = mt; m >= bot; m -= DORD) {
+        prefetch(m);
+        inv_step<NCH, 0, SIDE, PAIR>(m, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast, ct,
+                                     ncs, initr, C, red, blk, partA, partB);
+        if (m - 1 >= bot)
+            inv_step<NCH, 1, SIDE, PAIR>(m - 1, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
+                                         ct, ncs, initr, C, red, blk, partA, partB);
+        if (DORD == 4 && m - 2 >= bot) {
+            prefetch(m - 2);
+            inv_step<NCH, 0, SIDE, PAIR>(m - 2, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E, fast,
+                                         ct, ncs, initr, C, red, blk, partA, partB);
+            if (m - 3 >= bot)
+                inv_step<NCH, 1, SIDE, PAIR>(m - 3, L, nx, n, an, good, ms, ring0, nreg, nsw, lane, w, W, lb, X, Y, E,
                                              fast, ct, ncs, initr, C, red, blk, partA, partB);
         }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < DORD; ++q)
+            if (m - q >= bot)
+                inv_reduce<SIDE, PAIR>(m - q, L, W, good, ms, ring0, nreg, nsw,
+                                       red + (size_t)((m - q) & (NBUF - 1)) * SL, blk, partA, partB);
     }
     asm volatile("" ::"v"(pf));
 }

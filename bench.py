@@ -325,8 +325,8 @@ def main():
     ap.add_argument("--L", type=int, default=2048)
     ap.add_argument("--spin", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rings", type=int, default=64)
-    ap.add_argument("--cpu-orders", type=int, default=64)
+    ap.add_argument("--cpu-rings", type=int, default=160)
+    ap.add_argument("--cpu-orders", type=int, default=160)
     ap.add_argument("--mixed-batch", type=int, default=64,
                     help="maps per call of the matrix-core (FP32 / split-BF16) comparison; 0 skips it")
     ap.add_argument("--mixed-steps", type=int, default=3)

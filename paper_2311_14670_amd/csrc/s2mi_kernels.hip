@@ -24,7 +24,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <type_traits>
 
 #include "s2mi_fft.h"
 #include "s2mi_internal.h"
@@ -566,35 +565,27 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_inv(
 //   acc(l) = g_m^l sum_{slots} e * H[m][ring]   (e unscaled; see renorm),
 // reduced over the waves in LDS (rotating reducers) and written to
 // QA/QB[blk][l][m].  kappa and g of the next order are loaded one step ahead.
+
 // LDS reduction buffers of the forward sweep.  A two-sided run keeps the four
 // components of an order (A re, A im, B re, B im; W x 4 x 64 sums) in buffer m mod 4;
 // a one-sided run (SIDE 1 / 2) keeps its two (re, im) in buffer m mod 8 of half the
 // size, so the same LDS holds eight orders and its main loop reduces four orders per
 // barrier.  A buffer is rewritten only after a barrier that follows its reduction:
-// two consecutive loop iterations never span more orders than there are buffers.
-template <int SIDE> constexpr int fwd_nc() { return SIDE ? 2 : 4; }
-template <int SIDE>
-__device__ __forceinline__ size_t fwd_boff(int m, int W)
+// two consecutive barrier intervals never span more orders than there are buffers.
+// fwd_boff1: offset of a one-sided run's buffer for order m.
+__device__ __forceinline__ size_t fwd_boff1(int m, int W)
 {
-    constexpr int NB = SIDE ? 8 : 4;
-    return (size_t)(m & (NB - 1)) * W * fwd_nc<SIDE>() * 64;
+    return (size_t)(m & 7) * W * 2 * 64;
 }
 
-// This order's sums to its LDS buffer (wave w, lane).
+// A one-sided run's sums of this order to its LDS buffer (wave w, lane).
 template <int SIDE>
-__device__ __forceinline__ void fwd_put(double *red, int m, int w, int W, int lane, double g, double aAr, double aAi,
-                                        double aBr, double aBi)
+__device__ __forceinline__ void fwd_put1(double *red, int m, int w, int W, int lane, double g, double aAr, double aAi,
+                                         double aBr, double aBi)
 {
-    double *rb = red + fwd_boff<SIDE>(m, W);
-    if constexpr (SIDE == 0) {
-        rb[(w * 4 + 0) * 64 + lane] = aAr * g;
-        rb[(w * 4 + 1) * 64 + lane] = aAi * g;
-        rb[(w * 4 + 2) * 64 + lane] = aBr * g;
-        rb[(w * 4 + 3) * 64 + lane] = aBi * g;
-    } else {
-        rb[(w * 2 + 0) * 64 + lane] = (SIDE == 1 ? aAr : aBr) * g;
-        rb[(w * 2 + 1) * 64 + lane] = (SIDE == 1 ? aAi : aBi) * g;
-    }
+    double *rb = red + fwd_boff1(m, W);
+    rb[(w * 2 + 0) * 64 + lane] = (SIDE == 1 ? aAr : aBr) * g;
+    rb[(w * 2 + 1) * 64 + lane] = (SIDE == 1 ? aAi : aBi) * g;
 }
 
 __device__ __forceinline__ const double2 *init_tab_ptr(const double2 *init, int r0, int m, int L)
@@ -709,7 +700,15 @@ __device__ __forceinline__ void fwd_step(int m, int mend, int g, int l, int L, i
     if (!REAL && (m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
     // this order's sums go to its LDS buffer; the caller reduces two orders after
     // one barrier (fwd_reduce2)
-    fwd_put<SIDE>(red, m, w, W, lane, gcur, aAr, aAi, aBr, aBi);
+    if constexpr (SIDE == 0) {
+        double *rb = red + (size_t)(m & 3) * W * 4 * 64;
+        rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
+        rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
+        rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
+        rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
+    } else {
+        fwd_put1<SIDE>(red, m, w, W, lane, gcur, aAr, aAi, aBr, aBi);
+    }
 }
 
 // The main-loop order of a run whose two sides read one spectra array (SAME: run
@@ -740,7 +739,15 @@ __device__ __forceinline__ void fwd_step_same(int m, int lane, int w, int W, int
     Lp -= lstride;
     Hp -= hstep;
     if (!REAL && (m & (RN - 1)) == 0) renorm_chunks<NCH>(X, Y, E, NCH, real);
-    fwd_put<SIDE>(red, m, w, W, lane, gcur, aAr, aAi, aBr, aBi);
+    if constexpr (SIDE == 0) {
+        double *rb = red + (size_t)(m & 3) * W * 4 * 64;
+        rb[(w * 4 + 0) * 64 + lane] = aAr * gcur;
+        rb[(w * 4 + 1) * 64 + lane] = aAi * gcur;
+        rb[(w * 4 + 2) * 64 + lane] = aBr * gcur;
+        rb[(w * 4 + 3) * 64 + lane] = aBi * gcur;
+    } else {
+        fwd_put1<SIDE>(red, m, w, W, lane, gcur, aAr, aAi, aBr, aBi);
+    }
 }
 
 // Sum of order m's partials over the WT waves (its LDS buffer) and its store to
@@ -750,13 +757,15 @@ __device__ __forceinline__ void fwd_reduce(int m, int g, int L, int nxp, int n, 
                                            double *__restrict__ QA, double *__restrict__ QB, double *__restrict__ QxA,
                                            double *__restrict__ QxB)
 {
-    const double *rb = red + fwd_boff<SIDE>(m, WT);
+    const double *rb = SIDE == 0 ? red + (size_t)(m & 3) * WT * 4 * 64 : red + fwd_boff1(m, WT);
     const int am = MAIN ? m : (m < 0 ? -m : m);
     const int tr = (int)threadIdx.x - 256 * reducer_group(m, WT);
     if (tr >= 0 && tr < 256 && (SIDE == 0 || (SIDE == 1) == (tr < 128))) {
         const int ll = tr & 63, comp = tr >> 6;
         const int lo = PAIRF ? 128 * (g >> 1) + 2 * ll + (g & 1) : 64 * g + ll;
-        const double s = wave_sum<WT, fwd_nc<SIDE>()>(rb, SIDE ? (comp & 1) : comp, ll, WT);
+        double s;
+        if constexpr (SIDE == 0) s = wave_sum<WT>(rb, comp, ll, WT);
+        else s = wave_sum<WT, 2>(rb, comp & 1, ll, WT);
         if (MAIN) {
             if (lo < L && lo >= m && (m > 0 || comp < 2)) {
                 double *dst = comp < 2 ? QA : QB;
@@ -925,25 +934,33 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             double *dbase = rcomp < 2 ? QA : QB;
             const bool rok = lo < L && dbase != nullptr && (SIDE == 0 || (SIDE == 1) == (rcomp < 2));
             double *dcol = rok ? dbase + (((size_t)blk * L + lo) * L) * 4 + rcomp : nullptr;
-            // one barrier, then the reductions of orders mm .. mm - NO + 1 (four orders:
-            // a rolled loop, so that the loads of one order's sum are live at a time)
-            auto reduce_one = [&](int mo) {
-                if (rok && rgrp == reducer_group(mo, WT)) {
-                    const double *rb = red + fwd_boff<SIDE>(mo, WT);
-                    dcol[(size_t)mo * 4] = wave_sum<WT, fwd_nc<SIDE>()>(rb, SIDE ? (rcomp & 1) : rcomp, lane, WT);
-                }
-            };
-            auto reduce_orders = [&](int mm, auto no) {
+            auto reduce_pair = [&](int mm) {
                 __syncthreads();
-                if constexpr (decltype(no)::value == 2) {
-                    reduce_one(mm);
-                    reduce_one(mm - 1);
-                } else {
-#pragma unroll 1
-                    for (int o = 0; o < decltype(no)::value; ++o) reduce_one(mm - o);
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const int mo = mm - o;
+                    if (rok && rgrp == reducer_group(mo, WT)) {
+                        if constexpr (SIDE == 0) {
+                            const double *rb = red + (size_t)(mo & 3) * WT * 4 * 64;
+                            dcol[(size_t)mo * 4] = wave_sum<WT>(rb, rcomp, lane, WT);
+                        } else {
+                            dcol[(size_t)mo * 4] = wave_sum<WT, 2>(red + fwd_boff1(mo, WT), rcomp & 1, lane, WT);
+                        }
+                    }
                 }
             };
-            auto reduce_pair = [&](int mm) { reduce_orders(mm, std::integral_constant<int, 2>{}); };
+            // one-sided runs: one barrier, then the reductions of four orders (a rolled
+            // loop, so that the loads of one order's sum are live at a time)
+            auto reduce_quad = [&](int mm) {
+                __syncthreads();
+#pragma unroll 1
+                for (int o = 0; o < 4; ++o) {
+                    const int mo = mm - o;
+                    if (rok && rgrp == reducer_group(mo, WT)) {
+                        dcol[(size_t)mo * 4] = wave_sum<WT, 2>(red + fwd_boff1(mo, WT), rcomp & 1, lane, WT);
+                    }
+                }
+            };
             auto pull = [&]() {
                 asm volatile("" ::"v"(pf));
                 if (plane && pm >= an) pf = *reinterpret_cast<const int *>(pa);
@@ -956,21 +973,18 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
             // iteration (four orders per barrier), the last pair pending at most (not
             // the paired one-sided run: there the deferral costs registers and spills)
             bool pend = false;
-            auto reduce_step = [&](int mm) {
-                if constexpr (SIDE == 0 || PAIRF) {
-                    reduce_pair(mm);
-                } else {
-                    if (pend) reduce_orders(mm + 2, std::integral_constant<int, 4>{});
-                    pend = !pend;
-                }
-            };
             for (; m - 1 >= mlo && real != ALL; m -= 2) {
                 pull();
                 fwd_step_same<NCH, 0, false, SIDE>(m, lane, w, W, L, X, Y, E, real, kk, gm, Lp, Hp, kp, gp, lstride,
                                                    HST * hstep, red);
                 fwd_step_same<NCH, 1, false, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, PAIRF ? Hq : Hp,
                                                    kp, gp, lstride, HST * hstep, red);
-                reduce_step(m);
+                if constexpr (SIDE == 0 || PAIRF) {
+                    reduce_pair(m);
+                } else {
+                    if (pend) reduce_quad(m + 2);
+                    pend = !pend;
+                }
             }
             for (; m - 1 >= mlo; m -= 2) {               // realised: plain contributions
                 pull();
@@ -978,9 +992,15 @@ __global__ __launch_bounds__(64 * WT) void k_dstage_fwd(
                                                   HST * hstep, red);
                 fwd_step_same<NCH, 1, true, SIDE>(m - 1, lane, w, W, L, X, Y, E, real, kk, gm, Lp, PAIRF ? Hq : Hp,
                                                   kp, gp, lstride, HST * hstep, red);
-                reduce_step(m);
+                if constexpr (SIDE == 0 || PAIRF) {
+                    reduce_pair(m);
+                } else {
+                    if (pend) reduce_quad(m + 2);
+                    pend = !pend;
+                }
             }
-            if (pend) reduce_pair(m + 2);                // the last pair's orders m + 2, m + 1
+            if constexpr (SIDE != 0 && !PAIRF)
+                if (pend) reduce_pair(m + 2);            // the last pair's orders m + 2, m + 1
         }
         for (; m - 1 >= mlo && real != ALL; m -= 2) {
             prefetch(m);

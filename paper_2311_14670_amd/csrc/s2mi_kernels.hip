@@ -1129,9 +1129,12 @@ __global__ __launch_bounds__(1024) void k_phi_inv(
     const FftArgs *f = ffts + ring_fft[r];
     const int shift = ring_shift[r];
     const int M = 2 * L - 1;
-    if (r < nreg && nphi == M) {
-        // one bin per order (MW): a thread per |m| reads whole 32-byte records (order +|m|
-        // in components 0,1, order -|m| in 2,3) and fills bins |m| and nphi - |m|
+    if (r < nreg && nphi >= M) {
+        // at most one order per bin (MW, and rings of nphi >= 2L - 1 samples: HEALPix
+        // belt, DH, MWSS): a thread per |m| reads whole 32-byte records (order +|m| in
+        // components 0,1, order -|m| in 2,3) and fills bins |m| and nphi - |m|; the bins
+        // L .. nphi - L that no order reaches are zero
+        for (int k = L + tid; k <= nphi - L; k += T) buf[k] = make_double2(0.0, 0.0);
         const double *pr = part + (size_t)r * L * 4;
         const size_t bstride = (size_t)nreg * L * 4;
         for (int am = tid; am < L; am += T) {

@@ -89,6 +89,24 @@ def test_mw_radix9_ring_lengths(binding, L, spin):
         assert fp64_err(ar, oracle.s2_forward_real(gr, L)) < 1e-13
 
 
+@pytest.mark.parametrize("waves", ["4", "8", "16"])
+@pytest.mark.parametrize("L", [96, 97, 98, 99])
+def test_one_sided_forward_four_order_reduction(binding, monkeypatch, L, waves):
+    """One-sided forward runs (spin s != 0, where the runs n = -s and n = +s each feed
+    one side; real signals, orders m >= 0 only) reduce four orders per barrier in
+    their main loop and flush a last pending pair when the loop's pair count is odd.
+    Consecutive band-limits give both counts, and the forward workgroups are forced
+    to 4, 8 and 16 waves (one, two and four reducer groups).  Against the oracle's
+    direct sums."""
+    monkeypatch.setenv("S2MI_FWD_WAVES", waves)
+    g = map_gaussian((L, 2 * L - 1), seed=L)
+    plan = binding.Plan(L, spin=2)
+    assert fp64_err(host(plan.forward(dev(g))), oracle.s2_forward(g, L, 2)) < 1e-13
+    plan0 = binding.Plan(L)
+    gr = np.random.default_rng(L).standard_normal((L, 2 * L - 1))
+    assert fp64_err(host(plan0.forward_real(dev(gr))), oracle.s2_forward_real(gr, L)) < 1e-13
+
+
 @pytest.mark.parametrize("nside,L,spin", [(4, 8, 0), (8, 16, 0), (8, 16, 2), (16, 32, -9)])
 def test_healpix_inverse_and_forward(binding, nside, L, spin):
     tol = 1e-13 if abs(spin) <= 3 else 1e-12

@@ -387,16 +387,21 @@ def main():
     yh = y.cpu().numpy()
     rt_err = float(np.linalg.norm(yh - flm) / np.linalg.norm(flm))
 
-    # dominant kernel and its FP64 roofline
+    # dominant kernel and its FP64 roofline (stages: totals over the timed steps); a
+    # direction's algorithmic flops are split over its launches per step (spin s != 0:
+    # the runs n = -s and n = +s, one side each)
     dom = max(stages, key=lambda s: stages[s][0])
-    dom_ms = stages[dom][0] / max(stages[dom][1], 1)
+    nlaunch = max(stages[dom][1], 1)
+    dom_ms = stages[dom][0] / nlaunch
+    per_step = max(1, round(nlaunch / args.steps))
     flops = algorithmic_flops(L, spin, L)
     if dom in ("dstage_inv", "dstage_fwd"):
-        achieved = flops / (dom_ms * 1e-3) / 1e12
+        per_launch = flops / per_step
+        achieved = per_launch / (dom_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                 "traffic": measured_traffic("k_" + dom, L, spin),
-                "algorithmic_flops_per_launch": flops, "avg_launch_ms": dom_ms}
+                "algorithmic_flops_per_launch": per_launch, "avg_launch_ms": dom_ms, "launches_per_step": per_step}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "avg_launch_ms": dom_ms}
